@@ -1,0 +1,24 @@
+"""Compile the CPU oracle (plain C, FP64, OpenMP) into oracle/liboracle.so.
+
+Test infrastructure: building the checker is not using it.
+"""
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def build(verbose: bool = False) -> str:
+    out = os.path.join(_HERE, "liboracle.so")
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+           os.path.join(_HERE, "hisq_oracle.c"), "-o", tmp, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
