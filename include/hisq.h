@@ -1,0 +1,173 @@
+/*
+ * hisq.h -- C ABI of libhisq.so: the improved-staggered (HISQ) Dslash and the
+ * even-odd conjugate-gradient solves it drives, on one AMD MI355X (gfx950).
+ *
+ * Paper: R. Li, S. Gottlieb, "Staggered Dslash Performance on Intel Xeon Phi
+ * Architecture", Lattice 2014.  Sec. 3 defines the operator's per-site work
+ * (for each of the 8 directions +-mu a one-link "fat" matrix times the
+ * nearest neighbour and a three-link "long" matrix times the third-nearest
+ * neighbour: 16 matrix-vector products and 15 vector sums, 1146 flops) and
+ * puts it inside single-mass and multi-shift CG; Sec. 4 solves on one parity
+ * (even-odd preconditioning) with the staggered phases folded into the links.
+ *
+ * Conventions shared by every call
+ *   dims[4]   = {Lx, Ly, Lz, Lt}; each extent even and >= 4, else HISQ_EDIMS.
+ *             V = Lx*Ly*Lz*Lt sites, Vh = V/2 sites per parity.
+ *   sites     lex = x + Lx*(y + Ly*(z + Lz*t)); parity = (x+y+z+t) mod 2.
+ *   vectors   one parity, [h][color] complex, h = lex >> 1 (Vh x 3 complex).
+ *             complex128 (interleaved double re, im) for HISQ_F64,
+ *             complex64 (interleaved float) for HISQ_F32 and HISQ_F16S.
+ *   canonical links (input of hisq_pack_links): complex128
+ *             [mu = x,y,z,t][lex][row][col], staggered phases and the time
+ *             boundary sign already folded in (Sec. 4 absorbs the phases into
+ *             the gauge field), so the library indexes periodically.
+ *   operator  (D psi)(n) = sum_mu F_mu(n) psi(n+mu) - F_mu(n-mu)^dag psi(n-mu)
+ *                               + L_mu(n) psi(n+3mu) - L_mu(n-3mu)^dag psi(n-3mu)
+ *             (no factor 1/2); M = 2m + D; the even-odd system is
+ *             A x_e = b_e with A = 4 m^2 - D_eo D_oe, Hermitian positive definite.
+ *
+ * Memory: every pointer argument that names a field is DEVICE memory owned by
+ * the caller (for instance a torch tensor's data_ptr()); the library never
+ * frees caller memory and does not allocate device memory on the solve path:
+ * solvers take a caller-provided workspace sized by hisq_workspace_bytes().
+ * `stream` is a hipStream_t (NULL = the null stream).  Calls are asynchronous
+ * on `stream` except the solvers, which return when the solve has finished.
+ *
+ * Errors: every int-returning call returns HISQ_OK (0) or a negative
+ * hisq_status; hisq_last_error() gives a message (thread-local, valid until
+ * the next call on the same thread).  Errors of asynchronous GPU work surface
+ * at the next synchronising call as HISQ_EHIP.  No C++ exception crosses the
+ * ABI.
+ */
+#ifndef HISQ_H
+#define HISQ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HISQ_OK = 0,
+    HISQ_EINVAL = -1,      /* bad argument (NULL pointer, bad enum, bad size) */
+    HISQ_EDIMS = -2,       /* a lattice extent is odd or < 4 */
+    HISQ_EALIAS = -3,      /* an output buffer aliases an input */
+    HISQ_EHIP = -4,        /* HIP runtime error */
+    HISQ_ENOCONV = -5,     /* max_iter reached before tol (x holds the last iterate) */
+    HISQ_EBREAKDOWN = -6,  /* <p, A p> <= 0 or not finite */
+    HISQ_EWORKSPACE = -7   /* workspace NULL or smaller than hisq_workspace_bytes() */
+} hisq_status;
+
+/* Storage precision of links and vectors.
+ * HISQ_F64  : FP64 links and vectors.
+ * HISQ_F32  : FP32 links and vectors.
+ * HISQ_F16S : FP16 links with one FP32 scale per (site, direction, field)
+ *             matrix (the largest |re|, |im| of its 18 reals), FP32 vectors. */
+typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16S = 2 } hisq_prec;
+
+/* CG modes.
+ * PLAIN_F64  : every step in FP64.
+ * MIXED_F32  : FP32 Dslash and vector updates inside, FP64 dot-product
+ *              accumulation, FP64 reliable updates of the true residual
+ *              (x += x_inner, r = b - A x in FP64) and FP64 final residual.
+ * MIXED_F16S : as MIXED_F32 with HISQ_F16S links in the inner Dslash. */
+enum { HISQ_CG_PLAIN_F64 = 0, HISQ_CG_MIXED_F32 = 1, HISQ_CG_MIXED_F16S = 2 };
+
+/* cg_solve_multi modes.
+ * MULTI_RHS   : nrhs independent systems (A + 4 m_i^2 - 4 m_0^2 ...) i.e.
+ *               A(m_i) x_i = b_i, all sharing one Dslash launch per
+ *               application (each link load serves every right-hand side).
+ * MULTI_SHIFT : one source b, nrhs masses: A(m_i) x_i = b, solved together
+ *               by shifted CG (one Dslash pair per iteration for all shifts),
+ *               then each x_i refined to tol by reliable-update CG. */
+enum { HISQ_MULTI_RHS = 0, HISQ_MULTI_SHIFT = 1 };
+
+typedef struct {
+    int mode;          /* HISQ_CG_* */
+    int max_iter;      /* iteration cap over the whole solve (default 100000 if <= 0) */
+    int check_every;   /* iterations between host convergence checks (<= 0: automatic) */
+    int use_graph;     /* 1: replay check_every iterations as one captured HIP graph */
+    double delta;      /* reliable-update trigger |r| < delta * max|r| (<= 0: 0.1) */
+} hisq_cg_opts;
+
+typedef struct {
+    int iters;              /* CG iterations (sloppy iterations for mixed modes) */
+    int reliable_updates;   /* FP64 true-residual recomputations */
+    int restarts;           /* plain mode: restarts after a failed final check */
+    int status;             /* hisq_status of this solve */
+    double true_resid;      /* |b - A x| / |b| recomputed in FP64 on the GPU */
+    double time_s;          /* wall time of the solve, first kernel to final check */
+} hisq_cg_stats;
+
+/* Library version string. */
+const char *hisq_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *hisq_last_error(void);
+
+/* Bytes of ONE packed link field (fat or long) in precision `prec`, or 0 on
+ * bad arguments.  The packed form stores, for every site of each parity and
+ * for each of the 8 directions +-mu, the matrix that multiplies the
+ * neighbour: F_mu(n) for +mu and -F_mu(n-mu)^dag for -mu (Sec. 4 stores
+ * forward and backward links at every site for locality), in 64-site tiles
+ * ordered [parity][tile][direction][element plane][site in tile]. */
+size_t hisq_packed_link_bytes(const int dims[4], int prec);
+
+/* Pack canonical links (device, complex128, layout above) into the packed
+ * form of `prec` at fat_out / long_out (device, hisq_packed_link_bytes()
+ * each).  `hop` of the fat field is 1 and of the long field 3 (Sec. 3: one-
+ * and three-link terms).  Asynchronous on `stream`. */
+int hisq_pack_links(const void *fat_canon, const void *long_canon, const int dims[4], int prec, void *fat_out,
+                    void *long_out, void *stream);
+
+/* dst = D src on the sites of parity `parity` (src lives on 1 - parity):
+ * the Sec. 3 operator with 16 link matrices and 16 neighbour vectors per
+ * site.  fat/lng: packed links of precision `prec`; src/dst: Vh x 3 complex
+ * vectors of that precision's vector type.  src == dst -> HISQ_EALIAS.
+ * Asynchronous on `stream`. */
+int dslash_apply(const void *fat, const void *lng, const void *src, void *dst, int parity, const int dims[4],
+                 int prec, void *stream);
+
+/* y = A x = 4 m^2 x - D_eo (D_oe x) on the even sites (Sec. 4 even-odd
+ * system).  tmp: Vh x 3 vector scratch (odd sites).  x, y, tmp distinct.
+ * Asynchronous on `stream`. */
+int hisq_apply_A(double mass, const void *fat, const void *lng, const void *x, void *y, void *tmp,
+                 const int dims[4], int prec, void *stream);
+
+/* Deterministic FP64 reductions over n complex entries of precision `prec`
+ * vectors: out_host[0] = Re <x, y>, out_host[1] = Im <x, y> (y == x gives
+ * |x|^2).  Fixed order: wave64 tree, per-workgroup partials, one fixed final
+ * sum; results are bitwise reproducible.  Synchronises `stream`. */
+int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *stream);
+
+/* Workspace bytes for `solver` = "cg", "cg_multi" or "fcg" on `dims` with
+ * `nrhs` right-hand sides (1 for cg), `mode` (HISQ_CG_* for cg/fcg,
+ * HISQ_MULTI_* for cg_multi) and `channels` (fcg only).  0 on bad arguments. */
+size_t hisq_workspace_bytes(const char *solver, const int dims[4], int nrhs, int mode, int channels);
+
+/* Solve A(mass) x = b on the even sites to |b - A x| <= tol |b| (Sec. 3 CG;
+ * Sec. 4 even-odd).  fat/lng: HISQ_F64 packed links.  fat_lo/lng_lo:
+ * HISQ_F32 (MIXED_F32) or HISQ_F16S (MIXED_F16S) packed links, NULL for
+ * PLAIN_F64.  b, x: complex128 Vh x 3; x holds x0 on entry and the solution
+ * on exit (also on HISQ_ENOCONV).  opts NULL = plain FP64 defaults.  stats
+ * (may be NULL) is always written.  Returns when the solve has finished. */
+int cg_solve(double mass, double tol, const void *fat, const void *lng, const void *fat_lo, const void *lng_lo,
+             const void *b, void *x, const int dims[4], const hisq_cg_opts *opts, void *workspace,
+             size_t ws_bytes, hisq_cg_stats *stats, void *stream);
+
+/* Batched solves for nrhs masses (Sec. 3: multishift CG over 9 or 11
+ * masses).  masses: host array [nrhs].  b: complex128 [nrhs][Vh][3]
+ * (MULTI_RHS) or [Vh][3] (MULTI_SHIFT); x: complex128 [nrhs][Vh][3], solved
+ * from x0 = 0.  fat/lng: F64 packed links; fat_lo/lng_lo: F32 packed links
+ * (the inner precision).  stats: host array [nrhs] (may be NULL). */
+int cg_solve_multi(int nrhs, const double *masses, double tol, int mode, const void *fat, const void *lng,
+                   const void *fat_lo, const void *lng_lo, const void *b, void *x, const int dims[4],
+                   const hisq_cg_opts *opts, void *workspace, size_t ws_bytes, hisq_cg_stats *stats,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISQ_H */

@@ -62,6 +62,8 @@ def _load():
     lib.or_cg.argtypes = [ip, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, dp, dp,
                           ctypes.POINTER(ctypes.c_int), dp, dp]
     lib.or_cg.restype = ctypes.c_int
+    lib.or_num_threads.argtypes = []
+    lib.or_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -137,6 +139,11 @@ def cg(dims, mass, fat, lng, b, tol=1e-10, max_iter=100000, x0=None, history=Fal
     if history:
         info["history"] = hist[: it.value + 1]
     return x, info
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().or_num_threads())
 
 
 def norm2(x) -> float:

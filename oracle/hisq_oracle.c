@@ -239,3 +239,16 @@ int or_cg(const int L[4], double mass, double tol, int max_iter, const double *f
     free(r); free(p); free(ap); free(tmp);
     return status;
 }
+
+/* number of OpenMP threads the oracle's parallel loops use */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,176 @@
+"""Python binding of libhisq.so: the HISQ Dslash and the even-odd CG solves on MI355X.
+
+Argument marshalling only.  Every function keeps the name of the C-ABI entry
+point it calls (declared in include/hisq.h) and takes torch tensors, whose
+device pointers and the current HIP stream are handed to the library; every
+step of the computation runs in the library's HIP kernels.  There is no CPU
+fallback: importing this package without the built library raises.
+
+Paper: Li & Gottlieb, "Staggered Dslash Performance on Intel Xeon Phi
+Architecture" (Lattice 2014), Sec. 3 (the Dslash and the CG it drives) and
+Sec. 4 (even-odd preconditioning, staggered phases in the links).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhisq.so")
+
+HISQ_F64, HISQ_F32, HISQ_F16S = 0, 1, 2
+HISQ_CG_PLAIN_F64, HISQ_CG_MIXED_F32, HISQ_CG_MIXED_F16S = 0, 1, 2
+HISQ_MULTI_RHS, HISQ_MULTI_SHIFT = 0, 1
+STATUS = {0: "HISQ_OK", -1: "HISQ_EINVAL", -2: "HISQ_EDIMS", -3: "HISQ_EALIAS", -4: "HISQ_EHIP",
+          -5: "HISQ_ENOCONV", -6: "HISQ_EBREAKDOWN", -7: "HISQ_EWORKSPACE"}
+
+# Algorithmic bytes per output site of one Dslash (16 links, one source read,
+# one output write; Sec. 3 counts 16 matrices and 16 vectors per site), and
+# the paper's flop count.
+DSLASH_BYTES_PER_SITE = {HISQ_F64: 16 * 144 + 48 + 48, HISQ_F32: 16 * 72 + 24 + 24, HISQ_F16S: 16 * 40 + 24 + 24}
+DSLASH_FLOPS_PER_SITE = 1146
+
+
+class HisqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CGOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("delta", ctypes.c_double)]
+
+
+class CGStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("status", ctypes.c_int), ("true_resid", ctypes.c_double), ("time_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, sz, d = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_size_t, ctypes.c_double
+    lib.hisq_version.restype = ctypes.c_char_p
+    lib.hisq_last_error.restype = ctypes.c_char_p
+    lib.hisq_packed_link_bytes.argtypes = [ip, ctypes.c_int]
+    lib.hisq_packed_link_bytes.restype = sz
+    lib.hisq_pack_links.argtypes = [vp, vp, ip, ctypes.c_int, vp, vp, vp]
+    lib.dslash_apply.argtypes = [vp, vp, vp, vp, ctypes.c_int, ip, ctypes.c_int, vp]
+    lib.hisq_apply_A.argtypes = [d, vp, vp, vp, vp, vp, ip, ctypes.c_int, vp]
+    lib.hisq_dot.argtypes = [vp, vp, ctypes.c_longlong, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
+    lib.hisq_workspace_bytes.argtypes = [ctypes.c_char_p, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.hisq_workspace_bytes.restype = sz
+    lib.cg_solve.argtypes = [d, d, vp, vp, vp, vp, vp, vp, ip, ctypes.POINTER(CGOpts), vp, sz,
+                             ctypes.POINTER(CGStats), vp]
+    lib.cg_solve_multi.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), d, ctypes.c_int, vp, vp, vp, vp,
+                                   vp, vp, ip, ctypes.POINTER(CGOpts), vp, sz, ctypes.POINTER(CGStats), vp]
+    for name in ("hisq_pack_links", "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = ["hisq_version", "hisq_last_error", "hisq_packed_link_bytes", "hisq_pack_links", "dslash_apply",
+            "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi"]
+
+
+def _dims(dims):
+    return (ctypes.c_int * 4)(*[int(v) for v in dims])
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise HisqError(rc, f"{what}: {_lib.hisq_last_error().decode()}")
+
+
+def hisq_version() -> str:
+    return _lib.hisq_version().decode()
+
+
+def hisq_last_error() -> str:
+    return _lib.hisq_last_error().decode()
+
+
+def hisq_packed_link_bytes(dims, prec) -> int:
+    return int(_lib.hisq_packed_link_bytes(_dims(dims), int(prec)))
+
+
+def hisq_pack_links(fat_canon, long_canon, dims, prec, fat_out, long_out, stream=None):
+    _check(_lib.hisq_pack_links(_ptr(fat_canon), _ptr(long_canon), _dims(dims), int(prec), _ptr(fat_out),
+                                _ptr(long_out), _stream(stream)), "hisq_pack_links")
+
+
+def dslash_apply(fat, lng, src, dst, parity, dims, prec, stream=None):
+    _check(_lib.dslash_apply(_ptr(fat), _ptr(lng), _ptr(src), _ptr(dst), int(parity), _dims(dims), int(prec),
+                             _stream(stream)), "dslash_apply")
+
+
+def hisq_apply_A(mass, fat, lng, x, y, tmp, dims, prec, stream=None):
+    _check(_lib.hisq_apply_A(float(mass), _ptr(fat), _ptr(lng), _ptr(x), _ptr(y), _ptr(tmp), _dims(dims), int(prec),
+                             _stream(stream)), "hisq_apply_A")
+
+
+def hisq_dot(x, y, n, prec, stream=None) -> complex:
+    out = (ctypes.c_double * 2)()
+    _check(_lib.hisq_dot(_ptr(x), _ptr(y), int(n), int(prec), out, _stream(stream)), "hisq_dot")
+    return complex(out[0], out[1])
+
+
+def hisq_workspace_bytes(solver, dims, nrhs=1, mode=0, channels=0) -> int:
+    return int(_lib.hisq_workspace_bytes(solver.encode(), _dims(dims), int(nrhs), int(mode), int(channels)))
+
+
+def cg_solve(mass, tol, fat, lng, fat_lo, lng_lo, b, x, dims, opts: CGOpts | None, workspace, stream=None,
+             raise_on_noconv=False) -> dict:
+    st = CGStats()
+    rc = _lib.cg_solve(float(mass), float(tol), _ptr(fat), _ptr(lng), _ptr(fat_lo), _ptr(lng_lo), _ptr(b), _ptr(x),
+                       _dims(dims), ctypes.byref(opts) if opts is not None else None, _ptr(workspace),
+                       workspace.numel() * workspace.element_size(), ctypes.byref(st), _stream(stream))
+    if rc != 0 and (raise_on_noconv or rc not in (-5, -6)):
+        _check(rc, "cg_solve")
+    d = st.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def cg_solve_multi(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, dims, opts: CGOpts | None, workspace,
+                   stream=None, raise_on_noconv=False) -> list:
+    ms = (ctypes.c_double * nrhs)(*[float(m) for m in masses])
+    st = (CGStats * nrhs)()
+    rc = _lib.cg_solve_multi(int(nrhs), ms, float(tol), int(mode), _ptr(fat), _ptr(lng), _ptr(fat_lo), _ptr(lng_lo),
+                             _ptr(b), _ptr(x), _dims(dims), ctypes.byref(opts) if opts is not None else None,
+                             _ptr(workspace), workspace.numel() * workspace.element_size(), st, _stream(stream))
+    if rc != 0 and (raise_on_noconv or rc not in (-5, -6)):
+        _check(rc, "cg_solve_multi")
+    out = [s.as_dict() for s in st]
+    for o in out:
+        o["rc"] = rc
+    return out
+
+
+from . import fields  # noqa: E402  (device buffers for packed links and vectors)

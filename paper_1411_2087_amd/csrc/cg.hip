@@ -1,0 +1,741 @@
+// Even-odd conjugate gradient on A = 4 m^2 - D_eo D_oe (Sec. 3 CG driven by
+// the Dslash; Sec. 4 even-odd preconditioning), plain FP64 and mixed
+// precision with reliable updates.
+//
+// Everything stays on the GPU: alpha, beta and the residual norms live in a
+// device-resident state block, every dot product is a deterministic
+// two-stage reduction (wave64 butterfly -> per-workgroup partial -> the last
+// workgroup sums the partials in a fixed order), and kernels read the
+// state's `done` flag so iterations queued past convergence cost one launch
+// each and change nothing.  The host only looks at the state every
+// `check_every` iterations; those iterations are replayed as one captured
+// HIP graph.
+//
+// Per iteration (plain FP64):
+//   t  = D_oe p                                         (Dslash, parity 1)
+//   Ap = 4m^2 p - D_eo t ; pAp = Re<p,Ap> ; alpha       (Dslash + fused epilogue)
+//   x += alpha p ; r -= alpha Ap ; rr = |r|^2 ; beta    (one BLAS pass)
+//   p  = r + beta p
+// Mixed precision (Sleijpen & van der Vorst 1996 reliable updates, in the
+// form used for lattice QCD by Clark et al. 2010): the same iteration on FP32
+// vectors with FP32 or FP16+scale links and FP64 dot accumulation; when
+// |r_inner| < delta * max|r_inner| since the last update (or the inner
+// residual meets tol) the FP64 solution absorbs x_inner, the true residual
+// b - A x is recomputed with the FP64 operator and the inner residual is
+// replaced by it.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "cg_internal.hpp"
+
+namespace hisq {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double2 cv(double2 v) { return v; }
+__device__ __forceinline__ double2 cv_d(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 cv_d(double2 v) { return v; }
+
+template <class T> struct VecT;
+template <> struct VecT<double2> { using real = double; };
+template <> struct VecT<float2> { using real = float; };
+
+// ------------------------------------------------------------------ finalisers
+enum {
+    FIN_BB = 0,           // bb = v ; stop2 = tol2 * bb
+    FIN_PAP = 1,          // pAp = v ; alpha or breakdown
+    FIN_UPD_PLAIN = 2,    // rr_new = v ; iter++ ; converged? ; beta ; rr
+    FIN_UPD_MIXED = 3,    // as above, deciding reliable updates
+    FIN_INIT_PLAIN = 4,   // rr = rr_true = v ; done = v <= stop2
+    FIN_TRUE = 5,         // rr_true = v
+    FIN_RELIABLE = 6,     // rr_true = v ; beta = v / rr ; rr = maxrr = v ; reliable = 0 ; done?
+    FIN_INIT_MIXED = 7,   // rr = maxrr = rr_true = v ; done = v <= stop2
+};
+
+__device__ __forceinline__ void finalize(CGState *st, int mode, double v)
+{
+    switch (mode) {
+    case FIN_BB:
+        st->bb = v;
+        st->stop2 = st->tol2 * v;
+        break;
+    case FIN_PAP:
+        st->pAp = v;
+        if (!(v > 0.0) || !isfinite(v)) {
+            st->flags.done = CG_BREAKDOWN;
+        } else {
+            st->alpha = st->rr / v;
+        }
+        break;
+    case FIN_UPD_PLAIN:
+        st->rr_new = v;
+        st->iter += 1;
+        if (!isfinite(v)) {
+            st->flags.done = CG_BREAKDOWN;
+        } else if (v <= st->stop2) {
+            st->flags.done = CG_CONVERGED;
+            st->rr = v;
+        } else {
+            st->beta = v / st->rr;
+            st->rr = v;
+        }
+        break;
+    case FIN_UPD_MIXED:
+        st->rr_new = v;
+        st->iter += 1;
+        if (!isfinite(v)) {
+            st->flags.done = CG_BREAKDOWN;
+        } else if (v <= st->stop2 || v < st->delta2 * st->maxrr) {
+            st->flags.reliable = 1;
+        } else {
+            st->maxrr = fmax(st->maxrr, v);
+            st->beta = v / st->rr;
+            st->rr = v;
+        }
+        break;
+    case FIN_INIT_PLAIN:
+        st->rr = v;
+        st->rr_true = v;
+        st->flags.done = (v <= st->stop2) ? CG_CONVERGED : 0;
+        break;
+    case FIN_TRUE:
+        st->rr_true = v;
+        break;
+    case FIN_RELIABLE:
+        st->rr_true = v;
+        st->nupdates += 1;
+        st->beta = v / st->rr;
+        st->rr = v;
+        st->maxrr = v;
+        st->flags.reliable = 0;
+        if (!isfinite(v)) st->flags.done = CG_BREAKDOWN;
+        else if (v <= st->stop2) st->flags.done = CG_CONVERGED;
+        break;
+    case FIN_INIT_MIXED:
+        st->rr = v;
+        st->maxrr = v;
+        st->rr_true = v;
+        st->flags.reliable = 0;
+        st->flags.done = (v <= st->stop2) ? CG_CONVERGED : 0;
+        break;
+    }
+}
+
+// ------------------------------------------------------------------ BLAS kernels
+constexpr int BL_NT = 256;
+
+int blas_blocks(long long n)
+{
+    long long nb = (n + BL_NT - 1) / BL_NT;
+    return (int)(nb < BLAS_MAX_BLOCKS ? nb : BLAS_MAX_BLOCKS);
+}
+
+// Re<x, y> (or |x|^2) of n complex entries into the state (mode FIN_BB ...).
+template <class T>
+__global__ __launch_bounds__(BL_NT) void k_dot_state(const T *__restrict__ x, const T *__restrict__ y, long long n,
+                                                     double *partials, CGState *st, int cnt, int mode)
+{
+    double s = 0.0;
+    for (long long i = (long long)blockIdx.x * BL_NT + threadIdx.x; i < n; i += (long long)gridDim.x * BL_NT) {
+        double2 a = cv_d(x[i]), b = cv_d(y[i]);
+        s = fma(a.x, b.x, s);
+        s = fma(a.y, b.y, s);
+    }
+    grid_reduce<BL_NT>(s, partials, &st->cnt[cnt], gridDim.x, blockIdx.x,
+                       [&](double v) { finalize(st, mode, v); });
+}
+
+// x += alpha p ; r -= alpha Ap ; |r|^2 -> finaliser
+template <class T>
+__global__ __launch_bounds__(BL_NT) void k_cg_update(T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
+                                                     const T *__restrict__ ap, long long n, double *partials,
+                                                     CGState *st, int mode)
+{
+    if (st->flags.done) return;
+    using R = typename VecT<T>::real;
+    const R alpha = (R)st->alpha;
+    double s = 0.0;
+    for (long long i = (long long)blockIdx.x * BL_NT + threadIdx.x; i < n; i += (long long)gridDim.x * BL_NT) {
+        T pv = p[i], av = ap[i], xv = x[i], rv = r[i];
+        xv.x = fma(alpha, pv.x, xv.x);
+        xv.y = fma(alpha, pv.y, xv.y);
+        rv.x = fma(-alpha, av.x, rv.x);
+        rv.y = fma(-alpha, av.y, rv.y);
+        x[i] = xv;
+        r[i] = rv;
+        s = fma((double)rv.x, (double)rv.x, s);
+        s = fma((double)rv.y, (double)rv.y, s);
+    }
+    grid_reduce<BL_NT>(s, partials, &st->cnt[CNT_UPD], gridDim.x, blockIdx.x,
+                       [&](double v) { finalize(st, mode, v); });
+}
+
+// p = r + beta p
+template <class T>
+__global__ __launch_bounds__(BL_NT) void k_cg_p(T *__restrict__ p, const T *__restrict__ r, long long n,
+                                                const CGState *st)
+{
+    if (st->flags.done) return;
+    using R = typename VecT<T>::real;
+    const R beta = (R)st->beta;
+    for (long long i = (long long)blockIdx.x * BL_NT + threadIdx.x; i < n; i += (long long)gridDim.x * BL_NT) {
+        T pv = p[i], rv = r[i];
+        pv.x = fma(beta, pv.x, rv.x);
+        pv.y = fma(beta, pv.y, rv.y);
+        p[i] = pv;
+    }
+}
+
+// x64 += xs ; xs = 0   (reliable update)
+__global__ __launch_bounds__(BL_NT) void k_accum(double2 *__restrict__ x, float2 *__restrict__ xs, long long n,
+                                                 const CGState *st)
+{
+    if (st->flags.done || !st->flags.reliable) return;
+    for (long long i = (long long)blockIdx.x * BL_NT + threadIdx.x; i < n; i += (long long)gridDim.x * BL_NT) {
+        float2 v = xs[i];
+        double2 a = x[i];
+        a.x += (double)v.x;
+        a.y += (double)v.y;
+        x[i] = a;
+        xs[i] = make_float2(0.f, 0.f);
+    }
+}
+
+__global__ void k_state_init(CGState *st, double tol2, double delta2, double m4)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->flags.done = 0;
+        st->flags.reliable = 0;
+        st->iter = 0;
+        st->nupdates = 0;
+        st->tol2 = tol2;
+        st->delta2 = delta2;
+        st->m4 = m4;
+        st->rr = st->rr_new = st->rr_true = st->maxrr = 0.0;
+        st->alpha = st->beta = st->pAp = 0.0;
+    }
+}
+
+__global__ void k_force_reliable(CGState *st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && !st->flags.done) st->flags.reliable = 1;
+}
+
+__global__ void k_clear_done(CGState *st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->flags.done = 0;
+}
+
+// ------------------------------------------------------------------ Dslash-fused kernels
+// Ap = m4 p - D_eo t ; Re<p, Ap> -> FIN_PAP
+template <class P, int NT>
+__global__ __launch_bounds__(NT) void k_cg_Ap(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
+                                              const typename P::cvec *__restrict__ t,
+                                              const typename P::cvec *__restrict__ p,
+                                              typename P::cvec *__restrict__ ap, int nblocks, double *partials,
+                                              CGState *st)
+{
+    if (st->flags.done) return;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    if (blk >= nblocks) return;
+    const int tile = blk * (NT / TILE) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int h = tile * TILE + lane;
+    double s = 0.0;
+    if (tile < g.ntiles) {
+        const int hc = h < g.Vh ? h : g.Vh - 1;
+        typename P::real acc[6];
+        dslash_site<P>(g, fat, lng, t, 0, tile, lane, hc, acc);
+        if (h < g.Vh) {
+            const typename P::real m = (typename P::real)st->m4;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                typename P::cvec pv = p[(size_t)h * 3 + c], v;
+                v.x = fma(m, pv.x, -acc[2 * c]);
+                v.y = fma(m, pv.y, -acc[2 * c + 1]);
+                ap[(size_t)h * 3 + c] = v;
+                s = fma((double)pv.x, (double)v.x, s);
+                s = fma((double)pv.y, (double)v.y, s);
+            }
+        }
+    }
+    grid_reduce<NT>(s, partials, &st->cnt[CNT_PAP], nblocks, blk, [&](double v) { finalize(st, FIN_PAP, v); });
+}
+
+// r = b - (m4 x - D_eo t) in FP64 ; optional copies ; |r|^2 -> finaliser `mode`
+template <int NT>
+__global__ __launch_bounds__(NT) void k_resid(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
+                                              const double2 *__restrict__ t, const double2 *__restrict__ x,
+                                              const double2 *__restrict__ b, double2 *__restrict__ r,
+                                              double2 *__restrict__ p, float2 *__restrict__ rs,
+                                              float2 *__restrict__ ps, int nblocks, double *partials,
+                                              CGState *st, int mode, int gate)
+{
+    if (gate_closed(&st->flags, gate)) return;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    if (blk >= nblocks) return;
+    const int tile = blk * (NT / TILE) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int h = tile * TILE + lane;
+    double s = 0.0;
+    if (tile < g.ntiles) {
+        const int hc = h < g.Vh ? h : g.Vh - 1;
+        double acc[6];
+        dslash_site<PF64>(g, fat, lng, t, 0, tile, lane, hc, acc);
+        if (h < g.Vh) {
+            const double m = st->m4;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t i = (size_t)h * 3 + c;
+                double2 xv = x[i], bv = b[i], v;
+                v.x = bv.x - fma(m, xv.x, -acc[2 * c]);
+                v.y = bv.y - fma(m, xv.y, -acc[2 * c + 1]);
+                if (r) r[i] = v;
+                if (p) p[i] = v;
+                if (rs) rs[i] = make_float2((float)v.x, (float)v.y);
+                if (ps) ps[i] = make_float2((float)v.x, (float)v.y);
+                s = fma(v.x, v.x, s);
+                s = fma(v.y, v.y, s);
+            }
+        }
+    }
+    grid_reduce<NT>(s, partials, &st->cnt[CNT_RES], nblocks, blk, [&](double v) { finalize(st, mode, v); });
+}
+
+constexpr int CG_NT = 256;
+static inline int dslash_nb(const Geom &g) { return (g.ntiles + CG_NT / TILE - 1) / (CG_NT / TILE); }
+
+// ------------------------------------------------------------------ host side
+size_t cg_partials_count(const Geom &g)
+{
+    size_t a = (size_t)dslash_nb(g), b = (size_t)BLAS_MAX_BLOCKS;
+    return a > b ? a : b;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t cg_workspace_bytes(const Geom &g, int mode)
+{
+    const size_t v64 = align256((size_t)g.Vh * 3 * 16), v32 = align256((size_t)g.Vh * 3 * 8);
+    size_t bytes = align256(sizeof(CGState)) + align256(cg_partials_count(g) * sizeof(double));
+    if (mode == HISQ_CG_PLAIN_F64) bytes += 4 * v64;         // r p Ap t
+    else bytes += 2 * v64 + 5 * v32;                         // r64 t64 | xs rs ps Aps ts
+    return bytes;
+}
+
+// Pinned host mirror of a solver state (one per thread; allocated once).
+CGState *pinned_state()
+{
+    static thread_local CGState *h = nullptr;
+    if (!h) {
+        if (hipHostMalloc((void **)&h, sizeof(CGState) * 64, hipHostMallocDefault) != hipSuccess) h = nullptr;
+    }
+    return h;
+}
+
+hipStream_t capture_stream()
+{
+    static thread_local hipStream_t s = nullptr;
+    if (!s) {
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    }
+    return s;
+}
+
+// Run `iter_fn` (which enqueues one iteration on a stream) until the state
+// reports done or `max_iter` iterations were queued.  Every `K` iterations
+// the state is copied to pinned memory and inspected; with use_graph the K
+// iterations are captured once and replayed.
+template <class IterFn>
+static int run_iterations(IterFn iter_fn, hipStream_t s, CGState *dstate, CGState *hstate, int K, int max_iter,
+                          bool use_graph, int already)
+{
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (use_graph) {
+        hipStream_t cs = capture_stream();
+        if (!cs) return fail(HISQ_EHIP, "cannot create capture stream");
+        HISQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < K; ++k) {
+            hipError_t e = iter_fn(cs);
+            if (e != hipSuccess) {
+                hipGraph_t junk;
+                hipStreamEndCapture(cs, &junk);
+                if (junk) hipGraphDestroy(junk);
+                return hip_fail(e, "CG iteration launch (capture)");
+            }
+        }
+        HISQ_HIP(hipStreamEndCapture(cs, &graph));
+        HISQ_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    int queued = already;
+    int rc = HISQ_OK;
+    while (queued < max_iter) {
+        const int k = (max_iter - queued) < K ? (max_iter - queued) : K;
+        if (use_graph && k == K) {
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) { rc = hip_fail(e, "hipGraphLaunch"); break; }
+        } else {
+            for (int i = 0; i < k; ++i) {
+                hipError_t e = iter_fn(s);
+                if (e != hipSuccess) { rc = hip_fail(e, "CG iteration launch"); break; }
+            }
+            if (rc) break;
+        }
+        queued += k;
+        hipError_t e = hipMemcpyAsync(hstate, dstate, sizeof(CGState), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { rc = hip_fail(e, "CG state read-back"); break; }
+        if (hstate->flags.done) break;
+    }
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    return rc;
+}
+
+static int read_state(CGState *h, const CGState *d, hipStream_t s)
+{
+    HISQ_HIP(hipMemcpyAsync(h, d, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    HISQ_HIP(hipStreamSynchronize(s));
+    return HISQ_OK;
+}
+
+struct Carver {
+    char *p;
+    size_t left;
+    void *take(size_t n)
+    {
+        n = align256(n);
+        if (n > left) return nullptr;
+        void *r = p;
+        p += n;
+        left -= n;
+        return r;
+    }
+};
+
+int cg_plain_f64(double mass, double tol, const void *fat, const void *lng, const void *b, void *x, const Geom &g,
+                 const hisq_cg_opts &o, void *ws, size_t ws_bytes, hisq_cg_stats &stats, hipStream_t s)
+{
+    Carver c{ (char *)ws, ws_bytes };
+    const size_t v64 = (size_t)g.Vh * 3 * 16;
+    CGState *st = (CGState *)c.take(sizeof(CGState));
+    double *part = (double *)c.take(cg_partials_count(g) * sizeof(double));
+    double2 *r = (double2 *)c.take(v64), *p = (double2 *)c.take(v64), *ap = (double2 *)c.take(v64),
+            *t = (double2 *)c.take(v64);
+    if (!t) return fail(HISQ_EWORKSPACE, "cg_solve: workspace too small");
+    CGState *hs = pinned_state();
+    if (!hs) return fail(HISQ_EHIP, "cg_solve: pinned state allocation failed");
+    const long long n = (long long)g.Vh * 3;
+    const int nbl = blas_blocks(n), nbd = dslash_nb(g);
+    const dim3 gb(nbl), bb(BL_NT), gd(xcd_grid(nbd)), bd(CG_NT);
+
+    auto t0 = std::chrono::steady_clock::now();
+    HISQ_HIP(hipMemsetAsync(st, 0, sizeof(CGState), s));
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, tol * tol, 0.0, 4.0 * mass * mass);
+    hipLaunchKernelGGL((k_dot_state<double2>), gb, bb, 0, s, (const double2 *)b, (const double2 *)b, n, part, st,
+                       (int)CNT_DOT, (int)FIN_BB);
+    // r = p = b - A x0
+    HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t, 1, s));
+    hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, s, g, (const char *)fat, (const char *)lng, t,
+                       (const double2 *)x, (const double2 *)b, r, p, (float2 *)nullptr, (float2 *)nullptr, nbd, part,
+                       st, (int)FIN_INIT_PLAIN, (int)GATE_ALWAYS);
+    HISQ_HIP(hipGetLastError());
+    int rc = read_state(hs, st, s);
+    if (rc) return rc;
+    if (hs->bb == 0.0) {
+        HISQ_HIP(hipMemsetAsync(x, 0, v64, s));
+        HISQ_HIP(hipStreamSynchronize(s));
+        stats.iters = 0;
+        stats.true_resid = 0.0;
+        stats.status = HISQ_OK;
+        stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return HISQ_OK;
+    }
+
+    auto iter = [&](hipStream_t q) -> hipError_t {
+        hipError_t e = launch_dslash<PF64>(g, fat, lng, p, t, 1, q, &st->flags, GATE_NOT_DONE);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_cg_Ap<PF64, CG_NT>), gd, bd, 0, q, g, (const char *)fat, (const char *)lng,
+                           (const double2 *)t, (const double2 *)p, ap, nbd, part, st);
+        hipLaunchKernelGGL((k_cg_update<double2>), gb, bb, 0, q, (double2 *)x, r, (const double2 *)p,
+                           (const double2 *)ap, n, part, st, (int)FIN_UPD_PLAIN);
+        hipLaunchKernelGGL((k_cg_p<double2>), gb, bb, 0, q, p, (const double2 *)r, n, (const CGState *)st);
+        return hipGetLastError();
+    };
+
+    const int K = o.check_every;
+    int restarts = 0;
+    int status = HISQ_OK;
+    while (true) {
+        if (!hs->flags.done) {
+            rc = run_iterations(iter, s, st, hs, K, o.max_iter, o.use_graph != 0, hs->iter);
+            if (rc) return rc;
+        }
+        if (hs->flags.done == CG_BREAKDOWN) { status = HISQ_EBREAKDOWN; break; }
+        // true residual r = b - A x in FP64
+        HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t, 1, s));
+        hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, s, g, (const char *)fat, (const char *)lng, t,
+                           (const double2 *)x, (const double2 *)b, r, (double2 *)nullptr, (float2 *)nullptr,
+                           (float2 *)nullptr, nbd, part, st, (int)FIN_TRUE, (int)GATE_ALWAYS);
+        HISQ_HIP(hipGetLastError());
+        rc = read_state(hs, st, s);
+        if (rc) return rc;
+        if (hs->rr_true <= hs->stop2) { status = HISQ_OK; break; }
+        if (hs->iter >= o.max_iter || restarts >= 3) { status = HISQ_ENOCONV; break; }
+        // restart from x: r = p = b - A x
+        ++restarts;
+        hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, s, g, (const char *)fat, (const char *)lng, t,
+                           (const double2 *)x, (const double2 *)b, r, p, (float2 *)nullptr, (float2 *)nullptr, nbd,
+                           part, st, (int)FIN_INIT_PLAIN, (int)GATE_ALWAYS);
+        HISQ_HIP(hipGetLastError());
+        rc = read_state(hs, st, s);
+        if (rc) return rc;
+    }
+    stats.iters = hs->iter;
+    stats.restarts = restarts;
+    stats.reliable_updates = 0;
+    stats.true_resid = std::sqrt(hs->rr_true / hs->bb);
+    stats.status = status;
+    stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (status == HISQ_EBREAKDOWN) return fail(status, "cg_solve: breakdown (<p,Ap> <= 0 or not finite)");
+    if (status == HISQ_ENOCONV) return fail(status, "cg_solve: not converged within max_iter");
+    return HISQ_OK;
+}
+
+template <class PS>
+int cg_mixed(double mass, double tol, const void *fat, const void *lng, const void *fat_lo, const void *lng_lo,
+             const void *b, void *x, const Geom &g, const hisq_cg_opts &o, void *ws, size_t ws_bytes,
+             hisq_cg_stats &stats, hipStream_t s)
+{
+    Carver c{ (char *)ws, ws_bytes };
+    const size_t v64 = (size_t)g.Vh * 3 * 16, v32 = (size_t)g.Vh * 3 * 8;
+    CGState *st = (CGState *)c.take(sizeof(CGState));
+    double *part = (double *)c.take(cg_partials_count(g) * sizeof(double));
+    double2 *r64 = (double2 *)c.take(v64), *t64 = (double2 *)c.take(v64);
+    float2 *xs = (float2 *)c.take(v32), *rs = (float2 *)c.take(v32), *ps = (float2 *)c.take(v32),
+           *aps = (float2 *)c.take(v32), *ts = (float2 *)c.take(v32);
+    if (!ts) return fail(HISQ_EWORKSPACE, "cg_solve: workspace too small");
+    CGState *hs = pinned_state();
+    if (!hs) return fail(HISQ_EHIP, "cg_solve: pinned state allocation failed");
+    const long long n = (long long)g.Vh * 3;
+    const int nbl = blas_blocks(n), nbd = dslash_nb(g);
+    const dim3 gb(nbl), bb(BL_NT), gd(xcd_grid(nbd)), bd(CG_NT);
+    const double delta = o.delta > 0 ? o.delta : 0.1;
+
+    auto t0 = std::chrono::steady_clock::now();
+    HISQ_HIP(hipMemsetAsync(st, 0, sizeof(CGState), s));
+    HISQ_HIP(hipMemsetAsync(xs, 0, v32, s));
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, tol * tol, delta * delta, 4.0 * mass * mass);
+    hipLaunchKernelGGL((k_dot_state<double2>), gb, bb, 0, s, (const double2 *)b, (const double2 *)b, n, part, st,
+                       (int)CNT_DOT, (int)FIN_BB);
+    HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t64, 1, s));
+    hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, s, g, (const char *)fat, (const char *)lng, t64,
+                       (const double2 *)x, (const double2 *)b, r64, (double2 *)nullptr, rs, ps, nbd, part, st,
+                       (int)FIN_INIT_MIXED, (int)GATE_ALWAYS);
+    HISQ_HIP(hipGetLastError());
+    int rc = read_state(hs, st, s);
+    if (rc) return rc;
+    if (hs->bb == 0.0) {
+        HISQ_HIP(hipMemsetAsync(x, 0, v64, s));
+        HISQ_HIP(hipStreamSynchronize(s));
+        stats.iters = 0;
+        stats.true_resid = 0.0;
+        stats.status = HISQ_OK;
+        stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return HISQ_OK;
+    }
+
+    auto iter = [&](hipStream_t q) -> hipError_t {
+        hipError_t e = launch_dslash<PS>(g, fat_lo, lng_lo, ps, ts, 1, q, &st->flags, GATE_NOT_DONE);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_cg_Ap<PS, CG_NT>), gd, bd, 0, q, g, (const char *)fat_lo, (const char *)lng_lo,
+                           (const float2 *)ts, (const float2 *)ps, aps, nbd, part, st);
+        hipLaunchKernelGGL((k_cg_update<float2>), gb, bb, 0, q, xs, rs, (const float2 *)ps, (const float2 *)aps, n,
+                           part, st, (int)FIN_UPD_MIXED);
+        // reliable update (kernels return at once unless it was triggered)
+        hipLaunchKernelGGL(k_accum, gb, bb, 0, q, (double2 *)x, xs, n, (const CGState *)st);
+        e = launch_dslash<PF64>(g, fat, lng, x, t64, 1, q, &st->flags, GATE_RELIABLE);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, q, g, (const char *)fat, (const char *)lng,
+                           (const double2 *)t64, (const double2 *)x, (const double2 *)b, r64, (double2 *)nullptr, rs,
+                           (float2 *)nullptr, nbd, part, st, (int)FIN_RELIABLE, (int)GATE_RELIABLE);
+        hipLaunchKernelGGL((k_cg_p<float2>), gb, bb, 0, q, ps, (const float2 *)rs, n, (const CGState *)st);
+        return hipGetLastError();
+    };
+
+    rc = run_iterations(iter, s, st, hs, o.check_every, o.max_iter, o.use_graph != 0, 0);
+    if (rc) return rc;
+    int status = HISQ_OK;
+    if (hs->flags.done == CG_BREAKDOWN) {
+        status = HISQ_EBREAKDOWN;
+    } else if (hs->flags.done != CG_CONVERGED) {
+        // out of iterations: fold the inner solution in and measure the true residual
+        hipLaunchKernelGGL(k_force_reliable, dim3(1), dim3(1), 0, s, st);
+        hipLaunchKernelGGL(k_accum, gb, bb, 0, s, (double2 *)x, xs, n, (const CGState *)st);
+        HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t64, 1, s));
+        hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, s, g, (const char *)fat, (const char *)lng,
+                           (const double2 *)t64, (const double2 *)x, (const double2 *)b, r64, (double2 *)nullptr, rs,
+                           (float2 *)nullptr, nbd, part, st, (int)FIN_RELIABLE, (int)GATE_ALWAYS);
+        HISQ_HIP(hipGetLastError());
+        rc = read_state(hs, st, s);
+        if (rc) return rc;
+        status = hs->rr_true <= hs->stop2 ? HISQ_OK : HISQ_ENOCONV;
+    }
+    stats.iters = hs->iter;
+    stats.reliable_updates = hs->nupdates;
+    stats.restarts = 0;
+    stats.true_resid = std::sqrt(hs->rr_true / hs->bb);
+    stats.status = status;
+    stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (status == HISQ_EBREAKDOWN) return fail(status, "cg_solve: breakdown (<p,Ap> <= 0 or not finite)");
+    if (status == HISQ_ENOCONV) return fail(status, "cg_solve: not converged within max_iter");
+    return HISQ_OK;
+}
+
+int default_check_every(const Geom &g) { return g.Vh <= 65536 ? 50 : (g.Vh <= 1048576 ? 25 : 10); }
+
+hisq_cg_opts resolve_opts(const hisq_cg_opts *opts, const Geom &g)
+{
+    hisq_cg_opts o;
+    if (opts) o = *opts;
+    else {
+        o.mode = HISQ_CG_PLAIN_F64;
+        o.max_iter = 0;
+        o.check_every = 0;
+        o.use_graph = 1;
+        o.delta = 0.1;
+    }
+    if (o.max_iter <= 0) o.max_iter = 100000;
+    if (o.check_every <= 0) o.check_every = default_check_every(g);
+    if (o.delta <= 0) o.delta = 0.1;
+    return o;
+}
+
+// ------------------------------------------------------------------ standalone dot
+template <class T>
+__global__ __launch_bounds__(BL_NT) void k_dot2(const T *__restrict__ x, const T *__restrict__ y, long long n,
+                                                double *partials, double *out, unsigned *counter)
+{
+    double sr = 0.0, si = 0.0;
+    for (long long i = (long long)blockIdx.x * BL_NT + threadIdx.x; i < n; i += (long long)gridDim.x * BL_NT) {
+        double2 a = cv_d(x[i]), b = cv_d(y[i]);
+        sr = fma(a.x, b.x, sr);
+        sr = fma(a.y, b.y, sr);
+        si = fma(a.x, b.y, si);
+        si = fma(-a.y, b.x, si);
+    }
+    __shared__ double lds[2 * (BL_NT / 64)];
+    __shared__ bool last;
+    block_sum2<BL_NT>(sr, si, lds);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = sr;
+        partials[2 * blockIdx.x + 1] = si;
+        __threadfence();
+        last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double ar = 0.0, ai = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += BL_NT) {
+        ar += __builtin_nontemporal_load(&partials[2 * i]);
+        ai += __builtin_nontemporal_load(&partials[2 * i + 1]);
+    }
+    block_sum2<BL_NT>(ar, ai, lds);
+    if (threadIdx.x == 0) {
+        out[0] = ar;
+        out[1] = ai;
+        *counter = 0u;
+        __threadfence();
+    }
+}
+
+}  // namespace hisq
+
+using namespace hisq;
+
+extern "C" size_t hisq_workspace_bytes(const char *solver, const int dims[4], int nrhs, int mode, int channels)
+{
+    Geom g;
+    if (!solver || make_geom(dims, g)) return 0;
+    if (!std::strcmp(solver, "cg")) {
+        if (mode < HISQ_CG_PLAIN_F64 || mode > HISQ_CG_MIXED_F16S) return 0;
+        return cg_workspace_bytes(g, mode);
+    }
+    if (!std::strcmp(solver, "cg_multi")) return cg_multi_workspace_bytes(g, nrhs, mode);
+    (void)channels;
+    return 0;
+}
+
+extern "C" int cg_solve(double mass, double tol, const void *fat, const void *lng, const void *fat_lo,
+                        const void *lng_lo, const void *b, void *x, const int dims[4], const hisq_cg_opts *opts,
+                        void *workspace, size_t ws_bytes, hisq_cg_stats *stats, void *stream)
+{
+    hisq_cg_stats local;
+    std::memset(&local, 0, sizeof(local));
+    hisq_cg_stats &st = stats ? *stats : local;
+    std::memset(&st, 0, sizeof(st));
+    Geom g;
+    int rc = make_geom(dims, g);
+    if (rc) return st.status = rc;
+    hisq_cg_opts o = resolve_opts(opts, g);
+    if (!fat || !lng || !b || !x) return st.status = fail(HISQ_EINVAL, "cg_solve: NULL pointer");
+    if (b == x) return st.status = fail(HISQ_EALIAS, "cg_solve: b and x alias");
+    if (!(tol > 0) || !(mass >= 0)) return st.status = fail(HISQ_EINVAL, "cg_solve: need tol > 0 and mass >= 0");
+    if (o.mode != HISQ_CG_PLAIN_F64 && (!fat_lo || !lng_lo))
+        return st.status = fail(HISQ_EINVAL, "cg_solve: mixed mode needs fat_lo and lng_lo");
+    if (o.mode < HISQ_CG_PLAIN_F64 || o.mode > HISQ_CG_MIXED_F16S)
+        return st.status = fail(HISQ_EINVAL, "cg_solve: unknown mode");
+    if (!workspace || ws_bytes < cg_workspace_bytes(g, o.mode))
+        return st.status = fail(HISQ_EWORKSPACE, "cg_solve: workspace NULL or smaller than hisq_workspace_bytes()");
+    hipStream_t s = (hipStream_t)stream;
+    {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return st.status = hip_fail(e, "cg_solve: pending work failed");
+    }
+    switch (o.mode) {
+    case HISQ_CG_PLAIN_F64: rc = cg_plain_f64(mass, tol, fat, lng, b, x, g, o, workspace, ws_bytes, st, s); break;
+    case HISQ_CG_MIXED_F32:
+        rc = cg_mixed<PF32>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
+        break;
+    default: rc = cg_mixed<PF16S>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
+    }
+    st.status = rc;
+    return rc;
+}
+
+extern "C" int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *stream)
+{
+    if (!x || !y || !out_host || n < 0) return fail(HISQ_EINVAL, "hisq_dot: bad argument");
+    if (prec != HISQ_F64 && prec != HISQ_F32 && prec != HISQ_F16S) return fail(HISQ_EINVAL, "hisq_dot: bad precision");
+    // small persistent scratch: partials, result and the arrival counter
+    static thread_local char *scratch = nullptr;
+    const size_t part_bytes = 2 * sizeof(double) * BLAS_MAX_BLOCKS;
+    if (!scratch) {
+        HISQ_HIP(hipMalloc((void **)&scratch, part_bytes + 256));
+        HISQ_HIP(hipMemset(scratch, 0, part_bytes + 256));
+    }
+    double *part = (double *)scratch;
+    double *out = (double *)(scratch + part_bytes);
+    unsigned *cnt = (unsigned *)(scratch + part_bytes + 64);
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        out_host[0] = out_host[1] = 0.0;
+        return HISQ_OK;
+    }
+    const int nb = blas_blocks(n);
+    if (prec == HISQ_F64)
+        hipLaunchKernelGGL((k_dot2<double2>), dim3(nb), dim3(BL_NT), 0, s, (const double2 *)x, (const double2 *)y, n,
+                           part, out, cnt);
+    else
+        hipLaunchKernelGGL((k_dot2<float2>), dim3(nb), dim3(BL_NT), 0, s, (const float2 *)x, (const float2 *)y, n,
+                           part, out, cnt);
+    HISQ_HIP(hipGetLastError());
+    HISQ_HIP(hipMemcpyAsync(out_host, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HISQ_HIP(hipStreamSynchronize(s));
+    return HISQ_OK;
+}

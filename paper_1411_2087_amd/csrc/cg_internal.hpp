@@ -1,0 +1,38 @@
+// Solver state and helpers shared by the CG sources.
+#pragma once
+
+#include "dslash_core.hpp"
+
+namespace hisq {
+
+enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
+// arrival counters of the two-stage reductions, one per reduction site
+enum { CNT_DOT = 0, CNT_PAP = 1, CNT_UPD = 2, CNT_RES = 3, CNT_AUX = 4 };
+constexpr int BLAS_MAX_BLOCKS = 1024;
+
+// Device-resident scalars of one solve.  `flags` comes first: kernels gate on it.
+struct CGState {
+    SolverFlags flags;
+    int iter;        // iterations completed
+    int nupdates;    // reliable updates done
+    double tol2;     // tol^2
+    double bb;       // |b|^2
+    double stop2;    // tol^2 |b|^2
+    double m4;       // 4 m^2
+    double delta2;   // reliable-update threshold delta^2
+    double rr;       // |r|^2 of the current iterate (inner residual in mixed modes)
+    double rr_new;   // |r|^2 after the last update
+    double rr_true;  // last FP64 true residual |b - A x|^2
+    double maxrr;    // max |r_inner|^2 since the last reliable update
+    double alpha, beta, pAp;
+    unsigned cnt[8];
+};
+
+int blas_blocks(long long n);
+size_t cg_partials_count(const Geom &g);
+size_t cg_multi_workspace_bytes(const Geom &g, int nrhs, int mode);
+CGState *pinned_state();
+hipStream_t capture_stream();
+hisq_cg_opts resolve_opts(const hisq_cg_opts *opts, const Geom &g);
+
+}  // namespace hisq

@@ -1,0 +1,270 @@
+// Internal definitions shared by the HIP sources of libhisq.so (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/hisq.h"
+
+namespace hisq {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define HISQ_HIP(call)                                        \
+    do {                                                      \
+        hipError_t _e = (call);                               \
+        if (_e != hipSuccess) return ::hisq::hip_fail(_e, #call); \
+    } while (0)
+
+// ------------------------------------------------------------------ geometry
+// Sites of one parity are numbered h = lex >> 1; a tile is 64 consecutive h
+// (one wavefront), the unit of the packed link layout.
+constexpr int TILE = 64;
+
+struct Geom {
+    int L[4];    // Lx, Ly, Lz, Lt
+    int Lxh;     // Lx / 2
+    int Vh;      // sites per parity
+    int ntiles;  // ceil(Vh / 64)
+    int sy, sz, st;  // h-strides of y, z, t: Lxh, Lxh*Ly, Lxh*Ly*Lz
+};
+
+int make_geom(const int dims[4], Geom &g);  // HISQ_OK or HISQ_EDIMS/EINVAL
+
+// Packed bytes per (tile, direction) block and per field.
+size_t dir_block_bytes(int prec);
+size_t packed_field_bytes(const Geom &g, int prec);
+
+__device__ __forceinline__ void site_coords(const Geom &g, int h, int parity, int &x, int &y, int &z, int &t)
+{
+    int r = h / g.Lxh;
+    int xh = h - r * g.Lxh;
+    y = r % g.L[1];
+    int r2 = r / g.L[1];
+    z = r2 % g.L[2];
+    t = r2 / g.L[2];
+    x = 2 * xh + ((parity + y + z + t) & 1);
+}
+
+__device__ __forceinline__ int wrap(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+// h of the neighbour n + k * mu-hat (|k| <= 3 < L).  The neighbour has the
+// opposite parity when k is odd.
+__device__ __forceinline__ int nbr_h(const Geom &g, int h, int x, int y, int z, int t, int mu, int k)
+{
+    switch (mu) {
+    case 0: {
+        int xn = wrap(x + k, g.L[0]);
+        return h - (x >> 1) + (xn >> 1);
+    }
+    case 1: return h + (wrap(y + k, g.L[1]) - y) * g.sy;
+    case 2: return h + (wrap(z + k, g.L[2]) - z) * g.sz;
+    default: return h + (wrap(t + k, g.L[3]) - t) * g.st;
+    }
+}
+
+// XCD-aware workgroup order: the dispatcher hands consecutive workgroups to
+// the 8 XCDs in turn, so logical block b' = (b % 8) * (G / 8) + b / 8 gives
+// each XCD one contiguous slab of the lattice (its L2 then holds the slab's
+// neighbour vectors).  G is the launched grid, a multiple of 8.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int G) { return (b % NXCD) * (G / NXCD) + b / NXCD; }
+inline int xcd_grid(int nblocks) { return (nblocks + NXCD - 1) / NXCD * NXCD; }
+
+// ------------------------------------------------------------------ reductions
+// Wave64 sum by butterfly (xor) shuffles: every lane gets the total.  The
+// order is fixed, so results are reproducible.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide fixed-order sum; result valid in thread 0.  `lds` holds one
+// double per wave.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) s += lds[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+template <int NT>
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *lds)
+{
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { lds[2 * w] = a; lds[2 * w + 1] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) { sa += lds[2 * i]; sb += lds[2 * i + 1]; }
+        a = sa;
+        b = sb;
+    }
+    __syncthreads();
+}
+
+// Two-stage deterministic grid reduction.  Every block writes its partial;
+// the block that arrives last (device-scope counter) sums all partials in a
+// fixed order and calls fin(total) in thread 0, then re-arms the counter.
+// Returns true in the block that finalised.
+template <int NT, class Fin>
+__device__ __forceinline__ void grid_reduce(double v, double *partials, unsigned *counter, int nblocks, int blk,
+                                            Fin fin)
+{
+    __shared__ double lds[NT / 64];
+    __shared__ bool last;
+    double s = block_sum<NT>(v, lds);
+    if (threadIdx.x == 0) {
+        partials[blk] = s;
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        last = (prev == (unsigned)nblocks - 1u);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += NT) acc += __builtin_nontemporal_load(&partials[i]);
+    double tot = block_sum<NT>(acc, lds);
+    if (threadIdx.x == 0) {
+        fin(tot);
+        *counter = 0u;
+        __threadfence();
+    }
+}
+
+// ------------------------------------------------------------------ streaming loads / stores
+// Nontemporal (streaming) accesses on native clang vectors; the HIP vector
+// structs are reinterpreted as those.
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf2 __attribute__((ext_vector_type(2)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef unsigned nu2 __attribute__((ext_vector_type(2)));
+typedef unsigned nu4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 ntload(const double2 *p)
+{
+    nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2 *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ntload(const float2 *p)
+{
+    nf2 v = __builtin_nontemporal_load(reinterpret_cast<const nf2 *>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ntload(const float4 *p)
+{
+    nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint2 ntload(const uint2 *p)
+{
+    nu2 v = __builtin_nontemporal_load(reinterpret_cast<const nu2 *>(p));
+    return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 ntload(const uint4 *p)
+{
+    nu4 v = __builtin_nontemporal_load(reinterpret_cast<const nu4 *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void ntstore(double2 v, double2 *p)
+{
+    nd2 w = { v.x, v.y };
+    __builtin_nontemporal_store(w, reinterpret_cast<nd2 *>(p));
+}
+__device__ __forceinline__ void ntstore(float2 v, float2 *p)
+{
+    nf2 w = { v.x, v.y };
+    __builtin_nontemporal_store(w, reinterpret_cast<nf2 *>(p));
+}
+
+// ------------------------------------------------------------------ precision traits
+// Packed link block of one (tile, direction): the 9 complex entries of the
+// 64 sites' matrices in element planes, each plane contiguous over the 64
+// lanes so that one wavefront load instruction reads one contiguous span.
+//   F64 : 9 planes of double2                        (9216 B)
+//   F32 : 4 planes of float4 (entries 2q, 2q+1) + 1 plane of float2 (entry 8)   (4608 B)
+//   F16S: 2 planes of 4 x half2 (entries 0-3, 4-7) + 1 plane {half2 entry 8, float scale} (2560 B)
+struct PF64 {
+    using real = double;
+    using cvec = double2;
+    static constexpr int prec = HISQ_F64;
+    static constexpr size_t block_bytes = 9 * TILE * 16;
+    __device__ __forceinline__ static void load(const char *blk, int lane, double m[18])
+    {
+        const double2 *p = reinterpret_cast<const double2 *>(blk) + lane;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            double2 v = ntload(p + e * TILE);
+            m[2 * e] = v.x;
+            m[2 * e + 1] = v.y;
+        }
+    }
+};
+
+struct PF32 {
+    using real = float;
+    using cvec = float2;
+    static constexpr int prec = HISQ_F32;
+    static constexpr size_t block_bytes = TILE * 72;
+    __device__ __forceinline__ static void load(const char *blk, int lane, float m[18])
+    {
+        const float4 *p4 = reinterpret_cast<const float4 *>(blk) + lane;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float4 v = ntload(p4 + q * TILE);
+            m[4 * q] = v.x; m[4 * q + 1] = v.y; m[4 * q + 2] = v.z; m[4 * q + 3] = v.w;
+        }
+        const float2 *p2 = reinterpret_cast<const float2 *>(blk + 4 * TILE * 16) + lane;
+        float2 v = ntload(p2);
+        m[16] = v.x;
+        m[17] = v.y;
+    }
+};
+
+struct PF16S {
+    using real = float;
+    using cvec = float2;
+    static constexpr int prec = HISQ_F16S;
+    static constexpr size_t block_bytes = TILE * 40;
+    __device__ __forceinline__ static void load(const char *blk, int lane, float m[18])
+    {
+        const uint4 *p4 = reinterpret_cast<const uint4 *>(blk) + lane;
+        uint4 a = ntload(p4);
+        uint4 b = ntload(p4 + TILE);
+        const uint2 *p2 = reinterpret_cast<const uint2 *>(blk + 2 * TILE * 16) + lane;
+        uint2 c = ntload(p2);
+        const float s = __uint_as_float(c.y);
+        const unsigned w[9] = { a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x };
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            __half2 hv = *reinterpret_cast<const __half2 *>(&w[e]);
+            float2 f = __half22float2(hv);
+            m[2 * e] = f.x * s;
+            m[2 * e + 1] = f.y * s;
+        }
+    }
+};
+
+}  // namespace hisq

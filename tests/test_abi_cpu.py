@@ -1,0 +1,70 @@
+"""The C-ABI library loads and exports every symbol include/hisq.h declares;
+host-side validation paths (no GPU work) return the documented codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hisq.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|size_t|char|void)\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("dslash_apply", "cg_solve", "cg_solve_multi", "hisq_pack_links", "hisq_last_error"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1411_2087_amd as hq
+    lib = ctypes.CDLL(hq.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+    for n in hq.EXPORTED:
+        assert n in declared_functions()
+
+
+def test_validation_without_gpu():
+    import paper_1411_2087_amd as hq
+    lib = hq._lib
+    dims_bad = (ctypes.c_int * 4)(4, 4, 4, 5)
+    dims_ok = (ctypes.c_int * 4)(4, 4, 4, 4)
+    p1, p2 = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert lib.dslash_apply(p1, p1, p1, p2, 0, dims_bad, 0, None) == -2
+    assert b"even" in lib.hisq_last_error()
+    assert lib.dslash_apply(p1, p1, p1, p1, 0, dims_ok, 0, None) == -3
+    assert lib.dslash_apply(None, p1, p1, p2, 0, dims_ok, 0, None) == -1
+    assert lib.dslash_apply(p1, p1, p1, p2, 3, dims_ok, 0, None) == -1
+    assert lib.dslash_apply(p1, p1, p1, p2, 0, dims_ok, 7, None) == -1
+    assert lib.hisq_pack_links(p1, p1, dims_bad, 0, p1, p2, None) == -2
+    assert lib.hisq_pack_links(p1, p1, dims_ok, 0, p1, p1, None) == -3
+    assert lib.hisq_apply_A(0.1, p1, p1, p1, p1, p2, dims_ok, 0, None) == -3
+    dims_small = (ctypes.c_int * 4)(2, 4, 4, 4)
+    assert lib.dslash_apply(p1, p1, p1, p2, 0, dims_small, 0, None) == -2
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 6, 6, 6), (32, 32, 32, 32), (48, 48, 48, 96)])
+def test_packed_sizes(dims):
+    import paper_1411_2087_amd as hq
+    vh = int(np.prod(dims)) // 2
+    ntiles = -(-vh // 64)
+    for prec, per_matrix in ((0, 144), (1, 72), (2, 40)):
+        assert hq.hisq_packed_link_bytes(dims, prec) == 2 * ntiles * 64 * 8 * per_matrix
+    assert hq.hisq_packed_link_bytes((4, 4, 4, 3), 0) == 0
+
+
+def test_workspace_sizes():
+    import paper_1411_2087_amd as hq
+    dims = (8, 8, 8, 8)
+    assert hq.hisq_workspace_bytes("cg", dims, 1, 0) >= 4 * 2048 * 48
+    assert hq.hisq_workspace_bytes("cg", dims, 1, 1) >= 2 * 2048 * 48 + 5 * 2048 * 24
+    assert hq.hisq_workspace_bytes("nope", dims, 1, 0) == 0
+    assert hq.hisq_workspace_bytes("cg", (4, 4, 4, 5), 1, 0) == 0

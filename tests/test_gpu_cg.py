@@ -1,0 +1,115 @@
+"""GPU even-odd CG (plain FP64 and mixed precision) against the CPU oracle.
+
+Every solution's residual |b - A x| / |b| is recomputed by the FP64 CPU oracle.
+"""
+import numpy as np
+import pytest
+
+from helpers import CG_TOL, fields, oracle, say, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hq():
+    import torch
+    import paper_1411_2087_amd as hq
+    assert torch.cuda.is_available()
+    return hq
+
+
+def _solve(hq, dims, fat, lng, b, mass, mode, tol=CG_TOL, max_iter=0, use_graph=1, check_every=0, x0=None):
+    import torch
+    L64 = hq.fields.Links.pack(fat, lng, dims, 0)
+    Llo = None
+    if mode == 1:
+        Llo = hq.fields.Links.pack(fat, lng, dims, 1)
+    elif mode == 2:
+        Llo = hq.fields.Links.pack(fat, lng, dims, 2)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd) if x0 is None else torch.from_numpy(x0).cuda()
+    ws = hq.fields.workspace("cg", dims, 1, mode)
+    opts = hq.CGOpts(mode=mode, max_iter=max_iter, check_every=check_every, use_graph=use_graph, delta=0.1)
+    st = hq.cg_solve(mass, tol, L64.fat, L64.lng, Llo.fat if Llo else None, Llo.lng if Llo else None, bd, xd, dims,
+                     opts, ws)
+    return xd.cpu().numpy(), st
+
+
+def test_cg_config1_8_4(hq):
+    """Plain FP64 CG on 8^4, mass 0.05, tol 1e-10 (the small workload)."""
+    dims, mass = (8, 8, 8, 8), 0.05
+    fat, lng = fields(dims, synth.gauge_seed(1))
+    b = synth.source(dims, synth.source_seed(1))
+    x, st = _solve(hq, dims, fat, lng, b, mass, 0)
+    tr = oracle.true_residual(dims, mass, fat, lng, b, x)
+    xo, info = oracle.cg(dims, mass, fat, lng, b, tol=CG_TOL)
+    say(f"cg 8^4: gpu iters={st['iters']} gpu_resid={st['true_resid']:.3e} oracle_resid(gpu x)={tr:.3e} "
+        f"oracle iters={info['iters']} time={st['time_s']:.4f}s")
+    assert st["rc"] == 0 and tr <= CG_TOL
+    assert abs(st["iters"] - info["iters"]) <= max(2, 0.02 * info["iters"])
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-7
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_cg_graph_and_direct_agree(hq, use_graph):
+    dims, mass = (6, 6, 6, 6), 0.1
+    fat, lng = fields(dims)
+    b = synth.source(dims, 77)
+    x1, s1 = _solve(hq, dims, fat, lng, b, mass, 0, use_graph=use_graph, check_every=7)
+    x2, s2 = _solve(hq, dims, fat, lng, b, mass, 0, use_graph=1 - use_graph, check_every=13)
+    assert s1["iters"] == s2["iters"]
+    assert np.array_equal(x1, x2)  # same kernels, same order: bitwise
+    assert oracle.true_residual(dims, mass, fat, lng, b, x1) <= CG_TOL
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_cg_mixed(hq, mode):
+    dims, mass = (8, 8, 8, 8), 0.05
+    fat, lng = fields(dims, synth.gauge_seed(1))
+    b = synth.source(dims, synth.source_seed(1))
+    x, st = _solve(hq, dims, fat, lng, b, mass, mode)
+    tr = oracle.true_residual(dims, mass, fat, lng, b, x)
+    _, info = oracle.cg(dims, mass, fat, lng, b, tol=CG_TOL)
+    say(f"cg mixed mode={mode} 8^4: iters={st['iters']} updates={st['reliable_updates']} gpu_resid="
+        f"{st['true_resid']:.3e} oracle_resid={tr:.3e} (plain oracle iters {info['iters']})")
+    assert st["rc"] == 0 and tr <= CG_TOL
+
+
+def test_cg_zero_source_and_limits(hq):
+    dims, mass = (4, 4, 4, 4), 0.05
+    fat, lng = fields(dims)
+    b = np.zeros((128, 3), np.complex128)
+    x, st = _solve(hq, dims, fat, lng, b, mass, 0, x0=np.ones((128, 3), np.complex128))
+    assert st["rc"] == 0 and st["iters"] == 0 and not x.any()
+    b = synth.source(dims, 5)
+    x, st = _solve(hq, dims, fat, lng, b, mass, 0, max_iter=1)
+    assert st["rc"] == -5 and st["iters"] == 1
+    # warm start from the converged solution: zero iterations
+    x, st = _solve(hq, dims, fat, lng, b, mass, 0)
+    x2, st2 = _solve(hq, dims, fat, lng, b, mass, 0, x0=x)
+    assert st2["iters"] == 0 and st2["rc"] == 0
+
+
+def test_cg_nan_source_reports_breakdown(hq):
+    dims, mass = (4, 4, 4, 4), 0.05
+    fat, lng = fields(dims)
+    b = synth.source(dims, 5)
+    b[3, 1] = np.nan
+    x, st = _solve(hq, dims, fat, lng, b, mass, 0)
+    assert st["rc"] in (-5, -6)
+
+
+def test_cg_32_4(hq):
+    """Plain FP64 CG on 32^4, mass 0.01, tol 1e-10 (the bandwidth workload)."""
+    dims, mass = (32, 32, 32, 32), 0.01
+    fat, lng = fields(dims, synth.gauge_seed(2))
+    b = synth.source(dims, synth.source_seed(2))
+    x, st = _solve(hq, dims, fat, lng, b, mass, 0)
+    tr = oracle.true_residual(dims, mass, fat, lng, b, x)
+    say(f"cg 32^4: iters={st['iters']} gpu_resid={st['true_resid']:.3e} oracle_resid={tr:.3e} time={st['time_s']:.3f}s")
+    assert st["rc"] == 0 and tr <= CG_TOL
+    xm, sm = _solve(hq, dims, fat, lng, b, mass, 1)
+    trm = oracle.true_residual(dims, mass, fat, lng, b, xm)
+    say(f"cg 32^4 mixed f32: iters={sm['iters']} updates={sm['reliable_updates']} oracle_resid={trm:.3e} "
+        f"time={sm['time_s']:.3f}s")
+    assert sm["rc"] == 0 and trm <= CG_TOL

@@ -1,0 +1,145 @@
+"""GPU parity of the HISQ Dslash, the even-odd operator and the reductions
+against the CPU oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+from helpers import TOL_F16S, TOL_F32, TOL_F64, fields, oracle, say, synth, vh
+
+pytestmark = pytest.mark.gpu
+
+# 4^4: +3 aliases -1; 4x6x8x10: non-cubic (catches axis-order bugs);
+# 6x6x6x6 and 6x4x4x10: Vh not a multiple of the 64-site tile (ragged tail)
+DIMS = [(4, 4, 4, 4), (4, 6, 8, 10), (6, 6, 6, 6), (6, 4, 4, 10), (8, 8, 8, 8), (16, 8, 8, 12)]
+
+
+@pytest.fixture(scope="module")
+def hq():
+    import torch
+    import paper_1411_2087_amd as hq
+    assert torch.cuda.is_available()
+    return hq
+
+
+def _dslash_gpu(hq, dims, fat, lng, src, parity, prec):
+    import torch
+    L = hq.fields.Links.pack(fat, lng, dims, prec)
+    dt = hq.fields.VEC_DTYPE[prec]
+    s = torch.from_numpy(src).to(dt).cuda()
+    d = torch.full_like(s, float("nan"))
+    hq.dslash_apply(L.fat, L.lng, s, d, parity, dims, prec)
+    torch.cuda.synchronize()
+    return d.cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("prec,tol", [(0, TOL_F64), (1, TOL_F32), (2, TOL_F16S)])
+def test_dslash_parity(hq, dims, prec, tol):
+    fat, lng = fields(dims, 1000 + sum(dims))
+    r = np.random.default_rng(7)
+    for parity in (0, 1):
+        src = synth.source(dims, 3000 + parity)
+        if prec != 0:
+            # the FP32 kernel sees FP32 vectors; the oracle gets the same rounded values
+            src = src.astype(np.complex64).astype(np.complex128)
+        ref = oracle.dslash(dims, fat, lng, src, parity)
+        scale = oracle.dslash_scale(dims, fat, lng, src, parity)
+        got = _dslash_gpu(hq, dims, fat, lng, src, parity, prec)
+        assert np.isfinite(got).all(), "output not fully written"
+        err = oracle.componentwise_error(got, ref, scale)
+        nrm = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        say(f"dslash dims={dims} prec={prec} parity={parity}: componentwise {err:.3e} normwise {nrm:.3e}")
+        assert err <= tol
+
+
+def test_dslash_32_4_full(hq):
+    """Full 32^4 lattice (the bandwidth workload) against the oracle, both parities."""
+    dims = (32, 32, 32, 32)
+    fat, lng = fields(dims, 1002)
+    for parity in (0, 1):
+        src = synth.source(dims, 2128 + parity)
+        ref = oracle.dslash(dims, fat, lng, src, parity)
+        scale = oracle.dslash_scale(dims, fat, lng, src, parity)
+        got = _dslash_gpu(hq, dims, fat, lng, src, parity, 0)
+        err = oracle.componentwise_error(got, ref, scale)
+        say(f"dslash 32^4 f64 parity={parity}: componentwise {err:.3e}")
+        assert err <= TOL_F64
+
+
+def test_free_field_on_gpu(hq):
+    """The GPU Dslash reproduces the closed-form plane-wave result."""
+    from oracle import freefield, lattice
+    dims = (4, 6, 8, 10)
+    c1, c3 = 0.7, -0.25
+    fat, lng = synth.unit_links(dims, c1, c3)
+    k = [1, 2, 3, 4]
+    chi = np.array([1.0, 0.5j, -0.25 + 0.1j])
+    psi = freefield.plane_wave(dims, k, chi)
+    want = freefield.dslash_plane_wave(dims, k, chi, c1, c3)
+    pe, po = lattice.split(dims, psi)
+    we, wo = lattice.split(dims, want)
+    assert np.abs(_dslash_gpu(hq, dims, fat, lng, po, 0, 0) - we).max() < 1e-13
+    assert np.abs(_dslash_gpu(hq, dims, fat, lng, pe, 1, 0) - wo).max() < 1e-13
+
+
+def test_antihermiticity_on_gpu(hq):
+    dims = (8, 8, 8, 8)
+    fat, lng = fields(dims)
+    xe = synth.source(dims, 11)
+    yo = synth.source(dims, 12)
+    dx = _dslash_gpu(hq, dims, fat, lng, xe, 1, 0)
+    dy = _dslash_gpu(hq, dims, fat, lng, yo, 0, 0)
+    lhs, rhs = np.vdot(yo, dx), -np.vdot(dy, xe)
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(yo) * np.linalg.norm(dx)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 1e-5)])
+def test_apply_A(hq, prec, tol):
+    import torch
+    dims = (6, 6, 6, 6)
+    fat, lng = fields(dims)
+    mass = 0.05
+    x = synth.source(dims, 5)
+    if prec:
+        x = x.astype(np.complex64).astype(np.complex128)
+    ref = oracle.apply_A(dims, mass, fat, lng, x)
+    L = hq.fields.Links.pack(fat, lng, dims, prec)
+    dt = hq.fields.VEC_DTYPE[prec]
+    xd = torch.from_numpy(x).to(dt).cuda()
+    yd, td = torch.empty_like(xd), torch.empty_like(xd)
+    hq.hisq_apply_A(mass, L.fat, L.lng, xd, yd, td, dims, prec)
+    got = yd.cpu().numpy().astype(np.complex128)
+    rel = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"apply_A prec={prec}: max rel {rel:.3e}")
+    assert rel < tol
+
+
+def test_dot_deterministic(hq):
+    import torch
+    n = 3 * 100003
+    r = np.random.default_rng(3)
+    x = (r.standard_normal(n) + 1j * r.standard_normal(n))
+    y = (r.standard_normal(n) + 1j * r.standard_normal(n))
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    v1 = hq.hisq_dot(xd, yd, n, 0)
+    v2 = hq.hisq_dot(xd, yd, n, 0)
+    assert v1 == v2  # bitwise reproducible
+    ref = np.vdot(x, y)
+    assert abs(v1 - ref) < 1e-12 * np.sqrt(n) * 2
+    assert hq.hisq_dot(xd, yd, 0, 0) == 0
+
+
+def test_bad_arguments(hq):
+    import torch
+    dims = (4, 4, 4, 4)
+    fat, lng = fields(dims)
+    L = hq.fields.Links.pack(fat, lng, dims, 0)
+    s = torch.zeros((vh(dims), 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(hq.HisqError) as e:
+        hq.dslash_apply(L.fat, L.lng, s, s, 0, dims, 0)
+    assert e.value.code == -3
+    with pytest.raises(hq.HisqError) as e:
+        hq.dslash_apply(L.fat, L.lng, s, s.clone(), 0, (4, 4, 4, 5), 0)
+    assert e.value.code == -2
+    with pytest.raises(hq.HisqError) as e:
+        hq.dslash_apply(L.fat, L.lng, s, s.clone(), 2, dims, 0)
+    assert e.value.code == -1
