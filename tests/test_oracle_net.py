@@ -1,0 +1,159 @@
+"""Pins of the network and flexible-CG parts of the oracle.
+
+Checked against adjoint identities, closed forms (plane-wave shifts, the first
+Adam step), gauge equivariance, central finite differences, torch's own BF16
+conversion, and the special cases K = 1 (FCG = CG) and K = A^-1 (one step).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import dense, fcg, freefield, lattice
+from oracle import net as N
+
+DIMS = (4, 4, 4, 6)
+
+
+def cvec(r, shape):
+    return (r.standard_normal(shape) + 1j * r.standard_normal(shape)) / np.sqrt(2)
+
+
+def rand_weights(r, C, scale=0.3):
+    return [cvec(r, (9, co, ci)) * scale for co, ci in N.channels_of(C)]
+
+
+def test_transport_adjoint():
+    fat, _ = synth.links(DIMS, 1000)
+    r = np.random.default_rng(1)
+    V = int(np.prod(DIMS))
+    phi, psi = cvec(r, (V, 3)), cvec(r, (V, 3))
+    for k in range(9):
+        lhs = np.vdot(psi, N.transport(DIMS, fat, phi, k))
+        rhs = np.vdot(N.transport(DIMS, fat, psi, N.ADJOINT[k]), phi)
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_transport_is_a_shift_for_unit_links():
+    fat, _ = synth.unit_links(DIMS, 1.0, 1.0, fold=False, antiperiodic_t=False)
+    k = [1, 2, 3, 1]
+    chi = np.array([1.0, -0.5j, 0.25])
+    psi = freefield.plane_wave(DIMS, k, chi, antiperiodic_t=False)
+    p = freefield.momentum(DIMS, k, antiperiodic_t=False)
+    for mu in range(4):
+        assert np.abs(N.transport(DIMS, fat, psi, 1 + mu) - np.exp(1j * p[mu]) * psi).max() < 1e-13
+        assert np.abs(N.transport(DIMS, fat, psi, 5 + mu) - np.exp(-1j * p[mu]) * psi).max() < 1e-13
+
+
+def test_identity_weights_give_identity():
+    fat, _ = synth.links(DIMS, 1000)
+    r_e = synth.source(DIMS, 3)
+    y, _ = N.net_forward(DIMS, fat, N.identity_weights(4), r_e)
+    assert np.abs(y - r_e).max() < 1e-15
+
+
+def test_gauge_equivariance():
+    fat, lng = synth.links(DIMS, 1000)
+    V = int(np.prod(DIMS))
+    g = synth.haar(17, V)
+    from test_oracle_pins import gauge_transform
+    f2, _ = gauge_transform(DIMS, fat, lng, g)
+    r = np.random.default_rng(5)
+    Ws = rand_weights(r, 3)
+    r_e = synth.source(DIMS, 4)
+    ge, _ = lattice.split(DIMS, g)
+    y, _ = N.net_forward(DIMS, fat, Ws, r_e)
+    y2, _ = N.net_forward(DIMS, f2, Ws, np.einsum("nab,nb->na", ge, r_e))
+    assert np.abs(y2 - np.einsum("nab,nb->na", ge, y)).max() < 1e-12 * np.abs(y).max()
+
+
+def test_backward_matches_finite_differences():
+    fat, _ = synth.links(DIMS, 1000)
+    r = np.random.default_rng(9)
+    C = 2
+    Ws = rand_weights(r, C)
+    bs = [synth.source(DIMS, 40 + i) for i in range(2)]
+    xs = [synth.source(DIMS, 50 + i) for i in range(2)]
+
+    def loss(Ws_, bs_):
+        ys = [N.net_forward(DIMS, fat, Ws_, b)[0] for b in bs_]
+        return N.loss_and_grad(ys, xs)[0]
+
+    ys, acts = zip(*[N.net_forward(DIMS, fat, Ws, b) for b in bs])
+    l0, gys = N.loss_and_grad(list(ys), xs)
+    gW = [np.zeros_like(W) for W in Ws]
+    gb = []
+    for a, gy in zip(acts, gys):
+        gin, gws = N.net_backward(DIMS, fat, Ws, a, gy)
+        gb.append(gin)
+        for acc, gw in zip(gW, gws):
+            acc += gw
+    h = 1e-6
+    # directional derivative in weight space
+    dW = [cvec(r, W.shape) for W in Ws]
+    fd = (loss([W + h * d for W, d in zip(Ws, dW)], bs) - loss([W - h * d for W, d in zip(Ws, dW)], bs)) / (2 * h)
+    an = sum(np.sum((np.conj(g) * d).real) for g, d in zip(gW, dW))
+    assert abs(fd - an) <= 1e-6 * abs(an)
+    # and in input space
+    db = [cvec(r, b.shape) for b in bs]
+    fd = (loss(Ws, [b + h * d for b, d in zip(bs, db)]) - loss(Ws, [b - h * d for b, d in zip(bs, db)])) / (2 * h)
+    an = sum(np.sum((np.conj(g) * d).real) for g, d in zip(gb, db))
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    r = np.random.default_rng(2)
+    a = np.concatenate([r.standard_normal(10000).astype(np.float32),
+                        np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, -0.0, 3e38], np.float32)])
+    want = torch.from_numpy(a).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(N.bf16_round(a), want)
+    assert N.bf16_round(np.float32([1 + 2 ** -8]))[0] == 1.0           # tie to even
+    assert N.bf16_round(np.float32([1 + 3 * 2 ** -8]))[0] == 1 + 2 ** -6
+
+
+def test_adam_first_step_closed_form():
+    w = [np.array([1.0 + 2.0j, -1.0 + 0.5j])]
+    g = [np.array([0.3 - 2.0j, -1e-3 + 4.0j])]
+    m = [np.zeros(2, complex)]
+    v = [np.zeros(2, complex)]
+    w0 = w[0].copy()
+    N.adam_step(w, g, m, v, t=1, lr=0.01)
+    # first step: mhat = g, vhat = g^2 componentwise -> step lr * g / (|g| + eps)
+    exp = w0 - 0.01 * (np.sign(g[0].real) * np.abs(g[0].real) / (np.abs(g[0].real) + 1e-8)
+                       + 1j * np.sign(g[0].imag) * np.abs(g[0].imag) / (np.abs(g[0].imag) + 1e-8))
+    assert np.allclose(w[0], exp, rtol=0, atol=1e-12)
+
+
+def test_fcg_identity_is_cg():
+    dims, mass = (4, 4, 4, 6), 0.1
+    fat, lng = synth.links(dims, 1000)
+    b = synth.source(dims, 2)
+    x, info = fcg.fcg(dims, mass, fat, lng, b, lambda r: r, tol=1e-10)
+    _, cinfo = oracle.cg(dims, mass, fat, lng, b, tol=1e-10, history=True)
+    assert not info["fallback"]
+    # same iterates up to rounding: the first steps agree closely; later ones
+    # differ only as far as rounding in a non-orthogonal Krylov basis lets them
+    assert np.allclose(info["history"][:30], cinfo["history"][:30], rtol=1e-8, atol=0)
+    assert abs(info["iters"] - cinfo["iters"]) <= max(2, 0.03 * cinfo["iters"])
+    assert oracle.true_residual(dims, mass, fat, lng, b, x) <= 1e-10
+
+
+def test_fcg_exact_inverse_one_step():
+    dims, mass = (4, 4, 4, 4), 0.1
+    fat, lng = synth.links(dims, 1000)
+    A = dense.dense_A(dims, dense.dense_D(dims, fat, lng), mass)
+    Ainv = np.linalg.inv(A)
+    b = synth.source(dims, 2)
+    x, info = fcg.fcg(dims, mass, fat, lng, b, lambda r: (Ainv @ r.reshape(-1)).reshape(-1, 3), tol=1e-10)
+    assert info["iters"] == 1
+    assert oracle.true_residual(dims, mass, fat, lng, b, x) <= 1e-10
+
+
+def test_fcg_falls_back_on_a_bad_preconditioner():
+    dims, mass = (4, 4, 4, 6), 0.1
+    fat, lng = synth.links(dims, 1000)
+    b = synth.source(dims, 2)
+    x, info = fcg.fcg(dims, mass, fat, lng, b, lambda r: -r, tol=1e-10)
+    assert info["fallback"]
+    assert oracle.true_residual(dims, mass, fat, lng, b, x) <= 1e-10
