@@ -63,16 +63,21 @@ typedef enum {
  * HISQ_F64  : FP64 links and vectors.
  * HISQ_F32  : FP32 links and vectors.
  * HISQ_F16S : FP16 links with one FP32 scale per (site, direction, field)
- *             matrix (the largest |re|, |im| of its 18 reals), FP32 vectors. */
-typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16S = 2 } hisq_prec;
+ *             matrix (the largest |re|, |im| of its 18 reals), FP32 vectors.
+ * HISQ_I16S : 16-bit fixed-point links with the same per-matrix FP32 scale
+ *             (entry = q * scale / 32767), FP32 vectors; same 40 B per matrix
+ *             as HISQ_F16S with finer steps.
+ * The last three have FP32 (complex64) vectors. */
+typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16S = 2, HISQ_I16S = 3 } hisq_prec;
 
 /* CG modes.
  * PLAIN_F64  : every step in FP64.
  * MIXED_F32  : FP32 Dslash and vector updates inside, FP64 dot-product
  *              accumulation, FP64 reliable updates of the true residual
  *              (x += x_inner, r = b - A x in FP64) and FP64 final residual.
- * MIXED_F16S : as MIXED_F32 with HISQ_F16S links in the inner Dslash. */
-enum { HISQ_CG_PLAIN_F64 = 0, HISQ_CG_MIXED_F32 = 1, HISQ_CG_MIXED_F16S = 2 };
+ * MIXED_F16S : as MIXED_F32 with HISQ_F16S links in the inner Dslash.
+ * MIXED_I16S : as MIXED_F32 with HISQ_I16S links in the inner Dslash. */
+enum { HISQ_CG_PLAIN_F64 = 0, HISQ_CG_MIXED_F32 = 1, HISQ_CG_MIXED_F16S = 2, HISQ_CG_MIXED_I16S = 3 };
 
 /* cg_solve_multi modes.
  * MULTI_RHS   : nrhs independent systems (A + 4 m_i^2 - 4 m_0^2 ...) i.e.
@@ -141,6 +146,23 @@ int hisq_apply_A(double mass, const void *fat, const void *lng, const void *x, v
  * sum; results are bitwise reproducible.  Synchronises `stream`. */
 int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *stream);
 
+/* Autotuner of the single-RHS Dslash launch shape (threads per workgroup,
+ * occupancy target): times every shape with HIP events on the caller's
+ * buffers (dst = D src on parity 1, `reps` launches each, 20 if <= 0),
+ * remembers the fastest for (dims, prec) in this process -- and in the file
+ * named by the environment variable HISQ_TUNE_CACHE, if set -- and uses it
+ * in every later Dslash of that lattice and precision.  All shapes give
+ * bitwise-identical results.  best_shape (may be NULL) receives the chosen
+ * index, us_per_shape (may be NULL, room for hisq_dslash_shape(dims, prec,
+ * -2) entries) the measured microseconds.  Synchronises `stream`. */
+int hisq_tune_dslash(const void *fat, const void *lng, const void *src, void *dst, const int dims[4], int prec,
+                     int reps, int *best_shape, double *us_per_shape, void *stream);
+
+/* Launch shape of the single-RHS Dslash for (dims, prec): shape >= 0 sets
+ * it, shape == -1 only queries; returns the shape in use, or a negative
+ * hisq_status.  shape == -2 returns the number of shapes. */
+int hisq_dslash_shape(const int dims[4], int prec, int shape);
+
 /* Workspace bytes for `solver` = "cg", "cg_multi" or "fcg" on `dims` with
  * `nrhs` right-hand sides (1 for cg), `mode` (HISQ_CG_* for cg/fcg,
  * HISQ_MULTI_* for cg_multi) and `channels` (fcg only).  0 on bad arguments. */
@@ -148,7 +170,7 @@ size_t hisq_workspace_bytes(const char *solver, const int dims[4], int nrhs, int
 
 /* Solve A(mass) x = b on the even sites to |b - A x| <= tol |b| (Sec. 3 CG;
  * Sec. 4 even-odd).  fat/lng: HISQ_F64 packed links.  fat_lo/lng_lo:
- * HISQ_F32 (MIXED_F32) or HISQ_F16S (MIXED_F16S) packed links, NULL for
+ * HISQ_F32, HISQ_F16S or HISQ_I16S packed links matching the mode, NULL for
  * PLAIN_F64.  b, x: complex128 Vh x 3; x holds x0 on entry and the solution
  * on exit (also on HISQ_ENOCONV).  opts NULL = plain FP64 defaults.  stats
  * (may be NULL) is always written.  Returns when the solve has finished. */

@@ -20,8 +20,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhisq.so")
 
-HISQ_F64, HISQ_F32, HISQ_F16S = 0, 1, 2
-HISQ_CG_PLAIN_F64, HISQ_CG_MIXED_F32, HISQ_CG_MIXED_F16S = 0, 1, 2
+HISQ_F64, HISQ_F32, HISQ_F16S, HISQ_I16S = 0, 1, 2, 3
+HISQ_CG_PLAIN_F64, HISQ_CG_MIXED_F32, HISQ_CG_MIXED_F16S, HISQ_CG_MIXED_I16S = 0, 1, 2, 3
 HISQ_MULTI_RHS, HISQ_MULTI_SHIFT = 0, 1
 STATUS = {0: "HISQ_OK", -1: "HISQ_EINVAL", -2: "HISQ_EDIMS", -3: "HISQ_EALIAS", -4: "HISQ_EHIP",
           -5: "HISQ_ENOCONV", -6: "HISQ_EBREAKDOWN", -7: "HISQ_EWORKSPACE"}
@@ -29,7 +29,8 @@ STATUS = {0: "HISQ_OK", -1: "HISQ_EINVAL", -2: "HISQ_EDIMS", -3: "HISQ_EALIAS", 
 # Algorithmic bytes per output site of one Dslash (16 links, one source read,
 # one output write; Sec. 3 counts 16 matrices and 16 vectors per site), and
 # the paper's flop count.
-DSLASH_BYTES_PER_SITE = {HISQ_F64: 16 * 144 + 48 + 48, HISQ_F32: 16 * 72 + 24 + 24, HISQ_F16S: 16 * 40 + 24 + 24}
+DSLASH_BYTES_PER_SITE = {HISQ_F64: 16 * 144 + 48 + 48, HISQ_F32: 16 * 72 + 24 + 24, HISQ_F16S: 16 * 40 + 24 + 24,
+                         HISQ_I16S: 16 * 40 + 24 + 24}
 DSLASH_FLOPS_PER_SITE = 1146
 
 
@@ -71,7 +72,11 @@ def _load():
                              ctypes.POINTER(CGStats), vp]
     lib.cg_solve_multi.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), d, ctypes.c_int, vp, vp, vp, vp,
                                    vp, vp, ip, ctypes.POINTER(CGOpts), vp, sz, ctypes.POINTER(CGStats), vp]
-    for name in ("hisq_pack_links", "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi"):
+    lib.hisq_tune_dslash.argtypes = [vp, vp, vp, vp, ip, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_double), vp]
+    lib.hisq_dslash_shape.argtypes = [ip, ctypes.c_int, ctypes.c_int]
+    for name in ("hisq_pack_links", "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi",
+                 "hisq_tune_dslash", "hisq_dslash_shape"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -79,7 +84,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["hisq_version", "hisq_last_error", "hisq_packed_link_bytes", "hisq_pack_links", "dslash_apply",
-            "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi"]
+            "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi", "hisq_tune_dslash",
+            "hisq_dslash_shape"]
 
 
 def _dims(dims):
@@ -139,6 +145,23 @@ def hisq_dot(x, y, n, prec, stream=None) -> complex:
     out = (ctypes.c_double * 2)()
     _check(_lib.hisq_dot(_ptr(x), _ptr(y), int(n), int(prec), out, _stream(stream)), "hisq_dot")
     return complex(out[0], out[1])
+
+
+def hisq_tune_dslash(fat, lng, src, dst, dims, prec, reps=20, stream=None):
+    """Time every Dslash launch shape; returns (best_shape, [microseconds per shape])."""
+    n = int(_lib.hisq_dslash_shape(_dims(dims), int(prec), -2))
+    best = ctypes.c_int(-1)
+    us = (ctypes.c_double * n)()
+    _check(_lib.hisq_tune_dslash(_ptr(fat), _ptr(lng), _ptr(src), _ptr(dst), _dims(dims), int(prec), int(reps),
+                                 ctypes.byref(best), us, _stream(stream)), "hisq_tune_dslash")
+    return best.value, list(us)
+
+
+def hisq_dslash_shape(dims, prec, shape=-1) -> int:
+    rc = int(_lib.hisq_dslash_shape(_dims(dims), int(prec), int(shape)))
+    if rc < 0:
+        _check(rc, "hisq_dslash_shape")
+    return rc
 
 
 def hisq_workspace_bytes(solver, dims, nrhs=1, mode=0, channels=0) -> int:

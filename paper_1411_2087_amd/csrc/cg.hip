@@ -25,6 +25,7 @@
 // replaced by it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -125,52 +126,74 @@ __device__ __forceinline__ void finalize(CGState *st, int mode, double v)
 }
 
 // ------------------------------------------------------------------ BLAS kernels
+// Streaming vector kernels: each thread owns BL_U entries spaced BL_NT apart
+// (every load instruction of a wavefront is one contiguous span), issues all
+// its loads before any arithmetic, and the grid covers the vector once.
 constexpr int BL_NT = 256;
+constexpr int BL_U = 4;
 
 int blas_blocks(long long n)
 {
-    long long nb = (n + BL_NT - 1) / BL_NT;
-    return (int)(nb < BLAS_MAX_BLOCKS ? nb : BLAS_MAX_BLOCKS);
+    long long nb = (n + (long long)BL_NT * BL_U - 1) / ((long long)BL_NT * BL_U);
+    return (int)(nb > 0 ? nb : 1);
 }
 
-// Re<x, y> (or |x|^2) of n complex entries into the state (mode FIN_BB ...).
+__device__ __forceinline__ long long bl_index(int j) { return ((long long)blockIdx.x * BL_U + j) * BL_NT + threadIdx.x; }
+
+// Partials of Re<x, y> (or |x|^2) over n complex entries.
 template <class T>
 __global__ __launch_bounds__(BL_NT) void k_dot_state(const T *__restrict__ x, const T *__restrict__ y, long long n,
-                                                     double *partials, CGState *st, int cnt, int mode)
+                                                     double *partials)
 {
-    double s = 0.0;
-    for (long long i = (long long)blockIdx.x * BL_NT + threadIdx.x; i < n; i += (long long)gridDim.x * BL_NT) {
-        double2 a = cv_d(x[i]), b = cv_d(y[i]);
-        s = fma(a.x, b.x, s);
-        s = fma(a.y, b.y, s);
+    T a[BL_U], b[BL_U];
+#pragma unroll
+    for (int j = 0; j < BL_U; ++j) {
+        const long long i = bl_index(j);
+        if (i < n) { a[j] = x[i]; b[j] = y[i]; }
     }
-    grid_reduce<BL_NT>(s, partials, &st->cnt[cnt], gridDim.x, blockIdx.x,
-                       [&](double v) { finalize(st, mode, v); });
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < BL_U; ++j) {
+        if (bl_index(j) < n) {
+            double2 u = cv_d(a[j]), v = cv_d(b[j]);
+            s = fma(u.x, v.x, s);
+            s = fma(u.y, v.y, s);
+        }
+    }
+    block_partial<BL_NT>(s, partials, blockIdx.x);
 }
 
-// x += alpha p ; r -= alpha Ap ; |r|^2 -> finaliser
+// x += alpha p ; r -= alpha Ap ; partials of |r|^2
 template <class T>
 __global__ __launch_bounds__(BL_NT) void k_cg_update(T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
                                                      const T *__restrict__ ap, long long n, double *partials,
-                                                     CGState *st, int mode)
+                                                     const CGState *st)
 {
     if (st->flags.done) return;
     using R = typename VecT<T>::real;
     const R alpha = (R)st->alpha;
-    double s = 0.0;
-    for (long long i = (long long)blockIdx.x * BL_NT + threadIdx.x; i < n; i += (long long)gridDim.x * BL_NT) {
-        T pv = p[i], av = ap[i], xv = x[i], rv = r[i];
-        xv.x = fma(alpha, pv.x, xv.x);
-        xv.y = fma(alpha, pv.y, xv.y);
-        rv.x = fma(-alpha, av.x, rv.x);
-        rv.y = fma(-alpha, av.y, rv.y);
-        x[i] = xv;
-        r[i] = rv;
-        s = fma((double)rv.x, (double)rv.x, s);
-        s = fma((double)rv.y, (double)rv.y, s);
+    T pv[BL_U], av[BL_U], xv[BL_U], rv[BL_U];
+#pragma unroll
+    for (int j = 0; j < BL_U; ++j) {
+        const long long i = bl_index(j);
+        if (i < n) { pv[j] = p[i]; av[j] = ap[i]; xv[j] = x[i]; rv[j] = r[i]; }
     }
-    grid_reduce<BL_NT>(s, partials, &st->cnt[CNT_UPD], gridDim.x, blockIdx.x,
-                       [&](double v) { finalize(st, mode, v); });
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < BL_U; ++j) {
+        const long long i = bl_index(j);
+        if (i < n) {
+            xv[j].x = fma(alpha, pv[j].x, xv[j].x);
+            xv[j].y = fma(alpha, pv[j].y, xv[j].y);
+            rv[j].x = fma(-alpha, av[j].x, rv[j].x);
+            rv[j].y = fma(-alpha, av[j].y, rv[j].y);
+            x[i] = xv[j];
+            r[i] = rv[j];
+            s = fma((double)rv[j].x, (double)rv[j].x, s);
+            s = fma((double)rv[j].y, (double)rv[j].y, s);
+        }
+    }
+    block_partial<BL_NT>(s, partials, blockIdx.x);
 }
 
 // p = r + beta p
@@ -181,11 +204,20 @@ __global__ __launch_bounds__(BL_NT) void k_cg_p(T *__restrict__ p, const T *__re
     if (st->flags.done) return;
     using R = typename VecT<T>::real;
     const R beta = (R)st->beta;
-    for (long long i = (long long)blockIdx.x * BL_NT + threadIdx.x; i < n; i += (long long)gridDim.x * BL_NT) {
-        T pv = p[i], rv = r[i];
-        pv.x = fma(beta, pv.x, rv.x);
-        pv.y = fma(beta, pv.y, rv.y);
-        p[i] = pv;
+    T pv[BL_U], rv[BL_U];
+#pragma unroll
+    for (int j = 0; j < BL_U; ++j) {
+        const long long i = bl_index(j);
+        if (i < n) { pv[j] = p[i]; rv[j] = r[i]; }
+    }
+#pragma unroll
+    for (int j = 0; j < BL_U; ++j) {
+        const long long i = bl_index(j);
+        if (i < n) {
+            pv[j].x = fma(beta, pv[j].x, rv[j].x);
+            pv[j].y = fma(beta, pv[j].y, rv[j].y);
+            p[i] = pv[j];
+        }
     }
 }
 
@@ -194,14 +226,35 @@ __global__ __launch_bounds__(BL_NT) void k_accum(double2 *__restrict__ x, float2
                                                  const CGState *st)
 {
     if (st->flags.done || !st->flags.reliable) return;
-    for (long long i = (long long)blockIdx.x * BL_NT + threadIdx.x; i < n; i += (long long)gridDim.x * BL_NT) {
-        float2 v = xs[i];
-        double2 a = x[i];
-        a.x += (double)v.x;
-        a.y += (double)v.y;
-        x[i] = a;
-        xs[i] = make_float2(0.f, 0.f);
+    float2 v[BL_U];
+    double2 a[BL_U];
+#pragma unroll
+    for (int j = 0; j < BL_U; ++j) {
+        const long long i = bl_index(j);
+        if (i < n) { v[j] = xs[i]; a[j] = x[i]; }
     }
+#pragma unroll
+    for (int j = 0; j < BL_U; ++j) {
+        const long long i = bl_index(j);
+        if (i < n) {
+            a[j].x += (double)v[j].x;
+            a[j].y += (double)v[j].y;
+            x[i] = a[j];
+            xs[i] = make_float2(0.f, 0.f);
+        }
+    }
+}
+
+// Second stage of every reduction: one block sums the partials in a fixed
+// order and applies finaliser `mode` to the state.  It is gated like the
+// kernel that produced the partials, so a skipped producer is a no-op here.
+constexpr int FIN_NT = 256;
+__global__ __launch_bounds__(FIN_NT) void k_finalize(const double *__restrict__ partials, int n, CGState *st, int mode,
+                                                     int gate)
+{
+    if (gate_closed(&st->flags, gate)) return;
+    double v = sum_partials<FIN_NT>(partials, n);
+    if (threadIdx.x == 0) finalize(st, mode, v);
 }
 
 __global__ void k_state_init(CGState *st, double tol2, double delta2, double m4)
@@ -230,13 +283,13 @@ __global__ void k_clear_done(CGState *st)
 }
 
 // ------------------------------------------------------------------ Dslash-fused kernels
-// Ap = m4 p - D_eo t ; Re<p, Ap> -> FIN_PAP
+// Ap = m4 p - D_eo t ; partials of Re<p, Ap>
 template <class P, int NT>
-__global__ __launch_bounds__(NT) void k_cg_Ap(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
+__global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_cg_Ap(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
                                               const typename P::cvec *__restrict__ t,
                                               const typename P::cvec *__restrict__ p,
                                               typename P::cvec *__restrict__ ap, int nblocks, double *partials,
-                                              CGState *st)
+                                              const CGState *st)
 {
     if (st->flags.done) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -262,17 +315,17 @@ __global__ __launch_bounds__(NT) void k_cg_Ap(Geom g, const char *__restrict__ f
             }
         }
     }
-    grid_reduce<NT>(s, partials, &st->cnt[CNT_PAP], nblocks, blk, [&](double v) { finalize(st, FIN_PAP, v); });
+    block_partial<NT>(s, partials, blk);
 }
 
-// r = b - (m4 x - D_eo t) in FP64 ; optional copies ; |r|^2 -> finaliser `mode`
+// r = b - (m4 x - D_eo t) in FP64 ; optional copies ; partials of |r|^2
 template <int NT>
-__global__ __launch_bounds__(NT) void k_resid(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
+__global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_resid(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
                                               const double2 *__restrict__ t, const double2 *__restrict__ x,
                                               const double2 *__restrict__ b, double2 *__restrict__ r,
                                               double2 *__restrict__ p, float2 *__restrict__ rs,
                                               float2 *__restrict__ ps, int nblocks, double *partials,
-                                              CGState *st, int mode, int gate)
+                                              const CGState *st, int gate)
 {
     if (gate_closed(&st->flags, gate)) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -302,7 +355,7 @@ __global__ __launch_bounds__(NT) void k_resid(Geom g, const char *__restrict__ f
             }
         }
     }
-    grid_reduce<NT>(s, partials, &st->cnt[CNT_RES], nblocks, blk, [&](double v) { finalize(st, mode, v); });
+    block_partial<NT>(s, partials, blk);
 }
 
 constexpr int CG_NT = 256;
@@ -311,18 +364,22 @@ static inline int dslash_nb(const Geom &g) { return (g.ntiles + CG_NT / TILE - 1
 // ------------------------------------------------------------------ host side
 size_t cg_partials_count(const Geom &g)
 {
-    size_t a = (size_t)dslash_nb(g), b = (size_t)BLAS_MAX_BLOCKS;
+    size_t a = (size_t)dslash_nb(g), b = (size_t)blas_blocks((long long)g.Vh * 3);
     return a > b ? a : b;
 }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Gap between carved workspace buffers: consecutive vectors start at
+// different offsets modulo the HBM channel interleave.
+constexpr size_t SKEW = 4352;
+
 size_t cg_workspace_bytes(const Geom &g, int mode)
 {
     const size_t v64 = align256((size_t)g.Vh * 3 * 16), v32 = align256((size_t)g.Vh * 3 * 8);
-    size_t bytes = align256(sizeof(CGState)) + align256(cg_partials_count(g) * sizeof(double));
-    if (mode == HISQ_CG_PLAIN_F64) bytes += 4 * v64;         // r p Ap t
-    else bytes += 2 * v64 + 5 * v32;                         // r64 t64 | xs rs ps Aps ts
+    size_t bytes = align256(sizeof(CGState)) + align256(cg_partials_count(g) * sizeof(double)) + 2 * SKEW;
+    if (mode == HISQ_CG_PLAIN_F64) bytes += 4 * (v64 + SKEW);               // r p Ap t
+    else bytes += 2 * (v64 + SKEW) + 5 * (v32 + SKEW);                      // r64 t64 | xs rs ps Aps ts
     return bytes;
 }
 
@@ -408,7 +465,7 @@ struct Carver {
     size_t left;
     void *take(size_t n)
     {
-        n = align256(n);
+        n = align256(n) + SKEW;
         if (n > left) return nullptr;
         void *r = p;
         p += n;
@@ -416,6 +473,79 @@ struct Carver {
         return r;
     }
 };
+
+// Launch helpers shared by the solvers: every reduction is a producer
+// kernel writing per-block partials followed by k_finalize.
+struct Launch {
+    const Geom &g;
+    CGState *st;
+    double *part;
+    long long n;  // complex entries per vector
+    int nbl, nbd;
+    dim3 gb, gd;
+    Launch(const Geom &g_, CGState *st_, double *part_)
+        : g(g_), st(st_), part(part_), n((long long)g_.Vh * 3), nbl(blas_blocks((long long)g_.Vh * 3)),
+          nbd(dslash_nb(g_)), gb(nbl), gd(xcd_grid(dslash_nb(g_)))
+    {
+    }
+    void fin(hipStream_t q, int nparts, int mode, int gate) const
+    {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, q, (const double *)part, nparts, st, mode, gate);
+    }
+    template <class T> void norm2(hipStream_t q, const T *x, int mode) const
+    {
+        hipLaunchKernelGGL((k_dot_state<T>), gb, dim3(BL_NT), 0, q, x, x, n, part);
+        fin(q, nbl, mode, GATE_ALWAYS);
+    }
+    // r = b - (m4 x - D_eo t) [+ copies], |r|^2 -> mode; t must hold D_oe x
+    void resid(hipStream_t q, const void *fat, const void *lng, const double2 *t, const void *x, const void *b,
+               double2 *r, double2 *p, float2 *rs, float2 *ps, int mode, int gate) const
+    {
+        hipLaunchKernelGGL((k_resid<CG_NT>), gd, dim3(CG_NT), 0, q, g, (const char *)fat, (const char *)lng, t,
+                           (const double2 *)x, (const double2 *)b, r, p, rs, ps, nbd, part, (const CGState *)st, gate);
+        fin(q, nbd, mode, gate);
+    }
+    template <class P>
+    void ap(hipStream_t q, const void *fat, const void *lng, const void *t, const void *p, void *apv) const
+    {
+        using V = typename P::cvec;
+        hipLaunchKernelGGL((k_cg_Ap<P, CG_NT>), gd, dim3(CG_NT), 0, q, g, (const char *)fat, (const char *)lng,
+                           (const V *)t, (const V *)p, (V *)apv, nbd, part, (const CGState *)st);
+        fin(q, nbd, FIN_PAP, GATE_NOT_DONE);
+    }
+    template <class T> void update(hipStream_t q, T *x, T *r, const T *p, const T *apv, int mode) const
+    {
+        hipLaunchKernelGGL((k_cg_update<T>), gb, dim3(BL_NT), 0, q, x, r, p, apv, n, part, (const CGState *)st);
+        fin(q, nbl, mode, GATE_NOT_DONE);
+    }
+    template <class T> void pupd(hipStream_t q, T *p, const T *r) const
+    {
+        hipLaunchKernelGGL((k_cg_p<T>), gb, dim3(BL_NT), 0, q, p, r, n, (const CGState *)st);
+    }
+};
+
+static void finish_stats(hisq_cg_stats &stats, const CGState *hs, int status, int restarts,
+                         std::chrono::steady_clock::time_point t0)
+{
+    stats.iters = hs->iter;
+    stats.restarts = restarts;
+    stats.reliable_updates = hs->nupdates;
+    stats.true_resid = hs->bb > 0 ? std::sqrt(hs->rr_true / hs->bb) : 0.0;
+    stats.status = status;
+    stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+static int zero_source_exit(void *x, size_t v64, hipStream_t s, hisq_cg_stats &stats,
+                            std::chrono::steady_clock::time_point t0)
+{
+    HISQ_HIP(hipMemsetAsync(x, 0, v64, s));
+    HISQ_HIP(hipStreamSynchronize(s));
+    stats.iters = 0;
+    stats.true_resid = 0.0;
+    stats.status = HISQ_OK;
+    stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return HISQ_OK;
+}
 
 int cg_plain_f64(double mass, double tol, const void *fat, const void *lng, const void *b, void *x, const Geom &g,
                  const hisq_cg_opts &o, void *ws, size_t ws_bytes, hisq_cg_stats &stats, hipStream_t s)
@@ -429,78 +559,51 @@ int cg_plain_f64(double mass, double tol, const void *fat, const void *lng, cons
     if (!t) return fail(HISQ_EWORKSPACE, "cg_solve: workspace too small");
     CGState *hs = pinned_state();
     if (!hs) return fail(HISQ_EHIP, "cg_solve: pinned state allocation failed");
-    const long long n = (long long)g.Vh * 3;
-    const int nbl = blas_blocks(n), nbd = dslash_nb(g);
-    const dim3 gb(nbl), bb(BL_NT), gd(xcd_grid(nbd)), bd(CG_NT);
+    const Launch L(g, st, part);
 
     auto t0 = std::chrono::steady_clock::now();
     HISQ_HIP(hipMemsetAsync(st, 0, sizeof(CGState), s));
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, tol * tol, 0.0, 4.0 * mass * mass);
-    hipLaunchKernelGGL((k_dot_state<double2>), gb, bb, 0, s, (const double2 *)b, (const double2 *)b, n, part, st,
-                       (int)CNT_DOT, (int)FIN_BB);
-    // r = p = b - A x0
-    HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t, 1, s));
-    hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, s, g, (const char *)fat, (const char *)lng, t,
-                       (const double2 *)x, (const double2 *)b, r, p, (float2 *)nullptr, (float2 *)nullptr, nbd, part,
-                       st, (int)FIN_INIT_PLAIN, (int)GATE_ALWAYS);
+    L.norm2(s, (const double2 *)b, FIN_BB);
+    HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t, 1, s));  // r = p = b - A x0
+    L.resid(s, fat, lng, t, x, b, r, p, nullptr, nullptr, FIN_INIT_PLAIN, GATE_ALWAYS);
     HISQ_HIP(hipGetLastError());
     int rc = read_state(hs, st, s);
     if (rc) return rc;
-    if (hs->bb == 0.0) {
-        HISQ_HIP(hipMemsetAsync(x, 0, v64, s));
-        HISQ_HIP(hipStreamSynchronize(s));
-        stats.iters = 0;
-        stats.true_resid = 0.0;
-        stats.status = HISQ_OK;
-        stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        return HISQ_OK;
-    }
+    if (hs->bb == 0.0) return zero_source_exit(x, v64, s, stats, t0);
 
     auto iter = [&](hipStream_t q) -> hipError_t {
         hipError_t e = launch_dslash<PF64>(g, fat, lng, p, t, 1, q, &st->flags, GATE_NOT_DONE);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_cg_Ap<PF64, CG_NT>), gd, bd, 0, q, g, (const char *)fat, (const char *)lng,
-                           (const double2 *)t, (const double2 *)p, ap, nbd, part, st);
-        hipLaunchKernelGGL((k_cg_update<double2>), gb, bb, 0, q, (double2 *)x, r, (const double2 *)p,
-                           (const double2 *)ap, n, part, st, (int)FIN_UPD_PLAIN);
-        hipLaunchKernelGGL((k_cg_p<double2>), gb, bb, 0, q, p, (const double2 *)r, n, (const CGState *)st);
+        L.ap<PF64>(q, fat, lng, t, p, ap);
+        L.update<double2>(q, (double2 *)x, r, p, ap, FIN_UPD_PLAIN);
+        L.pupd<double2>(q, p, r);
         return hipGetLastError();
     };
 
-    const int K = o.check_every;
     int restarts = 0;
     int status = HISQ_OK;
     while (true) {
         if (!hs->flags.done) {
-            rc = run_iterations(iter, s, st, hs, K, o.max_iter, o.use_graph != 0, hs->iter);
+            rc = run_iterations(iter, s, st, hs, o.check_every, o.max_iter, o.use_graph != 0, hs->iter);
             if (rc) return rc;
         }
         if (hs->flags.done == CG_BREAKDOWN) { status = HISQ_EBREAKDOWN; break; }
         // true residual r = b - A x in FP64
         HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t, 1, s));
-        hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, s, g, (const char *)fat, (const char *)lng, t,
-                           (const double2 *)x, (const double2 *)b, r, (double2 *)nullptr, (float2 *)nullptr,
-                           (float2 *)nullptr, nbd, part, st, (int)FIN_TRUE, (int)GATE_ALWAYS);
+        L.resid(s, fat, lng, t, x, b, r, nullptr, nullptr, nullptr, FIN_TRUE, GATE_ALWAYS);
         HISQ_HIP(hipGetLastError());
         rc = read_state(hs, st, s);
         if (rc) return rc;
         if (hs->rr_true <= hs->stop2) { status = HISQ_OK; break; }
         if (hs->iter >= o.max_iter || restarts >= 3) { status = HISQ_ENOCONV; break; }
-        // restart from x: r = p = b - A x
-        ++restarts;
-        hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, s, g, (const char *)fat, (const char *)lng, t,
-                           (const double2 *)x, (const double2 *)b, r, p, (float2 *)nullptr, (float2 *)nullptr, nbd,
-                           part, st, (int)FIN_INIT_PLAIN, (int)GATE_ALWAYS);
+        ++restarts;  // restart from x: r = p = b - A x (t still holds D_oe x)
+        L.resid(s, fat, lng, t, x, b, r, p, nullptr, nullptr, FIN_INIT_PLAIN, GATE_ALWAYS);
         HISQ_HIP(hipGetLastError());
         rc = read_state(hs, st, s);
         if (rc) return rc;
     }
-    stats.iters = hs->iter;
-    stats.restarts = restarts;
-    stats.reliable_updates = 0;
-    stats.true_resid = std::sqrt(hs->rr_true / hs->bb);
-    stats.status = status;
-    stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    finish_stats(stats, hs, status, restarts, t0);
     if (status == HISQ_EBREAKDOWN) return fail(status, "cg_solve: breakdown (<p,Ap> <= 0 or not finite)");
     if (status == HISQ_ENOCONV) return fail(status, "cg_solve: not converged within max_iter");
     return HISQ_OK;
@@ -521,49 +624,33 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
     if (!ts) return fail(HISQ_EWORKSPACE, "cg_solve: workspace too small");
     CGState *hs = pinned_state();
     if (!hs) return fail(HISQ_EHIP, "cg_solve: pinned state allocation failed");
-    const long long n = (long long)g.Vh * 3;
-    const int nbl = blas_blocks(n), nbd = dslash_nb(g);
-    const dim3 gb(nbl), bb(BL_NT), gd(xcd_grid(nbd)), bd(CG_NT);
+    const Launch L(g, st, part);
     const double delta = o.delta > 0 ? o.delta : 0.1;
 
     auto t0 = std::chrono::steady_clock::now();
     HISQ_HIP(hipMemsetAsync(st, 0, sizeof(CGState), s));
     HISQ_HIP(hipMemsetAsync(xs, 0, v32, s));
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, tol * tol, delta * delta, 4.0 * mass * mass);
-    hipLaunchKernelGGL((k_dot_state<double2>), gb, bb, 0, s, (const double2 *)b, (const double2 *)b, n, part, st,
-                       (int)CNT_DOT, (int)FIN_BB);
+    L.norm2(s, (const double2 *)b, FIN_BB);
     HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t64, 1, s));
-    hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, s, g, (const char *)fat, (const char *)lng, t64,
-                       (const double2 *)x, (const double2 *)b, r64, (double2 *)nullptr, rs, ps, nbd, part, st,
-                       (int)FIN_INIT_MIXED, (int)GATE_ALWAYS);
+    L.resid(s, fat, lng, t64, x, b, r64, nullptr, rs, ps, FIN_INIT_MIXED, GATE_ALWAYS);
     HISQ_HIP(hipGetLastError());
     int rc = read_state(hs, st, s);
     if (rc) return rc;
-    if (hs->bb == 0.0) {
-        HISQ_HIP(hipMemsetAsync(x, 0, v64, s));
-        HISQ_HIP(hipStreamSynchronize(s));
-        stats.iters = 0;
-        stats.true_resid = 0.0;
-        stats.status = HISQ_OK;
-        stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        return HISQ_OK;
-    }
+    if (hs->bb == 0.0) return zero_source_exit(x, v64, s, stats, t0);
 
+    const dim3 gb(L.nbl), bb(BL_NT);
     auto iter = [&](hipStream_t q) -> hipError_t {
         hipError_t e = launch_dslash<PS>(g, fat_lo, lng_lo, ps, ts, 1, q, &st->flags, GATE_NOT_DONE);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_cg_Ap<PS, CG_NT>), gd, bd, 0, q, g, (const char *)fat_lo, (const char *)lng_lo,
-                           (const float2 *)ts, (const float2 *)ps, aps, nbd, part, st);
-        hipLaunchKernelGGL((k_cg_update<float2>), gb, bb, 0, q, xs, rs, (const float2 *)ps, (const float2 *)aps, n,
-                           part, st, (int)FIN_UPD_MIXED);
+        L.ap<PS>(q, fat_lo, lng_lo, ts, ps, aps);
+        L.update<float2>(q, xs, rs, ps, aps, FIN_UPD_MIXED);
         // reliable update (kernels return at once unless it was triggered)
-        hipLaunchKernelGGL(k_accum, gb, bb, 0, q, (double2 *)x, xs, n, (const CGState *)st);
+        hipLaunchKernelGGL(k_accum, gb, bb, 0, q, (double2 *)x, xs, L.n, (const CGState *)st);
         e = launch_dslash<PF64>(g, fat, lng, x, t64, 1, q, &st->flags, GATE_RELIABLE);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, q, g, (const char *)fat, (const char *)lng,
-                           (const double2 *)t64, (const double2 *)x, (const double2 *)b, r64, (double2 *)nullptr, rs,
-                           (float2 *)nullptr, nbd, part, st, (int)FIN_RELIABLE, (int)GATE_RELIABLE);
-        hipLaunchKernelGGL((k_cg_p<float2>), gb, bb, 0, q, ps, (const float2 *)rs, n, (const CGState *)st);
+        L.resid(q, fat, lng, t64, x, b, r64, nullptr, rs, nullptr, FIN_RELIABLE, GATE_RELIABLE);
+        L.pupd<float2>(q, ps, rs);
         return hipGetLastError();
     };
 
@@ -575,22 +662,15 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
     } else if (hs->flags.done != CG_CONVERGED) {
         // out of iterations: fold the inner solution in and measure the true residual
         hipLaunchKernelGGL(k_force_reliable, dim3(1), dim3(1), 0, s, st);
-        hipLaunchKernelGGL(k_accum, gb, bb, 0, s, (double2 *)x, xs, n, (const CGState *)st);
+        hipLaunchKernelGGL(k_accum, gb, bb, 0, s, (double2 *)x, xs, L.n, (const CGState *)st);
         HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t64, 1, s));
-        hipLaunchKernelGGL((k_resid<CG_NT>), gd, bd, 0, s, g, (const char *)fat, (const char *)lng,
-                           (const double2 *)t64, (const double2 *)x, (const double2 *)b, r64, (double2 *)nullptr, rs,
-                           (float2 *)nullptr, nbd, part, st, (int)FIN_RELIABLE, (int)GATE_ALWAYS);
+        L.resid(s, fat, lng, t64, x, b, r64, nullptr, rs, nullptr, FIN_RELIABLE, GATE_ALWAYS);
         HISQ_HIP(hipGetLastError());
         rc = read_state(hs, st, s);
         if (rc) return rc;
         status = hs->rr_true <= hs->stop2 ? HISQ_OK : HISQ_ENOCONV;
     }
-    stats.iters = hs->iter;
-    stats.reliable_updates = hs->nupdates;
-    stats.restarts = 0;
-    stats.true_resid = std::sqrt(hs->rr_true / hs->bb);
-    stats.status = status;
-    stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    finish_stats(stats, hs, status, 0, t0);
     if (status == HISQ_EBREAKDOWN) return fail(status, "cg_solve: breakdown (<p,Ap> <= 0 or not finite)");
     if (status == HISQ_ENOCONV) return fail(status, "cg_solve: not converged within max_iter");
     return HISQ_OK;
@@ -618,7 +698,7 @@ hisq_cg_opts resolve_opts(const hisq_cg_opts *opts, const Geom &g)
 // ------------------------------------------------------------------ standalone dot
 template <class T>
 __global__ __launch_bounds__(BL_NT) void k_dot2(const T *__restrict__ x, const T *__restrict__ y, long long n,
-                                                double *partials, double *out, unsigned *counter)
+                                                double *partials)
 {
     double sr = 0.0, si = 0.0;
     for (long long i = (long long)blockIdx.x * BL_NT + threadIdx.x; i < n; i += (long long)gridDim.x * BL_NT) {
@@ -629,28 +709,25 @@ __global__ __launch_bounds__(BL_NT) void k_dot2(const T *__restrict__ x, const T
         si = fma(-a.y, b.x, si);
     }
     __shared__ double lds[2 * (BL_NT / 64)];
-    __shared__ bool last;
     block_sum2<BL_NT>(sr, si, lds);
     if (threadIdx.x == 0) {
         partials[2 * blockIdx.x] = sr;
         partials[2 * blockIdx.x + 1] = si;
-        __threadfence();
-        last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+__global__ __launch_bounds__(FIN_NT) void k_dot2_fin(const double *__restrict__ partials, int nb, double *out)
+{
+    __shared__ double lds[2 * (FIN_NT / 64)];
     double ar = 0.0, ai = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += BL_NT) {
-        ar += __builtin_nontemporal_load(&partials[2 * i]);
-        ai += __builtin_nontemporal_load(&partials[2 * i + 1]);
+    for (int i = threadIdx.x; i < nb; i += FIN_NT) {
+        ar += partials[2 * i];
+        ai += partials[2 * i + 1];
     }
-    block_sum2<BL_NT>(ar, ai, lds);
+    block_sum2<FIN_NT>(ar, ai, lds);
     if (threadIdx.x == 0) {
         out[0] = ar;
         out[1] = ai;
-        *counter = 0u;
-        __threadfence();
     }
 }
 
@@ -663,7 +740,7 @@ extern "C" size_t hisq_workspace_bytes(const char *solver, const int dims[4], in
     Geom g;
     if (!solver || make_geom(dims, g)) return 0;
     if (!std::strcmp(solver, "cg")) {
-        if (mode < HISQ_CG_PLAIN_F64 || mode > HISQ_CG_MIXED_F16S) return 0;
+        if (mode < HISQ_CG_PLAIN_F64 || mode > HISQ_CG_MIXED_I16S) return 0;
         return cg_workspace_bytes(g, mode);
     }
     if (!std::strcmp(solver, "cg_multi")) return cg_multi_workspace_bytes(g, nrhs, mode);
@@ -688,7 +765,7 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
     if (!(tol > 0) || !(mass >= 0)) return st.status = fail(HISQ_EINVAL, "cg_solve: need tol > 0 and mass >= 0");
     if (o.mode != HISQ_CG_PLAIN_F64 && (!fat_lo || !lng_lo))
         return st.status = fail(HISQ_EINVAL, "cg_solve: mixed mode needs fat_lo and lng_lo");
-    if (o.mode < HISQ_CG_PLAIN_F64 || o.mode > HISQ_CG_MIXED_F16S)
+    if (o.mode < HISQ_CG_PLAIN_F64 || o.mode > HISQ_CG_MIXED_I16S)
         return st.status = fail(HISQ_EINVAL, "cg_solve: unknown mode");
     if (!workspace || ws_bytes < cg_workspace_bytes(g, o.mode))
         return st.status = fail(HISQ_EWORKSPACE, "cg_solve: workspace NULL or smaller than hisq_workspace_bytes()");
@@ -702,7 +779,10 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
     case HISQ_CG_MIXED_F32:
         rc = cg_mixed<PF32>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
         break;
-    default: rc = cg_mixed<PF16S>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
+    case HISQ_CG_MIXED_F16S:
+        rc = cg_mixed<PF16S>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
+        break;
+    default: rc = cg_mixed<PI16S>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
     }
     st.status = rc;
     return rc;
@@ -711,29 +791,26 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
 extern "C" int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *stream)
 {
     if (!x || !y || !out_host || n < 0) return fail(HISQ_EINVAL, "hisq_dot: bad argument");
-    if (prec != HISQ_F64 && prec != HISQ_F32 && prec != HISQ_F16S) return fail(HISQ_EINVAL, "hisq_dot: bad precision");
-    // small persistent scratch: partials, result and the arrival counter
+    if (prec < HISQ_F64 || prec > HISQ_I16S) return fail(HISQ_EINVAL, "hisq_dot: bad precision");
+    // small scratch (partials and the result), allocated once per thread
     static thread_local char *scratch = nullptr;
     const size_t part_bytes = 2 * sizeof(double) * BLAS_MAX_BLOCKS;
-    if (!scratch) {
-        HISQ_HIP(hipMalloc((void **)&scratch, part_bytes + 256));
-        HISQ_HIP(hipMemset(scratch, 0, part_bytes + 256));
-    }
+    if (!scratch) HISQ_HIP(hipMalloc((void **)&scratch, part_bytes + 256));
     double *part = (double *)scratch;
     double *out = (double *)(scratch + part_bytes);
-    unsigned *cnt = (unsigned *)(scratch + part_bytes + 64);
     hipStream_t s = (hipStream_t)stream;
     if (n == 0) {
         out_host[0] = out_host[1] = 0.0;
         return HISQ_OK;
     }
-    const int nb = blas_blocks(n);
+    const int nb = (int)std::min<long long>((n + 255) / 256, BLAS_MAX_BLOCKS);
     if (prec == HISQ_F64)
         hipLaunchKernelGGL((k_dot2<double2>), dim3(nb), dim3(BL_NT), 0, s, (const double2 *)x, (const double2 *)y, n,
-                           part, out, cnt);
+                           part);
     else
         hipLaunchKernelGGL((k_dot2<float2>), dim3(nb), dim3(BL_NT), 0, s, (const float2 *)x, (const float2 *)y, n,
-                           part, out, cnt);
+                           part);
+    hipLaunchKernelGGL(k_dot2_fin, dim3(1), dim3(FIN_NT), 0, s, (const double *)part, nb, out);
     HISQ_HIP(hipGetLastError());
     HISQ_HIP(hipMemcpyAsync(out_host, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HISQ_HIP(hipStreamSynchronize(s));

@@ -6,8 +6,6 @@
 namespace hisq {
 
 enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
-// arrival counters of the two-stage reductions, one per reduction site
-enum { CNT_DOT = 0, CNT_PAP = 1, CNT_UPD = 2, CNT_RES = 3, CNT_AUX = 4 };
 constexpr int BLAS_MAX_BLOCKS = 1024;
 
 // Device-resident scalars of one solve.  `flags` comes first: kernels gate on it.
@@ -25,7 +23,6 @@ struct CGState {
     double rr_true;  // last FP64 true residual |b - A x|^2
     double maxrr;    // max |r_inner|^2 since the last reliable update
     double alpha, beta, pAp;
-    unsigned cnt[8];
 };
 
 int blas_blocks(long long n);

@@ -1,13 +1,1109 @@
-// Batched solves: many right-hand sides / many shifts (placeholder until the
-// multi-RHS Dslash lands).
+// Batched solves of the even-odd system for several right-hand sides or
+// several masses (Sec. 3: the multishift CG of gauge generation solves one
+// source for 9 or 11 masses; its working set is (36 + 2 N_m) 48 V bytes).
+//
+// MULTI_RHS: nrhs systems A(m_i) x_i = b_i advance together.  Every Dslash is
+// one launch over all right-hand sides: a thread loads each link matrix once
+// and applies it to the G right-hand sides it owns, so the link stream (96% of
+// the single-RHS bytes) is shared by the batch.  Inner iterations run on FP32
+// vectors and links with FP64 dot accumulation; each right-hand side keeps
+// its own alpha, beta, reliable-update trigger and convergence flag, and the
+// FP64 reliable update / true-residual Dslash runs only for the right-hand
+// sides that asked for it (a per-RHS mask).
+//
+// MULTI_SHIFT: one source b and masses m_i: shifted CG (Jegerlehner 1996,
+// the residual polynomials of all shifted systems are collinear with the
+// base system's) runs one Dslash pair per iteration for all shifts in FP32,
+// then every x_i is refined to tol by the MULTI_RHS solver started from it.
+//
+// Internal vectors are site-major [Vh][N][3] so that the N right-hand sides
+// of a neighbour are one contiguous read.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "cg_internal.hpp"
 
 namespace hisq {
+
+constexpr int MAXR = 16;
+
+struct MultiState {
+    SolverFlags flags;  // done: every RHS finished ; reliable: some RHS has an update pending
+    int n;              // right-hand sides in use
+    unsigned active;    // bit r: RHS r still iterating
+    unsigned relmask;   // bit r: reliable update pending for RHS r
+    int iter;           // batch iterations
+    int iters[MAXR], nupd[MAXR], status[MAXR];
+    double tol2, delta2;
+    double m4[MAXR], bb[MAXR], stop2[MAXR], rr[MAXR], rr_true[MAXR], maxrr[MAXR], alpha[MAXR], beta[MAXR];
+    // shifted CG
+    double sigma0, rr0, bb0, stop0, alpha0, beta0, a_prev, b_prev;
+    double dsig[MAXR], zeta[MAXR], zeta_prev[MAXR], zeta_next[MAXR], alpha_s[MAXR], beta_s[MAXR];
+    int ms_status;
+};
+
+enum { EPI_STORE = 0, EPI_AP = 1, EPI_RESID = 2 };
+enum { MASK_ACTIVE = 0, MASK_RELIABLE = 1, MASK_ALL = 2 };
+
+__device__ __forceinline__ unsigned pick_mask(const MultiState *st, int which)
+{
+    return which == MASK_ACTIVE ? st->active : (which == MASK_RELIABLE ? st->relmask : ((1u << st->n) - 1u));
+}
+
+template <class P>
+__device__ __forceinline__ void cmac_m(typename P::real acc[6], const typename P::real m[18],
+                                       const typename P::cvec *s)
+{
+    cmac<P>(acc, m, s[0], s[1], s[2]);
+}
+
+// ------------------------------------------------------------------ multi-RHS Dslash
+// N right-hand sides in [Vh][N][3]; each thread owns G of them for one site,
+// N/G consecutive threads share a site (their link loads hit the same
+// addresses and are served once).  Persistent: blocks stride over site units
+// inside the slab of their XCD.
+//   EPI_STORE : dst = D src
+//   EPI_AP    : dst = m4_r x - D src, partial Re<x, dst> per RHS
+//   EPI_RESID : (FP64) dst = b - (m4_r x - D src), rs = float(dst), partial |dst|^2 per RHS
+template <class P, int N, int G, int NT, int EPI>
+__global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
+                                                const typename P::cvec *__restrict__ src,
+                                                typename P::cvec *__restrict__ dst,
+                                                const typename P::cvec *__restrict__ x,
+                                                const typename P::cvec *__restrict__ b, float2 *__restrict__ rs,
+                                                int parity, int nunits, double *partials, const MultiState *st,
+                                                int which_mask, int gate)
+{
+    using R = typename P::real;
+    using V = typename P::cvec;
+    constexpr int TPS = N / G;        // threads per site
+    constexpr int SPB = NT / TPS;     // sites per block per unit
+    if (gate_closed(&st->flags, gate)) return;
+    const unsigned mask = pick_mask(st, which_mask);
+    const int grp = threadIdx.x % TPS;
+    const int r0 = grp * G;
+    double part[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) part[j] = 0.0;
+    double m4[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) m4[j] = (EPI != EPI_STORE) ? st->m4[r0 + j] : 0.0;
+
+    // XCD-aware persistent order: XCD k walks the k-th slab of units
+    const int xcd = blockIdx.x % NXCD, local = blockIdx.x / NXCD, per_xcd = gridDim.x / NXCD;
+    const int units_per_xcd = (nunits + NXCD - 1) / NXCD;
+    for (int u = local; u < units_per_xcd; u += per_xcd) {
+        const int unit = xcd * units_per_xcd + u;
+        if (unit >= nunits) break;
+        const int site = unit * SPB + threadIdx.x / TPS;
+        const int h = site < g.Vh ? site : g.Vh - 1;
+        const int tile = h / TILE, lane = h % TILE;
+        int cx, cy, cz, ct;
+        site_coords(g, h, parity, cx, cy, cz, ct);
+        const size_t tile_off = ((size_t)parity * g.ntiles + tile) * 8 * P::block_bytes;
+        R acc[G][6];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+#pragma unroll
+            for (int i = 0; i < 6; ++i) acc[j][i] = 0;
+#pragma unroll 1
+        for (int d = 0; d < 16; ++d) {
+            const int mu = d & 3;
+            const bool is_long = d >= 8;
+            const int k = (is_long ? 3 : 1) * (((d >> 2) & 1) ? -1 : 1);
+            const int nh = nbr_h(g, h, cx, cy, cz, ct, mu, k);
+            R m[18];
+            P::load((is_long ? lng : fat) + tile_off + (size_t)(d & 7) * P::block_bytes, lane, m);
+            const V *s = src + ((size_t)nh * N + r0) * 3;
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (mask & (1u << (r0 + j))) cmac_m<P>(acc[j], m, s + 3 * j);
+        }
+        if (site < g.Vh) {
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (!(mask & (1u << (r0 + j)))) continue;
+                const size_t base = ((size_t)site * N + r0 + j) * 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    V v;
+                    if (EPI == EPI_STORE) {
+                        v.x = acc[j][2 * c];
+                        v.y = acc[j][2 * c + 1];
+                    } else if (EPI == EPI_AP) {
+                        V xv = x[base + c];
+                        v.x = fma((R)m4[j], xv.x, -acc[j][2 * c]);
+                        v.y = fma((R)m4[j], xv.y, -acc[j][2 * c + 1]);
+                        part[j] = fma((double)xv.x, (double)v.x, part[j]);
+                        part[j] = fma((double)xv.y, (double)v.y, part[j]);
+                    } else {
+                        V xv = x[base + c], bv = b[base + c];
+                        v.x = bv.x - fma((R)m4[j], xv.x, -acc[j][2 * c]);
+                        v.y = bv.y - fma((R)m4[j], xv.y, -acc[j][2 * c + 1]);
+                        rs[base + c] = make_float2((float)v.x, (float)v.y);
+                        part[j] = fma((double)v.x, (double)v.x, part[j]);
+                        part[j] = fma((double)v.y, (double)v.y, part[j]);
+                    }
+                    dst[base + c] = v;
+                }
+            }
+        }
+    }
+    if (EPI != EPI_STORE) {
+        // fixed-order per-RHS block partials: [blk][N]
+        __shared__ double red[NT * G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) red[threadIdx.x * G + j] = part[j];
+        __syncthreads();
+        if (threadIdx.x < N) {
+            const int r = threadIdx.x, gr = r / G, j = r % G;
+            double s = 0.0;
+            for (int t = 0; t < SPB; ++t) s += red[(t * TPS + gr) * G + j];
+            partials[(size_t)blockIdx.x * N + r] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ batched BLAS
+// One thread per (site, RHS) pair j = site * N + r: its 3 colours are 24 B
+// (FP32) or 48 B (FP64) contiguous and a wavefront covers 64 consecutive
+// pairs, so loads are contiguous; per-RHS scalars come from LDS.
+constexpr int MB_NT = 256;
+constexpr int FIN_NT_M = 256;
+constexpr int MULTI_MAX_BLOCKS = 2048;
+
+static inline int mblocks(long long pairs)
+{
+    long long nb = (pairs + MB_NT - 1) / MB_NT;
+    return (int)std::min<long long>(std::max<long long>(nb, 1), MULTI_MAX_BLOCKS);
+}
+
+// per-RHS block partials of the values `v` each thread accumulated for RHS
+// r = j % N (the same for every pair this thread visits, since the grid
+// stride is a multiple of N)
+template <int N>
+__device__ __forceinline__ void mblock_partials(double v, double *partials)
+{
+    __shared__ double red[MB_NT];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double s = 0.0;
+        for (int t = threadIdx.x; t < MB_NT; t += N) s += red[t];
+        partials[(size_t)blockIdx.x * N + threadIdx.x] = s;
+    }
+}
+
+// XS += alpha PS ; RS -= alpha APS (active RHS) ; partial |RS|^2 per RHS
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_mupdate(float2 *__restrict__ xs, float2 *__restrict__ rs,
+                                                   const float2 *__restrict__ ps, const float2 *__restrict__ aps,
+                                                   long long npairs, double *partials, const MultiState *st)
+{
+    if (st->flags.done) return;
+    const int r = threadIdx.x % N;  // MB_NT and the grid stride are multiples of N
+    const bool on = (st->active >> r) & 1u;
+    const float a = (float)st->alpha[r];
+    double acc = 0.0;
+    if (on) {
+        for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long long i = j * 3 + c;
+                float2 xv = xs[i], rv = rs[i], pv = ps[i], av = aps[i];
+                xv.x = fmaf(a, pv.x, xv.x);
+                xv.y = fmaf(a, pv.y, xv.y);
+                rv.x = fmaf(-a, av.x, rv.x);
+                rv.y = fmaf(-a, av.y, rv.y);
+                xs[i] = xv;
+                rs[i] = rv;
+                acc = fma((double)rv.x, (double)rv.x, fma((double)rv.y, (double)rv.y, acc));
+            }
+        }
+    }
+    mblock_partials<N>(acc, partials);
+}
+
+// PS = RS + beta PS (active RHS)
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_mp(float2 *__restrict__ ps, const float2 *__restrict__ rs, long long npairs,
+                                              const MultiState *st)
+{
+    if (st->flags.done) return;
+    const int r = threadIdx.x % N;
+    if (!((st->active >> r) & 1u)) return;
+    const float bt = (float)st->beta[r];
+    for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long long i = j * 3 + c;
+            float2 pv = ps[i], rv = rs[i];
+            pv.x = fmaf(bt, pv.x, rv.x);
+            pv.y = fmaf(bt, pv.y, rv.y);
+            ps[i] = pv;
+        }
+    }
+}
+
+// X64 += XS ; XS = 0 for the RHS in `which_mask`
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_maccum(double2 *__restrict__ x, float2 *__restrict__ xs, long long npairs,
+                                                  const MultiState *st, int which_mask, int gate)
+{
+    if (gate_closed(&st->flags, gate)) return;
+    const int r = threadIdx.x % N;
+    if (!((pick_mask(st, which_mask) >> r) & 1u)) return;
+    for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long long i = j * 3 + c;
+            float2 v = xs[i];
+            double2 a = x[i];
+            a.x += (double)v.x;
+            a.y += (double)v.y;
+            x[i] = a;
+            xs[i] = make_float2(0.f, 0.f);
+        }
+    }
+}
+
+// partial |V_r|^2 per RHS of an FP64 batched vector
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_mnorm(const double2 *__restrict__ v, long long npairs, double *partials)
+{
+    double acc = 0.0;
+    for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double2 a = v[j * 3 + c];
+            acc = fma(a.x, a.x, fma(a.y, a.y, acc));
+        }
+    mblock_partials<N>(acc, partials);
+}
+
+// ------------------------------------------------------------------ shifted CG (FP32)
+// base system (A0 + sigma0) on single vectors p, r, ap, t; shifted solutions
+// and directions x_i, p_i batched [Vh][N][3].
+__global__ __launch_bounds__(256) HISQ_WAVES(8) void k_ms_ap(Geom g, const char *__restrict__ fat,
+                                                          const char *__restrict__ lng,
+                                                          const float2 *__restrict__ t, const float2 *__restrict__ p,
+                                                          float2 *__restrict__ ap, int nblocks, double *partials,
+                                                          const MultiState *st)
+{
+    if (st->flags.done) return;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    if (blk >= nblocks) return;
+    const int tile = blk * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int h = tile * TILE + lane;
+    double s = 0.0;
+    if (tile < g.ntiles) {
+        const int hc = h < g.Vh ? h : g.Vh - 1;
+        float acc[6];
+        dslash_site<PF32>(g, fat, lng, t, 0, tile, lane, hc, acc);
+        if (h < g.Vh) {
+            const float m = (float)st->sigma0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float2 pv = p[(size_t)h * 3 + c], v;
+                v.x = fmaf(m, pv.x, -acc[2 * c]);
+                v.y = fmaf(m, pv.y, -acc[2 * c + 1]);
+                ap[(size_t)h * 3 + c] = v;
+                s = fma((double)pv.x, (double)v.x, fma((double)pv.y, (double)v.y, s));
+            }
+        }
+    }
+    block_partial<256>(s, partials, blk);
+}
+
+// r -= alpha ap ; partial |r|^2   (single vectors, n complex entries)
+__global__ __launch_bounds__(MB_NT) void k_ms_r(float2 *__restrict__ r, const float2 *__restrict__ ap, long long n,
+                                                double *partials, const MultiState *st)
+{
+    if (st->flags.done) return;
+    const float a = (float)st->alpha0;
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * MB_NT + threadIdx.x; i < n; i += (long long)gridDim.x * MB_NT) {
+        float2 rv = r[i], av = ap[i];
+        rv.x = fmaf(-a, av.x, rv.x);
+        rv.y = fmaf(-a, av.y, rv.y);
+        r[i] = rv;
+        acc = fma((double)rv.x, (double)rv.x, fma((double)rv.y, (double)rv.y, acc));
+    }
+    block_partial<MB_NT>(acc, partials, blockIdx.x);
+}
+
+// x_i += alpha_i p_i (active shifts)
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_ms_x(float2 *__restrict__ xs, const float2 *__restrict__ ps,
+                                                long long npairs, const MultiState *st)
+{
+    if (st->flags.done) return;
+    const int r = threadIdx.x % N;
+    if (!((st->active >> r) & 1u)) return;
+    const float a = (float)st->alpha_s[r];
+    for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long long i = j * 3 + c;
+            float2 xv = xs[i], pv = ps[i];
+            xv.x = fmaf(a, pv.x, xv.x);
+            xv.y = fmaf(a, pv.y, xv.y);
+            xs[i] = xv;
+        }
+    }
+}
+
+// p_i = zeta_i r + beta_i p_i (active shifts) ; p = r + beta p
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_ms_p(float2 *__restrict__ ps, float2 *__restrict__ p,
+                                                const float2 *__restrict__ rv_, long long npairs, const MultiState *st)
+{
+    if (st->flags.done) return;
+    const int r = threadIdx.x % N;
+    const bool on = (st->active >> r) & 1u;
+    const float z = (float)st->zeta[r], bt = (float)st->beta_s[r], b0 = (float)st->beta0;
+    for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT) {
+        const long long site = j / N;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float2 rv = rv_[site * 3 + c];
+            if (on) {
+                const long long i = j * 3 + c;
+                float2 pv = ps[i];
+                pv.x = fmaf(bt, pv.x, z * rv.x);
+                pv.y = fmaf(bt, pv.y, z * rv.y);
+                ps[i] = pv;
+            }
+            if (r == 0) {
+                float2 q = p[site * 3 + c];
+                q.x = fmaf(b0, q.x, rv.x);
+                q.y = fmaf(b0, q.y, rv.y);
+                p[site * 3 + c] = q;
+            }
+        }
+    }
+}
+
+enum { FS_BB = 0, FS_PAP = 1, FS_UPD = 2 };
+
+__global__ __launch_bounds__(FIN_NT_M) void k_msfinalize(const double *__restrict__ partials, int nb, MultiState *st,
+                                                         int mode)
+{
+    if (st->flags.done && mode != FS_BB) return;
+    __shared__ double lds[FIN_NT_M / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += FIN_NT_M) acc += partials[i];
+    const double v = block_sum<FIN_NT_M>(acc, lds);
+    if (threadIdx.x) return;
+    const int n = st->n;
+    switch (mode) {
+    case FS_BB:
+        st->bb0 = v;
+        st->rr0 = v;
+        st->stop0 = st->tol2 * v;
+        break;
+    case FS_PAP: {
+        if (!(v > 0.0) || !isfinite(v)) {
+            st->ms_status = HISQ_EBREAKDOWN;
+            st->flags.done = 1;
+            break;
+        }
+        const double al = st->rr0 / v;
+        st->alpha0 = al;
+        for (int i = 0; i < n; ++i) {
+            if (!(st->active & (1u << i))) continue;
+            const double z = st->zeta[i], zp = st->zeta_prev[i];
+            const double den = zp * st->a_prev * (1.0 + al * st->dsig[i]) + al * st->b_prev * (zp - z);
+            const double zn = z * zp * st->a_prev / den;
+            st->zeta_next[i] = zn;
+            st->alpha_s[i] = al * zn / z;
+        }
+        break;
+    }
+    case FS_UPD: {
+        st->iter += 1;
+        if (!isfinite(v)) {
+            st->ms_status = HISQ_EBREAKDOWN;
+            st->flags.done = 1;
+            break;
+        }
+        const double be = v / st->rr0;
+        st->beta0 = be;
+        for (int i = 0; i < n; ++i) {
+            if (!(st->active & (1u << i))) continue;
+            st->iters[i] += 1;
+            const double q = st->zeta_next[i] / st->zeta[i];
+            st->beta_s[i] = be * q * q;
+            st->zeta_prev[i] = st->zeta[i];
+            st->zeta[i] = st->zeta_next[i];
+            if (st->zeta[i] * st->zeta[i] * v <= st->stop0) st->active &= ~(1u << i);
+        }
+        st->a_prev = st->alpha0;
+        st->b_prev = be;
+        st->rr0 = v;
+        if (!st->active) st->flags.done = 1;
+        break;
+    }
+    }
+}
+
+__global__ void k_ms_init(MultiState *st, int n, double tol2, double sigma0, const double *dsig)
+{
+    if (threadIdx.x || blockIdx.x) return;
+    st->flags.done = 0;
+    st->flags.reliable = 0;
+    st->n = n;
+    st->active = (1u << n) - 1u;
+    st->relmask = 0;
+    st->iter = 0;
+    st->tol2 = tol2;
+    st->sigma0 = sigma0;
+    st->a_prev = 1.0;
+    st->b_prev = 0.0;
+    st->ms_status = HISQ_OK;
+    for (int i = 0; i < MAXR; ++i) {
+        st->dsig[i] = i < n ? dsig[i] : 0.0;
+        st->zeta[i] = st->zeta_prev[i] = st->zeta_next[i] = 1.0;
+        st->alpha_s[i] = st->beta_s[i] = 0.0;
+        st->iters[i] = 0;
+    }
+}
+
+// r = p = float(b), p_i = float(b) for all shifts, x_i = 0
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_ms_start(const double2 *__restrict__ b, float2 *__restrict__ r,
+                                                    float2 *__restrict__ p, float2 *__restrict__ ps,
+                                                    float2 *__restrict__ xs, long long npairs)
+{
+    for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT) {
+        const long long site = j / N;
+        const int rr = (int)(j % N);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double2 bv = b[site * 3 + c];
+            const float2 f = make_float2((float)bv.x, (float)bv.y);
+            ps[j * 3 + c] = f;
+            xs[j * 3 + c] = make_float2(0.f, 0.f);
+            if (rr == 0) {
+                r[site * 3 + c] = f;
+                p[site * 3 + c] = f;
+            }
+        }
+    }
+}
+
+// boundary [n][Vh][3] complex128 <-> internal [Vh][N][3]; slots r >= n are zero
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_to_batched(const double2 *__restrict__ in, double2 *__restrict__ out,
+                                                      long long vh, int n, int same_source)
+{
+    const long long tot = vh * N * 3;
+    for (long long i = (long long)blockIdx.x * MB_NT + threadIdx.x; i < tot; i += (long long)gridDim.x * MB_NT) {
+        const int c = (int)(i % 3);
+        const int r = (int)((i / 3) % N);
+        const long long h = i / (3 * N);
+        out[i] = r < n ? in[(same_source ? 0 : (long long)r * vh * 3) + h * 3 + c] : make_double2(0.0, 0.0);
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_from_batched(const double2 *__restrict__ in, double2 *__restrict__ out,
+                                                        long long vh, int n)
+{
+    const long long tot = (long long)n * vh * 3;
+    for (long long i = (long long)blockIdx.x * MB_NT + threadIdx.x; i < tot; i += (long long)gridDim.x * MB_NT) {
+        const int c = (int)(i % 3);
+        const long long h = (i / 3) % vh;
+        const int r = (int)(i / (3 * vh));
+        out[i] = in[(h * N + r) * 3 + c];
+    }
+}
+
+// float(x) of a batched FP64 vector
+__global__ __launch_bounds__(MB_NT) void k_to_float(const double2 *__restrict__ in, float2 *__restrict__ out,
+                                                    long long n)
+{
+    for (long long i = (long long)blockIdx.x * MB_NT + threadIdx.x; i < n; i += (long long)gridDim.x * MB_NT)
+        out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+__global__ __launch_bounds__(MB_NT) void k_to_double(const float2 *__restrict__ in, double2 *__restrict__ out,
+                                                     long long n)
+{
+    for (long long i = (long long)blockIdx.x * MB_NT + threadIdx.x; i < n; i += (long long)gridDim.x * MB_NT)
+        out[i] = make_double2((double)in[i].x, (double)in[i].y);
+}
+
+// ------------------------------------------------------------------ finalisers
+enum {
+    FM_BB = 0,        // bb_r, stop2_r
+    FM_INIT = 1,      // rr = rr_true = maxrr ; active = rr > stop2
+    FM_PAP = 2,       // alpha_r or breakdown
+    FM_UPD = 3,       // rr_new: reliable trigger or beta
+    FM_RELIABLE = 4,  // true residual of the updated RHS
+    FM_FINAL = 5,     // rr_true of every RHS (final check)
+};
+
+__device__ void mfinalize(MultiState *st, int mode, const double *v)
+{
+    const int n = st->n;
+    switch (mode) {
+    case FM_BB:
+        for (int r = 0; r < n; ++r) { st->bb[r] = v[r]; st->stop2[r] = st->tol2 * v[r]; }
+        break;
+    case FM_INIT: {
+        unsigned act = 0;
+        for (int r = 0; r < n; ++r) {
+            st->rr[r] = st->rr_true[r] = st->maxrr[r] = v[r];
+            if (st->bb[r] > 0.0 && v[r] > st->stop2[r]) act |= 1u << r;
+        }
+        st->active = act;
+        st->relmask = 0;
+        st->flags.reliable = 0;
+        st->flags.done = act == 0;
+        break;
+    }
+    case FM_PAP:
+        for (int r = 0; r < n; ++r) {
+            if (!(st->active & (1u << r))) continue;
+            if (!(v[r] > 0.0) || !isfinite(v[r])) {
+                st->status[r] = HISQ_EBREAKDOWN;
+                st->active &= ~(1u << r);
+                st->alpha[r] = 0.0;
+            } else {
+                st->alpha[r] = st->rr[r] / v[r];
+            }
+        }
+        if (!st->active) st->flags.done = 1;
+        break;
+    case FM_UPD:
+        st->iter += 1;
+        for (int r = 0; r < n; ++r) {
+            if (!(st->active & (1u << r))) continue;
+            st->iters[r] += 1;
+            const double x = v[r];
+            if (!isfinite(x)) {
+                st->status[r] = HISQ_EBREAKDOWN;
+                st->active &= ~(1u << r);
+            } else if (x <= st->stop2[r] || x < st->delta2 * st->maxrr[r]) {
+                st->relmask |= 1u << r;
+            } else {
+                st->maxrr[r] = fmax(st->maxrr[r], x);
+                st->beta[r] = x / st->rr[r];
+                st->rr[r] = x;
+            }
+        }
+        st->flags.reliable = st->relmask != 0;
+        if (!st->active) st->flags.done = 1;
+        break;
+    case FM_RELIABLE:
+        for (int r = 0; r < n; ++r) {
+            if (!(st->relmask & (1u << r))) continue;
+            const double x = v[r];
+            st->rr_true[r] = x;
+            st->nupd[r] += 1;
+            st->beta[r] = x / st->rr[r];
+            st->rr[r] = x;
+            st->maxrr[r] = x;
+            if (!isfinite(x)) {
+                st->status[r] = HISQ_EBREAKDOWN;
+                st->active &= ~(1u << r);
+            } else if (x <= st->stop2[r]) {
+                st->status[r] = HISQ_OK;
+                st->active &= ~(1u << r);
+            }
+        }
+        st->relmask = 0;
+        st->flags.reliable = 0;
+        if (!st->active) st->flags.done = 1;
+        break;
+    case FM_FINAL:
+        for (int r = 0; r < n; ++r) st->rr_true[r] = v[r];
+        break;
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(FIN_NT_M) void k_mfinalize(const double *__restrict__ partials, int nblocks,
+                                                        MultiState *st, int mode, int gate)
+{
+    if (gate_closed(&st->flags, gate)) return;
+    __shared__ double lds[FIN_NT_M / 64];
+    __shared__ double tot[N];
+    for (int r = 0; r < N; ++r) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < nblocks; i += FIN_NT_M) acc += partials[(size_t)i * N + r];
+        double s = block_sum<FIN_NT_M>(acc, lds);
+        if (threadIdx.x == 0) tot[r] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) mfinalize(st, mode, tot);
+}
+
+__global__ void k_mstate_init(MultiState *st, int n, double tol2, double delta2, const double *m4)
+{
+    if (threadIdx.x || blockIdx.x) return;
+    st->flags.done = 0;
+    st->flags.reliable = 0;
+    st->n = n;
+    st->active = 0;
+    st->relmask = 0;
+    st->iter = 0;
+    st->tol2 = tol2;
+    st->delta2 = delta2;
+    for (int r = 0; r < MAXR; ++r) {
+        st->iters[r] = st->nupd[r] = 0;
+        st->status[r] = HISQ_ENOCONV;
+        st->m4[r] = r < n ? m4[r] : 0.0;
+        st->alpha[r] = st->beta[r] = 0.0;
+    }
+}
+
+// every still-active RHS gets a reliable update (used when max_iter is hit)
+__global__ void k_mforce_reliable(MultiState *st)
+{
+    if (threadIdx.x || blockIdx.x) return;
+    st->relmask = st->active;
+    st->flags.reliable = st->relmask != 0;
+    st->flags.done = 0;
+}
+
+// ------------------------------------------------------------------ host side
+static int device_cus()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr size_t MSKEW = 4352;
+
+// Launch shapes of the multi-RHS Dslash: RHS per thread G (as a divisor of N)
+// and threads per block.  Chosen per (lattice, N) by hisq_tune_multi.
+struct MShape {
+    int gdiv;  // G = N / gdiv
+    int nt;
+};
+constexpr int N_MSHAPES = 4;
+static const MShape MSHAPES[N_MSHAPES] = { { 1, 256 }, { 2, 256 }, { 4, 256 }, { 1, 128 } };
+
+static int mshape_for(const Geom &g, int N) { return tuned_choice("mdslash", g, HISQ_F32, N, 0); }
+
+template <class P, int N, int G, int NT, int EPI>
+static hipError_t launch_md(const Geom &g, const void *fat, const void *lng, const void *src, void *dst,
+                            const void *x, const void *b, float2 *rs, int parity, double *part, const MultiState *st,
+                            int which, int gate, hipStream_t s, int *nblk_out)
+{
+    constexpr int SPB = NT / (N / G);
+    const int nunits = (g.Vh + SPB - 1) / SPB;
+    static int occ = -1;
+    if (occ < 0) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)k_mdslash<P, N, G, NT, EPI>, NT, 0) !=
+                hipSuccess || o <= 0)
+            o = 1;
+        occ = o;
+    }
+    int grid = std::min(nunits, device_cus() * occ);
+    grid = std::min(std::max((grid + NXCD - 1) / NXCD * NXCD, NXCD), MULTI_MAX_BLOCKS);
+    using V = typename P::cvec;
+    hipLaunchKernelGGL((k_mdslash<P, N, G, NT, EPI>), dim3(grid), dim3(NT), 0, s, g, (const char *)fat,
+                       (const char *)lng, (const V *)src, (V *)dst, (const V *)x, (const V *)b, rs, parity, nunits,
+                       part, st, which, gate);
+    if (nblk_out) *nblk_out = grid;
+    return hipGetLastError();
+}
+
+// dispatch over the tuned shape (FP32 inner kernels) or a fixed one (FP64)
+template <class P, int N, int EPI>
+static hipError_t launch_md_shape(int shape, const Geom &g, const void *fat, const void *lng, const void *src,
+                                  void *dst, const void *x, const void *b, float2 *rs, int parity, double *part,
+                                  const MultiState *st, int which, int gate, hipStream_t s, int *nblk)
+{
+    constexpr int G1 = N, G2 = N >= 2 ? N / 2 : 1, G4 = N >= 4 ? N / 4 : 1;
+    switch (shape) {
+    case 1: return launch_md<P, N, G2, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
+    case 2: return launch_md<P, N, G4, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
+    case 3: return launch_md<P, N, G1, 128, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
+    default: return launch_md<P, N, G1, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
+    }
+}
+
+struct MultiBufs {
+    MultiState *st;
+    double *part;
+    double2 *x64, *b64, *r64, *t64;     // [Vh][N][3] FP64
+    float2 *xs, *rs, *ps, *aps, *ts;    // [Vh][N][3] FP32
+    float2 *p1, *r1, *ap1, *t1;         // [Vh][3] FP32 (shifted CG base system)
+    double *dm;                          // small device array: masses or shifts
+};
+
+static size_t multi_partials(int N) { return (size_t)MULTI_MAX_BLOCKS * N + 64; }
+
+size_t cg_multi_ws_for(const Geom &g, int N)
+{
+    const size_t vp = (size_t)g.Vh * N * 3;
+    size_t b = al256(sizeof(MultiState)) + al256(multi_partials(N) * sizeof(double)) + al256(64 * sizeof(double));
+    b += 4 * (al256(vp * 16) + MSKEW) + 5 * (al256(vp * 8) + MSKEW) + 4 * (al256((size_t)g.Vh * 3 * 8) + MSKEW);
+    return b + 4096;
+}
+
+static int pad_n(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : 16; }
+
 size_t cg_multi_workspace_bytes(const Geom &g, int nrhs, int mode)
 {
-    (void)g; (void)nrhs; (void)mode;
-    return 0;
+    if (nrhs < 1 || nrhs > MAXR || (mode != HISQ_MULTI_RHS && mode != HISQ_MULTI_SHIFT)) return 0;
+    return cg_multi_ws_for(g, pad_n(nrhs));
 }
+
+static bool carve(MultiBufs &B, void *ws, size_t bytes, const Geom &g, int N)
+{
+    char *p = (char *)ws;
+    size_t left = bytes;
+    auto take = [&](size_t n) -> void * {
+        n = al256(n) + MSKEW;
+        if (n > left) return nullptr;
+        void *r = p;
+        p += n;
+        left -= n;
+        return r;
+    };
+    const size_t vp = (size_t)g.Vh * N * 3, v1 = (size_t)g.Vh * 3;
+    B.st = (MultiState *)take(sizeof(MultiState));
+    B.part = (double *)take(multi_partials(N) * sizeof(double));
+    B.dm = (double *)take(64 * sizeof(double));
+    B.x64 = (double2 *)take(vp * 16);
+    B.b64 = (double2 *)take(vp * 16);
+    B.r64 = (double2 *)take(vp * 16);
+    B.t64 = (double2 *)take(vp * 16);
+    B.xs = (float2 *)take(vp * 8);
+    B.rs = (float2 *)take(vp * 8);
+    B.ps = (float2 *)take(vp * 8);
+    B.aps = (float2 *)take(vp * 8);
+    B.ts = (float2 *)take(vp * 8);
+    B.p1 = (float2 *)take(v1 * 8);
+    B.r1 = (float2 *)take(v1 * 8);
+    B.ap1 = (float2 *)take(v1 * 8);
+    B.t1 = (float2 *)take(v1 * 8);
+    return B.t1 != nullptr;
+}
+
+struct MultiHost {
+    MultiState *h = nullptr;
+    MultiHost()
+    {
+        if (hipHostMalloc((void **)&h, sizeof(MultiState), hipHostMallocDefault) != hipSuccess) h = nullptr;
+    }
+    ~MultiHost()
+    {
+        if (h) hipHostFree(h);
+    }
+};
+
+template <class F>
+static int run_multi(F iter_fn, hipStream_t s, MultiState *dst, MultiState *hst, int K, int max_iter, bool graph)
+{
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t gr = nullptr;
+    if (graph) {
+        hipStream_t cs = capture_stream();
+        if (!cs) return fail(HISQ_EHIP, "cannot create capture stream");
+        HISQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < K; ++k) {
+            hipError_t e = iter_fn(cs);
+            if (e != hipSuccess) {
+                hipGraph_t junk = nullptr;
+                hipStreamEndCapture(cs, &junk);
+                if (junk) hipGraphDestroy(junk);
+                return hip_fail(e, "batched CG iteration launch (capture)");
+            }
+        }
+        HISQ_HIP(hipStreamEndCapture(cs, &gr));
+        HISQ_HIP(hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0));
+    }
+    int queued = 0, rc = HISQ_OK;
+    while (queued < max_iter) {
+        const int k = std::min(K, max_iter - queued);
+        if (graph && k == K) {
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) { rc = hip_fail(e, "hipGraphLaunch"); break; }
+        } else {
+            for (int i = 0; i < k && !rc; ++i) {
+                hipError_t e = iter_fn(s);
+                if (e != hipSuccess) rc = hip_fail(e, "batched CG iteration launch");
+            }
+            if (rc) break;
+        }
+        queued += k;
+        hipError_t e = hipMemcpyAsync(hst, dst, sizeof(MultiState), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { rc = hip_fail(e, "batched CG state read-back"); break; }
+        if (hst->flags.done) break;
+    }
+    if (exec) hipGraphExecDestroy(exec);
+    if (gr) hipGraphDestroy(gr);
+    return rc;
+}
+
+static int read_mstate(MultiState *h, const MultiState *d, hipStream_t s)
+{
+    HISQ_HIP(hipMemcpyAsync(h, d, sizeof(MultiState), hipMemcpyDeviceToHost, s));
+    HISQ_HIP(hipStreamSynchronize(s));
+    return HISQ_OK;
+}
+
+// Batched reliable-update CG on B.b64 from B.x64 (both [Vh][N][3] FP64).
+template <int N>
+static int multi_rhs_core(int n, const double *masses, double tol, const void *fat, const void *lng,
+                          const void *fat_lo, const void *lng_lo, const Geom &g, const hisq_cg_opts &o,
+                          MultiBufs &B, MultiState *hs, hipStream_t s, int iter_offset)
+{
+    const long long np = (long long)g.Vh * N;
+    const int nbm = mblocks(np);
+    const double delta = o.delta > 0 ? o.delta : 0.1;
+    double m4[MAXR];
+    for (int r = 0; r < n; ++r) m4[r] = 4.0 * masses[r] * masses[r];
+    HISQ_HIP(hipMemcpyAsync(B.dm, m4, n * sizeof(double), hipMemcpyHostToDevice, s));
+    HISQ_HIP(hipMemsetAsync(B.xs, 0, (size_t)np * 3 * 8, s));
+    hipLaunchKernelGGL(k_mstate_init, dim3(1), dim3(1), 0, s, B.st, n, tol * tol, delta * delta, (const double *)B.dm);
+    hipLaunchKernelGGL((k_mnorm<N>), dim3(nbm), dim3(MB_NT), 0, s, (const double2 *)B.b64, np, B.part);
+    hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nbm, B.st, (int)FM_BB,
+                       (int)GATE_ALWAYS);
+    // R64 = B - A X64 for every RHS, RS = float(R64), PS = RS
+    const int shape = mshape_for(g, N);
+    int nb = 0;
+    HISQ_HIP((launch_md_shape<PF64, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
+                                                  B.st, MASK_ALL, GATE_ALWAYS, s, &nb)));
+    HISQ_HIP((launch_md_shape<PF64, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
+                                                  MASK_ALL, GATE_ALWAYS, s, &nb)));
+    hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nb, B.st, (int)FM_INIT,
+                       (int)GATE_ALWAYS);
+    HISQ_HIP(hipMemcpyAsync(B.ps, B.rs, (size_t)np * 3 * 8, hipMemcpyDeviceToDevice, s));
+    int rc = read_mstate(hs, B.st, s);
+    if (rc) return rc;
+
+    auto iter = [&](hipStream_t q) -> hipError_t {
+        int nb1 = 0;
+        hipError_t e = launch_md_shape<PF32, N, EPI_STORE>(shape, g, fat_lo, lng_lo, B.ps, B.ts, nullptr, nullptr,
+                                                           nullptr, 1, B.part, B.st, MASK_ACTIVE, GATE_NOT_DONE, q, &nb1);
+        if (e != hipSuccess) return e;
+        e = launch_md_shape<PF32, N, EPI_AP>(shape, g, fat_lo, lng_lo, B.ts, B.aps, B.ps, nullptr, nullptr, 0, B.part,
+                                             B.st, MASK_ACTIVE, GATE_NOT_DONE, q, &nb1);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb1, B.st,
+                           (int)FM_PAP, (int)GATE_NOT_DONE);
+        hipLaunchKernelGGL((k_mupdate<N>), dim3(nbm), dim3(MB_NT), 0, q, B.xs, B.rs, (const float2 *)B.ps,
+                           (const float2 *)B.aps, np, B.part, (const MultiState *)B.st);
+        hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nbm, B.st,
+                           (int)FM_UPD, (int)GATE_NOT_DONE);
+        // reliable updates of the RHS that asked for one
+        hipLaunchKernelGGL((k_maccum<N>), dim3(nbm), dim3(MB_NT), 0, q, B.x64, B.xs, np, (const MultiState *)B.st,
+                           (int)MASK_RELIABLE, (int)GATE_RELIABLE);
+        int nb2 = 0;
+        e = launch_md_shape<PF64, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
+                                                B.st, MASK_RELIABLE, GATE_RELIABLE, q, &nb2);
+        if (e != hipSuccess) return e;
+        e = launch_md_shape<PF64, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
+                                                MASK_RELIABLE, GATE_RELIABLE, q, &nb2);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb2, B.st,
+                           (int)FM_RELIABLE, (int)GATE_RELIABLE);
+        hipLaunchKernelGGL((k_mp<N>), dim3(nbm), dim3(MB_NT), 0, q, B.ps, (const float2 *)B.rs, np,
+                           (const MultiState *)B.st);
+        return hipGetLastError();
+    };
+    if (!hs->flags.done) {
+        rc = run_multi(iter, s, B.st, hs, o.check_every, std::max(1, o.max_iter - iter_offset), o.use_graph != 0);
+        if (rc) return rc;
+    }
+    // fold the inner solutions of RHS still running and measure every true residual
+    hipLaunchKernelGGL(k_mforce_reliable, dim3(1), dim3(1), 0, s, B.st);
+    hipLaunchKernelGGL((k_maccum<N>), dim3(nbm), dim3(MB_NT), 0, s, B.x64, B.xs, np, (const MultiState *)B.st,
+                       (int)MASK_ALL, (int)GATE_ALWAYS);
+    HISQ_HIP((launch_md_shape<PF64, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
+                                                  B.st, MASK_ALL, GATE_ALWAYS, s, &nb)));
+    HISQ_HIP((launch_md_shape<PF64, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
+                                                  MASK_ALL, GATE_ALWAYS, s, &nb)));
+    hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nb, B.st, (int)FM_FINAL,
+                       (int)GATE_ALWAYS);
+    HISQ_HIP(hipGetLastError());
+    return read_mstate(hs, B.st, s);
+}
+
+// Shifted CG for one source and n shifts in FP32 (stage 1 of MULTI_SHIFT);
+// leaves the shifted solutions in B.xs.
+template <int N>
+static int multi_shift_core(int n, const double *masses, double tol_ms, const void *fat_lo, const void *lng_lo,
+                            const void *b, const Geom &g, const hisq_cg_opts &o, MultiBufs &B, MultiState *hs,
+                            hipStream_t s)
+{
+    const long long np = (long long)g.Vh * N, n1 = (long long)g.Vh * 3;
+    const int nbm = mblocks(np), nb1 = mblocks(n1);
+    const int nbd = (g.ntiles + 3) / 4;
+    double sig0 = 1e300;
+    for (int i = 0; i < n; ++i) sig0 = std::min(sig0, 4.0 * masses[i] * masses[i]);
+    double ds[MAXR];
+    for (int i = 0; i < n; ++i) ds[i] = 4.0 * masses[i] * masses[i] - sig0;
+    HISQ_HIP(hipMemcpyAsync(B.dm, ds, n * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(1), 0, s, B.st, n, tol_ms * tol_ms, sig0, (const double *)B.dm);
+    hipLaunchKernelGGL((k_ms_start<N>), dim3(nbm), dim3(MB_NT), 0, s, (const double2 *)b, B.r1, B.p1, B.ps, B.xs, np);
+    // |b|^2 from the FP64 source
+    hipLaunchKernelGGL((k_mnorm<1>), dim3(nb1), dim3(MB_NT), 0, s, (const double2 *)b, (long long)g.Vh, B.part);
+    hipLaunchKernelGGL(k_msfinalize, dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nb1, B.st, (int)FS_BB);
+    HISQ_HIP(hipGetLastError());
+    auto iter = [&](hipStream_t q) -> hipError_t {
+        hipError_t e = launch_dslash<PF32>(g, fat_lo, lng_lo, B.p1, B.t1, 1, q, &B.st->flags, GATE_NOT_DONE);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_ms_ap, dim3(xcd_grid(nbd)), dim3(256), 0, q, g, (const char *)fat_lo,
+                           (const char *)lng_lo, (const float2 *)B.t1, (const float2 *)B.p1, B.ap1, nbd, B.part,
+                           (const MultiState *)B.st);
+        hipLaunchKernelGGL(k_msfinalize, dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nbd, B.st,
+                           (int)FS_PAP);
+        hipLaunchKernelGGL((k_ms_x<N>), dim3(nbm), dim3(MB_NT), 0, q, B.xs, (const float2 *)B.ps, np,
+                           (const MultiState *)B.st);
+        hipLaunchKernelGGL(k_ms_r, dim3(nb1), dim3(MB_NT), 0, q, B.r1, (const float2 *)B.ap1, n1, B.part,
+                           (const MultiState *)B.st);
+        hipLaunchKernelGGL(k_msfinalize, dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb1, B.st,
+                           (int)FS_UPD);
+        hipLaunchKernelGGL((k_ms_p<N>), dim3(nbm), dim3(MB_NT), 0, q, B.ps, B.p1, (const float2 *)B.r1, np,
+                           (const MultiState *)B.st);
+        return hipGetLastError();
+    };
+    int rc = run_multi(iter, s, B.st, hs, o.check_every, o.max_iter, o.use_graph != 0);
+    if (rc) return rc;
+    return hs->ms_status;
+}
+
+template <int N>
+static int cg_multi_impl(int n, const double *masses, double tol, int mode, const void *fat, const void *lng,
+                         const void *fat_lo, const void *lng_lo, const void *b, void *x, const Geom &g,
+                         const hisq_cg_opts &o, void *ws, size_t ws_bytes, hisq_cg_stats *stats, hipStream_t s)
+{
+    MultiBufs B;
+    if (!carve(B, ws, ws_bytes, g, N)) return fail(HISQ_EWORKSPACE, "cg_solve_multi: workspace too small");
+    MultiHost H;
+    if (!H.h) return fail(HISQ_EHIP, "cg_solve_multi: pinned state allocation failed");
+    const long long np = (long long)g.Vh * N;
+    const int nbm = mblocks(np);
+    auto t0 = std::chrono::steady_clock::now();
+    HISQ_HIP(hipMemsetAsync(B.st, 0, sizeof(MultiState), s));
+    int ms_iters[MAXR] = { 0 };
+    int offset = 0;
+    if (mode == HISQ_MULTI_SHIFT) {
+        const double tol_ms = std::max(tol, 1e-5);
+        int rc = multi_shift_core<N>(n, masses, tol_ms, fat_lo, lng_lo, b, g, o, B, H.h, s);
+        if (rc) return fail(rc, "cg_solve_multi: shifted CG broke down");
+        for (int i = 0; i < n; ++i) ms_iters[i] = H.h->iters[i];
+        offset = H.h->iter;
+        const long long nv = np * 3;
+        hipLaunchKernelGGL(k_to_double, dim3(nbm), dim3(MB_NT), 0, s, (const float2 *)B.xs, B.x64, nv);
+        hipLaunchKernelGGL((k_to_batched<N>), dim3(nbm), dim3(MB_NT), 0, s, (const double2 *)b, B.b64, (long long)g.Vh,
+                           n, 1);
+    } else {
+        HISQ_HIP(hipMemsetAsync(B.x64, 0, (size_t)np * 3 * 16, s));
+        hipLaunchKernelGGL((k_to_batched<N>), dim3(nbm), dim3(MB_NT), 0, s, (const double2 *)b, B.b64, (long long)g.Vh,
+                           n, 0);
+    }
+    HISQ_HIP(hipGetLastError());
+    int rc = multi_rhs_core<N>(n, masses, tol, fat, lng, fat_lo, lng_lo, g, o, B, H.h, s, offset);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_from_batched<N>), dim3(nbm), dim3(MB_NT), 0, s, (const double2 *)B.x64, (double2 *)x,
+                       (long long)g.Vh, n);
+    HISQ_HIP(hipGetLastError());
+    HISQ_HIP(hipStreamSynchronize(s));
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = HISQ_OK;
+    for (int r = 0; r < n; ++r) {
+        const MultiState *h = H.h;
+        const double tr = h->bb[r] > 0 ? std::sqrt(h->rr_true[r] / h->bb[r]) : 0.0;
+        int st = h->bb[r] == 0.0 ? HISQ_OK : (tr <= tol ? HISQ_OK : (h->status[r] == HISQ_EBREAKDOWN ? HISQ_EBREAKDOWN : HISQ_ENOCONV));
+        if (st != HISQ_OK && worst == HISQ_OK) worst = st;
+        if (stats) {
+            stats[r].iters = h->iters[r] + ms_iters[r];
+            stats[r].reliable_updates = h->nupd[r];
+            stats[r].restarts = 0;
+            stats[r].status = st;
+            stats[r].true_resid = tr;
+            stats[r].time_s = dt;
+        }
+    }
+    if (worst == HISQ_EBREAKDOWN) return fail(worst, "cg_solve_multi: breakdown in some right-hand side");
+    if (worst == HISQ_ENOCONV) return fail(worst, "cg_solve_multi: some right-hand side not converged");
+    return HISQ_OK;
+}
+
+// ------------------------------------------------------------------ autotuner of the multi-RHS Dslash
+template <int N>
+static int tune_multi_impl(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, void *ws,
+                           size_t ws_bytes, int reps, int *best, double *us, hipStream_t s)
+{
+    if (ws_bytes < al256(sizeof(MultiState)) + 256) return fail(HISQ_EWORKSPACE, "hisq_tune_multi: workspace too small");
+    MultiState *st = (MultiState *)ws;
+    HISQ_HIP(hipMemsetAsync(st, 0, sizeof(MultiState), s));
+    // every RHS active for the timing
+    MultiState init;
+    std::memset(&init, 0, sizeof init);
+    init.n = N;
+    init.active = (N >= 32) ? ~0u : ((1u << N) - 1u);
+    HISQ_HIP(hipMemcpyAsync(st, &init, sizeof init, hipMemcpyHostToDevice, s));
+    hipEvent_t e0, e1;
+    HISQ_HIP(hipEventCreate(&e0));
+    HISQ_HIP(hipEventCreate(&e1));
+    double best_us = 1e300;
+    int best_i = 0, rc = HISQ_OK;
+    for (int i = 0; i < N_MSHAPES && !rc; ++i) {
+        if (N / MSHAPES[i].gdiv < 1 || (N % MSHAPES[i].gdiv)) { if (us) us[i] = -1; continue; }
+        auto go = [&]() {
+            return launch_md_shape<PF32, N, EPI_STORE>(i, g, fat, lng, src, dst, nullptr, nullptr, nullptr, 1, nullptr,
+                                                      st, MASK_ACTIVE, GATE_ALWAYS, s, nullptr);
+        };
+        for (int w = 0; w < 2; ++w) if (go() != hipSuccess) rc = HISQ_EHIP;
+        hipEventRecord(e0, s);
+        for (int k = 0; k < reps; ++k) if (go() != hipSuccess) rc = HISQ_EHIP;
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = HISQ_EHIP;
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        const double t = 1e3 * ms / reps;
+        if (us) us[i] = t;
+        if (t < best_us) { best_us = t; best_i = i; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return fail(rc, "hisq_tune_multi: launch failed");
+    set_tuned_choice("mdslash", g, HISQ_F32, N, best_i);
+    if (best) *best = best_i;
+    return HISQ_OK;
+}
+
+// one timed-or-plain launch of the multi-RHS FP32 Dslash (for benchmarks and tests)
+template <int N>
+static int mdslash_apply_impl(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, int parity,
+                              void *ws, hipStream_t s)
+{
+    MultiState *st = (MultiState *)ws;
+    MultiState init;
+    std::memset(&init, 0, sizeof init);
+    init.n = N;
+    init.active = (1u << N) - 1u;
+    HISQ_HIP(hipMemcpyAsync(st, &init, sizeof init, hipMemcpyHostToDevice, s));
+    HISQ_HIP((launch_md_shape<PF32, N, EPI_STORE>(mshape_for(g, N), g, fat, lng, src, dst, nullptr, nullptr, nullptr,
+                                                  parity, nullptr, st, MASK_ACTIVE, GATE_ALWAYS, s, nullptr)));
+    return HISQ_OK;
+}
+
 }  // namespace hisq
 
 using namespace hisq;
@@ -17,7 +1113,69 @@ extern "C" int cg_solve_multi(int nrhs, const double *masses, double tol, int mo
                               const hisq_cg_opts *opts, void *workspace, size_t ws_bytes, hisq_cg_stats *stats,
                               void *stream)
 {
-    (void)nrhs; (void)masses; (void)tol; (void)mode; (void)fat; (void)lng; (void)fat_lo; (void)lng_lo; (void)b;
-    (void)x; (void)dims; (void)opts; (void)workspace; (void)ws_bytes; (void)stats; (void)stream;
-    return fail(HISQ_EINVAL, "cg_solve_multi: not built yet");
+    if (stats && nrhs > 0) std::memset(stats, 0, sizeof(hisq_cg_stats) * std::min(nrhs, MAXR));
+    Geom g;
+    int rc = make_geom(dims, g);
+    if (rc) return rc;
+    if (nrhs < 1 || nrhs > MAXR) return fail(HISQ_EINVAL, "cg_solve_multi: nrhs must be 1..16");
+    if (mode != HISQ_MULTI_RHS && mode != HISQ_MULTI_SHIFT) return fail(HISQ_EINVAL, "cg_solve_multi: unknown mode");
+    if (!masses || !fat || !lng || !fat_lo || !lng_lo || !b || !x) return fail(HISQ_EINVAL, "cg_solve_multi: NULL pointer");
+    if (b == x) return fail(HISQ_EALIAS, "cg_solve_multi: b and x alias");
+    if (!(tol > 0)) return fail(HISQ_EINVAL, "cg_solve_multi: need tol > 0");
+    for (int r = 0; r < nrhs; ++r)
+        if (!(masses[r] > 0)) return fail(HISQ_EINVAL, "cg_solve_multi: masses must be > 0");
+    if (!workspace || ws_bytes < cg_multi_workspace_bytes(g, nrhs, mode))
+        return fail(HISQ_EWORKSPACE, "cg_solve_multi: workspace NULL or smaller than hisq_workspace_bytes()");
+    hisq_cg_opts o = resolve_opts(opts, g);
+    hipStream_t s = (hipStream_t)stream;
+    HISQ_HIP(hipStreamSynchronize(s));
+    switch (pad_n(nrhs)) {
+    case 1: return cg_multi_impl<1>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
+    case 2: return cg_multi_impl<2>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
+    case 4: return cg_multi_impl<4>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
+    case 8: return cg_multi_impl<8>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
+    default: return cg_multi_impl<16>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
+    }
+}
+
+extern "C" int hisq_tune_multi(const void *fat, const void *lng, const void *src, void *dst, const int dims[4], int nrhs,
+                               void *workspace, size_t ws_bytes, int reps, int *best_shape, double *us_per_shape,
+                               void *stream)
+{
+    Geom g;
+    int rc = make_geom(dims, g);
+    if (rc) return rc;
+    if (!fat || !lng || !src || !dst || !workspace) return fail(HISQ_EINVAL, "hisq_tune_multi: NULL pointer");
+    if (src == dst) return fail(HISQ_EALIAS, "hisq_tune_multi: src and dst alias");
+    if (nrhs != pad_n(nrhs) || nrhs > MAXR) return fail(HISQ_EINVAL, "hisq_tune_multi: nrhs must be 1, 2, 4, 8 or 16");
+    if (reps <= 0) reps = 10;
+    hipStream_t s = (hipStream_t)stream;
+    switch (nrhs) {
+    case 1: return tune_multi_impl<1>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
+    case 2: return tune_multi_impl<2>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
+    case 4: return tune_multi_impl<4>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
+    case 8: return tune_multi_impl<8>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
+    default: return tune_multi_impl<16>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
+    }
+}
+
+extern "C" int hisq_dslash_multi(const void *fat, const void *lng, const void *src, void *dst, int parity, int nrhs,
+                                 const int dims[4], void *workspace, size_t ws_bytes, void *stream)
+{
+    Geom g;
+    int rc = make_geom(dims, g);
+    if (rc) return rc;
+    if (!fat || !lng || !src || !dst || !workspace) return fail(HISQ_EINVAL, "hisq_dslash_multi: NULL pointer");
+    if (src == dst) return fail(HISQ_EALIAS, "hisq_dslash_multi: src and dst alias");
+    if (parity != 0 && parity != 1) return fail(HISQ_EINVAL, "hisq_dslash_multi: parity must be 0 or 1");
+    if (nrhs != pad_n(nrhs) || nrhs > MAXR) return fail(HISQ_EINVAL, "hisq_dslash_multi: nrhs must be 1, 2, 4, 8 or 16");
+    if (ws_bytes < al256(sizeof(MultiState))) return fail(HISQ_EWORKSPACE, "hisq_dslash_multi: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    switch (nrhs) {
+    case 1: return mdslash_apply_impl<1>(g, fat, lng, src, dst, parity, workspace, s);
+    case 2: return mdslash_apply_impl<2>(g, fat, lng, src, dst, parity, workspace, s);
+    case 4: return mdslash_apply_impl<4>(g, fat, lng, src, dst, parity, workspace, s);
+    case 8: return mdslash_apply_impl<8>(g, fat, lng, src, dst, parity, workspace, s);
+    default: return mdslash_apply_impl<16>(g, fat, lng, src, dst, parity, workspace, s);
+    }
 }

@@ -11,10 +11,8 @@
 
 namespace hisq {
 
-constexpr int DSLASH_NT = 256;
-
-template <class P, int NT>
-__global__ __launch_bounds__(NT) void k_dslash(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
+template <class P, int NT, int W, int UNR>
+__global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_dslash(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
                                                const typename P::cvec *__restrict__ src,
                                                typename P::cvec *__restrict__ dst, int parity, int nblocks,
                                                const SolverFlags *flags, int gate)
@@ -28,7 +26,7 @@ __global__ __launch_bounds__(NT) void k_dslash(Geom g, const char *__restrict__ 
     const int h = tile * TILE + lane;
     const int hc = h < g.Vh ? h : g.Vh - 1;
     typename P::real acc[6];
-    dslash_site<P>(g, fat, lng, src, parity, tile, lane, hc, acc);
+    dslash_site<P, UNR>(g, fat, lng, src, parity, tile, lane, hc, acc);
     if (h < g.Vh) {
         typename P::cvec *o = dst + (size_t)h * 3;
 #pragma unroll
@@ -43,7 +41,7 @@ __global__ __launch_bounds__(NT) void k_dslash(Geom g, const char *__restrict__ 
 
 // y = m4 * x - D src on parity 0 (second half of A = 4m^2 - D_eo D_oe)
 template <class P, int NT>
-__global__ __launch_bounds__(NT) void k_dslash_axmy(Geom g, const char *__restrict__ fat,
+__global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_dslash_axmy(Geom g, const char *__restrict__ fat,
                                                     const char *__restrict__ lng,
                                                     const typename P::cvec *__restrict__ src,
                                                     const typename P::cvec *__restrict__ x,
@@ -70,25 +68,61 @@ __global__ __launch_bounds__(NT) void k_dslash_axmy(Geom g, const char *__restri
     }
 }
 
-static inline int dslash_blocks(const Geom &g) { return (g.ntiles + DSLASH_NT / TILE - 1) / (DSLASH_NT / TILE); }
+// Launch shapes of the single-RHS Dslash: threads per block, minimum
+// wavefronts per SIMD (1 = no constraint) and how many of the 16 terms are
+// unrolled together.  All shapes compute every site with the same arithmetic
+// in the same order, so their outputs are bitwise identical; the autotuner
+// picks one per (lattice, precision).
+const DslashShape DSLASH_SHAPES[N_DSLASH_SHAPES] = {
+    { 256, 8, 1 }, { 128, 8, 1 }, { 64, 8, 1 }, { 256, 1, 16 }, { 256, 4, 4 }, { 512, 8, 1 },
+};
+
+static inline int blocks_for(const Geom &g, int nt) { return (g.ntiles + nt / TILE - 1) / (nt / TILE); }
+
+template <class P, int NT, int W, int UNR>
+static void launch_shape(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, int parity,
+                         hipStream_t s, const SolverFlags *flags, int gate)
+{
+    const int nb = blocks_for(g, NT);
+    hipLaunchKernelGGL((k_dslash<P, NT, W, UNR>), dim3(xcd_grid(nb)), dim3(NT), 0, s, g, (const char *)fat,
+                       (const char *)lng, (const typename P::cvec *)src, (typename P::cvec *)dst, parity, nb, flags,
+                       gate);
+}
+
+template <class P>
+hipError_t launch_dslash_shape(int shape, const Geom &g, const void *fat, const void *lng, const void *src, void *dst,
+                               int parity, hipStream_t s, const SolverFlags *flags, int gate)
+{
+    switch (shape) {
+    case 1: launch_shape<P, 128, 8, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 2: launch_shape<P, 64, 8, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 3: launch_shape<P, 256, 1, 16>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 4: launch_shape<P, 256, 4, 4>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 5: launch_shape<P, 512, 8, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    default: launch_shape<P, 256, 8, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    }
+    return hipGetLastError();
+}
 
 template <class P>
 hipError_t launch_dslash(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, int parity,
                          hipStream_t s, const SolverFlags *flags, int gate)
 {
-    const int nb = dslash_blocks(g);
-    hipLaunchKernelGGL((k_dslash<P, DSLASH_NT>), dim3(xcd_grid(nb)), dim3(DSLASH_NT), 0, s, g,
-                       (const char *)fat, (const char *)lng, (const typename P::cvec *)src,
-                       (typename P::cvec *)dst, parity, nb, flags, gate);
-    return hipGetLastError();
+    return launch_dslash_shape<P>(tuned_dslash_shape(g, P::prec), g, fat, lng, src, dst, parity, s, flags, gate);
 }
 
-template hipError_t launch_dslash<PF64>(const Geom &, const void *, const void *, const void *, void *, int,
-                                        hipStream_t, const SolverFlags *, int);
-template hipError_t launch_dslash<PF32>(const Geom &, const void *, const void *, const void *, void *, int,
-                                        hipStream_t, const SolverFlags *, int);
-template hipError_t launch_dslash<PF16S>(const Geom &, const void *, const void *, const void *, void *, int,
-                                         hipStream_t, const SolverFlags *, int);
+#define HISQ_INST(P)                                                                                             \
+    template hipError_t launch_dslash<P>(const Geom &, const void *, const void *, const void *, void *, int,    \
+                                         hipStream_t, const SolverFlags *, int);                                 \
+    template hipError_t launch_dslash_shape<P>(int, const Geom &, const void *, const void *, const void *,      \
+                                               void *, int, hipStream_t, const SolverFlags *, int);
+HISQ_INST(PF64)
+HISQ_INST(PF32)
+HISQ_INST(PF16S)
+HISQ_INST(PI16S)
+#undef HISQ_INST
+
+constexpr int AXMY_NT = 256;
 
 template <class P>
 static hipError_t launch_apply_A(const Geom &g, double mass, const void *fat, const void *lng, const void *x, void *y,
@@ -96,8 +130,8 @@ static hipError_t launch_apply_A(const Geom &g, double mass, const void *fat, co
 {
     hipError_t e = launch_dslash<P>(g, fat, lng, x, tmp, 1, s);
     if (e != hipSuccess) return e;
-    const int nb = dslash_blocks(g);
-    hipLaunchKernelGGL((k_dslash_axmy<P, DSLASH_NT>), dim3(xcd_grid(nb)), dim3(DSLASH_NT), 0, s, g,
+    const int nb = blocks_for(g, AXMY_NT);
+    hipLaunchKernelGGL((k_dslash_axmy<P, AXMY_NT>), dim3(xcd_grid(nb)), dim3(AXMY_NT), 0, s, g,
                        (const char *)fat, (const char *)lng, (const typename P::cvec *)tmp,
                        (const typename P::cvec *)x, (typename P::cvec *)y, 4.0 * mass * mass, nb);
     return hipGetLastError();
@@ -122,6 +156,7 @@ extern "C" int dslash_apply(const void *fat, const void *lng, const void *src, v
     case HISQ_F64: e = launch_dslash<PF64>(g, fat, lng, src, dst, parity, s); break;
     case HISQ_F32: e = launch_dslash<PF32>(g, fat, lng, src, dst, parity, s); break;
     case HISQ_F16S: e = launch_dslash<PF16S>(g, fat, lng, src, dst, parity, s); break;
+    case HISQ_I16S: e = launch_dslash<PI16S>(g, fat, lng, src, dst, parity, s); break;
     default: return fail(HISQ_EINVAL, "dslash_apply: unknown precision");
     }
     if (e != hipSuccess) return hip_fail(e, "dslash_apply launch");
@@ -142,6 +177,7 @@ extern "C" int hisq_apply_A(double mass, const void *fat, const void *lng, const
     case HISQ_F64: e = launch_apply_A<PF64>(g, mass, fat, lng, x, y, tmp, s); break;
     case HISQ_F32: e = launch_apply_A<PF32>(g, mass, fat, lng, x, y, tmp, s); break;
     case HISQ_F16S: e = launch_apply_A<PF16S>(g, mass, fat, lng, x, y, tmp, s); break;
+    case HISQ_I16S: e = launch_apply_A<PI16S>(g, mass, fat, lng, x, y, tmp, s); break;
     default: return fail(HISQ_EINVAL, "hisq_apply_A: unknown precision");
     }
     if (e != hipSuccess) return hip_fail(e, "hisq_apply_A launch");

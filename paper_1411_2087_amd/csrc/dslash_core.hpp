@@ -34,8 +34,11 @@ __device__ __forceinline__ void cmac(typename P::real acc[6], const typename P::
 }
 
 // acc = (D src)(h) for the site h of parity `parity` (h < Vh), whose links
-// sit at lane `lane` of tile `tile`.
-template <class P>
+// sit at lane `lane` of tile `tile`.  The 16 terms are taken UNR at a time:
+// a fully unrolled body lets the compiler hoist every load and run out of
+// registers, a partly unrolled one keeps UNR matrices in flight per thread
+// and leaves the latency hiding to the other resident wavefronts.
+template <class P, int UNR = 1>
 __device__ __forceinline__ void dslash_site(const Geom &g, const char *__restrict__ fat,
                                             const char *__restrict__ lng,
                                             const typename P::cvec *__restrict__ src, int parity, int tile,
@@ -48,7 +51,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, const char *__restric
     const char *lb = lng + tile_off;
 #pragma unroll
     for (int i = 0; i < 6; ++i) acc[i] = 0;
-#pragma unroll
+#pragma unroll UNR
     for (int d = 0; d < 16; ++d) {
         const int mu = d & 3;
         const bool is_long = d >= 8;
@@ -75,9 +78,25 @@ __device__ __forceinline__ bool gate_closed(const SolverFlags *f, int gate)
     return gate == GATE_RELIABLE && !f->reliable;
 }
 
-// Launch helpers (defined in dslash.hip).
+// Launch helpers (defined in dslash.hip).  launch_dslash uses the shape the
+// autotuner chose for (dims, precision), launch_dslash_shape a given one.
+struct DslashShape {
+    int nt;      // threads per block
+    int waves;   // minimum wavefronts per SIMD the compiler must allow
+    int unroll;  // terms of the 16 unrolled together
+};
+constexpr int N_DSLASH_SHAPES = 6;
+extern const DslashShape DSLASH_SHAPES[N_DSLASH_SHAPES];
+int tuned_dslash_shape(const Geom &g, int prec);            // tune.cpp
+int tuned_choice(const char *kind, const Geom &g, int prec, int n, int fallback);
+void set_tuned_choice(const char *kind, const Geom &g, int prec, int n, int v);
+void set_tuned_dslash_shape(const Geom &g, int prec, int shape);
+
 template <class P>
 hipError_t launch_dslash(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, int parity,
                          hipStream_t s, const SolverFlags *flags = nullptr, int gate = GATE_ALWAYS);
+template <class P>
+hipError_t launch_dslash_shape(int shape, const Geom &g, const void *fat, const void *lng, const void *src, void *dst,
+                               int parity, hipStream_t s, const SolverFlags *flags = nullptr, int gate = GATE_ALWAYS);
 
 }  // namespace hisq

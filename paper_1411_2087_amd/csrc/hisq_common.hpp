@@ -78,6 +78,11 @@ constexpr int NXCD = 8;
 __device__ __forceinline__ int xcd_block(int b, int G) { return (b % NXCD) * (G / NXCD) + b / NXCD; }
 inline int xcd_grid(int nblocks) { return (nblocks + NXCD - 1) / NXCD * NXCD; }
 
+// Occupancy target: at least W wavefronts per SIMD, i.e. at most 512/W VGPRs.
+// The Dslash kernels are latency-bound streams; 8 waves/SIMD keeps a whole
+// 32^4 half-lattice (8192 waves) resident in one round.
+#define HISQ_WAVES(W) __attribute__((amdgpu_waves_per_eu(W)))
+
 // ------------------------------------------------------------------ reductions
 // Wave64 sum by butterfly (xor) shuffles: every lane gets the total.  The
 // order is fixed, so results are reproducible.
@@ -124,34 +129,28 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *lds)
     __syncthreads();
 }
 
-// Two-stage deterministic grid reduction.  Every block writes its partial;
-// the block that arrives last (device-scope counter) sums all partials in a
-// fixed order and calls fin(total) in thread 0, then re-arms the counter.
-// Returns true in the block that finalised.
-template <int NT, class Fin>
-__device__ __forceinline__ void grid_reduce(double v, double *partials, unsigned *counter, int nblocks, int blk,
-                                            Fin fin)
+// First stage of a deterministic grid reduction: each block writes its
+// fixed-order partial sum to partials[blk].  A one-block finalize kernel
+// launched after it sums the partials in a fixed order.  (A last-block-done
+// scheme would need a device-scope release fence per block, which on a
+// multi-XCD part writes back the L2 each time; a separate kernel needs one
+// kernel boundary.)
+template <int NT>
+__device__ __forceinline__ void block_partial(double v, double *partials, int blk)
 {
     __shared__ double lds[NT / 64];
-    __shared__ bool last;
     double s = block_sum<NT>(v, lds);
-    if (threadIdx.x == 0) {
-        partials[blk] = s;
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
-        last = (prev == (unsigned)nblocks - 1u);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+    if (threadIdx.x == 0) partials[blk] = s;
+}
+
+// Fixed-order sum of n partials by one block of NT threads; valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double *partials, int n)
+{
+    __shared__ double lds[NT / 64];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < nblocks; i += NT) acc += __builtin_nontemporal_load(&partials[i]);
-    double tot = block_sum<NT>(acc, lds);
-    if (threadIdx.x == 0) {
-        fin(tot);
-        *counter = 0u;
-        __threadfence();
-    }
+    for (int i = threadIdx.x; i < n; i += NT) acc += partials[i];
+    return block_sum<NT>(acc, lds);
 }
 
 // ------------------------------------------------------------------ streaming loads / stores
@@ -263,6 +262,31 @@ struct PF16S {
             float2 f = __half22float2(hv);
             m[2 * e] = f.x * s;
             m[2 * e + 1] = f.y * s;
+        }
+    }
+};
+
+// 16-bit fixed point with the same per-matrix FP32 scale: entry = q * scale / 32767,
+// |q| <= 32767.  Same 40 B per matrix as PF16S, 16x finer steps for entries near
+// the scale (bounded values do not need an exponent).
+struct PI16S {
+    using real = float;
+    using cvec = float2;
+    static constexpr int prec = HISQ_I16S;
+    static constexpr size_t block_bytes = TILE * 40;
+    __device__ __forceinline__ static void load(const char *blk, int lane, float m[18])
+    {
+        const uint4 *p4 = reinterpret_cast<const uint4 *>(blk) + lane;
+        uint4 a = ntload(p4);
+        uint4 b = ntload(p4 + TILE);
+        const uint2 *p2 = reinterpret_cast<const uint2 *>(blk + 2 * TILE * 16) + lane;
+        uint2 c = ntload(p2);
+        const float s = __uint_as_float(c.y) * (1.0f / 32767.0f);
+        const unsigned w[9] = { a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x };
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            m[2 * e] = (float)(short)(w[e] & 0xFFFFu) * s;
+            m[2 * e + 1] = (float)(short)(w[e] >> 16) * s;
         }
     }
 };

@@ -54,6 +54,29 @@ __device__ __forceinline__ void store_block<HISQ_F16S>(char *blk, int lane, cons
     *p2 = make_uint2(w[8], __float_as_uint(scale));
 }
 
+template <>
+__device__ __forceinline__ void store_block<HISQ_I16S>(char *blk, int lane, const double m[18])
+{
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < 18; ++i) mx = fmax(mx, fabs(m[i]));
+    const float scale = (float)mx;
+    const double inv = scale > 0.0f ? 32767.0 / (double)scale : 0.0;
+    unsigned w[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        int qr = (int)rint(m[2 * e] * inv), qi = (int)rint(m[2 * e + 1] * inv);
+        qr = qr > 32767 ? 32767 : (qr < -32767 ? -32767 : qr);
+        qi = qi > 32767 ? 32767 : (qi < -32767 ? -32767 : qi);
+        w[e] = ((unsigned)qr & 0xFFFFu) | (((unsigned)qi & 0xFFFFu) << 16);
+    }
+    uint4 *p4 = reinterpret_cast<uint4 *>(blk) + lane;
+    p4[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    p4[TILE] = make_uint4(w[4], w[5], w[6], w[7]);
+    uint2 *p2 = reinterpret_cast<uint2 *>(blk + 2 * TILE * 16) + lane;
+    *p2 = make_uint2(w[8], __float_as_uint(scale));
+}
+
 template <int PREC>
 __global__ __launch_bounds__(256) void k_pack(const double2 *__restrict__ canon, char *__restrict__ out, Geom g,
                                               int hop, size_t block_bytes)
@@ -105,6 +128,7 @@ size_t dir_block_bytes(int prec)
     case HISQ_F64: return PF64::block_bytes;
     case HISQ_F32: return PF32::block_bytes;
     case HISQ_F16S: return PF16S::block_bytes;
+    case HISQ_I16S: return PI16S::block_bytes;
     default: return 0;
     }
 }
@@ -142,7 +166,8 @@ extern "C" int hisq_pack_links(const void *fat_canon, const void *long_canon, co
         switch (prec) {
         case HISQ_F64: hipLaunchKernelGGL(k_pack<HISQ_F64>, grid, block, 0, s, in, out, g, hop, bb); break;
         case HISQ_F32: hipLaunchKernelGGL(k_pack<HISQ_F32>, grid, block, 0, s, in, out, g, hop, bb); break;
-        default: hipLaunchKernelGGL(k_pack<HISQ_F16S>, grid, block, 0, s, in, out, g, hop, bb); break;
+        case HISQ_F16S: hipLaunchKernelGGL(k_pack<HISQ_F16S>, grid, block, 0, s, in, out, g, hop, bb); break;
+        default: hipLaunchKernelGGL(k_pack<HISQ_I16S>, grid, block, 0, s, in, out, g, hop, bb); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "hisq_pack_links launch");

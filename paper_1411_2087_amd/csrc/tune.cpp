@@ -1,0 +1,163 @@
+// Autotuner: times the launch shapes of a kernel on the caller's buffers and
+// remembers the fastest per (kernel, lattice, precision, batch).  Choices live
+// in a process-wide table; when HISQ_TUNE_CACHE names a file they are also
+// loaded from and saved to it (a flat JSON object of integers).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "dslash_core.hpp"
+
+namespace hisq {
+
+static std::mutex g_mu;
+static std::map<std::string, int> g_table;
+static bool g_loaded = false;
+
+static std::string key_of(const char *kind, const Geom &g, int prec, int n)
+{
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "%s:p%d:n%d:%dx%dx%dx%d", kind, prec, n, g.L[0], g.L[1], g.L[2], g.L[3]);
+    return buf;
+}
+
+static void load_locked()
+{
+    if (g_loaded) return;
+    g_loaded = true;
+    const char *path = std::getenv("HISQ_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    // entries look like "key": value
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char *q1 = std::strchr(line, '"');
+        if (!q1) continue;
+        char *q2 = std::strchr(q1 + 1, '"');
+        if (!q2) continue;
+        char *colon = std::strchr(q2, ':');
+        if (!colon) continue;
+        g_table[std::string(q1 + 1, q2)] = std::atoi(colon + 1);
+    }
+    std::fclose(f);
+}
+
+static void save_locked()
+{
+    const char *path = std::getenv("HISQ_TUNE_CACHE");
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (auto &kv : g_table) std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < g_table.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+int tuned_choice(const char *kind, const Geom &g, int prec, int n, int fallback)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_locked();
+    auto it = g_table.find(key_of(kind, g, prec, n));
+    return it == g_table.end() ? fallback : it->second;
+}
+
+void set_tuned_choice(const char *kind, const Geom &g, int prec, int n, int v)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_locked();
+    g_table[key_of(kind, g, prec, n)] = v;
+    save_locked();
+}
+
+int tuned_dslash_shape(const Geom &g, int prec)
+{
+    int v = tuned_choice("dslash", g, prec, 1, 0);
+    return (v >= 0 && v < N_DSLASH_SHAPES) ? v : 0;
+}
+
+void set_tuned_dslash_shape(const Geom &g, int prec, int shape) { set_tuned_choice("dslash", g, prec, 1, shape); }
+
+// Times `launch()` with HIP events on stream s: 2 warm-up launches, then
+// `reps` launches; returns microseconds per launch or a negative value.
+template <class F>
+static double time_launches(F launch, int reps, hipStream_t s)
+{
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) { hipEventDestroy(a); return -1; }
+    double us = -1;
+    bool ok = true;
+    for (int i = 0; i < 2 && ok; ++i) ok = launch() == hipSuccess;
+    if (ok && hipEventRecord(a, s) == hipSuccess) {
+        for (int i = 0; i < reps && ok; ++i) ok = launch() == hipSuccess;
+        if (ok && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, a, b) == hipSuccess) us = 1e3 * ms / reps;
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return us;
+}
+
+template <class P>
+static int tune_dslash_impl(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, int reps,
+                            int *best, double *us_out, hipStream_t s)
+{
+    double best_us = 1e300;
+    int best_i = 0;
+    for (int i = 0; i < N_DSLASH_SHAPES; ++i) {
+        double us = time_launches([&]() { return launch_dslash_shape<P>(i, g, fat, lng, src, dst, 1, s); }, reps, s);
+        if (us_out) us_out[i] = us;
+        if (us < 0) return fail(HISQ_EHIP, "autotune: timing failed");
+        if (us < best_us) { best_us = us; best_i = i; }
+    }
+    set_tuned_dslash_shape(g, P::prec, best_i);
+    if (best) *best = best_i;
+    return HISQ_OK;
+}
+
+}  // namespace hisq
+
+using namespace hisq;
+
+extern "C" int hisq_tune_dslash(const void *fat, const void *lng, const void *src, void *dst, const int dims[4],
+                                int prec, int reps, int *best_shape, double *us_per_shape, void *stream)
+{
+    Geom g;
+    int rc = make_geom(dims, g);
+    if (rc) return rc;
+    if (!fat || !lng || !src || !dst) return fail(HISQ_EINVAL, "hisq_tune_dslash: NULL pointer");
+    if (src == dst) return fail(HISQ_EALIAS, "hisq_tune_dslash: src and dst alias");
+    if (reps <= 0) reps = 20;
+    hipStream_t s = (hipStream_t)stream;
+    switch (prec) {
+    case HISQ_F64: return tune_dslash_impl<PF64>(g, fat, lng, src, dst, reps, best_shape, us_per_shape, s);
+    case HISQ_F32: return tune_dslash_impl<PF32>(g, fat, lng, src, dst, reps, best_shape, us_per_shape, s);
+    case HISQ_F16S: return tune_dslash_impl<PF16S>(g, fat, lng, src, dst, reps, best_shape, us_per_shape, s);
+    case HISQ_I16S: return tune_dslash_impl<PI16S>(g, fat, lng, src, dst, reps, best_shape, us_per_shape, s);
+    default: return fail(HISQ_EINVAL, "hisq_tune_dslash: unknown precision");
+    }
+}
+
+extern "C" int hisq_dslash_shape(const int dims[4], int prec, int shape)
+{
+    Geom g;
+    int rc = make_geom(dims, g);
+    if (rc) return rc;
+    if (prec < HISQ_F64 || prec > HISQ_I16S) return fail(HISQ_EINVAL, "hisq_dslash_shape: unknown precision");
+    if (shape == -2) return N_DSLASH_SHAPES;
+    if (shape < -2 || shape >= N_DSLASH_SHAPES) return fail(HISQ_EINVAL, "hisq_dslash_shape: no such shape");
+    if (shape >= 0) set_tuned_dslash_shape(g, prec, shape);
+    return tuned_dslash_shape(g, prec);
+}

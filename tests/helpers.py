@@ -15,7 +15,8 @@ import synth  # noqa: E402
 # a_i = sum |M||psi| over the terms feeding component i)
 TOL_F64 = 1e-13
 TOL_F32 = 1e-6
-TOL_F16S = 5e-3   # reported; FP16 links carry ~2^-11 relative rounding
+TOL_F16S = 5e-3   # FP16 links carry ~2^-12 relative rounding of each entry
+TOL_I16S = 5e-4   # 16-bit fixed point: steps of scale/32767
 CG_TOL = 1e-10
 
 

@@ -24,8 +24,8 @@ def _solve(hq, dims, fat, lng, b, mass, mode, tol=CG_TOL, max_iter=0, use_graph=
     Llo = None
     if mode == 1:
         Llo = hq.fields.Links.pack(fat, lng, dims, 1)
-    elif mode == 2:
-        Llo = hq.fields.Links.pack(fat, lng, dims, 2)
+    elif mode in (2, 3):
+        Llo = hq.fields.Links.pack(fat, lng, dims, mode)
     bd = torch.from_numpy(b).cuda()
     xd = torch.zeros_like(bd) if x0 is None else torch.from_numpy(x0).cuda()
     ws = hq.fields.workspace("cg", dims, 1, mode)
@@ -62,7 +62,7 @@ def test_cg_graph_and_direct_agree(hq, use_graph):
     assert oracle.true_residual(dims, mass, fat, lng, b, x1) <= CG_TOL
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_cg_mixed(hq, mode):
     dims, mass = (8, 8, 8, 8), 0.05
     fat, lng = fields(dims, synth.gauge_seed(1))

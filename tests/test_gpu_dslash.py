@@ -3,7 +3,7 @@ against the CPU oracle (through the C ABI)."""
 import numpy as np
 import pytest
 
-from helpers import TOL_F16S, TOL_F32, TOL_F64, fields, oracle, say, synth, vh
+from helpers import TOL_F16S, TOL_F32, TOL_F64, TOL_I16S, fields, oracle, say, synth, vh
 
 pytestmark = pytest.mark.gpu
 
@@ -32,7 +32,7 @@ def _dslash_gpu(hq, dims, fat, lng, src, parity, prec):
 
 
 @pytest.mark.parametrize("dims", DIMS)
-@pytest.mark.parametrize("prec,tol", [(0, TOL_F64), (1, TOL_F32), (2, TOL_F16S)])
+@pytest.mark.parametrize("prec,tol", [(0, TOL_F64), (1, TOL_F32), (2, TOL_F16S), (3, TOL_I16S)])
 def test_dslash_parity(hq, dims, prec, tol):
     fat, lng = fields(dims, 1000 + sum(dims))
     r = np.random.default_rng(7)
@@ -143,3 +143,31 @@ def test_bad_arguments(hq):
     with pytest.raises(hq.HisqError) as e:
         hq.dslash_apply(L.fat, L.lng, s, s.clone(), 2, dims, 0)
     assert e.value.code == -1
+
+
+def test_all_launch_shapes_bitwise_identical(hq):
+    """Every launch shape of the Dslash computes the same bits (no races, no order change)."""
+    import torch
+    dims = (6, 4, 4, 10)  # ragged last tile
+    fat, lng = fields(dims)
+    src = synth.source(dims, 9)
+    for prec in (0, 1, 2, 3):
+        L = hq.fields.Links.pack(fat, lng, dims, prec)
+        dt = hq.fields.VEC_DTYPE[prec]
+        s = torch.from_numpy(src).to(dt).cuda()
+        outs = []
+        n = hq.hisq_dslash_shape(dims, prec, -2)
+        for shape in range(n):
+            hq.hisq_dslash_shape(dims, prec, shape)
+            d = torch.full_like(s, float("nan"))
+            hq.dslash_apply(L.fat, L.lng, s, d, 1, dims, prec)
+            d2 = torch.full_like(s, float("nan"))
+            hq.dslash_apply(L.fat, L.lng, s, d2, 1, dims, prec)
+            torch.cuda.synchronize()
+            assert torch.equal(torch.view_as_real(d), torch.view_as_real(d2))  # repeatable
+            outs.append(d.cpu())
+        for o in outs[1:]:
+            assert torch.equal(torch.view_as_real(o), torch.view_as_real(outs[0]))
+        best, us = hq.hisq_tune_dslash(L.fat, L.lng, s, torch.empty_like(s), dims, prec, reps=3)
+        assert 0 <= best < n and len(us) == n and min(us) > 0
+        assert hq.hisq_dslash_shape(dims, prec) == best
