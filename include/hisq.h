@@ -178,15 +178,45 @@ int cg_solve(double mass, double tol, const void *fat, const void *lng, const vo
              const void *b, void *x, const int dims[4], const hisq_cg_opts *opts, void *workspace,
              size_t ws_bytes, hisq_cg_stats *stats, void *stream);
 
-/* Batched solves for nrhs masses (Sec. 3: multishift CG over 9 or 11
- * masses).  masses: host array [nrhs].  b: complex128 [nrhs][Vh][3]
- * (MULTI_RHS) or [Vh][3] (MULTI_SHIFT); x: complex128 [nrhs][Vh][3], solved
- * from x0 = 0.  fat/lng: F64 packed links; fat_lo/lng_lo: F32 packed links
- * (the inner precision).  stats: host array [nrhs] (may be NULL). */
+/* Batched solves for nrhs <= 16 masses (Sec. 3: multishift CG over 9 or 11
+ * masses).  masses: host array [nrhs], each > 0.  b: complex128
+ * [nrhs][Vh][3] (MULTI_RHS) or [Vh][3] (MULTI_SHIFT); x: complex128
+ * [nrhs][Vh][3], solved from x0 = 0 to |b_i - A(m_i) x_i| <= tol |b_i| for
+ * every i.  fat/lng: F64 packed links (reliable updates, final residuals);
+ * fat_lo/lng_lo: F32 packed links (inner iterations).  opts: max_iter,
+ * check_every, use_graph and delta as for cg_solve (mode is ignored).
+ * stats: host array [nrhs] (may be NULL), per right-hand side; iters counts
+ * the shifted-CG iterations plus the refinement iterations.  Returns
+ * HISQ_ENOCONV / HISQ_EBREAKDOWN if any right-hand side failed; x then holds
+ * every right-hand side's last iterate. */
 int cg_solve_multi(int nrhs, const double *masses, double tol, int mode, const void *fat, const void *lng,
                    const void *fat_lo, const void *lng_lo, const void *b, void *x, const int dims[4],
                    const hisq_cg_opts *opts, void *workspace, size_t ws_bytes, hisq_cg_stats *stats,
                    void *stream);
+
+/* Multi-RHS FP32 Dslash, the kernel inside the batched solver (Sec. 3
+ * operator applied to nrhs vectors with one pass over the links): dst = D src
+ * on parity `parity` for nrhs = 1, 2, 4, 8 or 16 right-hand sides stored
+ * site-major, complex64 [Vh][nrhs][3].  fat/lng: HISQ_F32 packed links.
+ * workspace: >= 4096 bytes of device memory (holds the launch's RHS mask).
+ * Uses the launch shape chosen by hisq_tune_multi.  Asynchronous. */
+int hisq_dslash_multi(const void *fat, const void *lng, const void *src, void *dst, int parity, int nrhs,
+                      const int dims[4], void *workspace, size_t ws_bytes, void *stream);
+
+/* Autotuner of the multi-RHS Dslash launch shape (right-hand sides per
+ * thread, threads per workgroup) for (dims, nrhs): times every shape with
+ * HIP events on the caller's buffers (as for hisq_dslash_multi, parity 1,
+ * `reps` launches each), remembers the fastest as hisq_tune_dslash does and
+ * uses it in cg_solve_multi.  us_per_shape (may be NULL) gets 4 entries
+ * (-1 for shapes that do not apply to nrhs).  Synchronises `stream`. */
+int hisq_tune_multi(const void *fat, const void *lng, const void *src, void *dst, const int dims[4], int nrhs,
+                    void *workspace, size_t ws_bytes, int reps, int *best_shape, double *us_per_shape,
+                    void *stream);
+
+/* Launch shape of the multi-RHS Dslash for (dims, nrhs): shape >= 0 sets it
+ * (HISQ_EINVAL if it does not apply to nrhs), -1 queries, -2 returns the
+ * number of shapes.  Returns the shape in use or a negative hisq_status. */
+int hisq_multi_shape(const int dims[4], int nrhs, int shape);
 
 #ifdef __cplusplus
 }

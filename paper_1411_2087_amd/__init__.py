@@ -75,8 +75,12 @@ def _load():
     lib.hisq_tune_dslash.argtypes = [vp, vp, vp, vp, ip, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                      ctypes.POINTER(ctypes.c_double), vp]
     lib.hisq_dslash_shape.argtypes = [ip, ctypes.c_int, ctypes.c_int]
+    lib.hisq_dslash_multi.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ip, vp, sz, vp]
+    lib.hisq_tune_multi.argtypes = [vp, vp, vp, vp, ip, ctypes.c_int, vp, sz, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), vp]
+    lib.hisq_multi_shape.argtypes = [ip, ctypes.c_int, ctypes.c_int]
     for name in ("hisq_pack_links", "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi",
-                 "hisq_tune_dslash", "hisq_dslash_shape"):
+                 "hisq_tune_dslash", "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -85,7 +89,7 @@ _lib = _load()
 
 EXPORTED = ["hisq_version", "hisq_last_error", "hisq_packed_link_bytes", "hisq_pack_links", "dslash_apply",
             "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi", "hisq_tune_dslash",
-            "hisq_dslash_shape"]
+            "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape"]
 
 
 def _dims(dims):
@@ -161,6 +165,29 @@ def hisq_dslash_shape(dims, prec, shape=-1) -> int:
     rc = int(_lib.hisq_dslash_shape(_dims(dims), int(prec), int(shape)))
     if rc < 0:
         _check(rc, "hisq_dslash_shape")
+    return rc
+
+
+def hisq_dslash_multi(fat, lng, src, dst, parity, nrhs, dims, workspace, stream=None):
+    _check(_lib.hisq_dslash_multi(_ptr(fat), _ptr(lng), _ptr(src), _ptr(dst), int(parity), int(nrhs), _dims(dims),
+                                  _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)),
+           "hisq_dslash_multi")
+
+
+def hisq_tune_multi(fat, lng, src, dst, dims, nrhs, workspace, reps=10, stream=None):
+    """Time every multi-RHS Dslash shape; returns (best_shape, [microseconds per shape, -1 if n/a])."""
+    best = ctypes.c_int(-1)
+    us = (ctypes.c_double * 4)()
+    _check(_lib.hisq_tune_multi(_ptr(fat), _ptr(lng), _ptr(src), _ptr(dst), _dims(dims), int(nrhs), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), int(reps), ctypes.byref(best), us,
+                                _stream(stream)), "hisq_tune_multi")
+    return best.value, list(us)
+
+
+def hisq_multi_shape(dims, nrhs, shape=-1) -> int:
+    rc = int(_lib.hisq_multi_shape(_dims(dims), int(nrhs), int(shape)))
+    if rc < 0:
+        _check(rc, "hisq_multi_shape")
     return rc
 
 

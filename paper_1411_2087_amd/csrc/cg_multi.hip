@@ -665,6 +665,17 @@ __global__ void k_mstate_init(MultiState *st, int n, double tol2, double delta2,
     }
 }
 
+// n right-hand sides, all active (standalone multi-RHS Dslash and its tuner)
+__global__ void k_mstate_all(MultiState *st, int n)
+{
+    if (threadIdx.x || blockIdx.x) return;
+    st->flags.done = 0;
+    st->flags.reliable = 0;
+    st->n = n;
+    st->active = (1u << n) - 1u;
+    st->relmask = 0;
+}
+
 // every still-active RHS gets a reliable update (used when max_iter is hit)
 __global__ void k_mforce_reliable(MultiState *st)
 {
@@ -750,12 +761,17 @@ struct MultiBufs {
     double *dm;                          // small device array: masses or shifts
 };
 
-static size_t multi_partials(int N) { return (size_t)MULTI_MAX_BLOCKS * N + 64; }
+// partials: per-RHS block sums of the batched kernels, or one per Dslash block of the shifted CG
+static size_t multi_partials(const Geom &g, int N)
+{
+    return std::max((size_t)MULTI_MAX_BLOCKS * N, (size_t)((g.ntiles + 3) / 4)) + 64;
+}
 
 size_t cg_multi_ws_for(const Geom &g, int N)
 {
     const size_t vp = (size_t)g.Vh * N * 3;
-    size_t b = al256(sizeof(MultiState)) + al256(multi_partials(N) * sizeof(double)) + al256(64 * sizeof(double));
+    size_t b = al256(sizeof(MultiState)) + al256(multi_partials(g, N) * sizeof(double)) + al256(64 * sizeof(double)) +
+               3 * MSKEW;
     b += 4 * (al256(vp * 16) + MSKEW) + 5 * (al256(vp * 8) + MSKEW) + 4 * (al256((size_t)g.Vh * 3 * 8) + MSKEW);
     return b + 4096;
 }
@@ -782,7 +798,7 @@ static bool carve(MultiBufs &B, void *ws, size_t bytes, const Geom &g, int N)
     };
     const size_t vp = (size_t)g.Vh * N * 3, v1 = (size_t)g.Vh * 3;
     B.st = (MultiState *)take(sizeof(MultiState));
-    B.part = (double *)take(multi_partials(N) * sizeof(double));
+    B.part = (double *)take(multi_partials(g, N) * sizeof(double));
     B.dm = (double *)take(64 * sizeof(double));
     B.x64 = (double2 *)take(vp * 16);
     B.b64 = (double2 *)take(vp * 16);
@@ -963,6 +979,9 @@ static int multi_shift_core(int n, const double *masses, double tol_ms, const vo
     hipLaunchKernelGGL((k_mnorm<1>), dim3(nb1), dim3(MB_NT), 0, s, (const double2 *)b, (long long)g.Vh, B.part);
     hipLaunchKernelGGL(k_msfinalize, dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nb1, B.st, (int)FS_BB);
     HISQ_HIP(hipGetLastError());
+    int rc0 = read_mstate(hs, B.st, s);
+    if (rc0) return rc0;
+    if (hs->bb0 == 0.0) return HISQ_OK;  // zero source: every x_i = 0 (already in B.xs)
     auto iter = [&](hipStream_t q) -> hipError_t {
         hipError_t e = launch_dslash<PF32>(g, fat_lo, lng_lo, B.p1, B.t1, 1, q, &B.st->flags, GATE_NOT_DONE);
         if (e != hipSuccess) return e;
@@ -1049,15 +1068,9 @@ template <int N>
 static int tune_multi_impl(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, void *ws,
                            size_t ws_bytes, int reps, int *best, double *us, hipStream_t s)
 {
-    if (ws_bytes < al256(sizeof(MultiState)) + 256) return fail(HISQ_EWORKSPACE, "hisq_tune_multi: workspace too small");
+    if (ws_bytes < 4096) return fail(HISQ_EWORKSPACE, "hisq_tune_multi: workspace too small");
     MultiState *st = (MultiState *)ws;
-    HISQ_HIP(hipMemsetAsync(st, 0, sizeof(MultiState), s));
-    // every RHS active for the timing
-    MultiState init;
-    std::memset(&init, 0, sizeof init);
-    init.n = N;
-    init.active = (N >= 32) ? ~0u : ((1u << N) - 1u);
-    HISQ_HIP(hipMemcpyAsync(st, &init, sizeof init, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_mstate_all, dim3(1), dim3(1), 0, s, st, N);  // every RHS active for the timing
     hipEvent_t e0, e1;
     HISQ_HIP(hipEventCreate(&e0));
     HISQ_HIP(hipEventCreate(&e1));
@@ -1094,11 +1107,7 @@ static int mdslash_apply_impl(const Geom &g, const void *fat, const void *lng, c
                               void *ws, hipStream_t s)
 {
     MultiState *st = (MultiState *)ws;
-    MultiState init;
-    std::memset(&init, 0, sizeof init);
-    init.n = N;
-    init.active = (1u << N) - 1u;
-    HISQ_HIP(hipMemcpyAsync(st, &init, sizeof init, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_mstate_all, dim3(1), dim3(1), 0, s, st, N);
     HISQ_HIP((launch_md_shape<PF32, N, EPI_STORE>(mshape_for(g, N), g, fat, lng, src, dst, nullptr, nullptr, nullptr,
                                                   parity, nullptr, st, MASK_ACTIVE, GATE_ALWAYS, s, nullptr)));
     return HISQ_OK;
@@ -1169,7 +1178,7 @@ extern "C" int hisq_dslash_multi(const void *fat, const void *lng, const void *s
     if (src == dst) return fail(HISQ_EALIAS, "hisq_dslash_multi: src and dst alias");
     if (parity != 0 && parity != 1) return fail(HISQ_EINVAL, "hisq_dslash_multi: parity must be 0 or 1");
     if (nrhs != pad_n(nrhs) || nrhs > MAXR) return fail(HISQ_EINVAL, "hisq_dslash_multi: nrhs must be 1, 2, 4, 8 or 16");
-    if (ws_bytes < al256(sizeof(MultiState))) return fail(HISQ_EWORKSPACE, "hisq_dslash_multi: workspace too small");
+    if (ws_bytes < 4096) return fail(HISQ_EWORKSPACE, "hisq_dslash_multi: workspace too small");
     hipStream_t s = (hipStream_t)stream;
     switch (nrhs) {
     case 1: return mdslash_apply_impl<1>(g, fat, lng, src, dst, parity, workspace, s);
@@ -1178,4 +1187,19 @@ extern "C" int hisq_dslash_multi(const void *fat, const void *lng, const void *s
     case 8: return mdslash_apply_impl<8>(g, fat, lng, src, dst, parity, workspace, s);
     default: return mdslash_apply_impl<16>(g, fat, lng, src, dst, parity, workspace, s);
     }
+}
+
+extern "C" int hisq_multi_shape(const int dims[4], int nrhs, int shape)
+{
+    Geom g;
+    int rc = make_geom(dims, g);
+    if (rc) return rc;
+    if (nrhs != pad_n(nrhs) || nrhs > MAXR) return fail(HISQ_EINVAL, "hisq_multi_shape: nrhs must be 1, 2, 4, 8 or 16");
+    if (shape == -2) return N_MSHAPES;
+    if (shape < -2 || shape >= N_MSHAPES) return fail(HISQ_EINVAL, "hisq_multi_shape: no such shape");
+    if (shape >= 0) {
+        if (nrhs % MSHAPES[shape].gdiv) return fail(HISQ_EINVAL, "hisq_multi_shape: shape does not divide nrhs");
+        set_tuned_choice("mdslash", g, HISQ_F32, nrhs, shape);
+    }
+    return mshape_for(g, nrhs);
 }
