@@ -103,6 +103,9 @@ typedef struct {
     int status;             /* hisq_status of this solve */
     double true_resid;      /* |b - A x| / |b| recomputed in FP64 on the GPU */
     double time_s;          /* wall time of the solve, first kernel to final check */
+    int fallback_used;      /* fcg_solve: 0 none; 1 K not positive on r or <p,Ap> <= 0; 2 stall;
+                               3 recursion converged but the true residual did not */
+    int fallback_iters;     /* fcg_solve: plain CG iterations after the fallback */
 } hisq_cg_stats;
 
 /* Library version string. */
@@ -212,6 +215,56 @@ int hisq_dslash_multi(const void *fat, const void *lng, const void *src, void *d
 int hisq_tune_multi(const void *fat, const void *lng, const void *src, void *dst, const int dims[4], int nrhs,
                     void *workspace, size_t ws_bytes, int reps, int *best_shape, double *us_per_shape,
                     void *stream);
+
+/* ---- learned preconditioner ------------------------------------------------
+ * A gauge-covariant linear network of four parallel-transport layers with
+ * channels 1 -> C -> C -> C -> 1 (C = 4, 8 or 16):
+ *     out^a(x) = sum_b sum_{k=0..8} W_k^{ab} (T_k in^b)(x),
+ * T_0 = 1, T_{+mu} phi(x) = F_mu(x) phi(x+mu), T_{-mu} phi(x) =
+ * F_mu(x-mu)^dag phi(x-mu), F the fat links of the operator (Sec. 3).  The
+ * channel mixing runs on BF16 MFMA with FP32 accumulation, features are FP32.
+ * Weights: complex64, the four layers' [9][C_out][C_in] arrays back to back
+ * (net_weight_count() complex numbers).  Fields: complex64.  An even-site
+ * input [batch][Vh][3] is embedded on the full lattice (odd sites zero); the
+ * output is the even part of the last layer, [batch][Vh][3].  fat: the
+ * HISQ_F32 packed fat links. */
+size_t net_weight_count(int channels);
+/* bytes of the activation buffer of net_forward (every layer's input is kept
+ * for net_backward) and of net_backward's workspace.  Activation layout: four
+ * BF16 weight-operand slots of 18432 bytes, then the inputs of layers 1..4
+ * and the output of layer 4, each [batch][channels][parity][Vh][3]
+ * complex64 (1, C, C, C and 1 channels), every block starting at a multiple
+ * of 256 bytes. */
+size_t net_act_bytes(const int dims[4], int channels, int batch);
+size_t net_backward_ws_bytes(const int dims[4], int channels, int batch);
+int net_forward(const void *fat, const void *weights, int channels, const void *in, void *out, void *acts,
+                size_t act_bytes, int batch, const int dims[4], void *stream);
+/* grad_out: dl/d out [batch][Vh][3]; grad_w: dl/dW summed over the batch
+ * (complex, dl/dRe + i dl/dIm); grad_in (may be NULL): dl/d in.  acts: the
+ * buffer filled by the net_forward of the same batch. */
+int net_backward(const void *fat, const void *weights, int channels, const void *acts, size_t act_bytes,
+                 const void *grad_out, void *grad_w, void *grad_in, int batch, const int dims[4], void *workspace,
+                 size_t ws_bytes, void *stream);
+/* l = mean_b |y_b - x_b|^2 / |x_b|^2 (FP64 accumulation) into *loss_host
+ * (may be NULL: no synchronisation) and dl/dy into grad_y (may be NULL).
+ * workspace >= 2048 * (batch + 1) bytes. */
+int net_loss(const void *y, const void *x, int batch, const int dims[4], double *loss_host, void *grad_y,
+             void *workspace, size_t ws_bytes, void *stream);
+/* Adam (Kingma & Ba 2014, beta1 0.9, beta2 0.999, eps 1e-8) on the real and
+ * imaginary parts of n_complex weights; m, v: FP32 state of 2 n_complex
+ * reals each, zero before step 1; step counts from 1. */
+int net_adam_step(void *weights, const void *grad_w, void *m, void *v, long long n_complex, double lr, int step,
+                  void *stream);
+/* Flexible CG (Notay 2000, one stored direction, Polak-Ribiere update)
+ * preconditioned by the network, on A(mass) x = b to tol; plain FP64 CG from
+ * the current x is the fallback when K is not positive on the residual, when
+ * <p, A p> <= 0, or after 50 iterations without a new lowest residual
+ * (stats.fallback_used says which).  fat/lng: HISQ_F64 packed links; fat32:
+ * HISQ_F32 packed fat links for the network.  Workspace from
+ * hisq_workspace_bytes("fcg", dims, 1, 0, channels). */
+int fcg_solve(double mass, double tol, const void *fat, const void *lng, const void *fat32, const void *weights,
+              int channels, const void *b, void *x, const int dims[4], const hisq_cg_opts *opts, void *workspace,
+              size_t ws_bytes, hisq_cg_stats *stats, void *stream);
 
 /* Launch shape of the multi-RHS Dslash for (dims, nrhs): shape >= 0 sets it
  * (HISQ_EINVAL if it does not apply to nrhs), -1 queries, -2 returns the

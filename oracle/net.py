@@ -84,14 +84,26 @@ def layer_forward(dims, fat, W, x, bf16=False):
     return np.einsum("kab,kbvc->avc", W, feats)
 
 
-def layer_backward(dims, fat, W, x, g):
-    """(dl/dx, dl/dW) of one layer given x (C_in, V, 3) and g = dl/dout (C_out, V, 3)."""
+def adjoint_weights(W):
+    """W'_{k}^{ba} = conj(W_{k^dag}^{ab}): the layer whose forward map is the input gradient."""
+    W = np.asarray(W)
+    return np.stack([np.conj(W[ADJOINT[k]]).T for k in range(9)])
+
+
+def layer_backward(dims, fat, W, x, g, bf16=False):
+    """(dl/dx, dl/dW) of one layer given x (C_in, V, 3) and g = dl/dout (C_out, V, 3).
+
+    bf16=True rounds the operands of the weight-gradient product (the
+    transported features and g) to BF16 via FP32, as the MFMA kernel does."""
     Cin = x.shape[0]
     gW = np.zeros_like(np.asarray(W, dtype=np.complex128))
+    gg = _bf16c(np.asarray(g).astype(np.complex64)) if bf16 else g
     for k in range(9):
         for b in range(Cin):
             f = transport(dims, fat, x[b], k)
-            gW[k, :, b] = np.einsum("vc,avc->a", f.conj(), g)
+            if bf16:
+                f = _bf16c(f.astype(np.complex64))
+            gW[k, :, b] = np.einsum("vc,avc->a", f.conj(), gg)
     gx = np.zeros_like(x, dtype=np.complex128)
     for k in range(9):
         for a in range(g.shape[0]):

@@ -47,7 +47,8 @@ class CGOpts(ctypes.Structure):
 
 class CGStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("restarts", ctypes.c_int),
-                ("status", ctypes.c_int), ("true_resid", ctypes.c_double), ("time_s", ctypes.c_double)]
+                ("status", ctypes.c_int), ("true_resid", ctypes.c_double), ("time_s", ctypes.c_double),
+                ("fallback_used", ctypes.c_int), ("fallback_iters", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,8 +80,21 @@ def _load():
     lib.hisq_tune_multi.argtypes = [vp, vp, vp, vp, ip, ctypes.c_int, vp, sz, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), vp]
     lib.hisq_multi_shape.argtypes = [ip, ctypes.c_int, ctypes.c_int]
+    lib.net_weight_count.argtypes = [ctypes.c_int]
+    lib.net_weight_count.restype = sz
+    lib.net_act_bytes.argtypes = [ip, ctypes.c_int, ctypes.c_int]
+    lib.net_act_bytes.restype = sz
+    lib.net_backward_ws_bytes.argtypes = [ip, ctypes.c_int, ctypes.c_int]
+    lib.net_backward_ws_bytes.restype = sz
+    lib.net_forward.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp, sz, ctypes.c_int, ip, vp]
+    lib.net_backward.argtypes = [vp, vp, ctypes.c_int, vp, sz, vp, vp, vp, ctypes.c_int, ip, vp, sz, vp]
+    lib.net_loss.argtypes = [vp, vp, ctypes.c_int, ip, ctypes.POINTER(ctypes.c_double), vp, vp, sz, vp]
+    lib.net_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_longlong, d, ctypes.c_int, vp]
+    lib.fcg_solve.argtypes = [d, d, vp, vp, vp, vp, ctypes.c_int, vp, vp, ip, ctypes.POINTER(CGOpts), vp, sz,
+                              ctypes.POINTER(CGStats), vp]
     for name in ("hisq_pack_links", "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi",
-                 "hisq_tune_dslash", "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape"):
+                 "hisq_tune_dslash", "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape",
+                 "net_forward", "net_backward", "net_loss", "net_adam_step", "fcg_solve"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -89,7 +103,9 @@ _lib = _load()
 
 EXPORTED = ["hisq_version", "hisq_last_error", "hisq_packed_link_bytes", "hisq_pack_links", "dslash_apply",
             "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi", "hisq_tune_dslash",
-            "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape"]
+            "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape", "net_weight_count",
+            "net_act_bytes", "net_backward_ws_bytes", "net_forward", "net_backward", "net_loss", "net_adam_step",
+            "fcg_solve"]
 
 
 def _dims(dims):
@@ -221,6 +237,58 @@ def cg_solve_multi(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, dims
     for o in out:
         o["rc"] = rc
     return out
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def net_weight_count(channels) -> int:
+    return int(_lib.net_weight_count(int(channels)))
+
+
+def net_act_bytes(dims, channels, batch) -> int:
+    return int(_lib.net_act_bytes(_dims(dims), int(channels), int(batch)))
+
+
+def net_backward_ws_bytes(dims, channels, batch) -> int:
+    return int(_lib.net_backward_ws_bytes(_dims(dims), int(channels), int(batch)))
+
+
+def net_forward(fat, weights, channels, inp, out, acts, batch, dims, stream=None):
+    _check(_lib.net_forward(_ptr(fat), _ptr(weights), int(channels), _ptr(inp), _ptr(out), _ptr(acts), _nbytes(acts),
+                            int(batch), _dims(dims), _stream(stream)), "net_forward")
+
+
+def net_backward(fat, weights, channels, acts, grad_out, grad_w, grad_in, batch, dims, workspace, stream=None):
+    _check(_lib.net_backward(_ptr(fat), _ptr(weights), int(channels), _ptr(acts), _nbytes(acts), _ptr(grad_out),
+                             _ptr(grad_w), _ptr(grad_in), int(batch), _dims(dims), _ptr(workspace),
+                             _nbytes(workspace), _stream(stream)), "net_backward")
+
+
+def net_loss(y, x, batch, dims, grad_y, workspace, sync=True, stream=None):
+    loss = ctypes.c_double(float("nan"))
+    _check(_lib.net_loss(_ptr(y), _ptr(x), int(batch), _dims(dims), ctypes.byref(loss) if sync else None,
+                         _ptr(grad_y), _ptr(workspace), _nbytes(workspace), _stream(stream)), "net_loss")
+    return loss.value
+
+
+def net_adam_step(weights, grad_w, m, v, n_complex, lr, step, stream=None):
+    _check(_lib.net_adam_step(_ptr(weights), _ptr(grad_w), _ptr(m), _ptr(v), int(n_complex), float(lr), int(step),
+                              _stream(stream)), "net_adam_step")
+
+
+def fcg_solve(mass, tol, fat, lng, fat32, weights, channels, b, x, dims, opts: CGOpts | None, workspace, stream=None,
+              raise_on_noconv=False) -> dict:
+    st = CGStats()
+    rc = _lib.fcg_solve(float(mass), float(tol), _ptr(fat), _ptr(lng), _ptr(fat32), _ptr(weights), int(channels),
+                        _ptr(b), _ptr(x), _dims(dims), ctypes.byref(opts) if opts is not None else None,
+                        _ptr(workspace), _nbytes(workspace), ctypes.byref(st), _stream(stream))
+    if rc != 0 and (raise_on_noconv or rc not in (-5, -6)):
+        _check(rc, "fcg_solve")
+    d = st.as_dict()
+    d["rc"] = rc
+    return d
 
 
 from . import fields  # noqa: E402  (device buffers for packed links and vectors)

@@ -28,6 +28,7 @@ struct CGState {
 int blas_blocks(long long n);
 size_t cg_partials_count(const Geom &g);
 size_t cg_multi_workspace_bytes(const Geom &g, int nrhs, int mode);
+size_t fcg_ws_bytes(const Geom &g, int channels);
 CGState *pinned_state();
 hipStream_t capture_stream();
 hisq_cg_opts resolve_opts(const hisq_cg_opts *opts, const Geom &g);

@@ -1,0 +1,149 @@
+"""Training of the gauge-covariant preconditioner on the GPU.
+
+Sequences the library's kernels (net_forward, net_loss, net_backward,
+net_adam_step) over batches of (b, x) pairs with A x = b produced by the
+library's own CG; the loss is mean_i |K(b_i) - x_i|^2 / |x_i|^2.  Every
+arithmetic step runs in libhisq; this module only orders the calls and owns
+the device buffers.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import (HISQ_F32, HISQ_F64, HISQ_MULTI_RHS, CGOpts, cg_solve_multi, net_act_bytes, net_adam_step,
+               net_backward, net_backward_ws_bytes, net_forward, net_loss, net_weight_count)
+from .fields import Links, workspace
+
+LAYER_SHAPES = lambda C: [(C, 1), (C, C), (C, C), (1, C)]  # (C_out, C_in) per layer
+
+
+def identity_weights(C, scale=1.0):
+    """Weights with K = scale * identity (every layer passes channel 0 through T_0)."""
+    Ws = []
+    for i, (co, ci) in enumerate(LAYER_SHAPES(C)):
+        W = np.zeros((9, co, ci), np.complex64)
+        W[0, 0, 0] = scale if i == 3 else 1.0
+        for a in range(1, min(co, ci)):
+            W[0, a, a] = 1.0
+        Ws.append(W)
+    return Ws
+
+
+def flatten(Ws):
+    return np.concatenate([W.reshape(-1) for W in Ws]).astype(np.complex64)
+
+
+def unflatten(w, C):
+    out, o = [], 0
+    for co, ci in LAYER_SHAPES(C):
+        n = 9 * co * ci
+        out.append(np.asarray(w[o:o + n]).reshape(9, co, ci))
+        o += n
+    return out
+
+
+def initial_weights(C, scale, noise, noise_seed):
+    """scale * identity plus complex Gaussian noise of size `noise` (drawn by the input generator)."""
+    import synth
+    w = flatten(identity_weights(C, scale))
+    z = synth.gauss(noise_seed, 7, w.size).astype(np.complex64)
+    return w + noise * z
+
+
+def make_pairs(dims, mass, links64: Links, links32: Links, sources: np.ndarray, tol=1e-8, device="cuda"):
+    """x_i = A(mass)^-1 b_i for every source, by the batched reliable-update CG, 16 at a time.
+    Returns (b, x) as device complex64 tensors [n][Vh][3], the total solve time and x in complex128."""
+    n = sources.shape[0]
+    vh = sources.shape[1]
+    bs = torch.from_numpy(np.ascontiguousarray(sources)).to(device)
+    xs = torch.zeros_like(bs)
+    opts = CGOpts(mode=0, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    seconds = 0.0
+    for s in range(0, n, 16):
+        k = min(16, n - s)
+        ws = workspace("cg_multi", dims, k, HISQ_MULTI_RHS)
+        b = bs[s:s + k].contiguous()
+        x = torch.zeros_like(b)
+        st = cg_solve_multi(k, [mass] * k, tol, HISQ_MULTI_RHS, links64.fat, links64.lng, links32.fat, links32.lng, b,
+                            x, dims, opts, ws, raise_on_noconv=True)
+        seconds += st[0]["time_s"]
+        xs[s:s + k] = x
+    return bs.to(torch.complex64), xs.to(torch.complex64), seconds, xs
+
+
+class Trainer:
+    """Adam on the network weights; buffers sized for `batch` sources."""
+
+    def __init__(self, dims, C, fat32, weights: np.ndarray, batch=16, device="cuda"):
+        self.dims, self.C, self.fat32, self.batch = tuple(dims), C, fat32, batch
+        n = net_weight_count(C)
+        assert weights.size == n
+        self.n = n
+        self.w = torch.from_numpy(weights.astype(np.complex64)).to(device)
+        self.m = torch.zeros(2 * n, dtype=torch.float32, device=device)
+        self.v = torch.zeros(2 * n, dtype=torch.float32, device=device)
+        self.gw = torch.zeros(n, dtype=torch.complex64, device=device)
+        vh = int(np.prod(dims)) // 2
+        self.acts = torch.empty(net_act_bytes(dims, C, batch), dtype=torch.uint8, device=device)
+        self.ws = torch.empty(net_backward_ws_bytes(dims, C, batch), dtype=torch.uint8, device=device)
+        self.lws = torch.empty(2048 * (batch + 1) + 4096, dtype=torch.uint8, device=device)
+        self.y = torch.empty((batch, vh, 3), dtype=torch.complex64, device=device)
+        self.gy = torch.empty_like(self.y)
+        self.step_count = 0
+
+    def forward(self, b):
+        k = b.shape[0]
+        net_forward(self.fat32, self.w, self.C, b, self.y[:k], self.acts, k, self.dims)
+        return self.y[:k]
+
+    def loss(self, b, x):
+        y = self.forward(b)
+        return net_loss(y, x, b.shape[0], self.dims, None, self.lws)
+
+    def step(self, b, x, lr, sync=False):
+        """One Adam step on a batch; returns the batch loss before the step if sync."""
+        k = b.shape[0]
+        assert k <= self.batch
+        y = self.forward(b)
+        loss = net_loss(y, x, k, self.dims, self.gy[:k], self.lws, sync=sync)
+        net_backward(self.fat32, self.w, self.C, self.acts, self.gy[:k], self.gw, None, k, self.dims, self.ws)
+        self.step_count += 1
+        net_adam_step(self.w, self.gw, self.m, self.v, self.n, lr, self.step_count)
+        return loss
+
+    def fit(self, b_train, x_train, steps, lr=1e-3, log_every=50, seed=0, log=None):
+        """`steps` Adam steps over shuffled batches; returns [(step, loss)] at log points."""
+        rng = np.random.default_rng(seed)
+        n = b_train.shape[0]
+        hist = []
+        order = rng.permutation(n)
+        pos = 0
+        for s in range(1, steps + 1):
+            if pos + self.batch > n:
+                order = rng.permutation(n)
+                pos = 0
+            idx = torch.from_numpy(order[pos:pos + self.batch]).to(b_train.device)
+            pos += self.batch
+            sync = (s % log_every == 0) or s == 1
+            l = self.step(b_train[idx].contiguous(), x_train[idx].contiguous(), lr, sync=sync)
+            if sync:
+                hist.append((s, l))
+                if log:
+                    log(f"[train] step {s} loss {l:.5f}")
+        return hist
+
+    def evaluate(self, b, x):
+        losses = []
+        for s in range(0, b.shape[0], self.batch):
+            bb, xx = b[s:s + self.batch].contiguous(), x[s:s + self.batch].contiguous()
+            y = self.forward(bb)
+            losses.append(net_loss(y, xx, bb.shape[0], self.dims, None, self.lws) * bb.shape[0])
+        return float(np.sum(losses) / b.shape[0])
+
+
+def least_squares_scale(b, x):
+    """The scalar s minimising sum |s b - x|^2 (starting point of K = s 1)."""
+    num = torch.sum((b.conj() * x).real).item()
+    den = torch.sum((b.conj() * b).real).item()
+    return num / den

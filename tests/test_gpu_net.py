@@ -1,0 +1,230 @@
+"""GPU network kernels (transport + BF16 MFMA mixing, backward, loss, Adam) and
+the flexible CG they precondition, against the CPU oracle."""
+import numpy as np
+import pytest
+
+from helpers import CG_TOL, fields, oracle, say, synth
+from oracle import lattice
+from oracle import net as N
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hq():
+    import torch
+    import paper_1411_2087_amd as hq
+    assert torch.cuda.is_available()
+    return hq
+
+
+def a256(v):
+    return (v + 255) // 256 * 256
+
+
+def eo_to_lex(dims, eo):
+    """[C][2][Vh][3] (GPU layout) -> (C, V, 3) lex order."""
+    C = eo.shape[0]
+    V = int(np.prod(dims))
+    out = np.zeros((C, V, 3), np.complex128)
+    for p in (0, 1):
+        out[:, lattice.parity_sites(dims, p)] = eo[:, p]
+    return out
+
+
+def acts_views(acts_np, dims, C, batch):
+    """Layer inputs and output from the activation buffer (layout documented in hisq.h)."""
+    vh = int(np.prod(dims)) // 2
+    off = 4 * a256(32 * 288 * 2)
+    chans = [1, C, C, C, 1]
+    views = []
+    for c in chans:
+        nbytes = batch * c * 2 * vh * 3 * 8
+        v = acts_np[off:off + nbytes].view(np.complex64).reshape(batch, c, 2, vh, 3)
+        views.append(v.astype(np.complex128))
+        off += a256(nbytes)
+    return views
+
+
+def rand_weights(C, seed, scale=0.4):
+    r = np.random.default_rng(seed)
+    Ws = []
+    for co, ci in N.channels_of(C):
+        Ws.append(((r.standard_normal((9, co, ci)) + 1j * r.standard_normal((9, co, ci))) * scale / np.sqrt(9 * ci)))
+    return Ws
+
+
+def gpu_forward(hq, dims, fat, Ws, C, bs):
+    import torch
+    from paper_1411_2087_amd import train
+    L32 = hq.fields.Links.pack(fat, fat, dims, hq.HISQ_F32)
+    w = torch.from_numpy(train.flatten([W.astype(np.complex64) for W in Ws])).cuda()
+    B = len(bs)
+    b = torch.from_numpy(np.stack(bs).astype(np.complex64)).cuda()
+    y = torch.empty_like(b)
+    acts = torch.empty(hq.net_act_bytes(dims, C, B), dtype=torch.uint8, device="cuda")
+    hq.net_forward(L32.fat, w, C, b, y, acts, B, dims)
+    torch.cuda.synchronize()
+    return L32, w, b, y, acts
+
+
+@pytest.mark.parametrize("C", [4, 8, 16])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 6), (6, 4, 4, 8)])
+def test_net_forward_layers(hq, C, dims):
+    fat, _ = fields(dims, 1000)
+    Ws = rand_weights(C, 3)
+    bs = [synth.source(dims, 60 + i) for i in range(2)]
+    L32, w, b, y, acts = gpu_forward(hq, dims, fat, Ws, C, bs)
+    views = acts_views(acts.cpu().numpy(), dims, C, 2)
+    fat32 = fat.astype(np.complex64).astype(np.complex128)  # the kernels read FP32 links
+    worst = 0.0
+    for bi in range(2):
+        for l in range(4):
+            xin = eo_to_lex(dims, views[l][bi])
+            want = N.layer_forward(dims, fat32, Ws[l].astype(np.complex64), xin, bf16=True)
+            got = eo_to_lex(dims, views[l + 1][bi])
+            rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+            worst = max(worst, rel)
+            assert rel < 1e-4, (bi, l, rel)
+        # output = even part of the last layer
+        assert np.array_equal(y.cpu().numpy()[bi], views[4][bi][0, 0].astype(np.complex64))
+    # end to end against pure FP64 (reported)
+    ye, _ = N.net_forward(dims, fat, Ws, bs[0])
+    e2e = np.linalg.norm(y.cpu().numpy()[0] - ye) / np.linalg.norm(ye)
+    say(f"net forward C={C} dims={dims}: layer vs BF16-emulating oracle {worst:.2e}; end-to-end vs FP64 {e2e:.2e}")
+    assert e2e < 5e-2
+
+
+@pytest.mark.parametrize("C", [4, 16])
+def test_net_backward(hq, C):
+    import torch
+    dims = (4, 4, 4, 6)
+    fat, _ = fields(dims, 1000)
+    Ws = rand_weights(C, 5)
+    bs = [synth.source(dims, 70 + i) for i in range(2)]
+    L32, w, b, y, acts = gpu_forward(hq, dims, fat, Ws, C, bs)
+    g = np.stack([synth.source(dims, 80 + i) for i in range(2)]).astype(np.complex64)
+    gd = torch.from_numpy(g).cuda()
+    gw = torch.zeros(hq.net_weight_count(C), dtype=torch.complex64, device="cuda")
+    gin = torch.empty_like(gd)
+    ws = torch.empty(hq.net_backward_ws_bytes(dims, C, 2), dtype=torch.uint8, device="cuda")
+    hq.net_backward(L32.fat, w, C, acts, gd, gw, gin, 2, dims, ws)
+    torch.cuda.synchronize()
+    from paper_1411_2087_amd import train
+    gws = train.unflatten(gw.cpu().numpy(), C)
+    views = acts_views(acts.cpu().numpy(), dims, C, 2)
+    fat32 = fat.astype(np.complex64).astype(np.complex128)
+    # last layer: same BF16 operands as the kernel -> tight
+    want4 = sum(N.layer_backward(dims, fat32, Ws[3], eo_to_lex(dims, views[3][bi]),
+                                 N.embed_even(dims, g[bi].astype(np.complex128)), bf16=True)[1] for bi in range(2))
+    rel4 = np.linalg.norm(gws[3] - want4) / np.linalg.norm(want4)
+    # every layer and the input gradient against the FP64 backward (reported)
+    rels = []
+    gin_ref = []
+    gW_ref = [np.zeros_like(W) for W in Ws]
+    for bi in range(2):
+        _, acts_o = N.net_forward(dims, fat, Ws, bs[bi])
+        gi, gws_o = N.net_backward(dims, fat, Ws, acts_o, g[bi].astype(np.complex128))
+        gin_ref.append(gi)
+        for acc, x in zip(gW_ref, gws_o):
+            acc += x
+    for l in range(4):
+        rels.append(np.linalg.norm(gws[l] - gW_ref[l]) / np.linalg.norm(gW_ref[l]))
+    rin = np.linalg.norm(gin.cpu().numpy() - np.stack(gin_ref)) / np.linalg.norm(np.stack(gin_ref))
+    say(f"net backward C={C}: last-layer dW vs BF16 oracle {rel4:.2e}; dW vs FP64 {['%.1e' % v for v in rels]}; "
+        f"d input vs FP64 {rin:.2e}")
+    assert rel4 < 1e-4
+    assert max(rels) < 5e-2 and rin < 5e-2
+
+
+def test_net_loss_and_adam(hq):
+    import torch
+    dims = (4, 4, 4, 6)
+    vh = 192
+    r = np.random.default_rng(1)
+    y = (r.standard_normal((3, vh, 3)) + 1j * r.standard_normal((3, vh, 3))).astype(np.complex64)
+    x = (r.standard_normal((3, vh, 3)) + 1j * r.standard_normal((3, vh, 3))).astype(np.complex64)
+    yd, xd = torch.from_numpy(y).cuda(), torch.from_numpy(x).cuda()
+    gd = torch.empty_like(yd)
+    ws = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    loss = hq.net_loss(yd, xd, 3, dims, gd, ws)
+    lo, gr = N.loss_and_grad(list(y.astype(np.complex128)), list(x.astype(np.complex128)))
+    assert abs(loss - lo) < 1e-12 * lo
+    assert np.abs(gd.cpu().numpy() - np.stack(gr)).max() < 1e-6 * np.abs(np.stack(gr)).max()
+    # Adam: two steps against the oracle's
+    n = 50
+    w = (r.standard_normal(n) + 1j * r.standard_normal(n))
+    g1 = (r.standard_normal(n) + 1j * r.standard_normal(n))
+    g2 = (r.standard_normal(n) + 1j * r.standard_normal(n))
+    wd = torch.from_numpy(w.astype(np.complex64)).cuda()
+    m = torch.zeros(2 * n, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(m)
+    wo, mo, vo = [w.copy()], [np.zeros(n, complex)], [np.zeros(n, complex)]
+    for t, gg in ((1, g1), (2, g2)):
+        hq.net_adam_step(wd, torch.from_numpy(gg.astype(np.complex64)).cuda(), m, v, n, 1e-2, t)
+        N.adam_step(wo, [gg.astype(np.complex64).astype(complex)], mo, vo, t, 1e-2)
+    assert np.abs(wd.cpu().numpy() - wo[0]).max() < 1e-5
+
+
+def test_training_reduces_loss(hq):
+    import torch
+    from paper_1411_2087_amd import train
+    dims, mass, C = (8, 8, 8, 8), 0.05, 8
+    fat, lng = fields(dims, synth.gauge_seed(5))
+    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
+    L32 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32)
+    src = np.stack([synth.source(dims, synth.source_seed(5, i)) for i in range(64)])
+    b, x, secs, x64 = train.make_pairs(dims, mass, L64, L32, src)
+    # the pairs solve A x = b (oracle check on two of them)
+    for i in (0, 63):
+        assert oracle.true_residual(dims, mass, fat, lng, src[i], x64[i].cpu().numpy()) < 1e-8
+    s = train.least_squares_scale(b, x)
+    w0 = train.initial_weights(C, s, 0.01, 99)
+    tr = train.Trainer(dims, C, L32.fat, w0, batch=16)
+    l0 = tr.evaluate(b[48:], x[48:])
+    hist = tr.fit(b[:48], x[:48], steps=200, lr=2e-3, log_every=50)
+    l1 = tr.evaluate(b[48:], x[48:])
+    say(f"training 8^4 C={C}: held-out loss {l0:.4f} -> {l1:.4f}; train log {[(s_, round(l, 4)) for s_, l in hist]}")
+    assert l1 < 0.9 * l0
+
+
+def _fcg(hq, dims, mass, fat, lng, b, w, C, max_iter=0):
+    import torch
+    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
+    L32 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    ws = hq.fields.workspace("fcg", dims, 1, 0, C)
+    wd = torch.from_numpy(w.astype(np.complex64)).cuda()
+    opts = hq.CGOpts(mode=0, max_iter=max_iter, check_every=0, use_graph=1, delta=0.1)
+    st = hq.fcg_solve(mass, CG_TOL, L64.fat, L64.lng, L32.fat, wd, C, bd, xd, dims, opts, ws)
+    return xd.cpu().numpy(), st
+
+
+def test_fcg_identity_is_cg(hq):
+    from paper_1411_2087_amd import train
+    dims, mass, C = (8, 8, 8, 8), 0.05, 4
+    fat, lng = fields(dims, synth.gauge_seed(1))
+    b = synth.source(dims, synth.source_seed(1))
+    x, st = _fcg(hq, dims, mass, fat, lng, b, train.flatten(train.identity_weights(C)), C)
+    tr = oracle.true_residual(dims, mass, fat, lng, b, x)
+    _, info = oracle.cg(dims, mass, fat, lng, b, tol=CG_TOL)
+    say(f"fcg K=1: iters={st['iters']} fallback={st['fallback_used']} oracle resid={tr:.2e}; plain CG {info['iters']}")
+    assert st["rc"] == 0 and tr <= CG_TOL
+    # K = 1 up to the BF16 rounding of the mixing operands: FCG tracks CG
+    assert abs(st["iters"] - info["iters"]) <= max(3, 0.10 * info["iters"])
+
+
+def test_fcg_falls_back_on_a_bad_network(hq):
+    from paper_1411_2087_amd import train
+    dims, mass, C = (8, 8, 8, 8), 0.05, 4
+    fat, lng = fields(dims, synth.gauge_seed(1))
+    b = synth.source(dims, synth.source_seed(1))
+    x, st = _fcg(hq, dims, mass, fat, lng, b, train.flatten(train.identity_weights(C, scale=-1.0)), C)
+    assert st["fallback_used"] == 1 and st["rc"] == 0
+    assert oracle.true_residual(dims, mass, fat, lng, b, x) <= CG_TOL
+    w = train.flatten(train.identity_weights(C))
+    w[3] = np.nan
+    x, st = _fcg(hq, dims, mass, fat, lng, b, w, C)
+    assert st["fallback_used"] in (1, 2) and st["rc"] == 0
+    assert oracle.true_residual(dims, mass, fat, lng, b, x) <= CG_TOL

@@ -157,3 +157,15 @@ def test_fcg_falls_back_on_a_bad_preconditioner():
     x, info = fcg.fcg(dims, mass, fat, lng, b, lambda r: -r, tol=1e-10)
     assert info["fallback"]
     assert oracle.true_residual(dims, mass, fat, lng, b, x) <= 1e-10
+
+
+def test_input_gradient_is_the_adjoint_layer():
+    """dl/dx of a layer equals the forward map of the layer with W' = adjoint_weights(W)."""
+    fat, _ = synth.links(DIMS, 1000)
+    r = np.random.default_rng(4)
+    V = int(np.prod(DIMS))
+    W = cvec(r, (9, 3, 2))
+    x = cvec(r, (2, V, 3))
+    g = cvec(r, (3, V, 3))
+    gx, _ = N.layer_backward(DIMS, fat, W, x, g)
+    assert np.abs(N.layer_forward(DIMS, fat, N.adjoint_weights(W), g) - gx).max() < 1e-12
