@@ -85,6 +85,136 @@ def cpu_baseline(fat, lng, b, vh, budget_s=15.0):
                       f"+ BLAS-1) in {dt:.1f} s; sustained algorithmic Dslash GB/s"}
 
 
+def form_batched(hq, dims, L64, L32, mode, n, log):
+    """Batched solve of n masses (log-spaced 0.002 - 0.2) against n sequential plain FP64 solves."""
+    import numpy as np
+    import torch
+    import synth
+    masses = synth.log_masses(n, 0.002, 0.2)
+    vh = int(np.prod(dims)) // 2
+    if mode == hq.HISQ_MULTI_RHS:
+        bs = np.stack([synth.source(dims, synth.source_seed(4, r)) for r in range(n)])
+    else:
+        bs = synth.source(dims, synth.source_seed(4))
+    b = torch.from_numpy(bs).cuda()
+    x = torch.zeros((n, vh, 3), dtype=torch.complex128, device="cuda")
+    ws = hq.fields.workspace("cg_multi", dims, n, mode)
+    opts = hq.CGOpts(mode=0, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = hq.cg_solve_multi(n, masses, TOL, mode, L64.fat, L64.lng, L32.fat, L32.lng, b, x, dims, opts, ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del ws, x
+    # the same systems one at a time with plain FP64 CG
+    wsp = hq.fields.workspace("cg", dims)
+    seq, seq_iters = 0.0, []
+    for r in range(n):
+        bb = (b[r] if mode == hq.HISQ_MULTI_RHS else b).contiguous()
+        xx = torch.zeros_like(bb)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s1 = hq.cg_solve(masses[r], TOL, L64.fat, L64.lng, None, None, bb, xx, dims, None, wsp)
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t1
+        seq_iters.append(s1["iters"])
+    name = "multi_rhs" if mode == hq.HISQ_MULTI_RHS else "multi_shift"
+    log(f"[form {name}_{n}] {dt:.2f}s vs sequential plain FP64 {seq:.2f}s")
+    return {"s": round(dt, 3), "n": n, "masses": "log-spaced 0.002-0.2", "iters": [s_["iters"] for s_ in st],
+            "worst_true_resid": max(s_["true_resid"] for s_ in st), "sequential_plain_f64_s": round(seq, 3),
+            "sequential_plain_iters": seq_iters, "speedup_vs_sequential_plain": round(seq / dt, 3)}
+
+
+def form_learned(hq, log, dims=(16, 16, 16, 16), mass=0.005, C=16, npairs=64, steps=300):
+    """Learned preconditioner: pairs from the batched CG, GPU training, flexible CG vs plain FP64 CG."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1411_2087_amd import train
+    fat, lng = synth.links(dims, synth.gauge_seed(5))
+    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
+    L32 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32)
+    src = np.stack([synth.source(dims, synth.source_seed(5, i)) for i in range(npairs + 1)])
+    t0 = time.perf_counter()
+    b, x, _, _ = train.make_pairs(dims, mass, L64, L32, src[:npairs])
+    t_pairs = time.perf_counter() - t0
+    tr = train.Trainer(dims, C, L32.fat, train.initial_weights(C, train.residual_scale(b[:16], L32, mass, dims), 0.05,
+                                                               99), batch=16, objective="residual", links32=L32,
+                       mass=mass)
+    t0 = time.perf_counter()
+    hist = tr.fit(b, x, steps=steps, lr=2e-3, log_every=100)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    bd = torch.from_numpy(src[npairs]).cuda()
+    xp = torch.zeros_like(bd)
+    sp = hq.cg_solve(mass, TOL, L64.fat, L64.lng, None, None, bd, xp, dims, None, hq.fields.workspace("cg", dims))
+    xf = torch.zeros_like(bd)
+    sf = hq.fcg_solve(mass, TOL, L64.fat, L64.lng, L32.fat, tr.w, C, bd, xf, dims, None,
+                      hq.fields.workspace("fcg", dims, 1, 0, C))
+    log(f"[form learned] pairs {t_pairs:.1f}s train {t_train:.1f}s; plain {sp['iters']} it {sp['time_s']:.3f}s; "
+        f"fcg {sf['iters']} it (fallback {sf['fallback_used']}) {sf['time_s']:.3f}s")
+    return {"workload": "16^4, m 0.005, C 16, residual objective", "pairs": npairs, "pair_s": round(t_pairs, 2),
+            "train_steps": steps, "train_s": round(t_train, 2), "loss_log": [(s_, round(l, 4)) for s_, l in hist],
+            "plain_f64_s": round(sp["time_s"], 4), "plain_iters": sp["iters"], "fcg_s": round(sf["time_s"], 4),
+            "fcg_iters": sf["iters"], "fallback_used": sf["fallback_used"], "fallback_iters": sf["fallback_iters"],
+            "fcg_true_resid": sf["true_resid"], "speedup_vs_plain": round(sp["time_s"] / sf["time_s"], 3)}
+
+
+def run_large(args):
+    """48^3 x 96, m = 0.005: seconds to 1e-10 of plain FP64 CG and of the mixed-precision forms."""
+    import numpy as np
+    import torch
+
+    import paper_1411_2087_amd as hq
+    import synth
+    dims, mass = (48, 48, 48, 96), 0.005
+    vh = int(np.prod(dims)) // 2
+    log("[setup] generating 48^3x96 links and source")
+    fat, lng = synth.links(dims, synth.gauge_seed(3))
+    b_np = synth.source(dims, synth.source_seed(3))
+    fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
+    precs = (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S, hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_F16S)
+    L = {p: hq.fields.Links.pack(fd, ld, dims, p) for p in precs}
+    del fd, ld
+    b = torch.from_numpy(b_np).cuda()
+    dsl = {}
+    for p in precs:
+        dt = hq.fields.VEC_DTYPE[p]
+        s_, d_ = b.to(dt), torch.empty(b.shape, dtype=dt, device="cuda")
+        best, us = hq.hisq_tune_dslash(L[p].fat, L[p].lng, s_, d_, dims, p, reps=10)
+        t = min(us) * 1e-6
+        dsl[p] = {"us": round(t * 1e6, 1), "gbs": round(hq.DSLASH_BYTES_PER_SITE[p] * vh / t / 1e9, 1)}
+        log(f"[dslash 48^3x96] prec {p}: {dsl[p]}")
+        del s_, d_
+    forms = {}
+    for name, mode, lo in (("plain_f64", hq.HISQ_CG_PLAIN_F64, None), ("plain_f64c", hq.HISQ_CG_PLAIN_F64C, None),
+                           ("mixed_f32", hq.HISQ_CG_MIXED_F32, hq.HISQ_F32),
+                           ("mixed_i16s", hq.HISQ_CG_MIXED_I16S, hq.HISQ_I16S),
+                           ("mixed_f32c", hq.HISQ_CG_MIXED_F32C, hq.HISQ_F32C),
+                           ("mixed_f16s", hq.HISQ_CG_MIXED_F16S, hq.HISQ_F16S)):
+        hi = L[hq.HISQ_F64C] if mode in (hq.HISQ_CG_PLAIN_F64C, hq.HISQ_CG_MIXED_F32C) else L[hq.HISQ_F64]
+        ws = hq.fields.workspace("cg", dims, 1, mode)
+        x = torch.zeros_like(b)
+        o = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = hq.cg_solve(mass, TOL, hi.fat, hi.lng, L[lo].fat if lo is not None else None,
+                         L[lo].lng if lo is not None else None, b, x, dims, o, ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        forms[name] = {"s": round(dt, 3), "iters": st["iters"], "reliable_updates": st["reliable_updates"],
+                       "true_resid": st["true_resid"], "rc": st["rc"]}
+        log(f"[48^3x96 {name}] {dt:.2f}s iters={st['iters']} resid={st['true_resid']:.2e}")
+        del ws, x
+    base = forms["plain_f64"]["s"]
+    for k in forms:
+        forms[k]["speedup_vs_plain"] = round(base / forms[k]["s"], 3)
+    print(json.dumps({"metric": "CG s to 1e-10 resid, FP64 plain vs chosen form (report line)", "unit": "s",
+                      "value": base, "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+                      "config": {"workload": "HISQ even-odd CG, 48^3x96, mass 0.005, tol 1e-10"},
+                      "dslash": {str(k): v for k, v in dsl.items()}, "forms": forms}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +223,11 @@ def main():
     ap.add_argument("--dslash-reps", type=int, default=100)
     ap.add_argument("--no-forms", action="store_true", help="skip the chosen-form solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched (multi-RHS / multi-shift) forms")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
+    ap.add_argument("--workload", default="32x32x32x32",
+                    help="32x32x32x32 (default: plain FP64 CG, the metric's workload) or 48x48x48x96 "
+                         "(mixed precision against plain FP64 on the large lattice; a report line, not the metric)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a 2 GiB copy and the FP64 Dslash (for rocprofv3 counter runs)")
     args = ap.parse_args()
@@ -107,6 +242,8 @@ def main():
     import paper_1411_2087_amd as hq
     import synth
 
+    if args.workload == "48x48x48x96":
+        return run_large(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     vh = int(np.prod(DIMS)) // 2
@@ -218,6 +355,12 @@ def main():
             log(f"[form {name}] {dt:.3f}s iters={sm['iters']} updates={sm['reliable_updates']} "
                 f"resid={sm['true_resid']:.2e}")
             del wsm, xm
+    if not args.no_forms and not args.no_batched:
+        forms["multi_rhs_8"] = form_batched(hq, DIMS, L64, L32, hq.HISQ_MULTI_RHS, 8, log)
+        forms["multi_shift_8"] = form_batched(hq, DIMS, L64, L32, hq.HISQ_MULTI_SHIFT, 8, log)
+    if not args.no_forms and not args.no_learned:
+        del L16, LI16
+        forms["learned"] = form_learned(hq, log)
 
     cpu = None
     if not args.no_cpu:

@@ -67,8 +67,14 @@ typedef enum {
  * HISQ_I16S : 16-bit fixed-point links with the same per-matrix FP32 scale
  *             (entry = q * scale / 32767), FP32 vectors; same 40 B per matrix
  *             as HISQ_F16S with finer steps.
- * The last three have FP32 (complex64) vectors. */
-typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16S = 2, HISQ_I16S = 3 } hisq_prec;
+ * HISQ_F64C : FP64 with the long links in two-row form: rows 0 and 1 stored,
+ *             row 2 rebuilt as c conj(row0 x row1), c = det = +-1 kept as a
+ *             bit (Sec. 4: compression of the three-link term; the smeared
+ *             fat links stay full).  Packing checks that every long link is
+ *             +-SU(3) to 1e-6 and fails with HISQ_EINVAL otherwise.
+ * HISQ_F32C : FP32 with two-row long links.
+ * HISQ_F32, HISQ_F16S, HISQ_I16S and HISQ_F32C have FP32 (complex64) vectors. */
+typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16S = 2, HISQ_I16S = 3, HISQ_F64C = 4, HISQ_F32C = 5 } hisq_prec;
 
 /* CG modes.
  * PLAIN_F64  : every step in FP64.
@@ -76,8 +82,17 @@ typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16S = 2, HISQ_I16S = 3 } hisq_p
  *              accumulation, FP64 reliable updates of the true residual
  *              (x += x_inner, r = b - A x in FP64) and FP64 final residual.
  * MIXED_F16S : as MIXED_F32 with HISQ_F16S links in the inner Dslash.
- * MIXED_I16S : as MIXED_F32 with HISQ_I16S links in the inner Dslash. */
-enum { HISQ_CG_PLAIN_F64 = 0, HISQ_CG_MIXED_F32 = 1, HISQ_CG_MIXED_F16S = 2, HISQ_CG_MIXED_I16S = 3 };
+ * MIXED_I16S : as MIXED_F32 with HISQ_I16S links in the inner Dslash.
+ * PLAIN_F64C : PLAIN_F64 with HISQ_F64C links.
+ * MIXED_F32C : MIXED_F32 with HISQ_F64C outer and HISQ_F32C inner links. */
+enum {
+    HISQ_CG_PLAIN_F64 = 0,
+    HISQ_CG_MIXED_F32 = 1,
+    HISQ_CG_MIXED_F16S = 2,
+    HISQ_CG_MIXED_I16S = 3,
+    HISQ_CG_PLAIN_F64C = 4,
+    HISQ_CG_MIXED_F32C = 5
+};
 
 /* cg_solve_multi modes.
  * MULTI_RHS   : nrhs independent systems (A + 4 m_i^2 - 4 m_0^2 ...) i.e.
@@ -103,7 +118,7 @@ typedef struct {
     int status;             /* hisq_status of this solve */
     double true_resid;      /* |b - A x| / |b| recomputed in FP64 on the GPU */
     double time_s;          /* wall time of the solve, first kernel to final check */
-    int fallback_used;      /* fcg_solve: 0 none; 1 K not positive on r or <p,Ap> <= 0; 2 stall;
+    int fallback_used;      /* fcg_solve: 0 none; 1 K not positive on r or <p,Ap> <= 0; 2 stall or slow;
                                3 recursion converged but the true residual did not */
     int fallback_iters;     /* fcg_solve: plain CG iterations after the fallback */
 } hisq_cg_stats;
@@ -114,8 +129,9 @@ const char *hisq_version(void);
 /* Message of the last failing call on this thread ("" if none). */
 const char *hisq_last_error(void);
 
-/* Bytes of ONE packed link field (fat or long) in precision `prec`, or 0 on
- * bad arguments.  The packed form stores, for every site of each parity and
+/* Bytes to allocate for EACH packed link field (fat and long; the larger of
+ * the two for the compressed precisions) in precision `prec`, or 0 on bad
+ * arguments.  The packed form stores, for every site of each parity and
  * for each of the 8 directions +-mu, the matrix that multiplies the
  * neighbour: F_mu(n) for +mu and -F_mu(n-mu)^dag for -mu (Sec. 4 stores
  * forward and backward links at every site for locality), in 64-site tiles
@@ -125,7 +141,9 @@ size_t hisq_packed_link_bytes(const int dims[4], int prec);
 /* Pack canonical links (device, complex128, layout above) into the packed
  * form of `prec` at fat_out / long_out (device, hisq_packed_link_bytes()
  * each).  `hop` of the fat field is 1 and of the long field 3 (Sec. 3: one-
- * and three-link terms).  Asynchronous on `stream`. */
+ * and three-link terms).  Asynchronous on `stream`, except for HISQ_F64C and
+ * HISQ_F32C, which synchronise to report HISQ_EINVAL when a long link is not
+ * +-SU(3). */
 int hisq_pack_links(const void *fat_canon, const void *long_canon, const int dims[4], int prec, void *fat_out,
                     void *long_out, void *stream);
 
@@ -172,9 +190,9 @@ int hisq_dslash_shape(const int dims[4], int prec, int shape);
 size_t hisq_workspace_bytes(const char *solver, const int dims[4], int nrhs, int mode, int channels);
 
 /* Solve A(mass) x = b on the even sites to |b - A x| <= tol |b| (Sec. 3 CG;
- * Sec. 4 even-odd).  fat/lng: HISQ_F64 packed links.  fat_lo/lng_lo:
- * HISQ_F32, HISQ_F16S or HISQ_I16S packed links matching the mode, NULL for
- * PLAIN_F64.  b, x: complex128 Vh x 3; x holds x0 on entry and the solution
+ * Sec. 4 even-odd).  fat/lng: HISQ_F64 packed links (HISQ_F64C for the *C
+ * modes).  fat_lo/lng_lo: HISQ_F32, HISQ_F16S, HISQ_I16S or HISQ_F32C packed
+ * links matching the mode, NULL for the plain modes.  b, x: complex128 Vh x 3; x holds x0 on entry and the solution
  * on exit (also on HISQ_ENOCONV).  opts NULL = plain FP64 defaults.  stats
  * (may be NULL) is always written.  Returns when the solve has finished. */
 int cg_solve(double mass, double tol, const void *fat, const void *lng, const void *fat_lo, const void *lng_lo,
@@ -258,8 +276,9 @@ int net_adam_step(void *weights, const void *grad_w, void *m, void *v, long long
 /* Flexible CG (Notay 2000, one stored direction, Polak-Ribiere update)
  * preconditioned by the network, on A(mass) x = b to tol; plain FP64 CG from
  * the current x is the fallback when K is not positive on the residual, when
- * <p, A p> <= 0, or after 50 iterations without a new lowest residual
- * (stats.fallback_used says which).  fat/lng: HISQ_F64 packed links; fat32:
+ * <p, A p> <= 0, after 50 iterations without a new lowest residual, or when
+ * |r| has not halved over a window of 500 iterations (stats.fallback_used
+ * says which).  fat/lng: HISQ_F64 packed links; fat32:
  * HISQ_F32 packed fat links for the network.  Workspace from
  * hisq_workspace_bytes("fcg", dims, 1, 0, channels). */
 int fcg_solve(double mass, double tol, const void *fat, const void *lng, const void *fat32, const void *weights,

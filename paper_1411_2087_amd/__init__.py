@@ -20,8 +20,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhisq.so")
 
-HISQ_F64, HISQ_F32, HISQ_F16S, HISQ_I16S = 0, 1, 2, 3
+HISQ_F64, HISQ_F32, HISQ_F16S, HISQ_I16S, HISQ_F64C, HISQ_F32C = 0, 1, 2, 3, 4, 5
 HISQ_CG_PLAIN_F64, HISQ_CG_MIXED_F32, HISQ_CG_MIXED_F16S, HISQ_CG_MIXED_I16S = 0, 1, 2, 3
+HISQ_CG_PLAIN_F64C, HISQ_CG_MIXED_F32C = 4, 5
 HISQ_MULTI_RHS, HISQ_MULTI_SHIFT = 0, 1
 STATUS = {0: "HISQ_OK", -1: "HISQ_EINVAL", -2: "HISQ_EDIMS", -3: "HISQ_EALIAS", -4: "HISQ_EHIP",
           -5: "HISQ_ENOCONV", -6: "HISQ_EBREAKDOWN", -7: "HISQ_EWORKSPACE"}
@@ -30,7 +31,8 @@ STATUS = {0: "HISQ_OK", -1: "HISQ_EINVAL", -2: "HISQ_EDIMS", -3: "HISQ_EALIAS", 
 # one output write; Sec. 3 counts 16 matrices and 16 vectors per site), and
 # the paper's flop count.
 DSLASH_BYTES_PER_SITE = {HISQ_F64: 16 * 144 + 48 + 48, HISQ_F32: 16 * 72 + 24 + 24, HISQ_F16S: 16 * 40 + 24 + 24,
-                         HISQ_I16S: 16 * 40 + 24 + 24}
+                         HISQ_I16S: 16 * 40 + 24 + 24, HISQ_F64C: 8 * 144 + 8 * 96 + 48 + 48,
+                         HISQ_F32C: 8 * 72 + 8 * 48 + 24 + 24}
 DSLASH_FLOPS_PER_SITE = 1146
 
 

@@ -319,7 +319,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_cg_Ap(Geom g, const char *
 }
 
 // r = b - (m4 x - D_eo t) in FP64 ; optional copies ; partials of |r|^2
-template <int NT>
+template <class PH, int NT>
 __global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_resid(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
                                               const double2 *__restrict__ t, const double2 *__restrict__ x,
                                               const double2 *__restrict__ b, double2 *__restrict__ r,
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_resid(Geom g, const char *
     if (tile < g.ntiles) {
         const int hc = h < g.Vh ? h : g.Vh - 1;
         double acc[6];
-        dslash_site<PF64>(g, fat, lng, t, 0, tile, lane, hc, acc);
+        dslash_site<PH>(g, fat, lng, t, 0, tile, lane, hc, acc);
         if (h < g.Vh) {
             const double m = st->m4;
 #pragma unroll
@@ -378,7 +378,7 @@ size_t cg_workspace_bytes(const Geom &g, int mode)
 {
     const size_t v64 = align256((size_t)g.Vh * 3 * 16), v32 = align256((size_t)g.Vh * 3 * 8);
     size_t bytes = align256(sizeof(CGState)) + align256(cg_partials_count(g) * sizeof(double)) + 2 * SKEW;
-    if (mode == HISQ_CG_PLAIN_F64) bytes += 4 * (v64 + SKEW);               // r p Ap t
+    if (mode == HISQ_CG_PLAIN_F64 || mode == HISQ_CG_PLAIN_F64C) bytes += 4 * (v64 + SKEW);  // r p Ap t
     else bytes += 2 * (v64 + SKEW) + 5 * (v32 + SKEW);                      // r64 t64 | xs rs ps Aps ts
     return bytes;
 }
@@ -498,10 +498,11 @@ struct Launch {
         fin(q, nbl, mode, GATE_ALWAYS);
     }
     // r = b - (m4 x - D_eo t) [+ copies], |r|^2 -> mode; t must hold D_oe x
+    template <class PH>
     void resid(hipStream_t q, const void *fat, const void *lng, const double2 *t, const void *x, const void *b,
                double2 *r, double2 *p, float2 *rs, float2 *ps, int mode, int gate) const
     {
-        hipLaunchKernelGGL((k_resid<CG_NT>), gd, dim3(CG_NT), 0, q, g, (const char *)fat, (const char *)lng, t,
+        hipLaunchKernelGGL((k_resid<PH, CG_NT>), gd, dim3(CG_NT), 0, q, g, (const char *)fat, (const char *)lng, t,
                            (const double2 *)x, (const double2 *)b, r, p, rs, ps, nbd, part, (const CGState *)st, gate);
         fin(q, nbd, mode, gate);
     }
@@ -547,8 +548,9 @@ static int zero_source_exit(void *x, size_t v64, hipStream_t s, hisq_cg_stats &s
     return HISQ_OK;
 }
 
-int cg_plain_f64(double mass, double tol, const void *fat, const void *lng, const void *b, void *x, const Geom &g,
-                 const hisq_cg_opts &o, void *ws, size_t ws_bytes, hisq_cg_stats &stats, hipStream_t s)
+template <class PH>
+int cg_plain(double mass, double tol, const void *fat, const void *lng, const void *b, void *x, const Geom &g,
+             const hisq_cg_opts &o, void *ws, size_t ws_bytes, hisq_cg_stats &stats, hipStream_t s)
 {
     Carver c{ (char *)ws, ws_bytes };
     const size_t v64 = (size_t)g.Vh * 3 * 16;
@@ -565,17 +567,17 @@ int cg_plain_f64(double mass, double tol, const void *fat, const void *lng, cons
     HISQ_HIP(hipMemsetAsync(st, 0, sizeof(CGState), s));
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, tol * tol, 0.0, 4.0 * mass * mass);
     L.norm2(s, (const double2 *)b, FIN_BB);
-    HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t, 1, s));  // r = p = b - A x0
-    L.resid(s, fat, lng, t, x, b, r, p, nullptr, nullptr, FIN_INIT_PLAIN, GATE_ALWAYS);
+    HISQ_HIP(launch_dslash<PH>(g, fat, lng, x, t, 1, s));  // r = p = b - A x0
+    L.template resid<PH>(s, fat, lng, t, x, b, r, p, nullptr, nullptr, FIN_INIT_PLAIN, GATE_ALWAYS);
     HISQ_HIP(hipGetLastError());
     int rc = read_state(hs, st, s);
     if (rc) return rc;
     if (hs->bb == 0.0) return zero_source_exit(x, v64, s, stats, t0);
 
     auto iter = [&](hipStream_t q) -> hipError_t {
-        hipError_t e = launch_dslash<PF64>(g, fat, lng, p, t, 1, q, &st->flags, GATE_NOT_DONE);
+        hipError_t e = launch_dslash<PH>(g, fat, lng, p, t, 1, q, &st->flags, GATE_NOT_DONE);
         if (e != hipSuccess) return e;
-        L.ap<PF64>(q, fat, lng, t, p, ap);
+        L.ap<PH>(q, fat, lng, t, p, ap);
         L.update<double2>(q, (double2 *)x, r, p, ap, FIN_UPD_PLAIN);
         L.pupd<double2>(q, p, r);
         return hipGetLastError();
@@ -590,15 +592,15 @@ int cg_plain_f64(double mass, double tol, const void *fat, const void *lng, cons
         }
         if (hs->flags.done == CG_BREAKDOWN) { status = HISQ_EBREAKDOWN; break; }
         // true residual r = b - A x in FP64
-        HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t, 1, s));
-        L.resid(s, fat, lng, t, x, b, r, nullptr, nullptr, nullptr, FIN_TRUE, GATE_ALWAYS);
+        HISQ_HIP(launch_dslash<PH>(g, fat, lng, x, t, 1, s));
+        L.template resid<PH>(s, fat, lng, t, x, b, r, nullptr, nullptr, nullptr, FIN_TRUE, GATE_ALWAYS);
         HISQ_HIP(hipGetLastError());
         rc = read_state(hs, st, s);
         if (rc) return rc;
         if (hs->rr_true <= hs->stop2) { status = HISQ_OK; break; }
         if (hs->iter >= o.max_iter || restarts >= 3) { status = HISQ_ENOCONV; break; }
         ++restarts;  // restart from x: r = p = b - A x (t still holds D_oe x)
-        L.resid(s, fat, lng, t, x, b, r, p, nullptr, nullptr, FIN_INIT_PLAIN, GATE_ALWAYS);
+        L.template resid<PH>(s, fat, lng, t, x, b, r, p, nullptr, nullptr, FIN_INIT_PLAIN, GATE_ALWAYS);
         HISQ_HIP(hipGetLastError());
         rc = read_state(hs, st, s);
         if (rc) return rc;
@@ -609,7 +611,13 @@ int cg_plain_f64(double mass, double tol, const void *fat, const void *lng, cons
     return HISQ_OK;
 }
 
-template <class PS>
+int cg_plain_f64(double mass, double tol, const void *fat, const void *lng, const void *b, void *x, const Geom &g,
+                 const hisq_cg_opts &o, void *ws, size_t ws_bytes, hisq_cg_stats &stats, hipStream_t s)
+{
+    return cg_plain<PF64>(mass, tol, fat, lng, b, x, g, o, ws, ws_bytes, stats, s);
+}
+
+template <class PH, class PS>
 int cg_mixed(double mass, double tol, const void *fat, const void *lng, const void *fat_lo, const void *lng_lo,
              const void *b, void *x, const Geom &g, const hisq_cg_opts &o, void *ws, size_t ws_bytes,
              hisq_cg_stats &stats, hipStream_t s)
@@ -632,8 +640,8 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
     HISQ_HIP(hipMemsetAsync(xs, 0, v32, s));
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, tol * tol, delta * delta, 4.0 * mass * mass);
     L.norm2(s, (const double2 *)b, FIN_BB);
-    HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t64, 1, s));
-    L.resid(s, fat, lng, t64, x, b, r64, nullptr, rs, ps, FIN_INIT_MIXED, GATE_ALWAYS);
+    HISQ_HIP(launch_dslash<PH>(g, fat, lng, x, t64, 1, s));
+    L.template resid<PH>(s, fat, lng, t64, x, b, r64, nullptr, rs, ps, FIN_INIT_MIXED, GATE_ALWAYS);
     HISQ_HIP(hipGetLastError());
     int rc = read_state(hs, st, s);
     if (rc) return rc;
@@ -647,9 +655,9 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
         L.update<float2>(q, xs, rs, ps, aps, FIN_UPD_MIXED);
         // reliable update (kernels return at once unless it was triggered)
         hipLaunchKernelGGL(k_accum, gb, bb, 0, q, (double2 *)x, xs, L.n, (const CGState *)st);
-        e = launch_dslash<PF64>(g, fat, lng, x, t64, 1, q, &st->flags, GATE_RELIABLE);
+        e = launch_dslash<PH>(g, fat, lng, x, t64, 1, q, &st->flags, GATE_RELIABLE);
         if (e != hipSuccess) return e;
-        L.resid(q, fat, lng, t64, x, b, r64, nullptr, rs, nullptr, FIN_RELIABLE, GATE_RELIABLE);
+        L.template resid<PH>(q, fat, lng, t64, x, b, r64, nullptr, rs, nullptr, FIN_RELIABLE, GATE_RELIABLE);
         L.pupd<float2>(q, ps, rs);
         return hipGetLastError();
     };
@@ -663,8 +671,8 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
         // out of iterations: fold the inner solution in and measure the true residual
         hipLaunchKernelGGL(k_force_reliable, dim3(1), dim3(1), 0, s, st);
         hipLaunchKernelGGL(k_accum, gb, bb, 0, s, (double2 *)x, xs, L.n, (const CGState *)st);
-        HISQ_HIP(launch_dslash<PF64>(g, fat, lng, x, t64, 1, s));
-        L.resid(s, fat, lng, t64, x, b, r64, nullptr, rs, nullptr, FIN_RELIABLE, GATE_ALWAYS);
+        HISQ_HIP(launch_dslash<PH>(g, fat, lng, x, t64, 1, s));
+        L.template resid<PH>(s, fat, lng, t64, x, b, r64, nullptr, rs, nullptr, FIN_RELIABLE, GATE_ALWAYS);
         HISQ_HIP(hipGetLastError());
         rc = read_state(hs, st, s);
         if (rc) return rc;
@@ -740,7 +748,7 @@ extern "C" size_t hisq_workspace_bytes(const char *solver, const int dims[4], in
     Geom g;
     if (!solver || make_geom(dims, g)) return 0;
     if (!std::strcmp(solver, "cg")) {
-        if (mode < HISQ_CG_PLAIN_F64 || mode > HISQ_CG_MIXED_I16S) return 0;
+        if (mode < HISQ_CG_PLAIN_F64 || mode > HISQ_CG_MIXED_F32C) return 0;
         return cg_workspace_bytes(g, mode);
     }
     if (!std::strcmp(solver, "cg_multi")) return cg_multi_workspace_bytes(g, nrhs, mode);
@@ -766,9 +774,9 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
     if (!fat || !lng || !b || !x) return st.status = fail(HISQ_EINVAL, "cg_solve: NULL pointer");
     if (b == x) return st.status = fail(HISQ_EALIAS, "cg_solve: b and x alias");
     if (!(tol > 0) || !(mass >= 0)) return st.status = fail(HISQ_EINVAL, "cg_solve: need tol > 0 and mass >= 0");
-    if (o.mode != HISQ_CG_PLAIN_F64 && (!fat_lo || !lng_lo))
+    if (o.mode != HISQ_CG_PLAIN_F64 && o.mode != HISQ_CG_PLAIN_F64C && (!fat_lo || !lng_lo))
         return st.status = fail(HISQ_EINVAL, "cg_solve: mixed mode needs fat_lo and lng_lo");
-    if (o.mode < HISQ_CG_PLAIN_F64 || o.mode > HISQ_CG_MIXED_I16S)
+    if (o.mode < HISQ_CG_PLAIN_F64 || o.mode > HISQ_CG_MIXED_F32C)
         return st.status = fail(HISQ_EINVAL, "cg_solve: unknown mode");
     if (!workspace || ws_bytes < cg_workspace_bytes(g, o.mode))
         return st.status = fail(HISQ_EWORKSPACE, "cg_solve: workspace NULL or smaller than hisq_workspace_bytes()");
@@ -778,14 +786,19 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
         if (e != hipSuccess) return st.status = hip_fail(e, "cg_solve: pending work failed");
     }
     switch (o.mode) {
-    case HISQ_CG_PLAIN_F64: rc = cg_plain_f64(mass, tol, fat, lng, b, x, g, o, workspace, ws_bytes, st, s); break;
+    case HISQ_CG_PLAIN_F64: rc = cg_plain<PF64>(mass, tol, fat, lng, b, x, g, o, workspace, ws_bytes, st, s); break;
+    case HISQ_CG_PLAIN_F64C: rc = cg_plain<PF64C>(mass, tol, fat, lng, b, x, g, o, workspace, ws_bytes, st, s); break;
     case HISQ_CG_MIXED_F32:
-        rc = cg_mixed<PF32>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
+        rc = cg_mixed<PF64, PF32>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
         break;
     case HISQ_CG_MIXED_F16S:
-        rc = cg_mixed<PF16S>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
+        rc = cg_mixed<PF64, PF16S>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
         break;
-    default: rc = cg_mixed<PI16S>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
+    case HISQ_CG_MIXED_I16S:
+        rc = cg_mixed<PF64, PI16S>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
+        break;
+    default:
+        rc = cg_mixed<PF64C, PF32C>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
     }
     st.status = rc;
     return rc;
@@ -794,7 +807,7 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
 extern "C" int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *stream)
 {
     if (!x || !y || !out_host || n < 0) return fail(HISQ_EINVAL, "hisq_dot: bad argument");
-    if (prec < HISQ_F64 || prec > HISQ_I16S) return fail(HISQ_EINVAL, "hisq_dot: bad precision");
+    if (prec < HISQ_F64 || prec > HISQ_F32C) return fail(HISQ_EINVAL, "hisq_dot: bad precision");
     // small scratch (partials and the result), allocated once per thread
     static thread_local char *scratch = nullptr;
     const size_t part_bytes = 2 * sizeof(double) * BLAS_MAX_BLOCKS;
@@ -807,7 +820,7 @@ extern "C" int hisq_dot(const void *x, const void *y, long long n, int prec, dou
         return HISQ_OK;
     }
     const int nb = (int)std::min<long long>((n + 255) / 256, BLAS_MAX_BLOCKS);
-    if (prec == HISQ_F64)
+    if (prec == HISQ_F64 || prec == HISQ_F64C)
         hipLaunchKernelGGL((k_dot2<double2>), dim3(nb), dim3(BL_NT), 0, s, (const double2 *)x, (const double2 *)y, n,
                            part);
     else

@@ -120,6 +120,8 @@ HISQ_INST(PF64)
 HISQ_INST(PF32)
 HISQ_INST(PF16S)
 HISQ_INST(PI16S)
+HISQ_INST(PF64C)
+HISQ_INST(PF32C)
 #undef HISQ_INST
 
 constexpr int AXMY_NT = 256;
@@ -157,6 +159,8 @@ extern "C" int dslash_apply(const void *fat, const void *lng, const void *src, v
     case HISQ_F32: e = launch_dslash<PF32>(g, fat, lng, src, dst, parity, s); break;
     case HISQ_F16S: e = launch_dslash<PF16S>(g, fat, lng, src, dst, parity, s); break;
     case HISQ_I16S: e = launch_dslash<PI16S>(g, fat, lng, src, dst, parity, s); break;
+    case HISQ_F64C: e = launch_dslash<PF64C>(g, fat, lng, src, dst, parity, s); break;
+    case HISQ_F32C: e = launch_dslash<PF32C>(g, fat, lng, src, dst, parity, s); break;
     default: return fail(HISQ_EINVAL, "dslash_apply: unknown precision");
     }
     if (e != hipSuccess) return hip_fail(e, "dslash_apply launch");
@@ -178,6 +182,8 @@ extern "C" int hisq_apply_A(double mass, const void *fat, const void *lng, const
     case HISQ_F32: e = launch_apply_A<PF32>(g, mass, fat, lng, x, y, tmp, s); break;
     case HISQ_F16S: e = launch_apply_A<PF16S>(g, mass, fat, lng, x, y, tmp, s); break;
     case HISQ_I16S: e = launch_apply_A<PI16S>(g, mass, fat, lng, x, y, tmp, s); break;
+    case HISQ_F64C: e = launch_apply_A<PF64C>(g, mass, fat, lng, x, y, tmp, s); break;
+    case HISQ_F32C: e = launch_apply_A<PF32C>(g, mass, fat, lng, x, y, tmp, s); break;
     default: return fail(HISQ_EINVAL, "hisq_apply_A: unknown precision");
     }
     if (e != hipSuccess) return hip_fail(e, "hisq_apply_A launch");

@@ -46,19 +46,25 @@ __device__ __forceinline__ void dslash_site(const Geom &g, const char *__restric
 {
     int x, y, z, t;
     site_coords(g, h, parity, x, y, z, t);
-    const size_t tile_off = ((size_t)parity * g.ntiles + tile) * 8 * P::block_bytes;
-    const char *fb = fat + tile_off;
-    const char *lb = lng + tile_off;
+    const size_t tix = (size_t)parity * g.ntiles + tile;
+    const char *fb = fat + tix * P::Fat::tile_bytes;
+    const char *lb = lng + tix * P::Long::tile_bytes;
 #pragma unroll
     for (int i = 0; i < 6; ++i) acc[i] = 0;
+    // one-link terms, then three-link terms (separate loops keep one loader live)
 #pragma unroll UNR
-    for (int d = 0; d < 16; ++d) {
-        const int mu = d & 3;
-        const bool is_long = d >= 8;
-        const int k = (is_long ? 3 : 1) * (((d >> 2) & 1) ? -1 : 1);
-        const int nh = nbr_h(g, h, x, y, z, t, mu, k);
+    for (int d = 0; d < 8; ++d) {
+        const int nh = nbr_h(g, h, x, y, z, t, d & 3, (d >> 2) ? -1 : 1);
         typename P::real m[18];
-        P::load((is_long ? lb : fb) + (size_t)(d & 7) * P::block_bytes, lane, m);
+        P::Fat::load_dir(fb, d, lane, m);
+        const typename P::cvec *s = src + (size_t)nh * 3;
+        cmac<P>(acc, m, s[0], s[1], s[2]);
+    }
+#pragma unroll UNR
+    for (int d = 0; d < 8; ++d) {
+        const int nh = nbr_h(g, h, x, y, z, t, d & 3, (d >> 2) ? -3 : 3);
+        typename P::real m[18];
+        P::Long::load_dir(lb, d, lane, m);
         const typename P::cvec *s = src + (size_t)nh * 3;
         cmac<P>(acc, m, s[0], s[1], s[2]);
     }

@@ -37,8 +37,13 @@ struct FState {
     int fallback;       // 1: K not positive on r / A-product <= 0 ; 2: stall
     int since_best;
     int stall;
+    int window_start;   // iteration at which the current progress window opened
     double m4, bb, stop2, rr, best_rr, zr, zr_old, zrp, pAp, alpha, beta, rr_true;
+    double rr_window;   // |r|^2 when the window opened
 };
+// progress rule: every FCG_WINDOW iterations |r| must have halved (|r|^2 / 4),
+// otherwise the preconditioner is not paying for itself and plain CG takes over
+constexpr int FCG_WINDOW = 500;
 
 constexpr int F_NT = 256;
 constexpr int F_U = 4;
@@ -215,7 +220,8 @@ __global__ __launch_bounds__(256) void k_f_fin(const double *__restrict__ partia
     switch (mode) {
     case FF_BB: st->bb = a; st->stop2 = st->stop2 * a; break;  // stop2 holds tol^2 until here
     case FF_INIT:
-        st->rr = st->best_rr = st->rr_true = a;
+        st->rr = st->best_rr = st->rr_true = st->rr_window = a;
+        st->window_start = 0;
         st->flags.done = a <= st->stop2;
         break;
     case FF_Z:
@@ -236,7 +242,12 @@ __global__ __launch_bounds__(256) void k_f_fin(const double *__restrict__ partia
         if (!isfinite(a)) { st->fallback = 1; st->flags.done = 1; break; }
         if (a <= st->stop2) { st->flags.done = 1; break; }
         if (a < st->best_rr) { st->best_rr = a; st->since_best = 0; }
-        else if (++st->since_best >= st->stall) { st->fallback = 2; st->flags.done = 1; }
+        else if (++st->since_best >= st->stall) { st->fallback = 2; st->flags.done = 1; break; }
+        if (st->iter - st->window_start >= FCG_WINDOW) {
+            if (a > 0.25 * st->rr_window) { st->fallback = 2; st->flags.done = 1; break; }
+            st->rr_window = a;
+            st->window_start = st->iter;
+        }
         break;
     case FF_TRUE: st->rr_true = a; break;
     }
@@ -247,7 +258,8 @@ __global__ void k_f_init(FState *st, double tol2, double m4, int stall)
     if (threadIdx.x || blockIdx.x) return;
     st->flags.done = 0;
     st->flags.reliable = 0;
-    st->iter = st->fallback = st->since_best = 0;
+    st->iter = st->fallback = st->since_best = st->window_start = 0;
+    st->rr_window = 0.0;
     st->stall = stall;
     st->m4 = m4;
     st->stop2 = tol2;

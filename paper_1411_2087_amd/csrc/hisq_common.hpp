@@ -210,6 +210,13 @@ struct PF64 {
     using cvec = double2;
     static constexpr int prec = HISQ_F64;
     static constexpr size_t block_bytes = 9 * TILE * 16;
+    using Fat = PF64;
+    using Long = PF64;
+    static constexpr size_t tile_bytes = 8 * block_bytes;  // the 8 directions of one 64-site tile
+    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, real m[18])
+    {
+        load(tile + (size_t)d * block_bytes, lane, m);
+    }
     __device__ __forceinline__ static void load(const char *blk, int lane, double m[18])
     {
         const double2 *p = reinterpret_cast<const double2 *>(blk) + lane;
@@ -227,6 +234,13 @@ struct PF32 {
     using cvec = float2;
     static constexpr int prec = HISQ_F32;
     static constexpr size_t block_bytes = TILE * 72;
+    using Fat = PF32;
+    using Long = PF32;
+    static constexpr size_t tile_bytes = 8 * block_bytes;  // the 8 directions of one 64-site tile
+    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, real m[18])
+    {
+        load(tile + (size_t)d * block_bytes, lane, m);
+    }
     __device__ __forceinline__ static void load(const char *blk, int lane, float m[18])
     {
         const float4 *p4 = reinterpret_cast<const float4 *>(blk) + lane;
@@ -247,6 +261,13 @@ struct PF16S {
     using cvec = float2;
     static constexpr int prec = HISQ_F16S;
     static constexpr size_t block_bytes = TILE * 40;
+    using Fat = PF16S;
+    using Long = PF16S;
+    static constexpr size_t tile_bytes = 8 * block_bytes;  // the 8 directions of one 64-site tile
+    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, real m[18])
+    {
+        load(tile + (size_t)d * block_bytes, lane, m);
+    }
     __device__ __forceinline__ static void load(const char *blk, int lane, float m[18])
     {
         const uint4 *p4 = reinterpret_cast<const uint4 *>(blk) + lane;
@@ -274,6 +295,13 @@ struct PI16S {
     using cvec = float2;
     static constexpr int prec = HISQ_I16S;
     static constexpr size_t block_bytes = TILE * 40;
+    using Fat = PI16S;
+    using Long = PI16S;
+    static constexpr size_t tile_bytes = 8 * block_bytes;  // the 8 directions of one 64-site tile
+    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, real m[18])
+    {
+        load(tile + (size_t)d * block_bytes, lane, m);
+    }
     __device__ __forceinline__ static void load(const char *blk, int lane, float m[18])
     {
         const uint4 *p4 = reinterpret_cast<const uint4 *>(blk) + lane;
@@ -289,6 +317,87 @@ struct PI16S {
             m[2 * e + 1] = (float)(short)(w[e] >> 16) * s;
         }
     }
+};
+
+// Two-row form of a long (three-link) matrix that is +-SU(3) (Sec. 4: store two
+// rows, rebuild the third; the staggered phase and boundary sign enter the
+// rebuild): rows 0 and 1 are stored, row 2 = c conj(row0 x row1) with c = det
+// = +-1 kept as one bit per lane in a 64-bit word per direction after the
+// tile's 8 direction blocks.
+__device__ __forceinline__ unsigned long long sign_word(const char *tile, size_t block_bytes, int d)
+{
+    return *reinterpret_cast<const unsigned long long *>(tile + 8 * block_bytes + 8 * (size_t)d);
+}
+
+template <class R>
+__device__ __forceinline__ void third_row(R m[18], R c)
+{
+    // r0 = m[0..5], r1 = m[6..11] (re, im pairs); x = r0 x r1 ; row2 = c * conj(x)
+    const R a0r = m[0], a0i = m[1], a1r = m[2], a1i = m[3], a2r = m[4], a2i = m[5];
+    const R b0r = m[6], b0i = m[7], b1r = m[8], b1i = m[9], b2r = m[10], b2i = m[11];
+    const R x0r = (a1r * b2r - a1i * b2i) - (a2r * b1r - a2i * b1i);
+    const R x0i = (a1r * b2i + a1i * b2r) - (a2r * b1i + a2i * b1r);
+    const R x1r = (a2r * b0r - a2i * b0i) - (a0r * b2r - a0i * b2i);
+    const R x1i = (a2r * b0i + a2i * b0r) - (a0r * b2i + a0i * b2r);
+    const R x2r = (a0r * b1r - a0i * b1i) - (a1r * b0r - a1i * b0i);
+    const R x2i = (a0r * b1i + a0i * b1r) - (a1r * b0i + a1i * b0r);
+    m[12] = c * x0r; m[13] = -c * x0i;
+    m[14] = c * x1r; m[15] = -c * x1i;
+    m[16] = c * x2r; m[17] = -c * x2i;
+}
+
+struct PF64R {
+    using real = double;
+    using cvec = double2;
+    static constexpr size_t block_bytes = 6 * TILE * 16;
+    static constexpr size_t tile_bytes = 8 * block_bytes + 64;
+    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, double m[18])
+    {
+        const double2 *p = reinterpret_cast<const double2 *>(tile + (size_t)d * block_bytes) + lane;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            double2 v = ntload(p + e * TILE);
+            m[2 * e] = v.x;
+            m[2 * e + 1] = v.y;
+        }
+        const double c = ((sign_word(tile, block_bytes, d) >> lane) & 1ull) ? -1.0 : 1.0;
+        third_row<double>(m, c);
+    }
+};
+
+struct PF32R {
+    using real = float;
+    using cvec = float2;
+    static constexpr size_t block_bytes = 3 * TILE * 16;
+    static constexpr size_t tile_bytes = 8 * block_bytes + 64;
+    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, float m[18])
+    {
+        const float4 *p = reinterpret_cast<const float4 *>(tile + (size_t)d * block_bytes) + lane;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            float4 v = ntload(p + q * TILE);
+            m[4 * q] = v.x; m[4 * q + 1] = v.y; m[4 * q + 2] = v.z; m[4 * q + 3] = v.w;
+        }
+        const float c = ((sign_word(tile, block_bytes, d) >> lane) & 1ull) ? -1.0f : 1.0f;
+        third_row<float>(m, c);
+    }
+};
+
+// FP64 / FP32 with two-row long links (the fat field stays full: smeared
+// links are not SU(3)).
+struct PF64C {
+    using real = double;
+    using cvec = double2;
+    static constexpr int prec = HISQ_F64C;
+    using Fat = PF64;
+    using Long = PF64R;
+};
+struct PF32C {
+    using real = float;
+    using cvec = float2;
+    static constexpr int prec = HISQ_F32C;
+    using Fat = PF32;
+    using Long = PF32R;
 };
 
 }  // namespace hisq

@@ -1,18 +1,21 @@
 """Training of the gauge-covariant preconditioner on the GPU.
 
 Sequences the library's kernels (net_forward, net_loss, net_backward,
-net_adam_step) over batches of (b, x) pairs with A x = b produced by the
-library's own CG; the loss is mean_i |K(b_i) - x_i|^2 / |x_i|^2.  Every
-arithmetic step runs in libhisq; this module only orders the calls and owns
-the device buffers.
+net_adam_step, hisq_apply_A, hisq_dot) over batches of (b, x) pairs with
+A x = b produced by the library's own CG.  Two objectives:
+  "error"    mean_i |K(b_i) - x_i|^2 / |x_i|^2         (fits K to A^-1 on the pairs)
+  "residual" mean_i |A K(b_i) - b_i|^2 / |b_i|^2       (approximate-inverse objective;
+             its gradient with respect to K(b_i) is A applied to the residual, A Hermitian)
+Every arithmetic step runs in libhisq; this module only orders the calls and
+owns the device buffers.
 """
 from __future__ import annotations
 
 import numpy as np
 import torch
 
-from . import (HISQ_F32, HISQ_F64, HISQ_MULTI_RHS, CGOpts, cg_solve_multi, net_act_bytes, net_adam_step,
-               net_backward, net_backward_ws_bytes, net_forward, net_loss, net_weight_count)
+from . import (HISQ_F32, HISQ_F64, HISQ_MULTI_RHS, CGOpts, cg_solve_multi, hisq_apply_A, hisq_dot, net_act_bytes,
+               net_adam_step, net_backward, net_backward_ws_bytes, net_forward, net_loss, net_weight_count)
 from .fields import Links, workspace
 
 LAYER_SHAPES = lambda C: [(C, 1), (C, C), (C, C), (1, C)]  # (C_out, C_in) per layer
@@ -75,8 +78,13 @@ def make_pairs(dims, mass, links64: Links, links32: Links, sources: np.ndarray, 
 class Trainer:
     """Adam on the network weights; buffers sized for `batch` sources."""
 
-    def __init__(self, dims, C, fat32, weights: np.ndarray, batch=16, device="cuda"):
+    def __init__(self, dims, C, fat32, weights: np.ndarray, batch=16, device="cuda", objective="error",
+                 links32: Links | None = None, mass: float | None = None):
         self.dims, self.C, self.fat32, self.batch = tuple(dims), C, fat32, batch
+        assert objective in ("error", "residual")
+        self.objective, self.links32, self.mass = objective, links32, mass
+        if objective == "residual":
+            assert links32 is not None and mass is not None
         n = net_weight_count(C)
         assert weights.size == n
         self.n = n
@@ -90,7 +98,14 @@ class Trainer:
         self.lws = torch.empty(2048 * (batch + 1) + 4096, dtype=torch.uint8, device=device)
         self.y = torch.empty((batch, vh, 3), dtype=torch.complex64, device=device)
         self.gy = torch.empty_like(self.y)
+        self.ay = torch.empty_like(self.y)
+        self.g1 = torch.empty_like(self.y)
+        self.tmp = torch.empty((vh, 3), dtype=torch.complex64, device=device)
         self.step_count = 0
+
+    def _apply_A(self, src, dst):
+        for i in range(src.shape[0]):
+            hisq_apply_A(self.mass, self.links32.fat, self.links32.lng, src[i], dst[i], self.tmp, self.dims, HISQ_F32)
 
     def forward(self, b):
         k = b.shape[0]
@@ -98,15 +113,24 @@ class Trainer:
         return self.y[:k]
 
     def loss(self, b, x):
+        k = b.shape[0]
         y = self.forward(b)
-        return net_loss(y, x, b.shape[0], self.dims, None, self.lws)
+        if self.objective == "residual":
+            self._apply_A(y, self.ay[:k])
+            return net_loss(self.ay[:k], b, k, self.dims, None, self.lws)
+        return net_loss(y, x, k, self.dims, None, self.lws)
 
     def step(self, b, x, lr, sync=False):
         """One Adam step on a batch; returns the batch loss before the step if sync."""
         k = b.shape[0]
         assert k <= self.batch
         y = self.forward(b)
-        loss = net_loss(y, x, k, self.dims, self.gy[:k], self.lws, sync=sync)
+        if self.objective == "residual":
+            self._apply_A(y, self.ay[:k])
+            loss = net_loss(self.ay[:k], b, k, self.dims, self.g1[:k], self.lws, sync=sync)
+            self._apply_A(self.g1[:k], self.gy[:k])
+        else:
+            loss = net_loss(y, x, k, self.dims, self.gy[:k], self.lws, sync=sync)
         net_backward(self.fat32, self.w, self.C, self.acts, self.gy[:k], self.gw, None, k, self.dims, self.ws)
         self.step_count += 1
         net_adam_step(self.w, self.gw, self.m, self.v, self.n, lr, self.step_count)
@@ -137,13 +161,26 @@ class Trainer:
         losses = []
         for s in range(0, b.shape[0], self.batch):
             bb, xx = b[s:s + self.batch].contiguous(), x[s:s + self.batch].contiguous()
-            y = self.forward(bb)
-            losses.append(net_loss(y, xx, bb.shape[0], self.dims, None, self.lws) * bb.shape[0])
+            losses.append(self.loss(bb, xx) * bb.shape[0])
         return float(np.sum(losses) / b.shape[0])
 
 
 def least_squares_scale(b, x):
-    """The scalar s minimising sum |s b - x|^2 (starting point of K = s 1)."""
-    num = torch.sum((b.conj() * x).real).item()
-    den = torch.sum((b.conj() * b).real).item()
+    """The scalar s minimising sum |s b - x|^2 (starting point of K = s 1 for the error objective)."""
+    n = b.shape[1] * 3
+    num = sum(hisq_dot(b[i], x[i], n, HISQ_F32).real for i in range(b.shape[0]))
+    den = sum(hisq_dot(b[i], b[i], n, HISQ_F32).real for i in range(b.shape[0]))
+    return num / den
+
+
+def residual_scale(b, links32: Links, mass, dims):
+    """The scalar s minimising sum |s A b - b|^2 (starting point for the residual objective)."""
+    n = b.shape[1] * 3
+    ab = torch.empty_like(b[0])
+    tmp = torch.empty_like(b[0])
+    num = den = 0.0
+    for i in range(b.shape[0]):
+        hisq_apply_A(mass, links32.fat, links32.lng, b[i].contiguous(), ab, tmp, dims, HISQ_F32)
+        num += hisq_dot(ab, b[i].contiguous(), n, HISQ_F32).real
+        den += hisq_dot(ab, ab, n, HISQ_F32).real
     return num / den

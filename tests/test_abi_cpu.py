@@ -56,7 +56,7 @@ def test_packed_sizes(dims):
     import paper_1411_2087_amd as hq
     vh = int(np.prod(dims)) // 2
     ntiles = -(-vh // 64)
-    for prec, per_matrix in ((0, 144), (1, 72), (2, 40)):
+    for prec, per_matrix in ((0, 144), (1, 72), (2, 40), (3, 40), (4, 144), (5, 72)):
         assert hq.hisq_packed_link_bytes(dims, prec) == 2 * ntiles * 64 * 8 * per_matrix
     assert hq.hisq_packed_link_bytes((4, 4, 4, 3), 0) == 0
 

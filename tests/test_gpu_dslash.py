@@ -32,13 +32,14 @@ def _dslash_gpu(hq, dims, fat, lng, src, parity, prec):
 
 
 @pytest.mark.parametrize("dims", DIMS)
-@pytest.mark.parametrize("prec,tol", [(0, TOL_F64), (1, TOL_F32), (2, TOL_F16S), (3, TOL_I16S)])
+@pytest.mark.parametrize("prec,tol", [(0, TOL_F64), (1, TOL_F32), (2, TOL_F16S), (3, TOL_I16S), (4, TOL_F64),
+                                      (5, TOL_F32)])
 def test_dslash_parity(hq, dims, prec, tol):
     fat, lng = fields(dims, 1000 + sum(dims))
     r = np.random.default_rng(7)
     for parity in (0, 1):
         src = synth.source(dims, 3000 + parity)
-        if prec != 0:
+        if prec not in (0, 4):
             # the FP32 kernel sees FP32 vectors; the oracle gets the same rounded values
             src = src.astype(np.complex64).astype(np.complex128)
         ref = oracle.dslash(dims, fat, lng, src, parity)
@@ -151,7 +152,7 @@ def test_all_launch_shapes_bitwise_identical(hq):
     dims = (6, 4, 4, 10)  # ragged last tile
     fat, lng = fields(dims)
     src = synth.source(dims, 9)
-    for prec in (0, 1, 2, 3):
+    for prec in (0, 1, 2, 3, 4, 5):
         L = hq.fields.Links.pack(fat, lng, dims, prec)
         dt = hq.fields.VEC_DTYPE[prec]
         s = torch.from_numpy(src).to(dt).cuda()
@@ -171,3 +172,24 @@ def test_all_launch_shapes_bitwise_identical(hq):
         best, us = hq.hisq_tune_dslash(L.fat, L.lng, s, torch.empty_like(s), dims, prec, reps=3)
         assert 0 <= best < n and len(us) == n and min(us) > 0
         assert hq.hisq_dslash_shape(dims, prec) == best
+
+
+def test_compressed_pack_rejects_non_su3_long_links(hq):
+    """Two-row packing needs +-SU(3) long links; the smeared fat field is not, and is refused."""
+    dims = (4, 4, 4, 6)
+    fat, lng = fields(dims)
+    with pytest.raises(hq.HisqError) as e:
+        hq.fields.Links.pack(fat, fat, dims, hq.HISQ_F64C)
+    assert e.value.code == -1
+    hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32C)  # Haar long links with folded signs pack
+
+
+def test_dslash_32_4_compressed(hq):
+    dims = (32, 32, 32, 32)
+    fat, lng = fields(dims, 1002)
+    src = synth.source(dims, 2129)
+    ref = oracle.dslash(dims, fat, lng, src, 1)
+    got = _dslash_gpu(hq, dims, fat, lng, src, 1, hq.HISQ_F64C)
+    err = oracle.componentwise_error(got, ref, oracle.dslash_scale(dims, fat, lng, src, 1))
+    say(f"dslash 32^4 f64 two-row long links: componentwise {err:.3e}")
+    assert err <= TOL_F64

@@ -1,0 +1,54 @@
+"""The full-size workloads: 48^3 x 96 mixed precision (FP32 / 16-bit links inside,
+FP64 reliable updates) with the FP64 Dslash checked at every site, certified by
+the CPU oracle."""
+import numpy as np
+import pytest
+
+from helpers import CG_TOL, TOL_F64, fields, oracle, say, synth
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (48, 48, 48, 96)
+MASS = 0.005
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    import paper_1411_2087_amd as hq
+    fat, lng = fields(DIMS, synth.gauge_seed(3))
+    b = synth.source(DIMS, synth.source_seed(3))
+    fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
+    L = {p: hq.fields.Links.pack(fd, ld, DIMS, p) for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S)}
+    del fd, ld
+    torch.cuda.synchronize()
+    return hq, fat, lng, b, L
+
+
+def test_dslash_f64_48x96(big):
+    import torch
+    hq, fat, lng, b, L = big
+    s = torch.from_numpy(b).cuda()
+    d = torch.full_like(s, float("nan"))
+    hq.dslash_apply(L[0].fat, L[0].lng, s, d, 1, DIMS, 0)
+    got = d.cpu().numpy()
+    ref = oracle.dslash(DIMS, fat, lng, b, 1)
+    err = oracle.componentwise_error(got, ref, oracle.dslash_scale(DIMS, fat, lng, b, 1))
+    say(f"dslash 48^3x96 f64 parity 1: componentwise {err:.2e}")
+    assert err <= TOL_F64
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_mixed_cg_48x96(big, mode):
+    import torch
+    hq, fat, lng, b, L = big
+    lo = L[hq.HISQ_F32] if mode == 1 else L[hq.HISQ_I16S]
+    bd = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(bd)
+    ws = hq.fields.workspace("cg", DIMS, 1, mode)
+    opts = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    st = hq.cg_solve(MASS, CG_TOL, L[0].fat, L[0].lng, lo.fat, lo.lng, bd, x, DIMS, opts, ws)
+    tr = oracle.true_residual(DIMS, MASS, fat, lng, b, x.cpu().numpy())
+    say(f"48^3x96 m={MASS} mode={mode}: iters={st['iters']} updates={st['reliable_updates']} "
+        f"time={st['time_s']:.2f}s gpu={st['true_resid']:.2e} oracle={tr:.2e}")
+    assert st["rc"] == 0 and tr <= CG_TOL
