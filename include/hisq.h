@@ -277,7 +277,7 @@ int net_adam_step(void *weights, const void *grad_w, void *m, void *v, long long
  * preconditioned by the network, on A(mass) x = b to tol; plain FP64 CG from
  * the current x is the fallback when K is not positive on the residual, when
  * <p, A p> <= 0, after 50 iterations without a new lowest residual, or when
- * |r| has not halved over a window of 500 iterations (stats.fallback_used
+ * |r| has not halved over a window of 200 iterations (stats.fallback_used
  * says which).  fat/lng: HISQ_F64 packed links; fat32:
  * HISQ_F32 packed fat links for the network.  Workspace from
  * hisq_workspace_bytes("fcg", dims, 1, 0, channels). */

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_dslash_axmy(Geom g, const 
 // in the same order, so their outputs are bitwise identical; the autotuner
 // picks one per (lattice, precision).
 const DslashShape DSLASH_SHAPES[N_DSLASH_SHAPES] = {
-    { 256, 8, 1 }, { 128, 8, 1 }, { 64, 8, 1 }, { 256, 1, 16 }, { 256, 4, 4 }, { 512, 8, 1 },
+    { 256, 8, 1 }, { 128, 8, 1 }, { 64, 8, 1 }, { 256, 1, 16 }, { 256, 4, 4 }, { 512, 8, 1 }, { 256, 6, 1 },
 };
 
 static inline int blocks_for(const Geom &g, int nt) { return (g.ntiles + nt / TILE - 1) / (nt / TILE); }
@@ -99,6 +99,7 @@ hipError_t launch_dslash_shape(int shape, const Geom &g, const void *fat, const 
     case 3: launch_shape<P, 256, 1, 16>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     case 4: launch_shape<P, 256, 4, 4>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     case 5: launch_shape<P, 512, 8, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 6: launch_shape<P, 256, 6, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     default: launch_shape<P, 256, 8, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     }
     return hipGetLastError();

@@ -91,7 +91,7 @@ struct DslashShape {
     int waves;   // minimum wavefronts per SIMD the compiler must allow
     int unroll;  // terms of the 16 unrolled together
 };
-constexpr int N_DSLASH_SHAPES = 6;
+constexpr int N_DSLASH_SHAPES = 7;
 extern const DslashShape DSLASH_SHAPES[N_DSLASH_SHAPES];
 int tuned_dslash_shape(const Geom &g, int prec);            // tune.cpp
 int tuned_choice(const char *kind, const Geom &g, int prec, int n, int fallback);

@@ -43,7 +43,7 @@ struct FState {
 };
 // progress rule: every FCG_WINDOW iterations |r| must have halved (|r|^2 / 4),
 // otherwise the preconditioner is not paying for itself and plain CG takes over
-constexpr int FCG_WINDOW = 500;
+constexpr int FCG_WINDOW = 200;
 
 constexpr int F_NT = 256;
 constexpr int F_U = 4;
