@@ -33,6 +33,47 @@ __device__ __forceinline__ void cmac(typename P::real acc[6], const typename P::
     }
 }
 
+// acc += M psi for a two-row matrix: rows 0 and 1 from m[0..11], row 2 =
+// c conj(row0 x row1) taken one entry at a time straight into acc[4..5], so
+// the third row is never held in registers.
+template <class P>
+__device__ __forceinline__ void cmac_two_row(typename P::real acc[6], const typename P::real m[12],
+                                             typename P::real c, typename P::cvec s0, typename P::cvec s1,
+                                             typename P::cvec s2)
+{
+    using R = typename P::real;
+    const R sr[3] = { s0.x, s1.x, s2.x };
+    const R si[3] = { s0.y, s1.y, s2.y };
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const R mr = m[2 * (3 * a + b)], mi = m[2 * (3 * a + b) + 1];
+            acc[2 * a] = fma(mr, sr[b], acc[2 * a]);
+            acc[2 * a] = fma(-mi, si[b], acc[2 * a]);
+            acc[2 * a + 1] = fma(mr, si[b], acc[2 * a + 1]);
+            acc[2 * a + 1] = fma(mi, sr[b], acc[2 * a + 1]);
+        }
+    }
+    R tr = 0, ti = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        const R ar1 = m[2 * j1], ai1 = m[2 * j1 + 1], ar2 = m[2 * j2], ai2 = m[2 * j2 + 1];
+        const R br1 = m[6 + 2 * j1], bi1 = m[6 + 2 * j1 + 1], br2 = m[6 + 2 * j2], bi2 = m[6 + 2 * j2 + 1];
+        // x_j = a_{j+1} b_{j+2} - a_{j+2} b_{j+1}
+        const R xr = (ar1 * br2 - ai1 * bi2) - (ar2 * br1 - ai2 * bi1);
+        const R xi = (ar1 * bi2 + ai1 * br2) - (ar2 * bi1 + ai2 * br1);
+        // conj(x_j) s_j
+        tr = fma(xr, sr[j], tr);
+        tr = fma(xi, si[j], tr);
+        ti = fma(xr, si[j], ti);
+        ti = fma(-xi, sr[j], ti);
+    }
+    acc[4] = fma(c, tr, acc[4]);
+    acc[5] = fma(c, ti, acc[5]);
+}
+
 // acc = (D src)(h) for the site h of parity `parity` (h < Vh), whose links
 // sit at lane `lane` of tile `tile`.  The 16 terms are taken UNR at a time:
 // a fully unrolled body lets the compiler hoist every load and run out of
@@ -63,10 +104,16 @@ __device__ __forceinline__ void dslash_site(const Geom &g, const char *__restric
 #pragma unroll UNR
     for (int d = 0; d < 8; ++d) {
         const int nh = nbr_h(g, h, x, y, z, t, d & 3, (d >> 2) ? -3 : 3);
-        typename P::real m[18];
-        P::Long::load_dir(lb, d, lane, m);
         const typename P::cvec *s = src + (size_t)nh * 3;
-        cmac<P>(acc, m, s[0], s[1], s[2]);
+        if constexpr (P::Long::two_row) {
+            typename P::real m[12];
+            const typename P::real c = P::Long::load_rows(lb, d, lane, m);
+            cmac_two_row<P>(acc, m, c, s[0], s[1], s[2]);
+        } else {
+            typename P::real m[18];
+            P::Long::load_dir(lb, d, lane, m);
+            cmac<P>(acc, m, s[0], s[1], s[2]);
+        }
     }
 }
 

@@ -206,6 +206,7 @@ __device__ __forceinline__ void ntstore(float2 v, float2 *p)
 //   F32 : 4 planes of float4 (entries 2q, 2q+1) + 1 plane of float2 (entry 8)   (4608 B)
 //   F16S: 2 planes of 4 x half2 (entries 0-3, 4-7) + 1 plane {half2 entry 8, float scale} (2560 B)
 struct PF64 {
+    static constexpr bool two_row = false;
     using real = double;
     using cvec = double2;
     static constexpr int prec = HISQ_F64;
@@ -230,6 +231,7 @@ struct PF64 {
 };
 
 struct PF32 {
+    static constexpr bool two_row = false;
     using real = float;
     using cvec = float2;
     static constexpr int prec = HISQ_F32;
@@ -257,6 +259,7 @@ struct PF32 {
 };
 
 struct PF16S {
+    static constexpr bool two_row = false;
     using real = float;
     using cvec = float2;
     static constexpr int prec = HISQ_F16S;
@@ -291,6 +294,7 @@ struct PF16S {
 // |q| <= 32767.  Same 40 B per matrix as PF16S, 16x finer steps for entries near
 // the scale (bounded values do not need an exponent).
 struct PI16S {
+    static constexpr bool two_row = false;
     using real = float;
     using cvec = float2;
     static constexpr int prec = HISQ_I16S;
@@ -350,8 +354,10 @@ struct PF64R {
     using real = double;
     using cvec = double2;
     static constexpr size_t block_bytes = 6 * TILE * 16;
+    static constexpr bool two_row = true;
     static constexpr size_t tile_bytes = 8 * block_bytes + 64;
-    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, double m[18])
+    // rows 0 and 1 into m[0..11]; returns the sign c of the third row
+    __device__ __forceinline__ static double load_rows(const char *tile, int d, int lane, double m[12])
     {
         const double2 *p = reinterpret_cast<const double2 *>(tile + (size_t)d * block_bytes) + lane;
 #pragma unroll
@@ -360,7 +366,11 @@ struct PF64R {
             m[2 * e] = v.x;
             m[2 * e + 1] = v.y;
         }
-        const double c = ((sign_word(tile, block_bytes, d) >> lane) & 1ull) ? -1.0 : 1.0;
+        return ((sign_word(tile, block_bytes, d) >> lane) & 1ull) ? -1.0 : 1.0;
+    }
+    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, double m[18])
+    {
+        const double c = load_rows(tile, d, lane, m);
         third_row<double>(m, c);
     }
 };
@@ -369,8 +379,9 @@ struct PF32R {
     using real = float;
     using cvec = float2;
     static constexpr size_t block_bytes = 3 * TILE * 16;
+    static constexpr bool two_row = true;
     static constexpr size_t tile_bytes = 8 * block_bytes + 64;
-    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, float m[18])
+    __device__ __forceinline__ static float load_rows(const char *tile, int d, int lane, float m[12])
     {
         const float4 *p = reinterpret_cast<const float4 *>(tile + (size_t)d * block_bytes) + lane;
 #pragma unroll
@@ -378,7 +389,11 @@ struct PF32R {
             float4 v = ntload(p + q * TILE);
             m[4 * q] = v.x; m[4 * q + 1] = v.y; m[4 * q + 2] = v.z; m[4 * q + 3] = v.w;
         }
-        const float c = ((sign_word(tile, block_bytes, d) >> lane) & 1ull) ? -1.0f : 1.0f;
+        return ((sign_word(tile, block_bytes, d) >> lane) & 1ull) ? -1.0f : 1.0f;
+    }
+    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, float m[18])
+    {
+        const float c = load_rows(tile, d, lane, m);
         third_row<float>(m, c);
     }
 };

@@ -79,10 +79,15 @@ void set_tuned_choice(const char *kind, const Geom &g, int prec, int n, int v)
     save_locked();
 }
 
+// Untuned default per precision: 6 waves per SIMD for the FP64 forms (the
+// two-row FP64 kernel needs more than 64 registers), 8 for the others.
+static int default_dslash_shape(int prec) { return (prec == HISQ_F64 || prec == HISQ_F64C) ? 6 : 0; }
+
 int tuned_dslash_shape(const Geom &g, int prec)
 {
-    int v = tuned_choice("dslash", g, prec, 1, 0);
-    return (v >= 0 && v < N_DSLASH_SHAPES) ? v : 0;
+    const int def = default_dslash_shape(prec);
+    int v = tuned_choice("dslash", g, prec, 1, def);
+    return (v >= 0 && v < N_DSLASH_SHAPES) ? v : def;
 }
 
 void set_tuned_dslash_shape(const Geom &g, int prec, int shape) { set_tuned_choice("dslash", g, prec, 1, shape); }

@@ -52,3 +52,33 @@ def test_mixed_cg_48x96(big, mode):
     say(f"48^3x96 m={MASS} mode={mode}: iters={st['iters']} updates={st['reliable_updates']} "
         f"time={st['time_s']:.2f}s gpu={st['true_resid']:.2e} oracle={tr:.2e}")
     assert st["rc"] == 0 and tr <= CG_TOL
+
+
+# The two lattices of the paper's single-coprocessor Dslash runs (Sec. 5,
+# Tables 1-2): every storage form compared with the oracle at every site.
+PAPER_GRIDS = [(32, 32, 32, 128), (32, 40, 24, 96)]
+
+
+@pytest.mark.parametrize("dims", PAPER_GRIDS, ids=lambda d: "x".join(map(str, d)))
+def test_dslash_paper_grids(dims):
+    import torch
+    import paper_1411_2087_amd as hq
+    from helpers import TOL_F16S, TOL_F32, TOL_I16S
+    fat, lng = fields(dims, synth.gauge_seed(6))
+    b = synth.source(dims, synth.source_seed(6))
+    ref = oracle.dslash(dims, fat, lng, b, 1)
+    scale = oracle.dslash_scale(dims, fat, lng, b, 1)
+    fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
+    tols = {hq.HISQ_F64: TOL_F64, hq.HISQ_F32: TOL_F32, hq.HISQ_F16S: TOL_F16S, hq.HISQ_I16S: TOL_I16S,
+            hq.HISQ_F64C: TOL_F64, hq.HISQ_F32C: TOL_F32}
+    for p, tol in tols.items():
+        L = hq.fields.Links.pack(fd, ld, dims, p)
+        dt = hq.fields.VEC_DTYPE[p]
+        s = torch.from_numpy(b).cuda().to(dt)
+        d = torch.full_like(s, float("nan"))
+        hq.dslash_apply(L.fat, L.lng, s, d, 1, dims, p)
+        got = d.cpu().numpy().astype(np.complex128)
+        err = oracle.componentwise_error(got, ref, scale)
+        say(f"dslash {'x'.join(map(str, dims))} prec={p}: componentwise {err:.2e}")
+        assert err <= tol
+        del L, s, d

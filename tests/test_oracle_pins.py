@@ -268,3 +268,44 @@ def test_pins_reject_planted_mistakes(dense44):
     want = freefield.dslash_plane_wave(dims, k, [1, 0.5j, -0.2], 0.7, 0.3)
     assert np.abs(Ds @ psi.reshape(-1) - want.reshape(-1)).max() > 1e-2
     assert np.abs(Dw @ psi.reshape(-1) - want.reshape(-1)).max() < 1e-13
+
+
+# ---------------------------------------------------------------- golden: the paper's printed counts
+def test_golden_paper_counts():
+    """The counts and sizes printed in Sec. 3-5 (tests/golden/paper_counts.json),
+    derived again here, and the byte model behind every GB/s the library reports."""
+    import json
+    import os
+    import paper_1411_2087_amd as hq
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_counts.json")) as f:
+        g = json.load(f)
+    d, s = g["dslash_per_site"], g["storage"]
+    # a 3x3 complex matrix times a 3-vector: 9 complex products (4 mul + 2 add each)
+    # and 6 complex accumulations (2 add each)
+    assert 9 * 4 == d["matvec_real_multiplies"] and 9 * 2 + 6 * 2 == d["matvec_real_adds"]
+    assert 3 * 2 == d["vector_add_real_adds"]
+    assert d["matrices"] * d["matvec_real_multiplies"] == d["real_multiplies"]
+    flops = d["matrices"] * (d["matvec_real_multiplies"] + d["matvec_real_adds"]) + \
+        d["vector_adds"] * d["vector_add_real_adds"]
+    assert flops == d["flops"] == oracle.FLOPS_PER_SITE
+    # the printed "576 real adds" is a slip: the adds are 16*30 + 15*6 = 570
+    assert flops - d["real_multiplies"] == 570
+    operands = d["matrices"] * 18 + d["vectors_in"] * 6
+    assert operands == d["input_operands"]
+    assert round(flops / operands, 2) == d["flops_per_operand"]
+    assert round(flops / (4 * operands), 2) == d["flops_per_byte_sp"]
+    assert int(100 * flops / (8 * operands)) / 100 == d["flops_per_byte_dp"]
+    assert 3 * 2 * 8 == s["dp_vector_bytes"] and 3 * s["dp_vector_bytes"] == s["dp_matrix_bytes"]
+    for nm, b in g["multishift"]["bytes_per_site"].items():
+        assert (36 + 2 * int(nm)) * s["dp_vector_bytes"] == b
+    # algorithmic bytes per output site: links once, the 16 neighbour vectors
+    # counted as one source read, one output write
+    vec, mat = s["dp_vector_bytes"], s["dp_matrix_bytes"]
+    two_row = mat * s["grows_compressed"] // s["grows_uncompressed"]
+    assert hq.DSLASH_BYTES_PER_SITE[hq.HISQ_F64] == d["matrices"] * mat + 2 * vec == 2400
+    assert hq.DSLASH_BYTES_PER_SITE[hq.HISQ_F32] == (d["matrices"] * mat + 2 * vec) // 2
+    assert hq.DSLASH_BYTES_PER_SITE[hq.HISQ_F64C] == 8 * mat + 8 * two_row + 2 * vec == 2016
+    assert hq.DSLASH_BYTES_PER_SITE[hq.HISQ_F32C] == (8 * mat + 8 * two_row + 2 * vec) // 2
+    # 16-bit links: 18 half-words + one FP32 scale per matrix, FP32 vectors
+    assert hq.DSLASH_BYTES_PER_SITE[hq.HISQ_F16S] == hq.DSLASH_BYTES_PER_SITE[hq.HISQ_I16S] == \
+        d["matrices"] * (18 * 2 + 4) + 2 * vec // 2 == 688
