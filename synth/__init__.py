@@ -150,3 +150,9 @@ def log_masses(n: int, lo: float = 0.002, hi: float = 0.2):
     if n == 1:
         return np.array([lo])
     return lo * (hi / lo) ** (np.arange(n) / (n - 1))
+
+
+def thin_links(dims, seed: int):
+    """Haar SU(3) thin links (4, V, 3, 3) complex128, no phases folded."""
+    dims = check_dims(dims)
+    return haar(seed, 4 * volume(dims)).reshape(4, volume(dims), 3, 3)
