@@ -215,6 +215,95 @@ def run_large(args):
                       "dslash": {str(k): v for k, v in dsl.items()}, "forms": forms}))
 
 
+PAPER_GRIDS = ((32, 32, 32, 128), (32, 40, 24, 96))
+MATMUL_FLOPS = 198        # 3x3 complex product: 27 complex multiplies (6) + 18 complex adds (2)
+
+
+def timed(fn, reps, stream):
+    """Microseconds per call of fn() with HIP events on `stream` (2 warm-up calls)."""
+    import torch
+    fn()
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def link_construction(hq, dims, log):
+    """Three-link products (Sec. 5) and the path-summed one-link matrices from Haar thin links."""
+    import numpy as np
+    import torch
+    import synth
+    V = int(np.prod(dims))
+    U = torch.from_numpy(synth.thin_links(dims, synth.gauge_seed(7))).cuda()
+    out = torch.empty_like(U)
+    stream = torch.cuda.current_stream()
+    us3 = timed(lambda: hq.hisq_three_link(U, out, dims), 20, stream)
+    n = 4 * V
+    row = {"three_link_us": round(us3, 1), "three_link_gflops": round(2 * MATMUL_FLOPS * n / us3 / 1e3, 1),
+           "three_link_gbs": round(288.0 * n / us3 / 1e3, 1)}
+    ws = hq.fields.workspace("fat_paths", dims)
+    coeff = (1 / 8, 1 / 16, 1 / 64, 1 / 384, -1 / 16)
+    us_f = timed(lambda: hq.hisq_fat_paths(U, coeff, out, dims, ws), 2, stream)
+    # staple launches: per (mu, nu) one 3-staple, two 5-staples, two 7-staples and two signed
+    # Lepage pairs, each with 4 (both signs) or 2 (one sign) products per site
+    prods = 4 * 3 * (4 + 2 * 4 + 2 * 4 + 2 * (2 + 2))
+    row.update({"fat_paths_ms": round(us_f / 1e3, 2), "fat_paths_gflops": round(prods * MATMUL_FLOPS * V / us_f / 1e3, 1),
+                "fat_paths_coeff": "fat7 weights + Lepage -1/16"})
+    log(f"[links {'x'.join(map(str, dims))}] {row}")
+    del U, out, ws
+    return row
+
+
+def run_paper_grids(args):
+    """Dslash alone on the two lattices of the paper's single-coprocessor runs (Sec. 5, Tables 1-2), every
+    storage form: microseconds, GFLOP/s at 1146 flops per site, algorithmic GB/s."""
+    import numpy as np
+    import torch
+
+    import paper_1411_2087_amd as hq
+    import synth
+    names = {hq.HISQ_F64: "f64", hq.HISQ_F32: "f32", hq.HISQ_F16S: "f16s", hq.HISQ_I16S: "i16s",
+             hq.HISQ_F64C: "f64c", hq.HISQ_F32C: "f32c"}
+    grids = {}
+    for dims in PAPER_GRIDS:
+        vh = int(np.prod(dims)) // 2
+        tag = "x".join(map(str, dims))
+        log(f"[setup] generating {tag} links and source")
+        fat, lng = synth.links(dims, synth.gauge_seed(6))
+        b = torch.from_numpy(synth.source(dims, synth.source_seed(6))).cuda()
+        fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
+        del fat, lng
+        rows = {}
+        for p in names:
+            L = hq.fields.Links.pack(fd, ld, dims, p)
+            dt = hq.fields.VEC_DTYPE[p]
+            s_, d_ = b.to(dt), torch.empty(b.shape, dtype=dt, device="cuda")
+            best, us = hq.hisq_tune_dslash(L.fat, L.lng, s_, d_, dims, p, reps=20)
+            t = min(us) * 1e-6
+            rows[names[p]] = {"us": round(t * 1e6, 1), "gflops": round(1146.0 * vh / t / 1e9, 1),
+                              "gbs": round(hq.DSLASH_BYTES_PER_SITE[p] * vh / t / 1e9, 1),
+                              "bytes_per_site": hq.DSLASH_BYTES_PER_SITE[p], "shape": best}
+            log(f"[dslash {tag}] {names[p]}: {rows[names[p]]}")
+            del L, s_, d_
+        del fd, ld, b
+        torch.cuda.empty_cache()
+        rows["link_construction"] = link_construction(hq, dims, log)
+        grids[tag] = rows
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "Dslash GFLOP/s and GB/s on the paper's lattices (report line)", "unit": "GFLOP/s",
+                      "value": grids["32x32x32x128"]["f32"]["gflops"], "n_gpus": 1, "higher_is_better": True,
+                      "data": "synthetic", "dtype": "f32",
+                      "config": {"workload": "HISQ Dslash (one-link + Naik three-link), 32^3x128 and 32x40x24x96, "
+                                             "parity 1, every link storage form"},
+                      "paper_xeon_phi_sp_naik_gflops": {"uncompressed": "136-140", "compressed": "178-193"},
+                      "grids": grids}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,8 +315,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (multi-RHS / multi-shift) forms")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
     ap.add_argument("--workload", default="32x32x32x32",
-                    help="32x32x32x32 (default: plain FP64 CG, the metric's workload) or 48x48x48x96 "
-                         "(mixed precision against plain FP64 on the large lattice; a report line, not the metric)")
+                    help="32x32x32x32 (default: plain FP64 CG, the metric's workload), 48x48x48x96 "
+                         "(mixed precision against plain FP64 on the large lattice) or paper-grids (the Dslash "
+                         "on 32^3x128 and 32x40x24x96); the last two are report lines, not the metric")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a 2 GiB copy and the FP64 Dslash (for rocprofv3 counter runs)")
     args = ap.parse_args()
@@ -244,6 +334,8 @@ def main():
 
     if args.workload == "48x48x48x96":
         return run_large(args)
+    if args.workload == "paper-grids":
+        return run_paper_grids(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     vh = int(np.prod(DIMS)) // 2
@@ -255,6 +347,8 @@ def main():
     L32 = hq.fields.Links.pack(fat_d, lng_d, DIMS, hq.HISQ_F32)
     L16 = hq.fields.Links.pack(fat_d, lng_d, DIMS, hq.HISQ_F16S)
     LI16 = hq.fields.Links.pack(fat_d, lng_d, DIMS, hq.HISQ_I16S)
+    L64C = hq.fields.Links.pack(fat_d, lng_d, DIMS, hq.HISQ_F64C)
+    L32C = hq.fields.Links.pack(fat_d, lng_d, DIMS, hq.HISQ_F32C)
     del fat_d, lng_d
     torch.cuda.synchronize()
     b = torch.from_numpy(b_np).to(dev)
@@ -279,11 +373,12 @@ def main():
     tuned = {}
     tmp = torch.empty_like(b)
     for name, prec, L in (("f64", hq.HISQ_F64, L64), ("f32", hq.HISQ_F32, L32), ("f16s", hq.HISQ_F16S, L16),
-                          ("i16s", hq.HISQ_I16S, LI16)):
+                          ("i16s", hq.HISQ_I16S, LI16), ("f64c", hq.HISQ_F64C, L64C), ("f32c", hq.HISQ_F32C, L32C)):
         dt = hq.fields.VEC_DTYPE[prec]
         s_, d_ = b.to(dt), torch.empty(b.shape, dtype=dt, device=dev)
         best, us = hq.hisq_tune_dslash(L.fat, L.lng, s_, d_, DIMS, prec, reps=20)
-        tuned[name] = {"shape": best, "us": [round(u, 1) for u in us]}
+        tuned[name] = {"shape": best, "us": [round(u, 1) for u in us],
+                       "gbs": round(hq.DSLASH_BYTES_PER_SITE[prec] * vh / (min(us) * 1e-6) / 1e9, 1)}
         log(f"[tune] {name}: shape {best}, us per shape {tuned[name]['us']}")
         del s_, d_
 
@@ -337,16 +432,20 @@ def main():
     forms = {"plain_f64": {"s": round(ms_per_step / 1e3, 4), "iters": stats[-1]["iters"],
                            "true_resid": stats[-1]["true_resid"]}}
     if not args.no_forms:
-        for name, mode, Llo in (("mixed_f32", hq.HISQ_CG_MIXED_F32, L32), ("mixed_f16s", hq.HISQ_CG_MIXED_F16S, L16),
-                                ("mixed_i16s", hq.HISQ_CG_MIXED_I16S, LI16)):
+        for name, mode, Lhi, Llo in (("mixed_f32", hq.HISQ_CG_MIXED_F32, L64, L32),
+                                     ("mixed_f16s", hq.HISQ_CG_MIXED_F16S, L64, L16),
+                                     ("mixed_i16s", hq.HISQ_CG_MIXED_I16S, L64, LI16),
+                                     ("plain_f64c", hq.HISQ_CG_PLAIN_F64C, L64C, None),
+                                     ("mixed_f32c", hq.HISQ_CG_MIXED_F32C, L64C, L32C)):
             wsm = hq.fields.workspace("cg", DIMS, 1, mode)
             om = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
             xm = torch.zeros_like(b)
-            hq.cg_solve(MASS, TOL, L64.fat, L64.lng, Llo.fat, Llo.lng, b, xm, DIMS, om, wsm)  # warm
+            lo_f, lo_l = (Llo.fat, Llo.lng) if Llo is not None else (None, None)
+            hq.cg_solve(MASS, TOL, Lhi.fat, Lhi.lng, lo_f, lo_l, b, xm, DIMS, om, wsm)  # warm
             xm.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sm = hq.cg_solve(MASS, TOL, L64.fat, L64.lng, Llo.fat, Llo.lng, b, xm, DIMS, om, wsm)
+            sm = hq.cg_solve(MASS, TOL, Lhi.fat, Lhi.lng, lo_f, lo_l, b, xm, DIMS, om, wsm)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             forms[name] = {"s": round(dt, 4), "iters": sm["iters"], "reliable_updates": sm["reliable_updates"],
@@ -359,7 +458,7 @@ def main():
         forms["multi_rhs_8"] = form_batched(hq, DIMS, L64, L32, hq.HISQ_MULTI_RHS, 8, log)
         forms["multi_shift_8"] = form_batched(hq, DIMS, L64, L32, hq.HISQ_MULTI_SHIFT, 8, log)
     if not args.no_forms and not args.no_learned:
-        del L16, LI16
+        del L16, LI16, L64C, L32C
         forms["learned"] = form_learned(hq, log)
 
     cpu = None

@@ -184,9 +184,10 @@ int hisq_tune_dslash(const void *fat, const void *lng, const void *src, void *ds
  * hisq_status.  shape == -2 returns the number of shapes. */
 int hisq_dslash_shape(const int dims[4], int prec, int shape);
 
-/* Workspace bytes for `solver` = "cg", "cg_multi" or "fcg" on `dims` with
- * `nrhs` right-hand sides (1 for cg), `mode` (HISQ_CG_* for cg/fcg,
- * HISQ_MULTI_* for cg_multi) and `channels` (fcg only).  0 on bad arguments. */
+/* Workspace bytes for `solver` = "cg", "cg_multi", "fcg" or "fat_paths" on
+ * `dims` with `nrhs` right-hand sides (1 for cg), `mode` (HISQ_CG_* for
+ * cg/fcg, HISQ_MULTI_* for cg_multi) and `channels` (fcg only); fat_paths
+ * ignores the last three.  0 on bad arguments. */
 size_t hisq_workspace_bytes(const char *solver, const int dims[4], int nrhs, int mode, int channels);
 
 /* Solve A(mass) x = b on the even sites to |b - A x| <= tol |b| (Sec. 3 CG;
@@ -284,6 +285,39 @@ int net_adam_step(void *weights, const void *grad_w, void *m, void *v, long long
 int fcg_solve(double mass, double tol, const void *fat, const void *lng, const void *fat32, const void *weights,
               int channels, const void *b, void *x, const int dims[4], const hisq_cg_opts *opts, void *workspace,
               size_t ws_bytes, hisq_cg_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------ link construction
+ * Sec. 5 of the paper: the three-link matrices of the Naik term are products
+ * of thin links (matrix-matrix work).  Fields here are canonical complex128
+ * [mu][t][z][y][x][3][3] device arrays (4 V matrices, 576 V bytes), periodic
+ * indexing, no phases; hisq_fold_links then folds the staggered phases and
+ * the time boundary sign in, and hisq_pack_links packs the result for the
+ * Dslash.  All three are asynchronous on `stream`. */
+
+/* out_mu(n) = U_mu(n) U_mu(n+mu) U_mu(n+2mu) for every site n and direction
+ * mu.  out must not overlap thin (HISQ_EALIAS). */
+int hisq_three_link(const void *thin, void *out, const int dims[4], void *stream);
+
+/* Path-summed (smeared) one-link matrices from thin links U:
+ *   out_mu(n) = coeff[0] U_mu(n) + coeff[1] S3 + coeff[2] S5 + coeff[3] S7 + coeff[4] SL,
+ * each S the sum of the link products along every path of its family from n
+ * to n+mu, over every direction nu != mu and both signs: 3-staples
+ * U_nu(n) U_mu(n+nu) U_nu(n+mu)^dag and their mirror images (6 paths),
+ * 5-staples (a 3-staple in rho around a 3-staple in nu, rho != nu: 24),
+ * 7-staples (one more distinct axis: 48) and Lepage paths (a 3-staple
+ * around a 3-staple in the same nu with the same sign: 6).  The weights are
+ * inputs: the paper does not fix them.  workspace: device memory of
+ * hisq_workspace_bytes("fat_paths", dims, 0, 0, 0) bytes (three one-direction
+ * link fields).  out must not overlap thin or the workspace. */
+int hisq_fat_paths(const void *thin, const double coeff[5], void *out, const int dims[4], void *workspace,
+                   size_t ws_bytes, void *stream);
+
+/* In place: links_mu(n) *= eta_mu(n) b_mu(n), with the staggered phases
+ * eta_x = 1, eta_y = (-1)^x, eta_z = (-1)^(x+y), eta_t = (-1)^(x+y+z), and
+ * b = -1 on the t-links whose hop of `hop` sites (1 for one-link, 3 for
+ * three-link matrices) crosses the last time slice when antiperiodic_t is
+ * nonzero, else 1.  HISQ_EINVAL unless hop is 1 or 3. */
+int hisq_fold_links(void *links, const int dims[4], int hop, int antiperiodic_t, void *stream);
 
 /* Launch shape of the multi-RHS Dslash for (dims, nrhs): shape >= 0 sets it
  * (HISQ_EINVAL if it does not apply to nrhs), -1 queries, -2 returns the

@@ -24,6 +24,8 @@ HISQ_F64, HISQ_F32, HISQ_F16S, HISQ_I16S, HISQ_F64C, HISQ_F32C = 0, 1, 2, 3, 4, 
 HISQ_CG_PLAIN_F64, HISQ_CG_MIXED_F32, HISQ_CG_MIXED_F16S, HISQ_CG_MIXED_I16S = 0, 1, 2, 3
 HISQ_CG_PLAIN_F64C, HISQ_CG_MIXED_F32C = 4, 5
 HISQ_MULTI_RHS, HISQ_MULTI_SHIFT = 0, 1
+HISQ_OK, HISQ_EINVAL, HISQ_EDIMS, HISQ_EALIAS, HISQ_EHIP = 0, -1, -2, -3, -4
+HISQ_ENOCONV, HISQ_EBREAKDOWN, HISQ_EWORKSPACE = -5, -6, -7
 STATUS = {0: "HISQ_OK", -1: "HISQ_EINVAL", -2: "HISQ_EDIMS", -3: "HISQ_EALIAS", -4: "HISQ_EHIP",
           -5: "HISQ_ENOCONV", -6: "HISQ_EBREAKDOWN", -7: "HISQ_EWORKSPACE"}
 
@@ -94,7 +96,10 @@ def _load():
     lib.net_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_longlong, d, ctypes.c_int, vp]
     lib.fcg_solve.argtypes = [d, d, vp, vp, vp, vp, ctypes.c_int, vp, vp, ip, ctypes.POINTER(CGOpts), vp, sz,
                               ctypes.POINTER(CGStats), vp]
-    for name in ("hisq_pack_links", "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi",
+    lib.hisq_three_link.argtypes = [vp, vp, ip, vp]
+    lib.hisq_fat_paths.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp, ip, vp, sz, vp]
+    lib.hisq_fold_links.argtypes = [vp, ip, ctypes.c_int, ctypes.c_int, vp]
+    for name in ("hisq_three_link", "hisq_fat_paths", "hisq_fold_links", "hisq_pack_links", "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi",
                  "hisq_tune_dslash", "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape",
                  "net_forward", "net_backward", "net_loss", "net_adam_step", "fcg_solve"):
         getattr(lib, name).restype = ctypes.c_int
@@ -107,7 +112,7 @@ EXPORTED = ["hisq_version", "hisq_last_error", "hisq_packed_link_bytes", "hisq_p
             "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi", "hisq_tune_dslash",
             "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape", "net_weight_count",
             "net_act_bytes", "net_backward_ws_bytes", "net_forward", "net_backward", "net_loss", "net_adam_step",
-            "fcg_solve"]
+            "fcg_solve", "hisq_three_link", "hisq_fat_paths", "hisq_fold_links"]
 
 
 def _dims(dims):
@@ -151,6 +156,22 @@ def hisq_packed_link_bytes(dims, prec) -> int:
 def hisq_pack_links(fat_canon, long_canon, dims, prec, fat_out, long_out, stream=None):
     _check(_lib.hisq_pack_links(_ptr(fat_canon), _ptr(long_canon), _dims(dims), int(prec), _ptr(fat_out),
                                 _ptr(long_out), _stream(stream)), "hisq_pack_links")
+
+
+def hisq_three_link(thin, out, dims, stream=None):
+    _check(_lib.hisq_three_link(_ptr(thin), _ptr(out), _dims(dims), _stream(stream)), "hisq_three_link")
+
+
+def hisq_fat_paths(thin, coeff, out, dims, workspace, stream=None):
+    c = (ctypes.c_double * 5)(*[float(v) for v in coeff])
+    _check(_lib.hisq_fat_paths(_ptr(thin), c, _ptr(out), _dims(dims), _ptr(workspace),
+                               workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                               _stream(stream)), "hisq_fat_paths")
+
+
+def hisq_fold_links(links, dims, hop, antiperiodic_t=True, stream=None):
+    _check(_lib.hisq_fold_links(_ptr(links), _dims(dims), int(hop), int(bool(antiperiodic_t)), _stream(stream)),
+           "hisq_fold_links")
 
 
 def dslash_apply(fat, lng, src, dst, parity, dims, prec, stream=None):

@@ -752,6 +752,7 @@ extern "C" size_t hisq_workspace_bytes(const char *solver, const int dims[4], in
         return cg_workspace_bytes(g, mode);
     }
     if (!std::strcmp(solver, "cg_multi")) return cg_multi_workspace_bytes(g, nrhs, mode);
+    if (!std::strcmp(solver, "fat_paths")) return fat_paths_ws_bytes(dims);
     if (!std::strcmp(solver, "fcg")) {
         if (channels != 4 && channels != 8 && channels != 16) return 0;
         return fcg_ws_bytes(g, channels);

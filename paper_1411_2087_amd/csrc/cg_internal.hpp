@@ -29,6 +29,7 @@ int blas_blocks(long long n);
 size_t cg_partials_count(const Geom &g);
 size_t cg_multi_workspace_bytes(const Geom &g, int nrhs, int mode);
 size_t fcg_ws_bytes(const Geom &g, int channels);
+size_t fat_paths_ws_bytes(const int dims[4]);  // links.hip
 CGState *pinned_state();
 hipStream_t capture_stream();
 hisq_cg_opts resolve_opts(const hisq_cg_opts *opts, const Geom &g);
