@@ -97,21 +97,75 @@ __device__ __forceinline__ long long lex_hop2(const Lex &g, long long n, const i
     return lex_hop(g, m, cc, nu, j);
 }
 
+// ------------------------------------------------------------------ LDS staging
+// A canonical matrix is 144 contiguous bytes, so a lane that loads its own
+// matrix touches a new cache line with every 16-byte load.  The block instead
+// reads the NT matrices its threads need cooperatively, consecutive lanes on
+// consecutive 16-byte words (contiguous wherever the sites' matrices are),
+// through LDS laid out [thread][element]; each thread then takes its 9
+// words.  Reads of 16 bytes at a 144-byte lane stride touch 16 different
+// bank groups per quarter-wave, so the LDS side runs conflict-free.
+template <int NT>
+struct Stage {
+    double2 m[NT * 9];
+    long long idx[NT];
+};
+
+// every thread of the block calls this (idx < 0: nothing to load for this thread)
+template <int NT>
+__device__ __forceinline__ M3 gather(Stage<NT> &st, const double2 *__restrict__ base, long long idx)
+{
+    __syncthreads();  // the previous use of st is finished
+    st.idx[threadIdx.x] = idx;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int q = threadIdx.x + NT * i;
+        const int j = q / 9;
+        const long long s = st.idx[j];
+        if (s >= 0) st.m[q] = base[9 * s + (q - 9 * j)];
+    }
+    __syncthreads();
+    M3 m;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m.e[e] = st.m[9 * threadIdx.x + e];
+    return m;
+}
+
+// store the block's NT matrices to the contiguous out[n0 .. n0 + count)
+template <int NT>
+__device__ __forceinline__ void scatter(Stage<NT> &st, double2 *__restrict__ out, long long n0, int count, const M3 &m)
+{
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 9; ++e) st.m[9 * threadIdx.x + e] = m.e[e];
+    __syncthreads();
+    double2 *o = out + 9 * n0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int q = threadIdx.x + NT * i;
+        if (q < 9 * count) ntstore(st.m[q], o + q);
+    }
+}
+
 // ------------------------------------------------------------------ three-link products
 template <int NT>
 __global__ void __launch_bounds__(NT) k_three_link(Lex g, const double2 *__restrict__ thin, double2 *__restrict__ out)
 {
-    const long long n = (long long)blockIdx.x * NT + threadIdx.x;
+    __shared__ Stage<NT> st;
+    const long long n0 = (long long)blockIdx.x * NT;
+    const long long n = n0 + threadIdx.x;
     const int mu = blockIdx.y;
-    if (n >= g.V) return;
-    int c[4];
-    lex_coords(g, n, c);
+    const bool live = n < g.V;
+    int c[4] = { 0, 0, 0, 0 };
+    if (live) lex_coords(g, n, c);
     const double2 *U = thin + 9 * (size_t)mu * g.V;
-    const long long n1 = lex_hop(g, n, c, mu, 1), n2 = lex_hop(g, n, c, mu, 2);
-    const M3 a = ld_m3(U + 9 * n), b = ld_m3(U + 9 * n1);
+    const M3 a = gather<NT>(st, U, live ? n : -1);
+    const M3 b = gather<NT>(st, U, live ? lex_hop(g, n, c, mu, 1) : -1);
     const M3 ab = mm<false, false>(a, b);
-    const M3 d = ld_m3(U + 9 * n2);
-    st_m3(out + 9 * ((size_t)mu * g.V + n), mm<false, false>(ab, d));
+    const M3 d = gather<NT>(st, U, live ? lex_hop(g, n, c, mu, 2) : -1);
+    const int count = (int)(g.V - n0 < NT ? g.V - n0 : NT);
+    scatter<NT>(st, out + 9 * (size_t)mu * g.V, n0, count, mm<false, false>(ab, d));
 }
 
 // ------------------------------------------------------------------ staples
@@ -128,49 +182,44 @@ __global__ void __launch_bounds__(NT) k_staple(Lex g, const double2 *__restrict_
                                                double2 *__restrict__ S_out, double2 *__restrict__ F, double c,
                                                const double2 *__restrict__ Uinit, double c_init)
 {
-    const long long n = (long long)blockIdx.x * NT + threadIdx.x;
-    if (n >= g.V) return;
-    int cd[4];
-    lex_coords(g, n, cd);
+    __shared__ Stage<NT> st;
+    const long long n0 = (long long)blockIdx.x * NT;
+    const long long n = n0 + threadIdx.x;
+    const bool live = n < g.V;
+    const int count = (int)(g.V - n0 < NT ? g.V - n0 : NT);
+    int cd[4] = { 0, 0, 0, 0 };
+    if (live) lex_coords(g, n, cd);
     const double2 *Un = thin + 9 * (size_t)nu * g.V;
     M3 S;
 #pragma unroll
     for (int i = 0; i < 9; ++i) S.e[i] = make_double2(0.0, 0.0);
     if (signs & ST_PLUS) {
-        const M3 a = ld_m3(Un + 9 * n);
-        const M3 v = ld_m3(Vf + 9 * lex_hop(g, n, cd, nu, 1));
+        const M3 a = gather<NT>(st, Un, live ? n : -1);
+        const M3 v = gather<NT>(st, Vf, live ? lex_hop(g, n, cd, nu, 1) : -1);
         const M3 av = mm<false, false>(a, v);
-        const M3 b = ld_m3(Un + 9 * lex_hop(g, n, cd, mu, 1));
-        const M3 t = mm<false, true>(av, b);
-        axpy_m3(1.0, t, S);
+        const M3 b = gather<NT>(st, Un, live ? lex_hop(g, n, cd, mu, 1) : -1);
+        axpy_m3(1.0, mm<false, true>(av, b), S);
     }
     if (signs & ST_MINUS) {
-        const long long m = lex_hop(g, n, cd, nu, -1);
-        const M3 a = ld_m3(Un + 9 * m);
-        const M3 v = ld_m3(Vf + 9 * m);
+        const long long m = live ? lex_hop(g, n, cd, nu, -1) : -1;
+        const M3 a = gather<NT>(st, Un, m);
+        const M3 v = gather<NT>(st, Vf, m);
         const M3 av = mm<true, false>(a, v);
-        const M3 b = ld_m3(Un + 9 * lex_hop2(g, n, cd, nu, -1, mu, 1));
-        const M3 t = mm<false, false>(av, b);
-        axpy_m3(1.0, t, S);
+        const M3 b = gather<NT>(st, Un, live ? lex_hop2(g, n, cd, nu, -1, mu, 1) : -1);
+        axpy_m3(1.0, mm<false, false>(av, b), S);
     }
-    if (S_out) {
-        double2 *p = S_out + 9 * n;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) p[i] = S.e[i];
-    }
+    if (S_out) scatter<NT>(st, S_out, n0, count, S);
     if (F) {
-        double2 *p = F + 9 * n;
         M3 f;
         if (Uinit) {
-            const M3 u = ld_m3(Uinit + 9 * n);
+            const M3 u = gather<NT>(st, Uinit, live ? n : -1);
 #pragma unroll
             for (int i = 0; i < 9; ++i) f.e[i] = make_double2(c_init * u.e[i].x, c_init * u.e[i].y);
         } else {
-            f = ld_m3(p);
+            f = gather<NT>(st, F, live ? n : -1);
         }
         axpy_m3(c, S, f);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) p[i] = f.e[i];
+        scatter<NT>(st, F, n0, count, f);
     }
 }
 
