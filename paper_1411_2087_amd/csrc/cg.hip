@@ -12,10 +12,12 @@
 // HIP graph.
 //
 // Per iteration (plain FP64):
-//   t  = D_oe p                                         (Dslash, parity 1)
-//   Ap = 4m^2 p - D_eo t ; pAp = Re<p,Ap> ; alpha       (Dslash + fused epilogue)
-//   x += alpha p ; r -= alpha Ap ; rr = |r|^2 ; beta    (one BLAS pass)
-//   p  = r + beta p
+//   t  = D_oe p ; |t|^2                                 (Dslash + norm epilogue)
+//   pAp = 4m^2 |p|^2 + |t|^2 ; alpha                    (D_eo = -D_oe^dag, so
+//                                                        <p, A p> needs no second pass)
+//   x += alpha p ; r -= alpha (4m^2 p - D_eo t) ; |r|^2 (Dslash + update epilogue:
+//                                                        A p never goes to memory)
+//   beta ; p = r + beta p ; |p|^2                       (one BLAS pass)
 // Mixed precision (Sleijpen & van der Vorst 1996 reliable updates, in the
 // form used for lattice QCD by Clark et al. 2010): the same iteration on FP32
 // vectors with FP32 or FP16+scale links and FP64 dot accumulation; when
@@ -129,6 +131,9 @@ __device__ __forceinline__ void finalize(CGState *st, int mode, double v)
 // Streaming vector kernels: each thread owns BL_U entries spaced BL_NT apart
 // (every load instruction of a wavefront is one contiguous span), issues all
 // its loads before any arithmetic, and the grid covers the vector once.
+// Every vector a solver kernel writes is stored nontemporally: a Dslash
+// whose source was written through the caches runs measurably slower than
+// one whose source was streamed out.
 constexpr int BL_NT = 256;
 constexpr int BL_U = 4;
 
@@ -163,43 +168,10 @@ __global__ __launch_bounds__(BL_NT) void k_dot_state(const T *__restrict__ x, co
     block_partial<BL_NT>(s, partials, blockIdx.x);
 }
 
-// x += alpha p ; r -= alpha Ap ; partials of |r|^2
+// p = r + beta p ; partials of |p|^2 (the first half of the next <p, A p>)
 template <class T>
-__global__ __launch_bounds__(BL_NT) void k_cg_update(T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
-                                                     const T *__restrict__ ap, long long n, double *partials,
-                                                     const CGState *st)
-{
-    if (st->flags.done) return;
-    using R = typename VecT<T>::real;
-    const R alpha = (R)st->alpha;
-    T pv[BL_U], av[BL_U], xv[BL_U], rv[BL_U];
-#pragma unroll
-    for (int j = 0; j < BL_U; ++j) {
-        const long long i = bl_index(j);
-        if (i < n) { pv[j] = p[i]; av[j] = ap[i]; xv[j] = x[i]; rv[j] = r[i]; }
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < BL_U; ++j) {
-        const long long i = bl_index(j);
-        if (i < n) {
-            xv[j].x = fma(alpha, pv[j].x, xv[j].x);
-            xv[j].y = fma(alpha, pv[j].y, xv[j].y);
-            rv[j].x = fma(-alpha, av[j].x, rv[j].x);
-            rv[j].y = fma(-alpha, av[j].y, rv[j].y);
-            x[i] = xv[j];
-            r[i] = rv[j];
-            s = fma((double)rv[j].x, (double)rv[j].x, s);
-            s = fma((double)rv[j].y, (double)rv[j].y, s);
-        }
-    }
-    block_partial<BL_NT>(s, partials, blockIdx.x);
-}
-
-// p = r + beta p
-template <class T>
-__global__ __launch_bounds__(BL_NT) void k_cg_p(T *__restrict__ p, const T *__restrict__ r, long long n,
-                                                const CGState *st)
+__global__ __launch_bounds__(BL_NT) void k_cg_p_norm(T *__restrict__ p, const T *__restrict__ r, long long n,
+                                                     double *partials, const CGState *st)
 {
     if (st->flags.done) return;
     using R = typename VecT<T>::real;
@@ -210,15 +182,19 @@ __global__ __launch_bounds__(BL_NT) void k_cg_p(T *__restrict__ p, const T *__re
         const long long i = bl_index(j);
         if (i < n) { pv[j] = p[i]; rv[j] = r[i]; }
     }
+    double s = 0.0;
 #pragma unroll
     for (int j = 0; j < BL_U; ++j) {
         const long long i = bl_index(j);
         if (i < n) {
             pv[j].x = fma(beta, pv[j].x, rv[j].x);
             pv[j].y = fma(beta, pv[j].y, rv[j].y);
-            p[i] = pv[j];
+            ntstore(pv[j], p + i);
+            s = fma((double)pv[j].x, (double)pv[j].x, s);
+            s = fma((double)pv[j].y, (double)pv[j].y, s);
         }
     }
+    block_partial<BL_NT>(s, partials, blockIdx.x);
 }
 
 // x64 += xs ; xs = 0   (reliable update)
@@ -239,8 +215,8 @@ __global__ __launch_bounds__(BL_NT) void k_accum(double2 *__restrict__ x, float2
         if (i < n) {
             a[j].x += (double)v[j].x;
             a[j].y += (double)v[j].y;
-            x[i] = a[j];
-            xs[i] = make_float2(0.f, 0.f);
+            ntstore(a[j], x + i);
+            ntstore(make_float2(0.f, 0.f), xs + i);
         }
     }
 }
@@ -255,6 +231,17 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const double *__restrict__ 
     if (gate_closed(&st->flags, gate)) return;
     double v = sum_partials<FIN_NT>(partials, n);
     if (threadIdx.x == 0) finalize(st, mode, v);
+}
+
+// pAp = m4 |p|^2 + |D_oe p|^2 from the partials of k_cg_p_norm (or k_dot_state)
+// and of k_cg_Dp, then alpha (FIN_PAP).
+__global__ __launch_bounds__(FIN_NT) void k_finalize_pap(const double *__restrict__ part_p, int np,
+                                                         const double *__restrict__ part_t, int nt, CGState *st)
+{
+    if (st->flags.done) return;
+    const double pp = sum_partials<FIN_NT>(part_p, np);
+    const double tt = sum_partials<FIN_NT>(part_t, nt);
+    if (threadIdx.x == 0) finalize(st, FIN_PAP, fma(st->m4, pp, tt));
 }
 
 __global__ void k_state_init(CGState *st, double tol2, double delta2, double m4)
@@ -283,13 +270,54 @@ __global__ void k_clear_done(CGState *st)
 }
 
 // ------------------------------------------------------------------ Dslash-fused kernels
-// Ap = m4 p - D_eo t ; partials of Re<p, Ap>
-template <class P, int NT>
-__global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_cg_Ap(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
-                                              const typename P::cvec *__restrict__ t,
-                                              const typename P::cvec *__restrict__ p,
-                                              typename P::cvec *__restrict__ ap, int nblocks, double *partials,
-                                              const CGState *st)
+// Waves per SIMD the fused kernels ask for: the two-row FP64 operator needs
+// more than the 64 registers that 8 waves leave.
+template <class P> constexpr int cg_waves() { return P::prec == HISQ_F64C ? 6 : 8; }
+
+// t = D_oe p on the odd sites ; partials of |t|^2
+template <class P, int NT, int W>
+__global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_cg_Dp(Geom g, const char *__restrict__ fat,
+                                                            const char *__restrict__ lng,
+                                                            const typename P::cvec *__restrict__ p,
+                                                            typename P::cvec *__restrict__ t, int nblocks,
+                                                            double *partials, const CGState *st)
+{
+    if (st->flags.done) return;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    if (blk >= nblocks) return;
+    const int tile = blk * (NT / TILE) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int h = tile * TILE + lane;
+    double s = 0.0;
+    if (tile < g.ntiles) {
+        const int hc = h < g.Vh ? h : g.Vh - 1;
+        typename P::real acc[6];
+        dslash_site<P>(g, fat, lng, p, 1, tile, lane, hc, acc);
+        if (h < g.Vh) {
+            typename P::cvec *o = t + (size_t)h * 3;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                typename P::cvec v;
+                v.x = acc[2 * c];
+                v.y = acc[2 * c + 1];
+                ntstore(v, o + c);
+                s = fma((double)v.x, (double)v.x, s);
+                s = fma((double)v.y, (double)v.y, s);
+            }
+        }
+    }
+    block_partial<NT>(s, partials, blk);
+}
+
+// A p = m4 p - D_eo t in registers ; x += alpha p ; r -= alpha A p ; partials of |r|^2
+template <class P, int NT, int W>
+__global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_cg_Ap_upd(Geom g, const char *__restrict__ fat,
+                                                                const char *__restrict__ lng,
+                                                                const typename P::cvec *__restrict__ t,
+                                                                const typename P::cvec *__restrict__ p,
+                                                                typename P::cvec *__restrict__ x,
+                                                                typename P::cvec *__restrict__ r, int nblocks,
+                                                                double *partials, const CGState *st)
 {
     if (st->flags.done) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -303,15 +331,22 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_cg_Ap(Geom g, const char *
         typename P::real acc[6];
         dslash_site<P>(g, fat, lng, t, 0, tile, lane, hc, acc);
         if (h < g.Vh) {
-            const typename P::real m = (typename P::real)st->m4;
+            using R = typename P::real;
+            const R m = (R)st->m4, a = (R)st->alpha;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                typename P::cvec pv = p[(size_t)h * 3 + c], v;
-                v.x = fma(m, pv.x, -acc[2 * c]);
-                v.y = fma(m, pv.y, -acc[2 * c + 1]);
-                ap[(size_t)h * 3 + c] = v;
-                s = fma((double)pv.x, (double)v.x, s);
-                s = fma((double)pv.y, (double)v.y, s);
+                const size_t i = (size_t)h * 3 + c;
+                const typename P::cvec pv = p[i];
+                typename P::cvec xv = x[i], rv = r[i];
+                const R apx = fma(m, pv.x, -acc[2 * c]), apy = fma(m, pv.y, -acc[2 * c + 1]);
+                xv.x = fma(a, pv.x, xv.x);
+                xv.y = fma(a, pv.y, xv.y);
+                rv.x = fma(-a, apx, rv.x);
+                rv.y = fma(-a, apy, rv.y);
+                ntstore(xv, x + i);
+                ntstore(rv, r + i);
+                s = fma((double)rv.x, (double)rv.x, s);
+                s = fma((double)rv.y, (double)rv.y, s);
             }
         }
     }
@@ -320,7 +355,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_cg_Ap(Geom g, const char *
 
 // r = b - (m4 x - D_eo t) in FP64 ; optional copies ; partials of |r|^2
 template <class PH, int NT>
-__global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_resid(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
+__global__ __launch_bounds__(NT) HISQ_WAVES(cg_waves<PH>()) void k_resid(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
                                               const double2 *__restrict__ t, const double2 *__restrict__ x,
                                               const double2 *__restrict__ b, double2 *__restrict__ r,
                                               double2 *__restrict__ p, float2 *__restrict__ rs,
@@ -346,10 +381,10 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(8) void k_resid(Geom g, const char *
                 double2 xv = x[i], bv = b[i], v;
                 v.x = bv.x - fma(m, xv.x, -acc[2 * c]);
                 v.y = bv.y - fma(m, xv.y, -acc[2 * c + 1]);
-                if (r) r[i] = v;
-                if (p) p[i] = v;
-                if (rs) rs[i] = make_float2((float)v.x, (float)v.y);
-                if (ps) ps[i] = make_float2((float)v.x, (float)v.y);
+                if (r) ntstore(v, r + i);
+                if (p) ntstore(v, p + i);
+                if (rs) ntstore(make_float2((float)v.x, (float)v.y), rs + i);
+                if (ps) ntstore(make_float2((float)v.x, (float)v.y), ps + i);
                 s = fma(v.x, v.x, s);
                 s = fma(v.y, v.y, s);
             }
@@ -377,9 +412,9 @@ constexpr size_t SKEW = 4352;
 size_t cg_workspace_bytes(const Geom &g, int mode)
 {
     const size_t v64 = align256((size_t)g.Vh * 3 * 16), v32 = align256((size_t)g.Vh * 3 * 8);
-    size_t bytes = align256(sizeof(CGState)) + align256(cg_partials_count(g) * sizeof(double)) + 2 * SKEW;
-    if (mode == HISQ_CG_PLAIN_F64 || mode == HISQ_CG_PLAIN_F64C) bytes += 4 * (v64 + SKEW);  // r p Ap t
-    else bytes += 2 * (v64 + SKEW) + 5 * (v32 + SKEW);                      // r64 t64 | xs rs ps Aps ts
+    size_t bytes = align256(sizeof(CGState)) + 2 * align256(cg_partials_count(g) * sizeof(double)) + 3 * SKEW;
+    if (mode == HISQ_CG_PLAIN_F64 || mode == HISQ_CG_PLAIN_F64C) bytes += 3 * (v64 + SKEW);  // r p t
+    else bytes += 2 * (v64 + SKEW) + 4 * (v32 + SKEW);                      // r64 t64 | xs rs ps ts
     return bytes;
 }
 
@@ -479,12 +514,13 @@ struct Carver {
 struct Launch {
     const Geom &g;
     CGState *st;
-    double *part;
-    long long n;  // complex entries per vector
+    double *part;    // partials of the reduction in flight
+    double *part_p;  // partials of |p|^2, kept from one iteration to the next
+    long long n;     // complex entries per vector
     int nbl, nbd;
     dim3 gb, gd;
-    Launch(const Geom &g_, CGState *st_, double *part_)
-        : g(g_), st(st_), part(part_), n((long long)g_.Vh * 3), nbl(blas_blocks((long long)g_.Vh * 3)),
+    Launch(const Geom &g_, CGState *st_, double *part_, double *part_p_)
+        : g(g_), st(st_), part(part_), part_p(part_p_), n((long long)g_.Vh * 3), nbl(blas_blocks((long long)g_.Vh * 3)),
           nbd(dslash_nb(g_)), gb(nbl), gd(xcd_grid(dslash_nb(g_)))
     {
     }
@@ -506,22 +542,35 @@ struct Launch {
                            (const double2 *)x, (const double2 *)b, r, p, rs, ps, nbd, part, (const CGState *)st, gate);
         fin(q, nbd, mode, gate);
     }
-    template <class P>
-    void ap(hipStream_t q, const void *fat, const void *lng, const void *t, const void *p, void *apv) const
+    // |p|^2 partials into part_p (before the first iteration and after restarts)
+    template <class T> void pnorm(hipStream_t q, const T *p) const
+    {
+        hipLaunchKernelGGL((k_dot_state<T>), gb, dim3(BL_NT), 0, q, p, p, n, part_p);
+    }
+    // t = D_oe p ; alpha = rr / (m4 |p|^2 + |t|^2)
+    template <class P> void dp(hipStream_t q, const void *fat, const void *lng, const void *p, void *t) const
     {
         using V = typename P::cvec;
-        hipLaunchKernelGGL((k_cg_Ap<P, CG_NT>), gd, dim3(CG_NT), 0, q, g, (const char *)fat, (const char *)lng,
-                           (const V *)t, (const V *)p, (V *)apv, nbd, part, (const CGState *)st);
-        fin(q, nbd, FIN_PAP, GATE_NOT_DONE);
+        hipLaunchKernelGGL((k_cg_Dp<P, CG_NT, cg_waves<P>()>), gd, dim3(CG_NT), 0, q, g, (const char *)fat,
+                           (const char *)lng, (const V *)p, (V *)t, nbd, part, (const CGState *)st);
+        hipLaunchKernelGGL(k_finalize_pap, dim3(1), dim3(FIN_NT), 0, q, (const double *)part_p, nbl,
+                           (const double *)part, nbd, st);
     }
-    template <class T> void update(hipStream_t q, T *x, T *r, const T *p, const T *apv, int mode) const
+    // x += alpha p ; r -= alpha (m4 p - D_eo t) ; |r|^2 -> mode
+    template <class P>
+    void ap_update(hipStream_t q, const void *fat, const void *lng, const void *t, const void *p, void *x, void *r,
+                   int mode) const
     {
-        hipLaunchKernelGGL((k_cg_update<T>), gb, dim3(BL_NT), 0, q, x, r, p, apv, n, part, (const CGState *)st);
-        fin(q, nbl, mode, GATE_NOT_DONE);
+        using V = typename P::cvec;
+        hipLaunchKernelGGL((k_cg_Ap_upd<P, CG_NT, cg_waves<P>()>), gd, dim3(CG_NT), 0, q, g, (const char *)fat,
+                           (const char *)lng, (const V *)t, (const V *)p, (V *)x, (V *)r, nbd, part,
+                           (const CGState *)st);
+        fin(q, nbd, mode, GATE_NOT_DONE);
     }
+    // p = r + beta p ; |p|^2 partials into part_p
     template <class T> void pupd(hipStream_t q, T *p, const T *r) const
     {
-        hipLaunchKernelGGL((k_cg_p<T>), gb, dim3(BL_NT), 0, q, p, r, n, (const CGState *)st);
+        hipLaunchKernelGGL((k_cg_p_norm<T>), gb, dim3(BL_NT), 0, q, p, r, n, part_p, (const CGState *)st);
     }
 };
 
@@ -556,12 +605,12 @@ int cg_plain(double mass, double tol, const void *fat, const void *lng, const vo
     const size_t v64 = (size_t)g.Vh * 3 * 16;
     CGState *st = (CGState *)c.take(sizeof(CGState));
     double *part = (double *)c.take(cg_partials_count(g) * sizeof(double));
-    double2 *r = (double2 *)c.take(v64), *p = (double2 *)c.take(v64), *ap = (double2 *)c.take(v64),
-            *t = (double2 *)c.take(v64);
+    double *part_p = (double *)c.take(cg_partials_count(g) * sizeof(double));
+    double2 *r = (double2 *)c.take(v64), *p = (double2 *)c.take(v64), *t = (double2 *)c.take(v64);
     if (!t) return fail(HISQ_EWORKSPACE, "cg_solve: workspace too small");
     CGState *hs = pinned_state();
     if (!hs) return fail(HISQ_EHIP, "cg_solve: pinned state allocation failed");
-    const Launch L(g, st, part);
+    const Launch L(g, st, part, part_p);
 
     auto t0 = std::chrono::steady_clock::now();
     HISQ_HIP(hipMemsetAsync(st, 0, sizeof(CGState), s));
@@ -569,16 +618,15 @@ int cg_plain(double mass, double tol, const void *fat, const void *lng, const vo
     L.norm2(s, (const double2 *)b, FIN_BB);
     HISQ_HIP(launch_dslash<PH>(g, fat, lng, x, t, 1, s));  // r = p = b - A x0
     L.template resid<PH>(s, fat, lng, t, x, b, r, p, nullptr, nullptr, FIN_INIT_PLAIN, GATE_ALWAYS);
+    L.pnorm<double2>(s, p);
     HISQ_HIP(hipGetLastError());
     int rc = read_state(hs, st, s);
     if (rc) return rc;
     if (hs->bb == 0.0) return zero_source_exit(x, v64, s, stats, t0);
 
     auto iter = [&](hipStream_t q) -> hipError_t {
-        hipError_t e = launch_dslash<PH>(g, fat, lng, p, t, 1, q, &st->flags, GATE_NOT_DONE);
-        if (e != hipSuccess) return e;
-        L.ap<PH>(q, fat, lng, t, p, ap);
-        L.update<double2>(q, (double2 *)x, r, p, ap, FIN_UPD_PLAIN);
+        L.dp<PH>(q, fat, lng, p, t);
+        L.ap_update<PH>(q, fat, lng, t, p, x, r, FIN_UPD_PLAIN);
         L.pupd<double2>(q, p, r);
         return hipGetLastError();
     };
@@ -601,6 +649,7 @@ int cg_plain(double mass, double tol, const void *fat, const void *lng, const vo
         if (hs->iter >= o.max_iter || restarts >= 3) { status = HISQ_ENOCONV; break; }
         ++restarts;  // restart from x: r = p = b - A x (t still holds D_oe x)
         L.template resid<PH>(s, fat, lng, t, x, b, r, p, nullptr, nullptr, FIN_INIT_PLAIN, GATE_ALWAYS);
+        L.pnorm<double2>(s, p);
         HISQ_HIP(hipGetLastError());
         rc = read_state(hs, st, s);
         if (rc) return rc;
@@ -626,13 +675,14 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
     const size_t v64 = (size_t)g.Vh * 3 * 16, v32 = (size_t)g.Vh * 3 * 8;
     CGState *st = (CGState *)c.take(sizeof(CGState));
     double *part = (double *)c.take(cg_partials_count(g) * sizeof(double));
+    double *part_p = (double *)c.take(cg_partials_count(g) * sizeof(double));
     double2 *r64 = (double2 *)c.take(v64), *t64 = (double2 *)c.take(v64);
     float2 *xs = (float2 *)c.take(v32), *rs = (float2 *)c.take(v32), *ps = (float2 *)c.take(v32),
-           *aps = (float2 *)c.take(v32), *ts = (float2 *)c.take(v32);
+           *ts = (float2 *)c.take(v32);
     if (!ts) return fail(HISQ_EWORKSPACE, "cg_solve: workspace too small");
     CGState *hs = pinned_state();
     if (!hs) return fail(HISQ_EHIP, "cg_solve: pinned state allocation failed");
-    const Launch L(g, st, part);
+    const Launch L(g, st, part, part_p);
     const double delta = o.delta > 0 ? o.delta : 0.1;
 
     auto t0 = std::chrono::steady_clock::now();
@@ -642,6 +692,7 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
     L.norm2(s, (const double2 *)b, FIN_BB);
     HISQ_HIP(launch_dslash<PH>(g, fat, lng, x, t64, 1, s));
     L.template resid<PH>(s, fat, lng, t64, x, b, r64, nullptr, rs, ps, FIN_INIT_MIXED, GATE_ALWAYS);
+    L.pnorm<float2>(s, ps);
     HISQ_HIP(hipGetLastError());
     int rc = read_state(hs, st, s);
     if (rc) return rc;
@@ -649,13 +700,11 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
 
     const dim3 gb(L.nbl), bb(BL_NT);
     auto iter = [&](hipStream_t q) -> hipError_t {
-        hipError_t e = launch_dslash<PS>(g, fat_lo, lng_lo, ps, ts, 1, q, &st->flags, GATE_NOT_DONE);
-        if (e != hipSuccess) return e;
-        L.ap<PS>(q, fat_lo, lng_lo, ts, ps, aps);
-        L.update<float2>(q, xs, rs, ps, aps, FIN_UPD_MIXED);
+        L.dp<PS>(q, fat_lo, lng_lo, ps, ts);
+        L.ap_update<PS>(q, fat_lo, lng_lo, ts, ps, xs, rs, FIN_UPD_MIXED);
         // reliable update (kernels return at once unless it was triggered)
         hipLaunchKernelGGL(k_accum, gb, bb, 0, q, (double2 *)x, xs, L.n, (const CGState *)st);
-        e = launch_dslash<PH>(g, fat, lng, x, t64, 1, q, &st->flags, GATE_RELIABLE);
+        hipError_t e = launch_dslash<PH>(g, fat, lng, x, t64, 1, q, &st->flags, GATE_RELIABLE);
         if (e != hipSuccess) return e;
         L.template resid<PH>(q, fat, lng, t64, x, b, r64, nullptr, rs, nullptr, FIN_RELIABLE, GATE_RELIABLE);
         L.pupd<float2>(q, ps, rs);

@@ -64,7 +64,10 @@ def test_packed_sizes(dims):
 def test_workspace_sizes():
     import paper_1411_2087_amd as hq
     dims = (8, 8, 8, 8)
-    assert hq.hisq_workspace_bytes("cg", dims, 1, 0) >= 4 * 2048 * 48
-    assert hq.hisq_workspace_bytes("cg", dims, 1, 1) >= 2 * 2048 * 48 + 5 * 2048 * 24
+    # plain: r, p, t (FP64); mixed: r, t (FP64) and x, r, p, t (FP32) -- A p stays in registers
+    assert hq.hisq_workspace_bytes("cg", dims, 1, 0) >= 3 * 2048 * 48
+    assert hq.hisq_workspace_bytes("cg", dims, 1, 1) >= 2 * 2048 * 48 + 4 * 2048 * 24
+    # fat paths: three one-direction link fields
+    assert hq.hisq_workspace_bytes("fat_paths", dims, 0, 0) >= 3 * 4096 * 144
     assert hq.hisq_workspace_bytes("nope", dims, 1, 0) == 0
     assert hq.hisq_workspace_bytes("cg", (4, 4, 4, 5), 1, 0) == 0
