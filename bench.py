@@ -54,16 +54,18 @@ def dslash_source_sha():
 
 
 def traffic_from_profile(vh, shape):
-    """HBM bytes per Dslash launch from committed rocprofv3 counter runs, or None
-    if absent or taken on another version or launch shape of the kernel."""
+    """HBM bytes per launch of the FP64 Dslash in launch shape `shape`, from committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (calibrated against a plain copy), or None
+    if absent or taken on another version of the kernel or lattice."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha") != dslash_source_sha() or t.get("vh") != vh or t.get("shape") != shape:
+    if t.get("source_sha") != dslash_source_sha() or t.get("vh") != vh:
         return None
-    return t.get("bytes_per_launch")
+    row = t.get("per_shape", {}).get(str(shape))
+    return round(row["bytes_per_launch"]) if row else None
 
 
 def cpu_baseline(fat, lng, b, vh, budget_s=15.0):
