@@ -236,7 +236,7 @@ def timed(fn, reps, stream):
 
 
 def link_construction(hq, dims, log):
-    """Three-link products (Sec. 5) and the path-summed one-link matrices from Haar thin links."""
+    """Three-link products (Sec. 4) and the path-summed one-link matrices from Haar thin links."""
     import numpy as np
     import torch
     import synth
@@ -262,7 +262,7 @@ def link_construction(hq, dims, log):
 
 
 def run_paper_grids(args):
-    """Dslash alone on the two lattices of the paper's single-coprocessor runs (Sec. 5, Tables 1-2), every
+    """Dslash alone on the two lattices of the paper's single-coprocessor runs (Sec. 4, Tables 1-2), every
     storage form: microseconds, GFLOP/s at 1146 flops per site, algorithmic GB/s."""
     import numpy as np
     import torch

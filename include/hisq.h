@@ -287,7 +287,7 @@ int fcg_solve(double mass, double tol, const void *fat, const void *lng, const v
               size_t ws_bytes, hisq_cg_stats *stats, void *stream);
 
 /* ------------------------------------------------------------------ link construction
- * Sec. 5 of the paper: the three-link matrices of the Naik term are products
+ * Sec. 4 of the paper: the three-link matrices of the Naik term are products
  * of thin links (matrix-matrix work).  Fields here are canonical complex128
  * [mu][t][z][y][x][3][3] device arrays (4 V matrices, 576 V bytes), periodic
  * indexing, no phases; hisq_fold_links then folds the staggered phases and

@@ -1,7 +1,7 @@
 """Link construction for the improved staggered operator: FP64 reference
 (TEST INFRASTRUCTURE ONLY: used by tests/, never by the library).
 
-Sec. 5 of the paper builds the three-link (Naik) matrices from the thin
+Sec. 4 of the paper builds the three-link (Naik) matrices from the thin
 links and notes that this is matrix-matrix work:
 
     L_mu(n) = U_mu(n) U_mu(n + mu) U_mu(n + 2 mu).

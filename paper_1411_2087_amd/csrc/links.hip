@@ -1,4 +1,4 @@
-// Link construction on the GPU: the three-link (Naik) products of Sec. 5 of
+// Link construction on the GPU: the three-link (Naik) products of Sec. 4 of
 // the paper, path-summed (smeared) one-link matrices and the folding of the
 // staggered phases.
 //

@@ -54,7 +54,7 @@ def test_mixed_cg_48x96(big, mode):
     assert st["rc"] == 0 and tr <= CG_TOL
 
 
-# The two lattices of the paper's single-coprocessor Dslash runs (Sec. 5,
+# The two lattices of the paper's single-coprocessor Dslash runs (Sec. 4,
 # Tables 1-2): every storage form compared with the oracle at every site.
 PAPER_GRIDS = [(32, 32, 32, 128), (32, 40, 24, 96)]
 

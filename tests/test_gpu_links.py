@@ -1,5 +1,5 @@
 """Link construction on the GPU (three-link products, path-summed one-link
-matrices, phase folding; Sec. 5 of the paper) against the oracle.
+matrices, phase folding; Sec. 4 of the paper) against the oracle.
 
 Inputs are Haar SU(3) thin links, so every path product has entries of
 modulus <= 1 and a sum of paths weighted by c is bounded entrywise by

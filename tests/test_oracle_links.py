@@ -1,5 +1,5 @@
 """Pins of the link-construction part of the oracle (three-link products and
-path-summed one-link matrices, Sec. 5 of the paper).
+path-summed one-link matrices, Sec. 4 of the paper).
 
 Checked against closed forms (unit links, pure-gauge fields), gauge
 covariance, an explicit walk along every path of every family at sampled
