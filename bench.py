@@ -205,8 +205,10 @@ def run_large(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         forms[name] = {"s": round(dt, 3), "iters": st["iters"], "reliable_updates": st["reliable_updates"],
-                       "true_resid": st["true_resid"], "rc": st["rc"]}
-        log(f"[48^3x96 {name}] {dt:.2f}s iters={st['iters']} resid={st['true_resid']:.2e}")
+                       "true_resid": st["true_resid"], "rc": st["rc"], "fallback_used": st["fallback_used"],
+                       "fallback_iters": st["fallback_iters"]}
+        log(f"[48^3x96 {name}] {dt:.2f}s iters={st['iters']} resid={st['true_resid']:.2e} "
+            f"fallback={st['fallback_used']} ({st['fallback_iters']} plain iterations)")
         del ws, x
     base = forms["plain_f64"]["s"]
     for k in forms:
@@ -452,7 +454,8 @@ def main():
             dt = time.perf_counter() - t0
             forms[name] = {"s": round(dt, 4), "iters": sm["iters"], "reliable_updates": sm["reliable_updates"],
                            "true_resid": sm["true_resid"], "speedup_vs_plain": round(ms_per_step / 1e3 / dt, 3),
-                           "rc": sm["rc"]}
+                           "rc": sm["rc"], "fallback_used": sm["fallback_used"],
+                           "fallback_iters": sm["fallback_iters"]}
             log(f"[form {name}] {dt:.3f}s iters={sm['iters']} updates={sm['reliable_updates']} "
                 f"resid={sm['true_resid']:.2e}")
             del wsm, xm

@@ -84,7 +84,12 @@ typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16S = 2, HISQ_I16S = 3, HISQ_F6
  * MIXED_F16S : as MIXED_F32 with HISQ_F16S links in the inner Dslash.
  * MIXED_I16S : as MIXED_F32 with HISQ_I16S links in the inner Dslash.
  * PLAIN_F64C : PLAIN_F64 with HISQ_F64C links.
- * MIXED_F32C : MIXED_F32 with HISQ_F64C outer and HISQ_F32C inner links. */
+ * MIXED_F32C : MIXED_F32 with HISQ_F64C outer and HISQ_F32C inner links.
+ * Every mixed mode watches for stagnation: two reliable updates in a row
+ * that do not halve the true residual, or an inner solve that runs ten times
+ * as long as its first cycle (plus 1000 iterations) without triggering an
+ * update, end the mixed iteration; x then absorbs the inner solution and
+ * plain CG on the outer links finishes the solve (stats.fallback_used = 1). */
 enum {
     HISQ_CG_PLAIN_F64 = 0,
     HISQ_CG_MIXED_F32 = 1,
@@ -119,8 +124,9 @@ typedef struct {
     double true_resid;      /* |b - A x| / |b| recomputed in FP64 on the GPU */
     double time_s;          /* wall time of the solve, first kernel to final check */
     int fallback_used;      /* fcg_solve: 0 none; 1 K not positive on r or <p,Ap> <= 0; 2 stall or slow;
-                               3 recursion converged but the true residual did not */
-    int fallback_iters;     /* fcg_solve: plain CG iterations after the fallback */
+                               3 recursion converged but the true residual did not.
+                               cg_solve mixed modes: 0 none; 1 stagnation, finished by plain CG */
+    int fallback_iters;     /* plain CG iterations after the fallback (included in iters) */
 } hisq_cg_stats;
 
 /* Library version string. */

@@ -97,6 +97,8 @@ __device__ __forceinline__ void finalize(CGState *st, int mode, double v)
             st->maxrr = fmax(st->maxrr, v);
             st->beta = v / st->rr;
             st->rr = v;
+            // the inner solve has gone ten times as long as its first cycle without a reliable update
+            if (st->first_gap > 0 && st->iter - st->last_upd > 10 * st->first_gap + 1000) st->flags.done = CG_STALLED;
         }
         break;
     case FIN_INIT_PLAIN:
@@ -107,7 +109,12 @@ __device__ __forceinline__ void finalize(CGState *st, int mode, double v)
     case FIN_TRUE:
         st->rr_true = v;
         break;
-    case FIN_RELIABLE:
+    case FIN_RELIABLE: {
+        const int gap = st->iter - st->last_upd;
+        if (st->first_gap == 0) st->first_gap = gap > 0 ? gap : 1;
+        st->poor = (v > 0.25 * st->rr_upd) ? st->poor + 1 : 0;
+        st->rr_upd = v;
+        st->last_upd = st->iter;
         st->rr_true = v;
         st->nupdates += 1;
         st->beta = v / st->rr;
@@ -116,11 +123,17 @@ __device__ __forceinline__ void finalize(CGState *st, int mode, double v)
         st->flags.reliable = 0;
         if (!isfinite(v)) st->flags.done = CG_BREAKDOWN;
         else if (v <= st->stop2) st->flags.done = CG_CONVERGED;
+        else if (st->poor >= 2) st->flags.done = CG_STALLED;  // the inner operator is too far from A
         break;
+    }
     case FIN_INIT_MIXED:
         st->rr = v;
         st->maxrr = v;
         st->rr_true = v;
+        st->rr_upd = v;
+        st->last_upd = 0;
+        st->first_gap = 0;
+        st->poor = 0;
         st->flags.reliable = 0;
         st->flags.done = (v <= st->stop2) ? CG_CONVERGED : 0;
         break;
@@ -713,6 +726,28 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
 
     rc = run_iterations(iter, s, st, hs, o.check_every, o.max_iter, o.use_graph != 0, 0);
     if (rc) return rc;
+    if (hs->flags.done == CG_STALLED) {
+        // The low-precision operator cannot drive the true residual down: fold
+        // the inner solution into x and finish with plain CG on the outer links.
+        hipLaunchKernelGGL(k_clear_done, dim3(1), dim3(1), 0, s, st);
+        hipLaunchKernelGGL(k_force_reliable, dim3(1), dim3(1), 0, s, st);
+        hipLaunchKernelGGL(k_accum, gb, bb, 0, s, (double2 *)x, xs, L.n, (const CGState *)st);
+        HISQ_HIP(hipGetLastError());
+        const int used = hs->iter, nupd = hs->nupdates;
+        hisq_cg_opts o2 = o;
+        o2.max_iter = o.max_iter - used;
+        if (o2.max_iter <= 0) o2.max_iter = 1;
+        hisq_cg_stats s2;
+        std::memset(&s2, 0, sizeof(s2));
+        rc = cg_plain<PH>(mass, tol, fat, lng, b, x, g, o2, ws, ws_bytes, s2, s);
+        stats = s2;
+        stats.iters = used + s2.iters;
+        stats.reliable_updates = nupd;
+        stats.fallback_used = 1;
+        stats.fallback_iters = s2.iters;
+        stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return rc;
+    }
     int status = HISQ_OK;
     if (hs->flags.done == CG_BREAKDOWN) {
         status = HISQ_EBREAKDOWN;

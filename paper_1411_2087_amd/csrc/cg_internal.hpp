@@ -5,7 +5,7 @@
 
 namespace hisq {
 
-enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
+enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2, CG_STALLED = 3 };
 constexpr int BLAS_MAX_BLOCKS = 1024;
 
 // Device-resident scalars of one solve.  `flags` comes first: kernels gate on it.
@@ -23,6 +23,13 @@ struct CGState {
     double rr_true;  // last FP64 true residual |b - A x|^2
     double maxrr;    // max |r_inner|^2 since the last reliable update
     double alpha, beta, pAp;
+    // stagnation watch of the mixed solver (reliable updates that do not
+    // reduce the true residual, or an inner solve that stops triggering them)
+    double rr_upd;   // true |r|^2 at the last reliable update (or the start)
+    int last_upd;    // iteration of the last reliable update
+    int first_gap;   // iterations from the start to the first reliable update
+    int poor;        // consecutive reliable updates that did not halve |r|
+    int pad_;
 };
 
 int blas_blocks(long long n);

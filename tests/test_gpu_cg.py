@@ -73,8 +73,35 @@ def test_cg_mixed(hq, mode):
     tr = oracle.true_residual(dims, mass, fat, lng, b, x)
     _, info = oracle.cg(dims, mass, fat, lng, b, tol=CG_TOL)
     say(f"cg mixed mode={mode} 8^4: iters={st['iters']} updates={st['reliable_updates']} gpu_resid="
-        f"{st['true_resid']:.3e} oracle_resid={tr:.3e} (plain oracle iters {info['iters']})")
+        f"{st['true_resid']:.3e} oracle_resid={tr:.3e} fallback={st['fallback_used']} "
+        f"(plain oracle iters {info['iters']})")
     assert st["rc"] == 0 and tr <= CG_TOL
+    if mode != 2:
+        assert st["fallback_used"] == 0
+
+
+def test_cg_mixed_falls_back_on_a_wrong_inner_operator(hq):
+    """Inner links of another gauge field: the inner solves converge to the wrong
+    answer, reliable updates stop reducing the true residual, and plain FP64 CG
+    on the outer links finishes the solve."""
+    import torch
+    dims, mass = (8, 8, 8, 8), 0.05
+    fat, lng = fields(dims, synth.gauge_seed(1))
+    fat_w, lng_w = fields(dims, synth.gauge_seed(12))
+    b = synth.source(dims, synth.source_seed(1))
+    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
+    Lw = hq.fields.Links.pack(fat_w, lng_w, dims, hq.HISQ_F32)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    opts = hq.CGOpts(mode=1, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    st = hq.cg_solve(mass, CG_TOL, L64.fat, L64.lng, Lw.fat, Lw.lng, bd, xd, dims, opts,
+                     hq.fields.workspace("cg", dims, 1, 1))
+    tr = oracle.true_residual(dims, mass, fat, lng, b, xd.cpu().numpy())
+    say(f"cg mixed, wrong inner links: iters={st['iters']} updates={st['reliable_updates']} "
+        f"fallback={st['fallback_used']} after {st['iters'] - st['fallback_iters']} inner iterations, "
+        f"oracle_resid={tr:.3e}")
+    assert st["rc"] == 0 and tr <= CG_TOL
+    assert st["fallback_used"] == 1 and 0 < st["fallback_iters"] < st["iters"]
 
 
 def test_cg_zero_source_and_limits(hq):
@@ -114,5 +141,5 @@ def test_cg_32_4(hq):
         xm, sm = _solve(hq, dims, fat, lng, b, mass, mode)
         trm = oracle.true_residual(dims, mass, fat, lng, b, xm)
         say(f"cg 32^4 mode {mode}: iters={sm['iters']} updates={sm['reliable_updates']} oracle_resid={trm:.3e} "
-            f"time={sm['time_s']:.3f}s")
-        assert sm["rc"] == 0 and trm <= CG_TOL
+            f"time={sm['time_s']:.3f}s fallback={sm['fallback_used']}")
+        assert sm["rc"] == 0 and trm <= CG_TOL and sm["fallback_used"] == 0
