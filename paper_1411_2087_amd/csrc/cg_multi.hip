@@ -540,6 +540,41 @@ __global__ __launch_bounds__(MB_NT) void k_to_double(const float2 *__restrict__ 
         out[i] = make_double2((double)in[i].x, (double)in[i].y);
 }
 
+// Column list of a batch compaction: new column c takes old column col[c]
+// (c < n); columns n..N2-1 of the new batch are zero.
+struct Cols {
+    int col[MAXR];
+    int n;
+};
+
+// dst [Vh][N2][3] <- the listed columns of src [Vh][N][3]
+template <class T, int N, int N2>
+__global__ __launch_bounds__(MB_NT) void k_mcompact(const T *__restrict__ src, T *__restrict__ dst, long long vh,
+                                                    Cols cols)
+{
+    const long long tot = vh * N2 * 3;
+    for (long long i = (long long)blockIdx.x * MB_NT + threadIdx.x; i < tot; i += (long long)gridDim.x * MB_NT) {
+        const int k = (int)(i % 3);
+        const int c = (int)((i / 3) % N2);
+        const long long h = i / (3 * N2);
+        T v;
+        v.x = 0;
+        v.y = 0;
+        if (c < cols.n) v = src[(h * N + cols.col[c]) * 3 + k];
+        dst[i] = v;
+    }
+}
+
+// out [Vh][3] <- column `col` of x [Vh][N][3]
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_mcolumn(const double2 *__restrict__ x, double2 *__restrict__ out,
+                                                   long long vh, int col)
+{
+    const long long tot = vh * 3;
+    for (long long i = (long long)blockIdx.x * MB_NT + threadIdx.x; i < tot; i += (long long)gridDim.x * MB_NT)
+        out[i] = x[((i / 3) * N + col) * 3 + (i % 3)];
+}
+
 // ------------------------------------------------------------------ finalisers
 enum {
     FM_BB = 0,        // bb_r, stop2_r
@@ -828,8 +863,13 @@ struct MultiHost {
     }
 };
 
+// run_multi returns MULTI_SHRINK (> 0) when at a state check no more than
+// `shrink_at` right-hand sides are still iterating.
+constexpr int MULTI_SHRINK = 1;
+
 template <class F>
-static int run_multi(F iter_fn, hipStream_t s, MultiState *dst, MultiState *hst, int K, int max_iter, bool graph)
+static int run_multi(F iter_fn, hipStream_t s, MultiState *dst, MultiState *hst, int K, int max_iter, bool graph,
+                     int shrink_at = -1)
 {
     hipGraphExec_t exec = nullptr;
     hipGraph_t gr = nullptr;
@@ -867,6 +907,7 @@ static int run_multi(F iter_fn, hipStream_t s, MultiState *dst, MultiState *hst,
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { rc = hip_fail(e, "batched CG state read-back"); break; }
         if (hst->flags.done) break;
+        if (shrink_at >= 0 && __builtin_popcount(hst->active) <= shrink_at) { rc = MULTI_SHRINK; break; }
     }
     if (exec) hipGraphExecDestroy(exec);
     if (gr) hipGraphDestroy(gr);
@@ -880,11 +921,19 @@ static int read_mstate(MultiState *h, const MultiState *d, hipStream_t s)
     return HISQ_OK;
 }
 
-// Batched reliable-update CG on B.b64 from B.x64 (both [Vh][N][3] FP64).
+// Results of the right-hand sides as they leave the batch, by caller index.
+struct MultiOut {
+    double2 *x;        // caller's x [n][Vh][3]
+    int orig[MAXR];    // batch column -> caller index
+    int iters[MAXR], nupd[MAXR], status[MAXR];
+    double rr_true[MAXR], bb[MAXR];
+};
+
+// Batched reliable-update CG, set-up: R64 = B - A X64 for every RHS, RS =
+// float(R64), PS = RS (B.b64 and B.x64 [Vh][N][3] FP64 on entry).
 template <int N>
-static int multi_rhs_core(int n, const double *masses, double tol, const void *fat, const void *lng,
-                          const void *fat_lo, const void *lng_lo, const Geom &g, const hisq_cg_opts &o,
-                          MultiBufs &B, MultiState *hs, hipStream_t s, int iter_offset)
+static int multi_rhs_init(int n, const double *masses, double tol, const void *fat, const void *lng, const Geom &g,
+                          const hisq_cg_opts &o, MultiBufs &B, MultiState *hs, hipStream_t s)
 {
     const long long np = (long long)g.Vh * N;
     const int nbm = mblocks(np);
@@ -897,8 +946,6 @@ static int multi_rhs_core(int n, const double *masses, double tol, const void *f
     hipLaunchKernelGGL((k_mnorm<N>), dim3(nbm), dim3(MB_NT), 0, s, (const double2 *)B.b64, np, B.part);
     hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nbm, B.st, (int)FM_BB,
                        (int)GATE_ALWAYS);
-    // R64 = B - A X64 for every RHS, RS = float(R64), PS = RS
-    const int shape = mshape_for(g, N);
     int nb = 0;
     HISQ_HIP((launch_md_shape<PF64, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
                                                   B.st, MASK_ALL, GATE_ALWAYS, s, &nb)));
@@ -907,9 +954,93 @@ static int multi_rhs_core(int n, const double *masses, double tol, const void *f
     hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nb, B.st, (int)FM_INIT,
                        (int)GATE_ALWAYS);
     HISQ_HIP(hipMemcpyAsync(B.ps, B.rs, (size_t)np * 3 * 8, hipMemcpyDeviceToDevice, s));
-    int rc = read_mstate(hs, B.st, s);
-    if (rc) return rc;
+    return read_mstate(hs, B.st, s);
+}
 
+template <int N>
+static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, const void *lng_lo, const Geom &g,
+                         const hisq_cg_opts &o, MultiBufs &B, MultiState *hs, hipStream_t s, int iter_offset,
+                         MultiOut &out);
+
+// column c of the batch leaves: its FP64 solution goes to the caller's x
+template <int N>
+static void retire(MultiBufs &B, const MultiState *hs, const Geom &g, int c, MultiOut &out, hipStream_t s)
+{
+    const int r = out.orig[c];
+    hipLaunchKernelGGL((k_mcolumn<N>), dim3(mblocks((long long)g.Vh)), dim3(MB_NT), 0, s, (const double2 *)B.x64,
+                       out.x + (size_t)r * g.Vh * 3, (long long)g.Vh, c);
+    out.iters[r] = hs->iters[c];
+    out.nupd[r] = hs->nupd[c];
+    out.status[r] = hs->status[c];
+    out.rr_true[r] = hs->rr_true[c];
+    out.bb[r] = hs->bb[c];
+}
+
+// The batch shrinks to the next power of two that holds the right-hand
+// sides still iterating: finished columns leave, the live ones are packed
+// into [Vh][N2][3] in the same buffers (through the scratch vectors t64 and
+// ts), their per-RHS state moves with them, and the iteration continues
+// with the N2 kernels.  Nothing restarts: x, r, p and every scalar are kept.
+template <int N, int N2>
+static int shrink_to(const void *fat, const void *lng, const void *fat_lo, const void *lng_lo, const Geom &g,
+                     const hisq_cg_opts &o, MultiBufs &B, MultiState *hs, hipStream_t s, int iter_offset,
+                     MultiOut &out, const Cols &live)
+{
+    const long long vh = g.Vh, np = vh * N, np2 = vh * N2;
+    const int nbm = mblocks(np), nb2 = mblocks(np2);
+    hipLaunchKernelGGL((k_mcompact<double2, N, N2>), dim3(nb2), dim3(MB_NT), 0, s, (const double2 *)B.x64, B.t64, vh,
+                       live);
+    HISQ_HIP(hipMemcpyAsync(B.x64, B.t64, (size_t)np2 * 48, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL((k_mcompact<double2, N, N2>), dim3(nb2), dim3(MB_NT), 0, s, (const double2 *)B.b64, B.t64, vh,
+                       live);
+    HISQ_HIP(hipMemcpyAsync(B.b64, B.t64, (size_t)np2 * 48, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL((k_mcompact<float2, N, N2>), dim3(nb2), dim3(MB_NT), 0, s, (const float2 *)B.rs, B.ts, vh, live);
+    HISQ_HIP(hipMemcpyAsync(B.rs, B.ts, (size_t)np2 * 24, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL((k_mcompact<float2, N, N2>), dim3(nb2), dim3(MB_NT), 0, s, (const float2 *)B.ps, B.ts, vh, live);
+    HISQ_HIP(hipMemcpyAsync(B.ps, B.ts, (size_t)np2 * 24, hipMemcpyDeviceToDevice, s));
+    HISQ_HIP(hipMemsetAsync(B.xs, 0, (size_t)np * 24, s));
+    (void)nbm;
+    // the state, compacted on the host
+    MultiState ns = *hs;
+    int orig2[MAXR];
+    for (int c = 0; c < MAXR; ++c) {
+        const bool on = c < live.n;
+        const int k = on ? live.col[c] : 0;
+        orig2[c] = on ? out.orig[k] : -1;
+        ns.iters[c] = on ? hs->iters[k] : 0;
+        ns.nupd[c] = on ? hs->nupd[k] : 0;
+        ns.status[c] = on ? hs->status[k] : HISQ_OK;
+        ns.m4[c] = on ? hs->m4[k] : 0.0;
+        ns.bb[c] = on ? hs->bb[k] : 0.0;
+        ns.stop2[c] = on ? hs->stop2[k] : 0.0;
+        ns.rr[c] = on ? hs->rr[k] : 0.0;
+        ns.rr_true[c] = on ? hs->rr_true[k] : 0.0;
+        ns.maxrr[c] = on ? hs->maxrr[k] : 0.0;
+        ns.alpha[c] = on ? hs->alpha[k] : 0.0;
+        ns.beta[c] = on ? hs->beta[k] : 0.0;
+    }
+    ns.n = live.n;
+    ns.active = (1u << live.n) - 1u;
+    ns.relmask = 0;
+    ns.flags.done = 0;
+    ns.flags.reliable = 0;
+    *hs = ns;
+    std::memcpy(out.orig, orig2, sizeof(orig2));
+    HISQ_HIP(hipMemcpyAsync(B.st, hs, sizeof(MultiState), hipMemcpyHostToDevice, s));
+    HISQ_HIP(hipStreamSynchronize(s));
+    return multi_rhs_run<N2>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out);
+}
+
+// Batched reliable-update CG iterations from the state multi_rhs_init (or a
+// shrink) left; every right-hand side ends in the caller's x and in `out`.
+template <int N>
+static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, const void *lng_lo, const Geom &g,
+                         const hisq_cg_opts &o, MultiBufs &B, MultiState *hs, hipStream_t s, int iter_offset,
+                         MultiOut &out)
+{
+    const long long np = (long long)g.Vh * N;
+    const int nbm = mblocks(np);
+    const int shape = mshape_for(g, N);
     auto iter = [&](hipStream_t q) -> hipError_t {
         int nb1 = 0;
         hipError_t e = launch_md_shape<PF32, N, EPI_STORE>(shape, g, fat_lo, lng_lo, B.ps, B.ts, nullptr, nullptr,
@@ -940,14 +1071,38 @@ static int multi_rhs_core(int n, const double *masses, double tol, const void *f
                            (const MultiState *)B.st);
         return hipGetLastError();
     };
+    int rc = HISQ_OK;
     if (!hs->flags.done) {
-        rc = run_multi(iter, s, B.st, hs, o.check_every, std::max(1, o.max_iter - iter_offset), o.use_graph != 0);
-        if (rc) return rc;
+        const int budget = std::max(1, o.max_iter - iter_offset - hs->iter);
+        rc = run_multi(iter, s, B.st, hs, o.check_every, budget, o.use_graph != 0, N > 1 ? N / 2 : -1);
+        if (rc < 0) return rc;
+    }
+    if constexpr (N > 1) {
+        if (rc == MULTI_SHRINK) {
+            // fold every inner solution (x64 += xs, xs = 0), let the finished columns leave
+            hipLaunchKernelGGL(k_mforce_reliable, dim3(1), dim3(1), 0, s, B.st);
+            hipLaunchKernelGGL((k_maccum<N>), dim3(nbm), dim3(MB_NT), 0, s, B.x64, B.xs, np, (const MultiState *)B.st,
+                               (int)MASK_ALL, (int)GATE_ALWAYS);
+            Cols live;
+            live.n = 0;
+            for (int c = 0; c < hs->n; ++c) {
+                if ((hs->active >> c) & 1u) live.col[live.n++] = c;
+                else retire<N>(B, hs, g, c, out, s);
+            }
+            HISQ_HIP(hipGetLastError());
+            const int n2 = pad_n(live.n);
+            if (n2 == 1) return shrink_to<N, 1>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
+            if constexpr (N > 2) if (n2 == 2) return shrink_to<N, 2>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
+            if constexpr (N > 4) if (n2 == 4) return shrink_to<N, 4>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
+            if constexpr (N > 8) if (n2 == 8) return shrink_to<N, 8>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
+            return fail(HISQ_EINVAL, "cg_solve_multi: internal batch size error");
+        }
     }
     // fold the inner solutions of RHS still running and measure every true residual
     hipLaunchKernelGGL(k_mforce_reliable, dim3(1), dim3(1), 0, s, B.st);
     hipLaunchKernelGGL((k_maccum<N>), dim3(nbm), dim3(MB_NT), 0, s, B.x64, B.xs, np, (const MultiState *)B.st,
                        (int)MASK_ALL, (int)GATE_ALWAYS);
+    int nb = 0;
     HISQ_HIP((launch_md_shape<PF64, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
                                                   B.st, MASK_ALL, GATE_ALWAYS, s, &nb)));
     HISQ_HIP((launch_md_shape<PF64, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
@@ -955,7 +1110,11 @@ static int multi_rhs_core(int n, const double *masses, double tol, const void *f
     hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nb, B.st, (int)FM_FINAL,
                        (int)GATE_ALWAYS);
     HISQ_HIP(hipGetLastError());
-    return read_mstate(hs, B.st, s);
+    rc = read_mstate(hs, B.st, s);
+    if (rc) return rc;
+    for (int c = 0; c < hs->n; ++c) retire<N>(B, hs, g, c, out, s);
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
 }
 
 // Shifted CG for one source and n shifts in FP32 (stage 1 of MULTI_SHIFT);
@@ -1036,22 +1195,25 @@ static int cg_multi_impl(int n, const double *masses, double tol, int mode, cons
                            n, 0);
     }
     HISQ_HIP(hipGetLastError());
-    int rc = multi_rhs_core<N>(n, masses, tol, fat, lng, fat_lo, lng_lo, g, o, B, H.h, s, offset);
+    int rc = multi_rhs_init<N>(n, masses, tol, fat, lng, g, o, B, H.h, s);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_from_batched<N>), dim3(nbm), dim3(MB_NT), 0, s, (const double2 *)B.x64, (double2 *)x,
-                       (long long)g.Vh, n);
-    HISQ_HIP(hipGetLastError());
+    MultiOut out;
+    std::memset(&out, 0, sizeof(out));
+    out.x = (double2 *)x;
+    for (int c = 0; c < MAXR; ++c) out.orig[c] = c < n ? c : -1;
+    rc = multi_rhs_run<N>(fat, lng, fat_lo, lng_lo, g, o, B, H.h, s, offset, out);
+    if (rc) return rc;
     HISQ_HIP(hipStreamSynchronize(s));
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     int worst = HISQ_OK;
     for (int r = 0; r < n; ++r) {
-        const MultiState *h = H.h;
-        const double tr = h->bb[r] > 0 ? std::sqrt(h->rr_true[r] / h->bb[r]) : 0.0;
-        int st = h->bb[r] == 0.0 ? HISQ_OK : (tr <= tol ? HISQ_OK : (h->status[r] == HISQ_EBREAKDOWN ? HISQ_EBREAKDOWN : HISQ_ENOCONV));
+        const double tr = out.bb[r] > 0 ? std::sqrt(out.rr_true[r] / out.bb[r]) : 0.0;
+        int st = out.bb[r] == 0.0 ? HISQ_OK
+                                  : (tr <= tol ? HISQ_OK : (out.status[r] == HISQ_EBREAKDOWN ? HISQ_EBREAKDOWN : HISQ_ENOCONV));
         if (st != HISQ_OK && worst == HISQ_OK) worst = st;
         if (stats) {
-            stats[r].iters = h->iters[r] + ms_iters[r];
-            stats[r].reliable_updates = h->nupd[r];
+            stats[r].iters = out.iters[r] + ms_iters[r];
+            stats[r].reliable_updates = out.nupd[r];
             stats[r].restarts = 0;
             stats[r].status = st;
             stats[r].true_resid = tr;
