@@ -41,7 +41,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_dslash(Geom g, const char 
 
 // y = m4 * x - D src on parity 0 (second half of A = 4m^2 - D_eo D_oe)
 template <class P, int NT>
-__global__ __launch_bounds__(NT) HISQ_WAVES(P::prec == HISQ_F64C ? 6 : 8) void k_dslash_axmy(Geom g, const char *__restrict__ fat,
+__global__ __launch_bounds__(NT) HISQ_WAVES((P::prec == HISQ_F64 || P::prec == HISQ_F64C) ? 6 : 8) void k_dslash_axmy(Geom g, const char *__restrict__ fat,
                                                     const char *__restrict__ lng,
                                                     const typename P::cvec *__restrict__ src,
                                                     const typename P::cvec *__restrict__ x,
