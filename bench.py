@@ -219,6 +219,31 @@ def run_large(args):
                       "dslash": {str(k): v for k, v in dsl.items()}, "forms": forms}))
 
 
+def traffic_probe_at(workload):
+    """A 1 GiB copy (counter calibration) and 5 FP64 Dslash launches in launch shape 6 on the lattice
+    `workload` ("LxxLyxLzxLt"), for rocprofv3 counter runs."""
+    import torch
+    import paper_1411_2087_amd as hq
+    import synth
+    dims = tuple(int(v) for v in workload.split("x"))
+    fat, lng = synth.links(dims, synth.gauge_seed(3))
+    L = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
+    del fat, lng
+    b = torch.from_numpy(synth.source(dims, synth.source_seed(3))).cuda()
+    t = torch.empty_like(b)
+    n = 1 << 30
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    hq.hisq_dslash_shape(dims, hq.HISQ_F64, 6)
+    for _ in range(5):
+        hq.dslash_apply(L.fat, L.lng, b, t, 1, dims, hq.HISQ_F64)
+    torch.cuda.synchronize()
+    print(json.dumps({"traffic_probe": True, "copy_bytes": n, "dslash_launches": 5, "vh": int(b.shape[0]),
+                      "shape": 6, "workload": workload}))
+
+
 PAPER_GRIDS = ((32, 32, 32, 128), (32, 40, 24, 96))
 MATMUL_FLOPS = 198        # 3x3 complex product: 27 complex multiplies (6) + 18 complex adds (2)
 
@@ -323,7 +348,8 @@ def main():
                          "(mixed precision against plain FP64 on the large lattice) or paper-grids (the Dslash "
                          "on 32^3x128 and 32x40x24x96); the last two are report lines, not the metric")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="only run a 2 GiB copy and the FP64 Dslash (for rocprofv3 counter runs)")
+                    help="only run a 1 GiB copy and the FP64 Dslash (for rocprofv3 counter runs); with --workload "
+                         "LxxLyxLzxLt on that lattice")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path has no multi-GPU "
@@ -336,6 +362,8 @@ def main():
     import paper_1411_2087_amd as hq
     import synth
 
+    if args.traffic_probe and args.workload != "32x32x32x32":
+        return traffic_probe_at(args.workload)
     if args.workload == "48x48x48x96":
         return run_large(args)
     if args.workload == "paper-grids":
