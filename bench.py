@@ -185,7 +185,8 @@ def run_large(args):
         s_, d_ = b.to(dt), torch.empty(b.shape, dtype=dt, device="cuda")
         best, us = hq.hisq_tune_dslash(L[p].fat, L[p].lng, s_, d_, dims, p, reps=10)
         t = min(us) * 1e-6
-        dsl[p] = {"us": round(t * 1e6, 1), "gbs": round(hq.DSLASH_BYTES_PER_SITE[p] * vh / t / 1e9, 1)}
+        dsl[p] = {"us": round(t * 1e6, 1), "gbs": round(hq.DSLASH_BYTES_PER_SITE[p] * vh / t / 1e9, 1), "shape": best,
+                  "us_per_shape": [round(u, 1) for u in us]}
         log(f"[dslash 48^3x96] prec {p}: {dsl[p]}")
         del s_, d_
     forms = {}
@@ -220,8 +221,8 @@ def run_large(args):
 
 
 def traffic_probe_at(workload):
-    """A 1 GiB copy (counter calibration) and 5 FP64 Dslash launches in launch shape 6 on the lattice
-    `workload` ("LxxLyxLzxLt"), for rocprofv3 counter runs."""
+    """A 1 GiB copy (counter calibration) and 5 FP64 Dslash launches in each of launch shapes 6 and 8 (plain
+    and blocked tile order) on the lattice `workload` ("LxxLyxLzxLt"), for rocprofv3 counter runs."""
     import torch
     import paper_1411_2087_amd as hq
     import synth
@@ -236,12 +237,13 @@ def traffic_probe_at(workload):
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
-    hq.hisq_dslash_shape(dims, hq.HISQ_F64, 6)
-    for _ in range(5):
-        hq.dslash_apply(L.fat, L.lng, b, t, 1, dims, hq.HISQ_F64)
+    for shape in (6, 8):  # plain and blocked tile order, 5 launches each
+        hq.hisq_dslash_shape(dims, hq.HISQ_F64, shape)
+        for _ in range(5):
+            hq.dslash_apply(L.fat, L.lng, b, t, 1, dims, hq.HISQ_F64)
     torch.cuda.synchronize()
     print(json.dumps({"traffic_probe": True, "copy_bytes": n, "dslash_launches": 5, "vh": int(b.shape[0]),
-                      "shape": 6, "workload": workload}))
+                      "shapes": [6, 8], "workload": workload}))
 
 
 PAPER_GRIDS = ((32, 32, 32, 128), (32, 40, 24, 96))

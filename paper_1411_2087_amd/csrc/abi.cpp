@@ -42,7 +42,25 @@ int make_geom(const int dims[4], Geom &g)
     g.sy = g.Lxh;
     g.sz = g.Lxh * dims[1];
     g.st = g.Lxh * dims[1] * dims[2];
+    g.oP = g.otb = g.ozb = g.ontb = 0;
     return HISQ_OK;
+}
+
+static int block_of(int L)
+{
+    for (int b : { 8, 6, 4, 2 })
+        if (L % b == 0) return b;
+    return 1;
+}
+
+bool blocked_order(Geom &g)
+{
+    if ((g.Lxh * g.L[1]) % TILE) return false;
+    g.oP = g.Lxh * g.L[1] / TILE;
+    g.otb = block_of(g.L[3]);
+    g.ozb = block_of(g.L[2]);
+    g.ontb = g.L[3] / g.otb;
+    return true;
 }
 
 }  // namespace hisq

@@ -298,11 +298,12 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_cg_Dp(Geom g, const char *
     if (st->flags.done) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     if (blk >= nblocks) return;
-    const int tile = blk * (NT / TILE) + (threadIdx.x >> 6);
+    const int k = blk * (NT / TILE) + (threadIdx.x >> 6);
+    const int tile = k < g.ntiles ? tile_of(g, k) : 0;
     const int lane = threadIdx.x & 63;
     const int h = tile * TILE + lane;
     double s = 0.0;
-    if (tile < g.ntiles) {
+    if (k < g.ntiles) {
         const int hc = h < g.Vh ? h : g.Vh - 1;
         typename P::real acc[6];
         dslash_site<P>(g, fat, lng, p, 1, tile, lane, hc, acc);
@@ -335,11 +336,12 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_cg_Ap_upd(Geom g, const ch
     if (st->flags.done) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     if (blk >= nblocks) return;
-    const int tile = blk * (NT / TILE) + (threadIdx.x >> 6);
+    const int k = blk * (NT / TILE) + (threadIdx.x >> 6);
+    const int tile = k < g.ntiles ? tile_of(g, k) : 0;
     const int lane = threadIdx.x & 63;
     const int h = tile * TILE + lane;
     double s = 0.0;
-    if (tile < g.ntiles) {
+    if (k < g.ntiles) {
         const int hc = h < g.Vh ? h : g.Vh - 1;
         typename P::real acc[6];
         dslash_site<P>(g, fat, lng, t, 0, tile, lane, hc, acc);
@@ -378,11 +380,12 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(cg_waves<PH>()) void k_resid(Geom g,
     if (gate_closed(&st->flags, gate)) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     if (blk >= nblocks) return;
-    const int tile = blk * (NT / TILE) + (threadIdx.x >> 6);
+    const int k = blk * (NT / TILE) + (threadIdx.x >> 6);
+    const int tile = k < g.ntiles ? tile_of(g, k) : 0;
     const int lane = threadIdx.x & 63;
     const int h = tile * TILE + lane;
     double s = 0.0;
-    if (tile < g.ntiles) {
+    if (k < g.ntiles) {
         const int hc = h < g.Vh ? h : g.Vh - 1;
         double acc[6];
         dslash_site<PH>(g, fat, lng, t, 0, tile, lane, hc, acc);
@@ -587,6 +590,15 @@ struct Launch {
     }
 };
 
+// The fused CG kernels follow the tile order of the Dslash shape tuned for
+// (lattice, precision of their links).
+static Geom cg_geom(const Geom &g, int prec)
+{
+    Geom c = g;
+    if (DSLASH_SHAPES[tuned_dslash_shape(g, prec)].order) blocked_order(c);
+    return c;
+}
+
 static void finish_stats(hisq_cg_stats &stats, const CGState *hs, int status, int restarts,
                          std::chrono::steady_clock::time_point t0)
 {
@@ -623,7 +635,8 @@ int cg_plain(double mass, double tol, const void *fat, const void *lng, const vo
     if (!t) return fail(HISQ_EWORKSPACE, "cg_solve: workspace too small");
     CGState *hs = pinned_state();
     if (!hs) return fail(HISQ_EHIP, "cg_solve: pinned state allocation failed");
-    const Launch L(g, st, part, part_p);
+    const Geom gc = cg_geom(g, PH::prec);
+    const Launch L(gc, st, part, part_p);
 
     auto t0 = std::chrono::steady_clock::now();
     HISQ_HIP(hipMemsetAsync(st, 0, sizeof(CGState), s));
@@ -695,7 +708,8 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
     if (!ts) return fail(HISQ_EWORKSPACE, "cg_solve: workspace too small");
     CGState *hs = pinned_state();
     if (!hs) return fail(HISQ_EHIP, "cg_solve: pinned state allocation failed");
-    const Launch L(g, st, part, part_p);
+    const Geom gc = cg_geom(g, PS::prec);
+    const Launch L(gc, st, part, part_p);
     const double delta = o.delta > 0 ? o.delta : 0.1;
 
     auto t0 = std::chrono::steady_clock::now();

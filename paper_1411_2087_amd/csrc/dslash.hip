@@ -11,7 +11,7 @@
 
 namespace hisq {
 
-template <class P, int NT, int W, int UNR>
+template <class P, int NT, int W, int UNR, int ORD>
 __global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_dslash(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
                                                const typename P::cvec *__restrict__ src,
                                                typename P::cvec *__restrict__ dst, int parity, int nblocks,
@@ -20,8 +20,9 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_dslash(Geom g, const char 
     if (gate_closed(flags, gate)) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     if (blk >= nblocks) return;
-    const int tile = blk * (NT / TILE) + (threadIdx.x >> 6);
-    if (tile >= g.ntiles) return;
+    const int k = blk * (NT / TILE) + (threadIdx.x >> 6);
+    if (k >= g.ntiles) return;
+    const int tile = ORD ? tile_of(g, k) : k;
     const int lane = threadIdx.x & 63;
     const int h = tile * TILE + lane;
     const int hc = h < g.Vh ? h : g.Vh - 1;
@@ -69,22 +70,28 @@ __global__ __launch_bounds__(NT) HISQ_WAVES((P::prec == HISQ_F64 || P::prec == H
 }
 
 // Launch shapes of the single-RHS Dslash: threads per block, minimum
-// wavefronts per SIMD (1 = no constraint) and how many of the 16 terms are
-// unrolled together.  All shapes compute every site with the same arithmetic
-// in the same order, so their outputs are bitwise identical; the autotuner
-// picks one per (lattice, precision).
+// wavefronts per SIMD (1 = no constraint), how many of the 16 terms are
+// unrolled together and the tile order.  All shapes compute every site with
+// the same arithmetic in the same order, so their outputs are bitwise
+// identical; the autotuner picks one per (lattice, precision).
 const DslashShape DSLASH_SHAPES[N_DSLASH_SHAPES] = {
-    { 256, 8, 1 }, { 128, 8, 1 }, { 64, 8, 1 }, { 256, 1, 16 }, { 256, 4, 4 }, { 512, 8, 1 }, { 256, 6, 1 },
+    { 256, 8, 1, 0 }, { 128, 8, 1, 0 }, { 64, 8, 1, 0 }, { 256, 1, 16, 0 }, { 256, 4, 4, 0 },
+    { 512, 8, 1, 0 }, { 256, 6, 1, 0 }, { 256, 8, 1, 1 }, { 256, 6, 1, 1 },
 };
 
 static inline int blocks_for(const Geom &g, int nt) { return (g.ntiles + nt / TILE - 1) / (nt / TILE); }
 
-template <class P, int NT, int W, int UNR>
-static void launch_shape(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, int parity,
+template <class P, int NT, int W, int UNR, int ORD = 0>
+static void launch_shape(const Geom &g0, const void *fat, const void *lng, const void *src, void *dst, int parity,
                          hipStream_t s, const SolverFlags *flags, int gate)
 {
+    Geom g = g0;
+    if (ORD && !blocked_order(g)) {  // the lattice has no blocked order: plain order
+        launch_shape<P, NT, W, UNR, 0>(g0, fat, lng, src, dst, parity, s, flags, gate);
+        return;
+    }
     const int nb = blocks_for(g, NT);
-    hipLaunchKernelGGL((k_dslash<P, NT, W, UNR>), dim3(xcd_grid(nb)), dim3(NT), 0, s, g, (const char *)fat,
+    hipLaunchKernelGGL((k_dslash<P, NT, W, UNR, ORD>), dim3(xcd_grid(nb)), dim3(NT), 0, s, g, (const char *)fat,
                        (const char *)lng, (const typename P::cvec *)src, (typename P::cvec *)dst, parity, nb, flags,
                        gate);
 }
@@ -100,6 +107,8 @@ hipError_t launch_dslash_shape(int shape, const Geom &g, const void *fat, const 
     case 4: launch_shape<P, 256, 4, 4>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     case 5: launch_shape<P, 512, 8, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     case 6: launch_shape<P, 256, 6, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 7: launch_shape<P, 256, 8, 1, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 8: launch_shape<P, 256, 6, 1, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     default: launch_shape<P, 256, 8, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     }
     return hipGetLastError();

@@ -34,9 +34,32 @@ struct Geom {
     int Vh;      // sites per parity
     int ntiles;  // ceil(Vh / 64)
     int sy, sz, st;  // h-strides of y, z, t: Lxh, Lxh*Ly, Lxh*Ly*Lz
+    // Tile processing order (oP == 0: tile k is processed k-th).  Blocked:
+    // the oP tiles of one (z, t) plane, then otb planes along t, then ozb
+    // along z, then the next t block, then the next z block, so that the
+    // +-1 and +-3 neighbours in t and z of the tiles in flight were read a
+    // few hundred tiles earlier and are still in L2.
+    int oP, otb, ozb, ontb;
 };
 
 int make_geom(const int dims[4], Geom &g);  // HISQ_OK or HISQ_EDIMS/EINVAL
+// Switch g to the blocked tile order; false (g unchanged) when a tile would
+// straddle two (z, t) planes (Lx/2 * Ly not a multiple of 64).
+bool blocked_order(Geom &g);
+
+// tile processed k-th
+__device__ __forceinline__ int tile_of(const Geom &g, int k)
+{
+    if (g.oP == 0) return k;
+    const int p = k % g.oP;
+    int r = k / g.oP;
+    const int ti = r % g.otb;
+    r /= g.otb;
+    const int zi = r % g.ozb;
+    r /= g.ozb;
+    const int tB = r % g.ontb, zB = r / g.ontb;
+    return p + g.oP * (zB * g.ozb + zi + g.L[2] * (tB * g.otb + ti));
+}
 
 // Packed bytes per (tile, direction) block and per field.
 size_t dir_block_bytes(int prec);

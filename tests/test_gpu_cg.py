@@ -143,3 +143,25 @@ def test_cg_32_4(hq):
         say(f"cg 32^4 mode {mode}: iters={sm['iters']} updates={sm['reliable_updates']} oracle_resid={trm:.3e} "
             f"time={sm['time_s']:.3f}s fallback={sm['fallback_used']}")
         assert sm["rc"] == 0 and trm <= CG_TOL and sm["fallback_used"] == 0
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_cg_blocked_tile_order(hq, mode):
+    """CG with the fused kernels in the blocked (z, t) tile order (the order of Dslash
+    shapes 7 and 8): same solution to tol, certified by the oracle."""
+    dims, mass = (16, 16, 16, 16), 0.02
+    fat, lng = fields(dims, synth.gauge_seed(13))
+    b = synth.source(dims, synth.source_seed(13))
+    before = {p: hq.hisq_dslash_shape(dims, p) for p in (hq.HISQ_F64, hq.HISQ_F32)}
+    x0, s0 = _solve(hq, dims, fat, lng, b, mass, mode)
+    for prec in before:
+        hq.hisq_dslash_shape(dims, prec, 8)
+    try:
+        x1, s1 = _solve(hq, dims, fat, lng, b, mass, mode)
+    finally:
+        for prec, shape in before.items():
+            hq.hisq_dslash_shape(dims, prec, shape)
+    tr = oracle.true_residual(dims, mass, fat, lng, b, x1)
+    say(f"cg blocked order 16^4 mode={mode}: iters {s1['iters']} (plain order {s0['iters']}), oracle_resid={tr:.3e}")
+    assert s1["rc"] == 0 and tr <= CG_TOL
+    assert abs(s1["iters"] - s0["iters"]) <= 3

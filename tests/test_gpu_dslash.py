@@ -146,10 +146,10 @@ def test_bad_arguments(hq):
     assert e.value.code == -1
 
 
-def test_all_launch_shapes_bitwise_identical(hq):
+@pytest.mark.parametrize("dims", [(6, 4, 4, 10), (16, 8, 8, 12)], ids=["ragged", "blocked-order"])
+def test_all_launch_shapes_bitwise_identical(hq, dims):
     """Every launch shape of the Dslash computes the same bits (no races, no order change)."""
     import torch
-    dims = (6, 4, 4, 10)  # ragged last tile
     fat, lng = fields(dims)
     src = synth.source(dims, 9)
     for prec in (0, 1, 2, 3, 4, 5):
