@@ -962,6 +962,24 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
                          const hisq_cg_opts &o, MultiBufs &B, MultiState *hs, hipStream_t s, int iter_offset,
                          MultiOut &out);
 
+template <int N>
+static int tune_multi_impl(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, void *ws,
+                           size_t ws_bytes, int reps, int *best, double *us, hipStream_t s);
+
+// Launch shape of the N-RHS FP32 Dslash on this lattice: the tuned one, or
+// tuned now on the batch's own vectors (scratch state in the partials
+// buffer, which holds nothing live before the iteration starts).
+template <int N>
+static int md_shape_or_tune(const Geom &g, const void *fat_lo, const void *lng_lo, MultiBufs &B, hipStream_t s)
+{
+    int shape = tuned_choice("mdslash", g, HISQ_F32, N, -1);
+    if (shape >= 0) return shape;
+    if (tune_multi_impl<N>(g, fat_lo, lng_lo, B.ps, B.ts, B.part, multi_partials(g, N) * sizeof(double), 5, &shape,
+                           nullptr, s) != HISQ_OK)
+        return 0;
+    return shape;
+}
+
 // column c of the batch leaves: its FP64 solution goes to the caller's x
 template <int N>
 static void retire(MultiBufs &B, const MultiState *hs, const Geom &g, int c, MultiOut &out, hipStream_t s)
@@ -1040,7 +1058,7 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
 {
     const long long np = (long long)g.Vh * N;
     const int nbm = mblocks(np);
-    const int shape = mshape_for(g, N);
+    const int shape = md_shape_or_tune<N>(g, fat_lo, lng_lo, B, s);
     auto iter = [&](hipStream_t q) -> hipError_t {
         int nb1 = 0;
         hipError_t e = launch_md_shape<PF32, N, EPI_STORE>(shape, g, fat_lo, lng_lo, B.ps, B.ts, nullptr, nullptr,
