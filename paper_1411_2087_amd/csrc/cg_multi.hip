@@ -47,7 +47,7 @@ struct MultiState {
     int ms_status;
 };
 
-enum { EPI_STORE = 0, EPI_AP = 1, EPI_RESID = 2 };
+enum { EPI_STORE = 0, EPI_RESID = 2, EPI_STORE_NORM = 3, EPI_UPD = 4 };
 enum { MASK_ACTIVE = 0, MASK_RELIABLE = 1, MASK_ALL = 2 };
 
 __device__ __forceinline__ unsigned pick_mask(const MultiState *st, int which)
@@ -67,9 +67,11 @@ __device__ __forceinline__ void cmac_m(typename P::real acc[6], const typename P
 // N/G consecutive threads share a site (their link loads hit the same
 // addresses and are served once).  Persistent: blocks stride over site units
 // inside the slab of their XCD.
-//   EPI_STORE : dst = D src
-//   EPI_AP    : dst = m4_r x - D src, partial Re<x, dst> per RHS
-//   EPI_RESID : (FP64) dst = b - (m4_r x - D src), rs = float(dst), partial |dst|^2 per RHS
+//   EPI_STORE      : dst = D src
+//   EPI_STORE_NORM : dst = D src, partial |dst|^2 per RHS
+//   EPI_UPD        : (FP32) with x = p: a = m4_r p - D src in registers, dst (= xs) += alpha_r p,
+//                    rs -= alpha_r a, partial |rs|^2 per RHS
+//   EPI_RESID      : (FP64) dst = b - (m4_r x - D src), rs = float(dst), partial |dst|^2 per RHS
 template <class P, int N, int G, int NT, int EPI>
 __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
                                                 const typename P::cvec *__restrict__ src,
@@ -90,9 +92,12 @@ __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__
     double part[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) part[j] = 0.0;
-    double m4[G];
+    double m4[G], al[G];
 #pragma unroll
-    for (int j = 0; j < G; ++j) m4[j] = (EPI != EPI_STORE) ? st->m4[r0 + j] : 0.0;
+    for (int j = 0; j < G; ++j) {
+        m4[j] = (EPI == EPI_RESID || EPI == EPI_UPD) ? st->m4[r0 + j] : 0.0;
+        al[j] = (EPI == EPI_UPD) ? st->alpha[r0 + j] : 0.0;
+    }
 
     // XCD-aware persistent order: XCD k walks the k-th slab of units
     const int xcd = blockIdx.x % NXCD, local = blockIdx.x / NXCD, per_xcd = gridDim.x / NXCD;
@@ -132,15 +137,29 @@ __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     V v;
-                    if (EPI == EPI_STORE) {
+                    if (EPI == EPI_UPD) {
+                        const V pv = x[base + c];
+                        const R ax = fma((R)m4[j], pv.x, -acc[j][2 * c]), ay = fma((R)m4[j], pv.y, -acc[j][2 * c + 1]);
+                        const R a = (R)al[j];
+                        V xv = dst[base + c];
+                        float2 rv = rs[base + c];
+                        xv.x = fma(a, pv.x, xv.x);
+                        xv.y = fma(a, pv.y, xv.y);
+                        rv.x = fmaf(-(float)a, (float)ax, rv.x);
+                        rv.y = fmaf(-(float)a, (float)ay, rv.y);
+                        ntstore(rv, rs + base + c);
+                        part[j] = fma((double)rv.x, (double)rv.x, part[j]);
+                        part[j] = fma((double)rv.y, (double)rv.y, part[j]);
+                        ntstore(xv, dst + base + c);
+                        continue;
+                    }
+                    if (EPI == EPI_STORE || EPI == EPI_STORE_NORM) {
                         v.x = acc[j][2 * c];
                         v.y = acc[j][2 * c + 1];
-                    } else if (EPI == EPI_AP) {
-                        V xv = x[base + c];
-                        v.x = fma((R)m4[j], xv.x, -acc[j][2 * c]);
-                        v.y = fma((R)m4[j], xv.y, -acc[j][2 * c + 1]);
-                        part[j] = fma((double)xv.x, (double)v.x, part[j]);
-                        part[j] = fma((double)xv.y, (double)v.y, part[j]);
+                        if (EPI == EPI_STORE_NORM) {
+                            part[j] = fma((double)v.x, (double)v.x, part[j]);
+                            part[j] = fma((double)v.y, (double)v.y, part[j]);
+                        }
                     } else {
                         V xv = x[base + c], bv = b[base + c];
                         v.x = bv.x - fma((R)m4[j], xv.x, -acc[j][2 * c]);
@@ -199,55 +218,44 @@ __device__ __forceinline__ void mblock_partials(double v, double *partials)
     }
 }
 
-// XS += alpha PS ; RS -= alpha APS (active RHS) ; partial |RS|^2 per RHS
+// PS = RS + beta PS (active RHS) ; partial |PS|^2 per RHS (the first half of the next <p, A p>)
 template <int N>
-__global__ __launch_bounds__(MB_NT) void k_mupdate(float2 *__restrict__ xs, float2 *__restrict__ rs,
-                                                   const float2 *__restrict__ ps, const float2 *__restrict__ aps,
+__global__ __launch_bounds__(MB_NT) void k_mp_norm(float2 *__restrict__ ps, const float2 *__restrict__ rs,
                                                    long long npairs, double *partials, const MultiState *st)
 {
     if (st->flags.done) return;
-    const int r = threadIdx.x % N;  // MB_NT and the grid stride are multiples of N
+    const int r = threadIdx.x % N;
     const bool on = (st->active >> r) & 1u;
-    const float a = (float)st->alpha[r];
+    const float bt = (float)st->beta[r];
     double acc = 0.0;
     if (on) {
         for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const long long i = j * 3 + c;
-                float2 xv = xs[i], rv = rs[i], pv = ps[i], av = aps[i];
-                xv.x = fmaf(a, pv.x, xv.x);
-                xv.y = fmaf(a, pv.y, xv.y);
-                rv.x = fmaf(-a, av.x, rv.x);
-                rv.y = fmaf(-a, av.y, rv.y);
-                xs[i] = xv;
-                rs[i] = rv;
-                acc = fma((double)rv.x, (double)rv.x, fma((double)rv.y, (double)rv.y, acc));
+                float2 pv = ps[i], rv = rs[i];
+                pv.x = fmaf(bt, pv.x, rv.x);
+                pv.y = fmaf(bt, pv.y, rv.y);
+                ntstore(pv, ps + i);
+                acc = fma((double)pv.x, (double)pv.x, fma((double)pv.y, (double)pv.y, acc));
             }
         }
     }
     mblock_partials<N>(acc, partials);
 }
 
-// PS = RS + beta PS (active RHS)
+// partial |V_r|^2 per RHS of an FP32 batched vector
 template <int N>
-__global__ __launch_bounds__(MB_NT) void k_mp(float2 *__restrict__ ps, const float2 *__restrict__ rs, long long npairs,
-                                              const MultiState *st)
+__global__ __launch_bounds__(MB_NT) void k_mnorm32(const float2 *__restrict__ v, long long npairs, double *partials)
 {
-    if (st->flags.done) return;
-    const int r = threadIdx.x % N;
-    if (!((st->active >> r) & 1u)) return;
-    const float bt = (float)st->beta[r];
-    for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT) {
+    double acc = 0.0;
+    for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const long long i = j * 3 + c;
-            float2 pv = ps[i], rv = rs[i];
-            pv.x = fmaf(bt, pv.x, rv.x);
-            pv.y = fmaf(bt, pv.y, rv.y);
-            ps[i] = pv;
+            float2 a = v[j * 3 + c];
+            acc = fma((double)a.x, (double)a.x, fma((double)a.y, (double)a.y, acc));
         }
-    }
+    mblock_partials<N>(acc, partials);
 }
 
 // X64 += XS ; XS = 0 for the RHS in `which_mask`
@@ -664,21 +672,75 @@ __device__ void mfinalize(MultiState *st, int mode, const double *v)
     }
 }
 
+// One pass over the [nblocks][N] partials: thread i keeps the N sums of
+// blocks i, i + 256, ... in registers (all its loads in flight at once), then
+// thread r adds column r of those 256 x N sums in a fixed order.
 template <int N>
 __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize(const double *__restrict__ partials, int nblocks,
                                                         MultiState *st, int mode, int gate)
 {
     if (gate_closed(&st->flags, gate)) return;
-    __shared__ double lds[FIN_NT_M / 64];
+    __shared__ double red[FIN_NT_M * N];
     __shared__ double tot[N];
-    for (int r = 0; r < N; ++r) {
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < nblocks; i += FIN_NT_M) acc += partials[(size_t)i * N + r];
-        double s = block_sum<FIN_NT_M>(acc, lds);
-        if (threadIdx.x == 0) tot[r] = s;
+    double acc[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += FIN_NT_M) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) acc[r] += partials[(size_t)i * N + r];
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) red[threadIdx.x * N + r] = acc[r];
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double sum = 0.0;
+        for (int t = 0; t < FIN_NT_M; ++t) sum += red[t * N + threadIdx.x];
+        tot[threadIdx.x] = sum;
     }
     __syncthreads();
     if (threadIdx.x == 0) mfinalize(st, mode, tot);
+}
+
+// <p_r, A p_r> = m4_r |p_r|^2 + |D_oe p_r|^2 (D_eo = -D_oe^dag) from the partials of
+// k_mp_norm / k_mnorm32 ([npp][N]) and of the EPI_STORE_NORM Dslash ([ntt][N]), then FM_PAP.
+template <int N>
+__global__ __launch_bounds__(FIN_NT_M) void k_mfinalize_pap(const double *__restrict__ part_t, int ntt,
+                                                            const double *__restrict__ part_p, int npp, MultiState *st)
+{
+    if (st->flags.done) return;
+    __shared__ double red[FIN_NT_M * N];
+    __shared__ double tot[N];
+    double acc[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] = 0.0;
+    for (int i = threadIdx.x; i < ntt; i += FIN_NT_M) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) acc[r] += part_t[(size_t)i * N + r];
+    }
+    double accp[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) accp[r] = 0.0;
+    for (int i = threadIdx.x; i < npp; i += FIN_NT_M) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) accp[r] += part_p[(size_t)i * N + r];
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) red[threadIdx.x * N + r] = acc[r];
+    __syncthreads();
+    double tt = 0.0;
+    if (threadIdx.x < N)
+        for (int t = 0; t < FIN_NT_M; ++t) tt += red[t * N + threadIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < N; ++r) red[threadIdx.x * N + r] = accp[r];
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double pp = 0.0;
+        for (int t = 0; t < FIN_NT_M; ++t) pp += red[t * N + threadIdx.x];
+        tot[threadIdx.x] = fma(st->m4[threadIdx.x], pp, tt);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) mfinalize(st, FM_PAP, tot);
 }
 
 __global__ void k_mstate_init(MultiState *st, int n, double tol2, double delta2, const double *m4)
@@ -790,8 +852,9 @@ static hipError_t launch_md_shape(int shape, const Geom &g, const void *fat, con
 struct MultiBufs {
     MultiState *st;
     double *part;
+    double *part_p;                     // partials of |p|^2, kept from one iteration to the next
     double2 *x64, *b64, *r64, *t64;     // [Vh][N][3] FP64
-    float2 *xs, *rs, *ps, *aps, *ts;    // [Vh][N][3] FP32
+    float2 *xs, *rs, *ps, *ts;          // [Vh][N][3] FP32
     float2 *p1, *r1, *ap1, *t1;         // [Vh][3] FP32 (shifted CG base system)
     double *dm;                          // small device array: masses or shifts
 };
@@ -805,9 +868,9 @@ static size_t multi_partials(const Geom &g, int N)
 size_t cg_multi_ws_for(const Geom &g, int N)
 {
     const size_t vp = (size_t)g.Vh * N * 3;
-    size_t b = al256(sizeof(MultiState)) + al256(multi_partials(g, N) * sizeof(double)) + al256(64 * sizeof(double)) +
-               3 * MSKEW;
-    b += 4 * (al256(vp * 16) + MSKEW) + 5 * (al256(vp * 8) + MSKEW) + 4 * (al256((size_t)g.Vh * 3 * 8) + MSKEW);
+    size_t b = al256(sizeof(MultiState)) + 2 * al256(multi_partials(g, N) * sizeof(double)) +
+               al256(64 * sizeof(double)) + 4 * MSKEW;
+    b += 4 * (al256(vp * 16) + MSKEW) + 4 * (al256(vp * 8) + MSKEW) + 4 * (al256((size_t)g.Vh * 3 * 8) + MSKEW);
     return b + 4096;
 }
 
@@ -834,6 +897,7 @@ static bool carve(MultiBufs &B, void *ws, size_t bytes, const Geom &g, int N)
     const size_t vp = (size_t)g.Vh * N * 3, v1 = (size_t)g.Vh * 3;
     B.st = (MultiState *)take(sizeof(MultiState));
     B.part = (double *)take(multi_partials(g, N) * sizeof(double));
+    B.part_p = (double *)take(multi_partials(g, N) * sizeof(double));
     B.dm = (double *)take(64 * sizeof(double));
     B.x64 = (double2 *)take(vp * 16);
     B.b64 = (double2 *)take(vp * 16);
@@ -842,7 +906,6 @@ static bool carve(MultiBufs &B, void *ws, size_t bytes, const Geom &g, int N)
     B.xs = (float2 *)take(vp * 8);
     B.rs = (float2 *)take(vp * 8);
     B.ps = (float2 *)take(vp * 8);
-    B.aps = (float2 *)take(vp * 8);
     B.ts = (float2 *)take(vp * 8);
     B.p1 = (float2 *)take(v1 * 8);
     B.r1 = (float2 *)take(v1 * 8);
@@ -954,6 +1017,8 @@ static int multi_rhs_init(int n, const double *masses, double tol, const void *f
     hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nb, B.st, (int)FM_INIT,
                        (int)GATE_ALWAYS);
     HISQ_HIP(hipMemcpyAsync(B.ps, B.rs, (size_t)np * 3 * 8, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL((k_mnorm32<N>), dim3(nbm), dim3(MB_NT), 0, s, (const float2 *)B.ps, np, B.part_p);
+    HISQ_HIP(hipGetLastError());
     return read_mstate(hs, B.st, s);
 }
 
@@ -1017,6 +1082,8 @@ static int shrink_to(const void *fat, const void *lng, const void *fat_lo, const
     hipLaunchKernelGGL((k_mcompact<float2, N, N2>), dim3(nb2), dim3(MB_NT), 0, s, (const float2 *)B.ps, B.ts, vh, live);
     HISQ_HIP(hipMemcpyAsync(B.ps, B.ts, (size_t)np2 * 24, hipMemcpyDeviceToDevice, s));
     HISQ_HIP(hipMemsetAsync(B.xs, 0, (size_t)np * 24, s));
+    hipLaunchKernelGGL((k_mnorm32<N2>), dim3(nb2), dim3(MB_NT), 0, s, (const float2 *)B.ps, np2, B.part_p);
+    HISQ_HIP(hipGetLastError());
     (void)nbm;
     // the state, compacted on the host
     MultiState ns = *hs;
@@ -1060,18 +1127,19 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
     const int nbm = mblocks(np);
     const int shape = md_shape_or_tune<N>(g, fat_lo, lng_lo, B, s);
     auto iter = [&](hipStream_t q) -> hipError_t {
+        // t = D_oe p and |t|^2 ; alpha = rr / (m4 |p|^2 + |t|^2)
         int nb1 = 0;
-        hipError_t e = launch_md_shape<PF32, N, EPI_STORE>(shape, g, fat_lo, lng_lo, B.ps, B.ts, nullptr, nullptr,
-                                                           nullptr, 1, B.part, B.st, MASK_ACTIVE, GATE_NOT_DONE, q, &nb1);
+        hipError_t e = launch_md_shape<PF32, N, EPI_STORE_NORM>(shape, g, fat_lo, lng_lo, B.ps, B.ts, nullptr,
+                                                                nullptr, nullptr, 1, B.part, B.st, MASK_ACTIVE,
+                                                                GATE_NOT_DONE, q, &nb1);
         if (e != hipSuccess) return e;
-        e = launch_md_shape<PF32, N, EPI_AP>(shape, g, fat_lo, lng_lo, B.ts, B.aps, B.ps, nullptr, nullptr, 0, B.part,
-                                             B.st, MASK_ACTIVE, GATE_NOT_DONE, q, &nb1);
+        hipLaunchKernelGGL((k_mfinalize_pap<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb1,
+                           (const double *)B.part_p, nbm, B.st);
+        // x += alpha p ; r -= alpha (m4 p - D_eo t) ; |r|^2
+        e = launch_md_shape<PF32, N, EPI_UPD>(shape, g, fat_lo, lng_lo, B.ts, B.xs, B.ps, nullptr, B.rs, 0, B.part,
+                                              B.st, MASK_ACTIVE, GATE_NOT_DONE, q, &nb1);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb1, B.st,
-                           (int)FM_PAP, (int)GATE_NOT_DONE);
-        hipLaunchKernelGGL((k_mupdate<N>), dim3(nbm), dim3(MB_NT), 0, q, B.xs, B.rs, (const float2 *)B.ps,
-                           (const float2 *)B.aps, np, B.part, (const MultiState *)B.st);
-        hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nbm, B.st,
                            (int)FM_UPD, (int)GATE_NOT_DONE);
         // reliable updates of the RHS that asked for one
         hipLaunchKernelGGL((k_maccum<N>), dim3(nbm), dim3(MB_NT), 0, q, B.x64, B.xs, np, (const MultiState *)B.st,
@@ -1085,7 +1153,8 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb2, B.st,
                            (int)FM_RELIABLE, (int)GATE_RELIABLE);
-        hipLaunchKernelGGL((k_mp<N>), dim3(nbm), dim3(MB_NT), 0, q, B.ps, (const float2 *)B.rs, np,
+        // p = r + beta p ; |p|^2
+        hipLaunchKernelGGL((k_mp_norm<N>), dim3(nbm), dim3(MB_NT), 0, q, B.ps, (const float2 *)B.rs, np, B.part_p,
                            (const MultiState *)B.st);
         return hipGetLastError();
     };
