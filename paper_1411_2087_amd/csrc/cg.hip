@@ -186,7 +186,7 @@ template <class T>
 __global__ __launch_bounds__(BL_NT) void k_cg_p_norm(T *__restrict__ p, const T *__restrict__ r, long long n,
                                                      double *partials, const CGState *st)
 {
-    if (st->flags.done) return;
+    if (paused(st->flags)) return;
     using R = typename VecT<T>::real;
     const R beta = (R)st->beta;
     T pv[BL_U], rv[BL_U];
@@ -241,7 +241,7 @@ constexpr int FIN_NT = 256;
 __global__ __launch_bounds__(FIN_NT) void k_finalize(const double *__restrict__ partials, int n, CGState *st, int mode,
                                                      int gate)
 {
-    if (gate_closed(&st->flags, gate)) return;
+    if (solver_gate_closed(&st->flags, gate)) return;
     double v = sum_partials<FIN_NT>(partials, n);
     if (threadIdx.x == 0) finalize(st, mode, v);
 }
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const double *__restrict__ 
 __global__ __launch_bounds__(FIN_NT) void k_finalize_pap(const double *__restrict__ part_p, int np,
                                                          const double *__restrict__ part_t, int nt, CGState *st)
 {
-    if (st->flags.done) return;
+    if (paused(st->flags)) return;
     const double pp = sum_partials<FIN_NT>(part_p, np);
     const double tt = sum_partials<FIN_NT>(part_t, nt);
     if (threadIdx.x == 0) finalize(st, FIN_PAP, fma(st->m4, pp, tt));
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_cg_Dp(Geom g, const char *
                                                             typename P::cvec *__restrict__ t, int nblocks,
                                                             double *partials, const CGState *st)
 {
-    if (st->flags.done) return;
+    if (paused(st->flags)) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     if (blk >= nblocks) return;
     const int k = blk * (NT / TILE) + (threadIdx.x >> 6);
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_cg_Ap_upd(Geom g, const ch
                                                                 typename P::cvec *__restrict__ r, int nblocks,
                                                                 double *partials, const CGState *st)
 {
-    if (st->flags.done) return;
+    if (paused(st->flags)) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     if (blk >= nblocks) return;
     const int k = blk * (NT / TILE) + (threadIdx.x >> 6);
@@ -457,9 +457,15 @@ hipStream_t capture_stream()
 // reports done or `max_iter` iterations were queued.  Every `K` iterations
 // the state is copied to pinned memory and inspected; with use_graph the K
 // iterations are captured once and replayed.
-template <class IterFn>
+struct NoPause {
+    hipError_t operator()(hipStream_t) const { return hipSuccess; }
+};
+
+// pause_fn (mixed solvers): enqueues the reliable update when a state check
+// finds one pending; the iterations then resume.
+template <class IterFn, class PauseFn = NoPause>
 static int run_iterations(IterFn iter_fn, hipStream_t s, CGState *dstate, CGState *hstate, int K, int max_iter,
-                          bool use_graph, int already)
+                          bool use_graph, int already, PauseFn pause_fn = PauseFn())
 {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -498,6 +504,10 @@ static int run_iterations(IterFn iter_fn, hipStream_t s, CGState *dstate, CGStat
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { rc = hip_fail(e, "CG state read-back"); break; }
         if (hstate->flags.done) break;
+        if (hstate->flags.reliable) {
+            e = pause_fn(s);
+            if (e != hipSuccess) { rc = hip_fail(e, "reliable update launch"); break; }
+        }
     }
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
@@ -581,7 +591,7 @@ struct Launch {
         hipLaunchKernelGGL((k_cg_Ap_upd<P, CG_NT, cg_waves<P>()>), gd, dim3(CG_NT), 0, q, g, (const char *)fat,
                            (const char *)lng, (const V *)t, (const V *)p, (V *)x, (V *)r, nbd, part,
                            (const CGState *)st);
-        fin(q, nbd, mode, GATE_NOT_DONE);
+        fin(q, nbd, mode, GATE_PAUSE);
     }
     // p = r + beta p ; |p|^2 partials into part_p
     template <class T> void pupd(hipStream_t q, T *p, const T *r) const
@@ -726,10 +736,15 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
     if (hs->bb == 0.0) return zero_source_exit(x, v64, s, stats, t0);
 
     const dim3 gb(L.nbl), bb(BL_NT);
+    // one inner iteration; a reliable update request pauses the rest of the graph
     auto iter = [&](hipStream_t q) -> hipError_t {
         L.dp<PS>(q, fat_lo, lng_lo, ps, ts);
         L.ap_update<PS>(q, fat_lo, lng_lo, ts, ps, xs, rs, FIN_UPD_MIXED);
-        // reliable update (kernels return at once unless it was triggered)
+        L.pupd<float2>(q, ps, rs);
+        return hipGetLastError();
+    };
+    // the reliable update: x += xs, r = b - A x in FP64, rs = float(r), then the direction update
+    auto reliable = [&](hipStream_t q) -> hipError_t {
         hipLaunchKernelGGL(k_accum, gb, bb, 0, q, (double2 *)x, xs, L.n, (const CGState *)st);
         hipError_t e = launch_dslash<PH>(g, fat, lng, x, t64, 1, q, &st->flags, GATE_RELIABLE);
         if (e != hipSuccess) return e;
@@ -738,7 +753,7 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
         return hipGetLastError();
     };
 
-    rc = run_iterations(iter, s, st, hs, o.check_every, o.max_iter, o.use_graph != 0, 0);
+    rc = run_iterations(iter, s, st, hs, o.check_every, o.max_iter, o.use_graph != 0, 0, reliable);
     if (rc) return rc;
     if (hs->flags.done == CG_STALLED) {
         // The low-precision operator cannot drive the true residual down: fold

@@ -6,6 +6,17 @@
 namespace hisq {
 
 enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2, CG_STALLED = 3 };
+
+// Gate of the kernels of a solver iteration: closed when the solve is done
+// or a reliable update is pending.  The iteration pauses there; the host
+// runs the update outside the captured graph at its next state check and
+// the iterations resume.
+enum { GATE_PAUSE = 3 };
+__device__ __forceinline__ bool paused(const SolverFlags &f) { return f.done || f.reliable; }
+__device__ __forceinline__ bool solver_gate_closed(const SolverFlags *f, int gate)
+{
+    return gate == GATE_PAUSE ? paused(*f) : gate_closed(f, gate);
+}
 constexpr int BLAS_MAX_BLOCKS = 1024;
 
 // Device-resident scalars of one solve.  `flags` comes first: kernels gate on it.

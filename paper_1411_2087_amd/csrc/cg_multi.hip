@@ -85,7 +85,7 @@ __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__
     using V = typename P::cvec;
     constexpr int TPS = N / G;        // threads per site
     constexpr int SPB = NT / TPS;     // sites per block per unit
-    if (gate_closed(&st->flags, gate)) return;
+    if (solver_gate_closed(&st->flags, gate)) return;
     const unsigned mask = pick_mask(st, which_mask);
     const int grp = threadIdx.x % TPS;
     const int r0 = grp * G;
@@ -223,7 +223,7 @@ template <int N>
 __global__ __launch_bounds__(MB_NT) void k_mp_norm(float2 *__restrict__ ps, const float2 *__restrict__ rs,
                                                    long long npairs, double *partials, const MultiState *st)
 {
-    if (st->flags.done) return;
+    if (paused(st->flags)) return;
     const int r = threadIdx.x % N;
     const bool on = (st->active >> r) & 1u;
     const float bt = (float)st->beta[r];
@@ -679,7 +679,7 @@ template <int N>
 __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize(const double *__restrict__ partials, int nblocks,
                                                         MultiState *st, int mode, int gate)
 {
-    if (gate_closed(&st->flags, gate)) return;
+    if (solver_gate_closed(&st->flags, gate)) return;
     __shared__ double red[FIN_NT_M * N];
     __shared__ double tot[N];
     double acc[N];
@@ -707,7 +707,7 @@ template <int N>
 __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize_pap(const double *__restrict__ part_t, int ntt,
                                                             const double *__restrict__ part_p, int npp, MultiState *st)
 {
-    if (st->flags.done) return;
+    if (paused(st->flags)) return;
     __shared__ double red[FIN_NT_M * N];
     __shared__ double tot[N];
     double acc[N];
@@ -930,9 +930,13 @@ struct MultiHost {
 // `shrink_at` right-hand sides are still iterating.
 constexpr int MULTI_SHRINK = 1;
 
-template <class F>
+struct NoMultiPause {
+    hipError_t operator()(hipStream_t) const { return hipSuccess; }
+};
+
+template <class F, class PauseFn = NoMultiPause>
 static int run_multi(F iter_fn, hipStream_t s, MultiState *dst, MultiState *hst, int K, int max_iter, bool graph,
-                     int shrink_at = -1)
+                     int shrink_at = -1, PauseFn pause_fn = PauseFn())
 {
     hipGraphExec_t exec = nullptr;
     hipGraph_t gr = nullptr;
@@ -970,6 +974,14 @@ static int run_multi(F iter_fn, hipStream_t s, MultiState *dst, MultiState *hst,
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { rc = hip_fail(e, "batched CG state read-back"); break; }
         if (hst->flags.done) break;
+        if (hst->flags.reliable) {
+            e = pause_fn(s);
+            if (e != hipSuccess) { rc = hip_fail(e, "reliable update launch"); break; }
+            e = hipMemcpyAsync(hst, dst, sizeof(MultiState), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) { rc = hip_fail(e, "batched CG state read-back"); break; }
+            if (hst->flags.done) break;
+        }
         if (shrink_at >= 0 && __builtin_popcount(hst->active) <= shrink_at) { rc = MULTI_SHRINK; break; }
     }
     if (exec) hipGraphExecDestroy(exec);
@@ -1131,19 +1143,26 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
         int nb1 = 0;
         hipError_t e = launch_md_shape<PF32, N, EPI_STORE_NORM>(shape, g, fat_lo, lng_lo, B.ps, B.ts, nullptr,
                                                                 nullptr, nullptr, 1, B.part, B.st, MASK_ACTIVE,
-                                                                GATE_NOT_DONE, q, &nb1);
+                                                                GATE_PAUSE, q, &nb1);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mfinalize_pap<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb1,
                            (const double *)B.part_p, nbm, B.st);
         // x += alpha p ; r -= alpha (m4 p - D_eo t) ; |r|^2
         e = launch_md_shape<PF32, N, EPI_UPD>(shape, g, fat_lo, lng_lo, B.ts, B.xs, B.ps, nullptr, B.rs, 0, B.part,
-                                              B.st, MASK_ACTIVE, GATE_NOT_DONE, q, &nb1);
+                                              B.st, MASK_ACTIVE, GATE_PAUSE, q, &nb1);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb1, B.st,
-                           (int)FM_UPD, (int)GATE_NOT_DONE);
-        // reliable updates of the RHS that asked for one
+                           (int)FM_UPD, (int)GATE_PAUSE);
+        // p = r + beta p ; |p|^2 (a pending reliable update pauses the batch here)
+        hipLaunchKernelGGL((k_mp_norm<N>), dim3(nbm), dim3(MB_NT), 0, q, B.ps, (const float2 *)B.rs, np, B.part_p,
+                           (const MultiState *)B.st);
+        return hipGetLastError();
+    };
+    // reliable updates of the RHS that asked for one, outside the captured iterations
+    auto reliable = [&](hipStream_t q) -> hipError_t {
         hipLaunchKernelGGL((k_maccum<N>), dim3(nbm), dim3(MB_NT), 0, q, B.x64, B.xs, np, (const MultiState *)B.st,
                            (int)MASK_RELIABLE, (int)GATE_RELIABLE);
+        hipError_t e;
         int nb2 = 0;
         e = launch_md_shape<PF64, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
                                                 B.st, MASK_RELIABLE, GATE_RELIABLE, q, &nb2);
@@ -1153,7 +1172,6 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb2, B.st,
                            (int)FM_RELIABLE, (int)GATE_RELIABLE);
-        // p = r + beta p ; |p|^2
         hipLaunchKernelGGL((k_mp_norm<N>), dim3(nbm), dim3(MB_NT), 0, q, B.ps, (const float2 *)B.rs, np, B.part_p,
                            (const MultiState *)B.st);
         return hipGetLastError();
@@ -1161,7 +1179,7 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
     int rc = HISQ_OK;
     if (!hs->flags.done) {
         const int budget = std::max(1, o.max_iter - iter_offset - hs->iter);
-        rc = run_multi(iter, s, B.st, hs, o.check_every, budget, o.use_graph != 0, N > 1 ? N / 2 : -1);
+        rc = run_multi(iter, s, B.st, hs, o.check_every, budget, o.use_graph != 0, N > 1 ? N / 2 : -1, reliable);
         if (rc < 0) return rc;
     }
     if constexpr (N > 1) {
