@@ -162,6 +162,71 @@ def form_learned(hq, log, dims=(16, 16, 16, 16), mass=0.005, C=16, npairs=64, st
             "fcg_true_resid": sf["true_resid"], "speedup_vs_plain": round(sp["time_s"] / sf["time_s"], 3)}
 
 
+def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, steps=600):
+    """The learned-preconditioner workload: 512 training pairs per gauge field (448 to train, 64 held out), the
+    network trained on the GPU for C = 8 and 16 channels with the residual objective, and flexible CG with the
+    trained network against plain FP64 CG and against flexible CG with K = identity on held-out sources."""
+    import numpy as np
+    import torch
+
+    import paper_1411_2087_amd as hq
+    import synth
+    from paper_1411_2087_amd import train
+    fat, lng = synth.links(dims, synth.gauge_seed(5))
+    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
+    L32 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32)
+    src = np.stack([synth.source(dims, synth.source_seed(5, i)) for i in range(npairs)])
+    t0 = time.perf_counter()
+    b, x, _, _ = train.make_pairs(dims, mass, L64, L32, src)
+    t_pairs = time.perf_counter() - t0
+    log(f"[learned] {npairs} pairs in {t_pairs:.1f}s")
+    ntrain = npairs - nheld
+    held = [torch.from_numpy(src[ntrain + i]).cuda() for i in range(4)]
+
+    def solve_all(fn):
+        its, secs = [], []
+        for bd in held:
+            xx = torch.zeros_like(bd)
+            st = fn(bd, xx)
+            its.append(st["iters"])
+            secs.append(st["time_s"])
+        return its, secs, st
+    wsp = hq.fields.workspace("cg", dims)
+    p_its, p_s, _ = solve_all(lambda bd, xx: hq.cg_solve(mass, TOL, L64.fat, L64.lng, None, None, bd, xx, dims, None,
+                                                           wsp))
+    out = {"workload": f"{'x'.join(map(str, dims))}, m {mass}, {npairs} pairs ({ntrain} train / {nheld} held out), "
+                       f"residual objective, {steps} Adam steps, batch 16",
+           "pair_s": round(t_pairs, 2), "plain_f64": {"iters": p_its, "s": [round(v, 4) for v in p_s]}, "nets": {}}
+    for C in (8, 16):
+        w0 = train.initial_weights(C, train.residual_scale(b[:16], L32, mass, dims), 0.05, 99)
+        tr = train.Trainer(dims, C, L32.fat, w0, batch=16, objective="residual", links32=L32, mass=mass)
+        l0 = tr.evaluate(b[ntrain:], x[ntrain:])
+        t0 = time.perf_counter()
+        hist = tr.fit(b[:ntrain], x[:ntrain], steps=steps, lr=2e-3, log_every=200)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        l1 = tr.evaluate(b[ntrain:], x[ntrain:])
+        wsf = hq.fields.workspace("fcg", dims, 1, 0, C)
+        f_its, f_s, last = solve_all(lambda bd, xx: hq.fcg_solve(mass, TOL, L64.fat, L64.lng, L32.fat, tr.w, C, bd,
+                                                                 xx, dims, None, wsf))
+        wid = torch.from_numpy(train.flatten(train.identity_weights(C))).cuda()
+        i_its, i_s, _ = solve_all(lambda bd, xx: hq.fcg_solve(mass, TOL, L64.fat, L64.lng, L32.fat, wid, C, bd, xx,
+                                                              dims, None, wsf))
+        out["nets"][f"C{C}"] = {"held_out_loss": [round(l0, 4), round(l1, 4)], "train_s": round(t_train, 2),
+                                "loss_log": [(s_, round(l, 4)) for s_, l in hist],
+                                "fcg_trained": {"iters": f_its, "s": [round(v, 4) for v in f_s],
+                                                "fallback_used": last["fallback_used"],
+                                                "fallback_iters": last["fallback_iters"]},
+                                "fcg_identity": {"iters": i_its, "s": [round(v, 4) for v in i_s]},
+                                "speedup_vs_plain": round(sum(p_s) / sum(f_s), 3)}
+        log(f"[learned C={C}] held-out loss {l0:.4f} -> {l1:.4f}, train {t_train:.1f}s; fcg {f_its} "
+            f"(fallback {last['fallback_used']}) {sum(f_s):.3f}s, identity {i_its}, plain {p_its} {sum(p_s):.3f}s")
+    print(json.dumps({"metric": "CG s to 1e-10 resid, flexible CG with the trained network vs plain FP64 (report line)",
+                      "unit": "s", "value": round(sum(out["nets"]["C16"]["fcg_trained"]["s"]), 4), "n_gpus": 1,
+                      "higher_is_better": False, "data": "synthetic", "config": {"workload": out["workload"]},
+                      "learned": out}))
+
+
 def run_large(args):
     """48^3 x 96, m = 0.005: seconds to 1e-10 of plain FP64 CG and of the mixed-precision forms."""
     import numpy as np
@@ -347,8 +412,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
     ap.add_argument("--workload", default="32x32x32x32",
                     help="32x32x32x32 (default: plain FP64 CG, the metric's workload), 48x48x48x96 "
-                         "(mixed precision against plain FP64 on the large lattice) or paper-grids (the Dslash "
-                         "on 32^3x128 and 32x40x24x96); the last two are report lines, not the metric")
+                         "(mixed precision against plain FP64 on the large lattice), paper-grids (the Dslash "
+                         "on 32^3x128 and 32x40x24x96) or learned (512 training pairs on 16^4, C = 8 and 16); "
+                         "all but the first are report lines, not the metric")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a 1 GiB copy and the FP64 Dslash (for rocprofv3 counter runs); with --workload "
                          "LxxLyxLzxLt on that lattice")
@@ -370,6 +436,8 @@ def main():
         return run_large(args)
     if args.workload == "paper-grids":
         return run_paper_grids(args)
+    if args.workload == "learned":
+        return run_learned(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     vh = int(np.prod(DIMS)) // 2

@@ -19,7 +19,8 @@ def big():
     fat, lng = fields(DIMS, synth.gauge_seed(3))
     b = synth.source(DIMS, synth.source_seed(3))
     fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
-    L = {p: hq.fields.Links.pack(fd, ld, DIMS, p) for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S)}
+    L = {p: hq.fields.Links.pack(fd, ld, DIMS, p)
+         for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S, hq.HISQ_F64C, hq.HISQ_F32C)}
     del fd, ld
     torch.cuda.synchronize()
     return hq, fat, lng, b, L
@@ -29,25 +30,27 @@ def test_dslash_f64_48x96(big):
     import torch
     hq, fat, lng, b, L = big
     s = torch.from_numpy(b).cuda()
-    d = torch.full_like(s, float("nan"))
-    hq.dslash_apply(L[0].fat, L[0].lng, s, d, 1, DIMS, 0)
-    got = d.cpu().numpy()
     ref = oracle.dslash(DIMS, fat, lng, b, 1)
-    err = oracle.componentwise_error(got, ref, oracle.dslash_scale(DIMS, fat, lng, b, 1))
-    say(f"dslash 48^3x96 f64 parity 1: componentwise {err:.2e}")
-    assert err <= TOL_F64
+    scale = oracle.dslash_scale(DIMS, fat, lng, b, 1)
+    for prec in (hq.HISQ_F64, hq.HISQ_F64C):
+        d = torch.full_like(s, float("nan"))
+        hq.dslash_apply(L[prec].fat, L[prec].lng, s, d, 1, DIMS, prec)
+        err = oracle.componentwise_error(d.cpu().numpy(), ref, scale)
+        say(f"dslash 48^3x96 prec={prec} parity 1: componentwise {err:.2e}")
+        assert err <= TOL_F64
 
 
-@pytest.mark.parametrize("mode", [1, 3])
+@pytest.mark.parametrize("mode", [1, 3, 5])
 def test_mixed_cg_48x96(big, mode):
     import torch
     hq, fat, lng, b, L = big
-    lo = L[hq.HISQ_F32] if mode == 1 else L[hq.HISQ_I16S]
+    lo = {1: L[hq.HISQ_F32], 3: L[hq.HISQ_I16S], 5: L[hq.HISQ_F32C]}[mode]
+    hi = L[hq.HISQ_F64C] if mode == 5 else L[hq.HISQ_F64]
     bd = torch.from_numpy(b).cuda()
     x = torch.zeros_like(bd)
     ws = hq.fields.workspace("cg", DIMS, 1, mode)
     opts = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
-    st = hq.cg_solve(MASS, CG_TOL, L[0].fat, L[0].lng, lo.fat, lo.lng, bd, x, DIMS, opts, ws)
+    st = hq.cg_solve(MASS, CG_TOL, hi.fat, hi.lng, lo.fat, lo.lng, bd, x, DIMS, opts, ws)
     tr = oracle.true_residual(DIMS, MASS, fat, lng, b, x.cpu().numpy())
     say(f"48^3x96 m={MASS} mode={mode}: iters={st['iters']} updates={st['reliable_updates']} "
         f"time={st['time_s']:.2f}s gpu={st['true_resid']:.2e} oracle={tr:.2e}")
