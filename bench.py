@@ -528,8 +528,19 @@ def main():
     e1.record(stream)
     e1.synchronize()
     copy_gbs = 2 * nbytes * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
-    del cs, cd
-    log(f"[dslash] f64 kernel {t_dslash * 1e6:.1f} us -> {achieved:.0f} GB/s; copy probe {copy_gbs:.0f} GB/s")
+    # and a read-only stream (a sum over 4 GiB), the pattern of the Dslash (reads dominate)
+    del cd
+    rd = torch.empty(nbytes // 4 * 2, dtype=torch.float32, device=dev).fill_(1.0)
+    rd.sum()
+    e0.record(stream)
+    for _ in range(5):
+        rd.sum()
+    e1.record(stream)
+    e1.synchronize()
+    read_gbs = rd.numel() * 4 * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del cs, rd
+    log(f"[dslash] f64 kernel {t_dslash * 1e6:.1f} us -> {achieved:.0f} GB/s; copy probe {copy_gbs:.0f} GB/s, "
+        f"read probe {read_gbs:.0f} GB/s")
 
     forms = {"plain_f64": {"s": round(ms_per_step / 1e3, 4), "iters": stats[-1]["iters"],
                            "true_resid": stats[-1]["true_resid"]}}
@@ -596,7 +607,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_dslash<PF64> (parity 1, 32^4, tuned shape)", "avg_us": round(t_dslash * 1e6, 2),
-                     "bytes_per_launch": 2400 * vh, "copy_probe_gbs": round(copy_gbs, 1),
+                     "bytes_per_launch": 2400 * vh, "copy_probe_gbs": round(copy_gbs, 1), "read_probe_gbs": round(read_gbs, 1),
                      "gflops": round(1146.0 * vh / t_dslash / 1e9, 1)},
         "cpu_baseline": cpu,
         "forms": forms,
