@@ -528,17 +528,12 @@ def main():
     e1.record(stream)
     e1.synchronize()
     copy_gbs = 2 * nbytes * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
-    # and a read-only stream (a sum over 4 GiB), the pattern of the Dslash (reads dominate)
+    # and the achievable read rate: the library's nontemporal read stream over 4 GiB (reads dominate the Dslash)
     del cd
-    rd = torch.empty(nbytes // 4 * 2, dtype=torch.float32, device=dev).fill_(1.0)
-    rd.sum()
-    e0.record(stream)
-    for _ in range(5):
-        rd.sum()
-    e1.record(stream)
-    e1.synchronize()
-    read_gbs = rd.numel() * 4 * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
-    del cs, rd
+    rd = torch.ones(nbytes // 4 * 2, dtype=torch.float32, device=dev)
+    sink = torch.empty(8192, dtype=torch.float64, device=dev)
+    read_gbs = rd.numel() * 4 / hq.hisq_read_probe(rd, sink, reps=5) / 1e3
+    del cs, rd, sink
     log(f"[dslash] f64 kernel {t_dslash * 1e6:.1f} us -> {achieved:.0f} GB/s; copy probe {copy_gbs:.0f} GB/s, "
         f"read probe {read_gbs:.0f} GB/s")
 

@@ -325,6 +325,15 @@ int hisq_fat_paths(const void *thin, const double coeff[5], void *out, const int
  * nonzero, else 1.  HISQ_EINVAL unless hop is 1 or 3. */
 int hisq_fold_links(void *links, const int dims[4], int hop, int antiperiodic_t, void *stream);
 
+/* Measurement aid: microseconds per pass of a stream of nontemporal 16-byte
+ * loads over `bytes` of device memory at `buf` (the load style of the Dslash's
+ * link stream, 8 loads in flight per thread), averaged over `reps` passes after
+ * one warm-up; the achievable HBM read rate that bounds every Dslash form.
+ * sink: device scratch of >= 65536 bytes (block sums, so no load is dropped).
+ * Synchronises `stream`. */
+int hisq_read_probe(const void *buf, size_t bytes, void *sink, size_t sink_bytes, int reps, double *us,
+                    void *stream);
+
 /* Launch shape of the multi-RHS Dslash for (dims, nrhs): shape >= 0 sets it
  * (HISQ_EINVAL if it does not apply to nrhs), -1 queries, -2 returns the
  * number of shapes.  Returns the shape in use or a negative hisq_status. */

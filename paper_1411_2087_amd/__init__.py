@@ -99,7 +99,9 @@ def _load():
     lib.hisq_three_link.argtypes = [vp, vp, ip, vp]
     lib.hisq_fat_paths.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp, ip, vp, sz, vp]
     lib.hisq_fold_links.argtypes = [vp, ip, ctypes.c_int, ctypes.c_int, vp]
-    for name in ("hisq_three_link", "hisq_fat_paths", "hisq_fold_links", "hisq_pack_links", "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi",
+    lib.hisq_read_probe.argtypes = [vp, sz, vp, sz, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
+    for name in ("hisq_three_link", "hisq_fat_paths", "hisq_fold_links", "hisq_read_probe", "hisq_pack_links",
+                 "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi",
                  "hisq_tune_dslash", "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape",
                  "net_forward", "net_backward", "net_loss", "net_adam_step", "fcg_solve"):
         getattr(lib, name).restype = ctypes.c_int
@@ -112,7 +114,7 @@ EXPORTED = ["hisq_version", "hisq_last_error", "hisq_packed_link_bytes", "hisq_p
             "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi", "hisq_tune_dslash",
             "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape", "net_weight_count",
             "net_act_bytes", "net_backward_ws_bytes", "net_forward", "net_backward", "net_loss", "net_adam_step",
-            "fcg_solve", "hisq_three_link", "hisq_fat_paths", "hisq_fold_links"]
+            "fcg_solve", "hisq_three_link", "hisq_fat_paths", "hisq_fold_links", "hisq_read_probe"]
 
 
 def _dims(dims):
@@ -156,6 +158,15 @@ def hisq_packed_link_bytes(dims, prec) -> int:
 def hisq_pack_links(fat_canon, long_canon, dims, prec, fat_out, long_out, stream=None):
     _check(_lib.hisq_pack_links(_ptr(fat_canon), _ptr(long_canon), _dims(dims), int(prec), _ptr(fat_out),
                                 _ptr(long_out), _stream(stream)), "hisq_pack_links")
+
+
+def hisq_read_probe(buf, sink, reps=5, stream=None) -> float:
+    """Microseconds per nontemporal streaming read of the whole of `buf` (device tensor)."""
+    us = ctypes.c_double()
+    _check(_lib.hisq_read_probe(_ptr(buf), buf.numel() * buf.element_size(), _ptr(sink),
+                                sink.numel() * sink.element_size(), int(reps), ctypes.byref(us), _stream(stream)),
+           "hisq_read_probe")
+    return us.value
 
 
 def hisq_three_link(thin, out, dims, stream=None):

@@ -672,9 +672,23 @@ __device__ void mfinalize(MultiState *st, int mode, const double *v)
     }
 }
 
+// Column sums of red[FIN_NT_M][N] into tot[N]: wave w takes columns w, w + 4,
+// ..., each lane adds 4 rows and a butterfly finishes (fixed order).
+template <int N>
+__device__ __forceinline__ void column_sums(const double *red, double *tot)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int r = w; r < N; r += FIN_NT_M / 64) {
+        double v = 0.0;
+        for (int t = l; t < FIN_NT_M; t += 64) v += red[t * N + r];
+        v = wave_sum(v);
+        if (l == 0) tot[r] = v;
+    }
+}
+
 // One pass over the [nblocks][N] partials: thread i keeps the N sums of
 // blocks i, i + 256, ... in registers (all its loads in flight at once), then
-// thread r adds column r of those 256 x N sums in a fixed order.
+// the 256 x N sums are added column by column.
 template <int N>
 __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize(const double *__restrict__ partials, int nblocks,
                                                         MultiState *st, int mode, int gate)
@@ -692,11 +706,7 @@ __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize(const double *__restrict
 #pragma unroll
     for (int r = 0; r < N; ++r) red[threadIdx.x * N + r] = acc[r];
     __syncthreads();
-    if (threadIdx.x < N) {
-        double sum = 0.0;
-        for (int t = 0; t < FIN_NT_M; ++t) sum += red[t * N + threadIdx.x];
-        tot[threadIdx.x] = sum;
-    }
+    column_sums<N>(red, tot);
     __syncthreads();
     if (threadIdx.x == 0) mfinalize(st, mode, tot);
 }
@@ -724,21 +734,18 @@ __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize_pap(const double *__rest
 #pragma unroll
         for (int r = 0; r < N; ++r) accp[r] += part_p[(size_t)i * N + r];
     }
+    __shared__ double tt[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) red[threadIdx.x * N + r] = acc[r];
     __syncthreads();
-    double tt = 0.0;
-    if (threadIdx.x < N)
-        for (int t = 0; t < FIN_NT_M; ++t) tt += red[t * N + threadIdx.x];
+    column_sums<N>(red, tt);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < N; ++r) red[threadIdx.x * N + r] = accp[r];
     __syncthreads();
-    if (threadIdx.x < N) {
-        double pp = 0.0;
-        for (int t = 0; t < FIN_NT_M; ++t) pp += red[t * N + threadIdx.x];
-        tot[threadIdx.x] = fma(st->m4[threadIdx.x], pp, tt);
-    }
+    column_sums<N>(red, tot);
+    __syncthreads();
+    if (threadIdx.x < N) tot[threadIdx.x] = fma(st->m4[threadIdx.x], tot[threadIdx.x], tt[threadIdx.x]);
     __syncthreads();
     if (threadIdx.x == 0) mfinalize(st, FM_PAP, tot);
 }

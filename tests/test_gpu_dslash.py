@@ -193,3 +193,17 @@ def test_dslash_32_4_compressed(hq):
     err = oracle.componentwise_error(got, ref, oracle.dslash_scale(dims, fat, lng, src, 1))
     say(f"dslash 32^4 f64 two-row long links: componentwise {err:.3e}")
     assert err <= TOL_F64
+
+
+def test_read_probe_reads_every_byte_once(hq):
+    """The read-rate probe's block sums add up to the sum of the buffer (every 16-byte
+    word read exactly once), including a ragged tail shorter than one grid pass."""
+    import torch
+    n = (1 << 21) + 4 * 1000 + 2        # doubles: not a multiple of the grid's pass
+    buf = torch.ones(n, dtype=torch.float64, device="cuda")
+    sink = torch.zeros(8192, dtype=torch.float64, device="cuda")
+    us = hq.hisq_read_probe(buf, sink, reps=2)
+    assert us > 0
+    assert float(sink.sum()) == float(n)
+    with pytest.raises(hq.HisqError):
+        hq.hisq_read_probe(buf, torch.zeros(16, dtype=torch.float64, device="cuda"))
