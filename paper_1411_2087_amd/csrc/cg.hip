@@ -285,7 +285,10 @@ __global__ void k_clear_done(CGState *st)
 // ------------------------------------------------------------------ Dslash-fused kernels
 // Waves per SIMD the fused kernels ask for: the two-row FP64 operator needs
 // more than the 64 registers that 8 waves leave.
-template <class P> constexpr int cg_waves() { return P::prec == HISQ_F64C ? 6 : 8; }
+template <class P> constexpr int cg_waves() { return (P::prec == HISQ_F64 || P::prec == HISQ_F64C) ? 5 : 8; }
+// terms of the 16 unrolled together: two for the FP64 forms, so that a wave
+// has two directions' link loads in flight (their best Dslash launch shape)
+template <class P> constexpr int cg_unroll() { return (P::prec == HISQ_F64 || P::prec == HISQ_F64C) ? 2 : 1; }
 
 // t = D_oe p on the odd sites ; partials of |t|^2
 template <class P, int NT, int W>
@@ -306,7 +309,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_cg_Dp(Geom g, const char *
     if (k < g.ntiles) {
         const int hc = h < g.Vh ? h : g.Vh - 1;
         typename P::real acc[6];
-        dslash_site<P>(g, fat, lng, p, 1, tile, lane, hc, acc);
+        dslash_site<P, cg_unroll<P>()>(g, fat, lng, p, 1, tile, lane, hc, acc);
         if (h < g.Vh) {
             typename P::cvec *o = t + (size_t)h * 3;
 #pragma unroll
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_cg_Ap_upd(Geom g, const ch
     if (k < g.ntiles) {
         const int hc = h < g.Vh ? h : g.Vh - 1;
         typename P::real acc[6];
-        dslash_site<P>(g, fat, lng, t, 0, tile, lane, hc, acc);
+        dslash_site<P, cg_unroll<P>()>(g, fat, lng, t, 0, tile, lane, hc, acc);
         if (h < g.Vh) {
             using R = typename P::real;
             const R m = (R)st->m4, a = (R)st->alpha;

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES((P::prec == HISQ_F64 || P::prec == H
 // identical; the autotuner picks one per (lattice, precision).
 const DslashShape DSLASH_SHAPES[N_DSLASH_SHAPES] = {
     { 256, 8, 1, 0 }, { 128, 8, 1, 0 }, { 64, 8, 1, 0 }, { 256, 1, 16, 0 }, { 256, 4, 4, 0 },
-    { 512, 8, 1, 0 }, { 256, 6, 1, 0 }, { 256, 8, 1, 1 }, { 256, 6, 1, 1 },
+    { 512, 8, 1, 0 }, { 256, 6, 1, 0 }, { 256, 8, 1, 1 }, { 256, 6, 1, 1 }, { 256, 6, 2, 0 }, { 256, 5, 2, 0 },
 };
 
 static inline int blocks_for(const Geom &g, int nt) { return (g.ntiles + nt / TILE - 1) / (nt / TILE); }
@@ -109,6 +109,8 @@ hipError_t launch_dslash_shape(int shape, const Geom &g, const void *fat, const 
     case 6: launch_shape<P, 256, 6, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     case 7: launch_shape<P, 256, 8, 1, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     case 8: launch_shape<P, 256, 6, 1, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 9: launch_shape<P, 256, 6, 2>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 10: launch_shape<P, 256, 5, 2>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     default: launch_shape<P, 256, 8, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     }
     return hipGetLastError();

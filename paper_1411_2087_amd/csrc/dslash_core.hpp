@@ -139,7 +139,7 @@ struct DslashShape {
     int unroll;  // terms of the 16 unrolled together
     int order;   // 1: blocked tile order (blocked_order), 0: tile k k-th
 };
-constexpr int N_DSLASH_SHAPES = 9;
+constexpr int N_DSLASH_SHAPES = 11;
 extern const DslashShape DSLASH_SHAPES[N_DSLASH_SHAPES];
 int tuned_dslash_shape(const Geom &g, int prec);            // tune.cpp
 int tuned_choice(const char *kind, const Geom &g, int prec, int n, int fallback);
