@@ -79,9 +79,9 @@ void set_tuned_choice(const char *kind, const Geom &g, int prec, int n, int v)
     save_locked();
 }
 
-// Untuned default per precision: 6 waves per SIMD for the FP64 forms (the
-// two-row FP64 kernel needs more than 64 registers), 8 for the others.
-static int default_dslash_shape(int prec) { return (prec == HISQ_F64 || prec == HISQ_F64C) ? 6 : 0; }
+// Untuned default per precision: two terms unrolled at 5 waves per SIMD for
+// the FP64 forms, one term at 8 waves for the others.
+static int default_dslash_shape(int prec) { return (prec == HISQ_F64 || prec == HISQ_F64C) ? 10 : 0; }
 
 int tuned_dslash_shape(const Geom &g, int prec)
 {
