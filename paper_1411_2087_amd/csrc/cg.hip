@@ -241,8 +241,13 @@ constexpr int FIN_NT = 256;
 __global__ __launch_bounds__(FIN_NT) void k_finalize(const double *__restrict__ partials, int n, CGState *st, int mode,
                                                      int gate)
 {
-    if (solver_gate_closed(&st->flags, gate)) return;
-    double v = sum_partials<FIN_NT>(partials, n);
+    // the gate and the partials are loaded together; a closed gate discards the partials
+    const bool closed = solver_gate_closed(&st->flags, gate);
+    double acc[1] = { 0.0 };
+    strided_sums<FIN_NT, 1, 8>(partials, n, acc);
+    if (closed) return;
+    __shared__ double lds[FIN_NT / 64];
+    const double v = block_sum<FIN_NT>(acc[0], lds);
     if (threadIdx.x == 0) finalize(st, mode, v);
 }
 
@@ -251,9 +256,14 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const double *__restrict__ 
 __global__ __launch_bounds__(FIN_NT) void k_finalize_pap(const double *__restrict__ part_p, int np,
                                                          const double *__restrict__ part_t, int nt, CGState *st)
 {
-    if (paused(st->flags)) return;
-    const double pp = sum_partials<FIN_NT>(part_p, np);
-    const double tt = sum_partials<FIN_NT>(part_t, nt);
+    const bool closed = paused(st->flags);
+    double ap[1] = { 0.0 }, at[1] = { 0.0 };
+    strided_sums<FIN_NT, 1, 8>(part_p, np, ap);
+    strided_sums<FIN_NT, 1, 8>(part_t, nt, at);
+    if (closed) return;
+    __shared__ double lds[FIN_NT / 64];
+    const double pp = block_sum<FIN_NT>(ap[0], lds);
+    const double tt = block_sum<FIN_NT>(at[0], lds);
     if (threadIdx.x == 0) finalize(st, FIN_PAP, fma(st->m4, pp, tt));
 }
 
@@ -843,11 +853,9 @@ __global__ __launch_bounds__(BL_NT) void k_dot2(const T *__restrict__ x, const T
 __global__ __launch_bounds__(FIN_NT) void k_dot2_fin(const double *__restrict__ partials, int nb, double *out)
 {
     __shared__ double lds[2 * (FIN_NT / 64)];
-    double ar = 0.0, ai = 0.0;
-    for (int i = threadIdx.x; i < nb; i += FIN_NT) {
-        ar += partials[2 * i];
-        ai += partials[2 * i + 1];
-    }
+    double acc[2] = { 0.0, 0.0 };
+    strided_sums<FIN_NT, 2, 4>(partials, nb, acc);
+    double ar = acc[0], ai = acc[1];
     block_sum2<FIN_NT>(ar, ai, lds);
     if (threadIdx.x == 0) {
         out[0] = ar;

@@ -405,9 +405,9 @@ __global__ __launch_bounds__(FIN_NT_M) void k_msfinalize(const double *__restric
 {
     if (st->flags.done && mode != FS_BB) return;
     __shared__ double lds[FIN_NT_M / 64];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nb; i += FIN_NT_M) acc += partials[i];
-    const double v = block_sum<FIN_NT_M>(acc, lds);
+    double acc[1] = { 0.0 };
+    strided_sums<FIN_NT_M, 1, 8>(partials, nb, acc);
+    const double v = block_sum<FIN_NT_M>(acc[0], lds);
     if (threadIdx.x) return;
     const int n = st->n;
     switch (mode) {
@@ -686,23 +686,25 @@ __device__ __forceinline__ void column_sums(const double *red, double *tot)
     }
 }
 
+// Rows of partials [nblocks][N] a finaliser thread loads before adding any:
+// 16 loads in flight per thread whatever N is.
+template <int N> constexpr int fin_rows() { return N >= 16 ? 1 : 16 / N; }
+
 // One pass over the [nblocks][N] partials: thread i keeps the N sums of
-// blocks i, i + 256, ... in registers (all its loads in flight at once), then
-// the 256 x N sums are added column by column.
+// blocks i, i + 256, ... in registers, then the 256 x N sums are added
+// column by column.
 template <int N>
 __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize(const double *__restrict__ partials, int nblocks,
                                                         MultiState *st, int mode, int gate)
 {
-    if (solver_gate_closed(&st->flags, gate)) return;
     __shared__ double red[FIN_NT_M * N];
     __shared__ double tot[N];
     double acc[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) acc[r] = 0.0;
-    for (int i = threadIdx.x; i < nblocks; i += FIN_NT_M) {
-#pragma unroll
-        for (int r = 0; r < N; ++r) acc[r] += partials[(size_t)i * N + r];
-    }
+    const bool closed = solver_gate_closed(&st->flags, gate);  // loaded together with the partials
+    strided_sums<FIN_NT_M, N, fin_rows<N>()>(partials, nblocks, acc);
+    if (closed) return;
 #pragma unroll
     for (int r = 0; r < N; ++r) red[threadIdx.x * N + r] = acc[r];
     __syncthreads();
@@ -717,23 +719,18 @@ template <int N>
 __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize_pap(const double *__restrict__ part_t, int ntt,
                                                             const double *__restrict__ part_p, int npp, MultiState *st)
 {
-    if (paused(st->flags)) return;
     __shared__ double red[FIN_NT_M * N];
     __shared__ double tot[N];
+    const bool closed = paused(st->flags);
     double acc[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) acc[r] = 0.0;
-    for (int i = threadIdx.x; i < ntt; i += FIN_NT_M) {
-#pragma unroll
-        for (int r = 0; r < N; ++r) acc[r] += part_t[(size_t)i * N + r];
-    }
+    strided_sums<FIN_NT_M, N, fin_rows<N>()>(part_t, ntt, acc);
     double accp[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) accp[r] = 0.0;
-    for (int i = threadIdx.x; i < npp; i += FIN_NT_M) {
-#pragma unroll
-        for (int r = 0; r < N; ++r) accp[r] += part_p[(size_t)i * N + r];
-    }
+    strided_sums<FIN_NT_M, N, fin_rows<N>()>(part_p, npp, accp);
+    if (closed) return;
     __shared__ double tt[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) red[threadIdx.x * N + r] = acc[r];

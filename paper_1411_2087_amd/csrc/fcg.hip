@@ -210,11 +210,10 @@ __global__ __launch_bounds__(256) void k_f_fin(const double *__restrict__ partia
 {
     if (st->flags.done && (mode == FF_Z || mode == FF_PAP || mode == FF_UPD)) return;
     __shared__ double lds[2 * 4];
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 256) {
-        if (pairs) { a += partials[2 * i]; b += partials[2 * i + 1]; }
-        else a += partials[i];
-    }
+    double acc[2] = { 0.0, 0.0 };
+    if (pairs) strided_sums<256, 2, 4>(partials, nb, acc);
+    else strided_sums<256, 1, 8>(partials, nb, acc);
+    double a = acc[0], b = acc[1];
     block_sum2<256>(a, b, lds);
     if (threadIdx.x) return;
     switch (mode) {

@@ -166,15 +166,32 @@ __device__ __forceinline__ void block_partial(double v, double *partials, int bl
     if (threadIdx.x == 0) partials[blk] = s;
 }
 
-// Fixed-order sum of n partials by one block of NT threads; valid in thread 0.
-template <int NT>
-__device__ __forceinline__ double sum_partials(const double *partials, int n)
+// acc[r] += p[i * W + r] for r < W and i = threadIdx.x, threadIdx.x + NT, ...
+// < n, in increasing i.  U rows are loaded before any is added, so a thread
+// has U * W loads in flight per round trip (a plain strided loop waits for
+// each load before the next: one memory latency per row).  The order of the
+// additions is that of the plain loop, so the sums are the same to the bit.
+template <int NT, int W, int U>
+__device__ __forceinline__ void strided_sums(const double *__restrict__ p, int n, double acc[W])
 {
-    __shared__ double lds[NT / 64];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += NT) acc += partials[i];
-    return block_sum<NT>(acc, lds);
+    for (int i0 = threadIdx.x; i0 < n; i0 += U * NT) {
+        double v[U][W];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * NT;
+#pragma unroll
+            for (int r = 0; r < W; ++r) v[u][r] = i < n ? p[(size_t)i * W + r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u * NT < n) {
+#pragma unroll
+                for (int r = 0; r < W; ++r) acc[r] += v[u][r];
+            }
+        }
+    }
 }
+
 
 // ------------------------------------------------------------------ streaming loads / stores
 // Nontemporal (streaming) accesses on native clang vectors; the HIP vector
