@@ -763,14 +763,13 @@ template <int N>
 __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize(const double *__restrict__ partials, int nblocks,
                                                         MultiState *st, int mode, int gate)
 {
+    if (solver_gate_closed(&st->flags, gate)) return;  // first: paused iterations stay cheap
     __shared__ double red[FIN_NT_M * N];
     __shared__ double tot[N];
     double acc[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) acc[r] = 0.0;
-    const bool closed = solver_gate_closed(&st->flags, gate);  // loaded together with the partials
     strided_sums<FIN_NT_M, N, fin_rows<N>()>(partials, nblocks, acc);
-    if (closed) return;
 #pragma unroll
     for (int r = 0; r < N; ++r) red[threadIdx.x * N + r] = acc[r];
     __syncthreads();
@@ -785,9 +784,9 @@ template <int N>
 __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize_pap(const double *__restrict__ part_t, int ntt,
                                                             const double *__restrict__ part_p, int npp, MultiState *st)
 {
+    if (paused(st->flags)) return;
     __shared__ double red[FIN_NT_M * N];
     __shared__ double tot[N];
-    const bool closed = paused(st->flags);
     double acc[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) acc[r] = 0.0;
@@ -796,7 +795,6 @@ __global__ __launch_bounds__(FIN_NT_M) void k_mfinalize_pap(const double *__rest
 #pragma unroll
     for (int r = 0; r < N; ++r) accp[r] = 0.0;
     strided_sums<FIN_NT_M, N, fin_rows<N>()>(part_p, npp, accp);
-    if (closed) return;
     __shared__ double tt[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) red[threadIdx.x * N + r] = acc[r];
