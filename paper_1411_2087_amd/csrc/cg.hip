@@ -290,12 +290,24 @@ __global__ void k_clear_done(CGState *st)
 }
 
 // ------------------------------------------------------------------ Dslash-fused kernels
-// Waves per SIMD the fused kernels ask for: the two-row FP64 operator needs
-// more than the 64 registers that 8 waves leave.
-template <class P> constexpr int cg_waves() { return (P::prec == HISQ_F64 || P::prec == HISQ_F64C) ? 5 : 8; }
-// terms of the 16 unrolled together: two for the FP64 forms, so that a wave
-// has two directions' link loads in flight (their best Dslash launch shape)
-template <class P> constexpr int cg_unroll() { return (P::prec == HISQ_F64 || P::prec == HISQ_F64C) ? 2 : 1; }
+// Waves per SIMD the fused kernels ask for and terms of the 16 unrolled
+// together, per link storage (measured with the mixed solves at 32^4):
+//   FP64 forms        5 waves, 2 terms: a wave has two directions' link loads
+//                     in flight (their best Dslash launch shape)
+//   I16S, FP32 two-row 4 waves, 4 terms (2-3 % faster solves than 8 / 1)
+//   FP32, FP16S       8 waves, 1 term
+template <class P> constexpr bool cg_wide()
+{
+    return P::prec == HISQ_I16S || P::prec == HISQ_F32C;
+}
+template <class P> constexpr int cg_waves()
+{
+    return (P::prec == HISQ_F64 || P::prec == HISQ_F64C) ? 5 : (cg_wide<P>() ? 4 : 8);
+}
+template <class P> constexpr int cg_unroll()
+{
+    return (P::prec == HISQ_F64 || P::prec == HISQ_F64C) ? 2 : (cg_wide<P>() ? 4 : 1);
+}
 
 // t = D_oe p on the odd sites ; partials of |t|^2
 template <class P, int NT, int W>
