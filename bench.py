@@ -87,8 +87,10 @@ def cpu_baseline(fat, lng, b, vh, budget_s=15.0):
                       f"+ BLAS-1) in {dt:.1f} s; sustained algorithmic Dslash GB/s"}
 
 
-def form_batched(hq, dims, L64, L32, mode, n, log):
-    """Batched solve of n masses (log-spaced 0.002 - 0.2) against n sequential plain FP64 solves."""
+def form_batched(hq, dims, L64, L32, mode, n, log, cg_mode=0, seq_from=None):
+    """Batched solve of n masses (log-spaced 0.002 - 0.2) against n sequential plain FP64 solves.
+    cg_mode HISQ_CG_MIXED_F32C: L64 / L32 hold two-row long links (F64C / F32C).  seq_from: a previous
+    result of the same systems whose sequential plain FP64 time is reused."""
     import numpy as np
     import torch
     import synth
@@ -101,27 +103,32 @@ def form_batched(hq, dims, L64, L32, mode, n, log):
     b = torch.from_numpy(bs).cuda()
     x = torch.zeros((n, vh, 3), dtype=torch.complex128, device="cuda")
     ws = hq.fields.workspace("cg_multi", dims, n, mode)
-    opts = hq.CGOpts(mode=0, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    opts = hq.CGOpts(mode=cg_mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = hq.cg_solve_multi(n, masses, TOL, mode, L64.fat, L64.lng, L32.fat, L32.lng, b, x, dims, opts, ws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     del ws, x
-    # the same systems one at a time with plain FP64 CG
-    wsp = hq.fields.workspace("cg", dims)
-    seq, seq_iters = 0.0, []
-    for r in range(n):
-        bb = (b[r] if mode == hq.HISQ_MULTI_RHS else b).contiguous()
-        xx = torch.zeros_like(bb)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        s1 = hq.cg_solve(masses[r], TOL, L64.fat, L64.lng, None, None, bb, xx, dims, None, wsp)
-        torch.cuda.synchronize()
-        seq += time.perf_counter() - t1
-        seq_iters.append(s1["iters"])
-    name = "multi_rhs" if mode == hq.HISQ_MULTI_RHS else "multi_shift"
-    log(f"[form {name}_{n}] {dt:.2f}s vs sequential plain FP64 {seq:.2f}s")
+    if seq_from is not None:
+        seq, seq_iters = seq_from["sequential_plain_f64_s"], seq_from["sequential_plain_iters"]
+    else:
+        # the same systems one at a time with plain FP64 CG
+        wsp = hq.fields.workspace("cg", dims)
+        seq, seq_iters = 0.0, []
+        for r in range(n):
+            bb = (b[r] if mode == hq.HISQ_MULTI_RHS else b).contiguous()
+            xx = torch.zeros_like(bb)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s1 = hq.cg_solve(masses[r], TOL, L64.fat, L64.lng, None, None, bb, xx, dims, None, wsp)
+            torch.cuda.synchronize()
+            seq += time.perf_counter() - t1
+            seq_iters.append(s1["iters"])
+    name = ("multi_rhs" if mode == hq.HISQ_MULTI_RHS else "multi_shift") + f"_{n}"
+    if cg_mode == hq.HISQ_CG_MIXED_F32C:
+        name += "_f32c"
+    log(f"[form {name}] {dt:.2f}s vs sequential plain FP64 {seq:.2f}s")
     return {"s": round(dt, 3), "n": n, "masses": "log-spaced 0.002-0.2", "iters": [s_["iters"] for s_ in st],
             "worst_true_resid": max(s_["true_resid"] for s_ in st), "sequential_plain_f64_s": round(seq, 3),
             "sequential_plain_iters": seq_iters, "speedup_vs_sequential_plain": round(seq / dt, 3)}
@@ -566,6 +573,11 @@ def main():
     if not args.no_forms and not args.no_batched:
         forms["multi_rhs_8"] = form_batched(hq, DIMS, L64, L32, hq.HISQ_MULTI_RHS, 8, log)
         forms["multi_shift_8"] = form_batched(hq, DIMS, L64, L32, hq.HISQ_MULTI_SHIFT, 8, log)
+        # the same with two-row long links on both levels
+        forms["multi_rhs_8_f32c"] = form_batched(hq, DIMS, L64C, L32C, hq.HISQ_MULTI_RHS, 8, log,
+                                                 hq.HISQ_CG_MIXED_F32C, forms["multi_rhs_8"])
+        forms["multi_shift_8_f32c"] = form_batched(hq, DIMS, L64C, L32C, hq.HISQ_MULTI_SHIFT, 8, log,
+                                                   hq.HISQ_CG_MIXED_F32C, forms["multi_shift_8"])
     if not args.no_forms and not args.no_learned:
         del L16, LI16, L64C, L32C
         forms["learned"] = form_learned(hq, log)

@@ -135,7 +135,9 @@ __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__
         const int tile = h / TILE, lane = h % TILE;
         int cx, cy, cz, ct;
         site_coords(g, h, parity, cx, cy, cz, ct);
-        const size_t tile_off = ((size_t)parity * g.ntiles + tile) * 8 * P::block_bytes;
+        const size_t tix = (size_t)parity * g.ntiles + tile;
+        const char *fat_t = fat + tix * P::Fat::tile_bytes;
+        const char *lng_t = lng + tix * P::Long::tile_bytes;
         R acc[G][6];
 #pragma unroll
         for (int j = 0; j < G; ++j)
@@ -147,8 +149,9 @@ __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__
             const bool is_long = d >= 8;
             const int k = (is_long ? 3 : 1) * (((d >> 2) & 1) ? -1 : 1);
             const int nh = nbr_h(g, h, cx, cy, cz, ct, mu, k);
-            R m[18];
-            P::load((is_long ? lng : fat) + tile_off + (size_t)(d & 7) * P::block_bytes, lane, m);
+            R m[18];  // a two-row long link is rebuilt in full: it serves G right-hand sides
+            if (is_long) P::Long::load_dir(lng_t, d & 7, lane, m);
+            else P::Fat::load_dir(fat_t, d & 7, lane, m);
             if constexpr (MD_LDS) {
                 wave_sync();  // every lane has read the previous direction's blocks
 #pragma unroll
@@ -364,6 +367,7 @@ __global__ __launch_bounds__(MB_NT) void k_mnorm(const double2 *__restrict__ v, 
 // ------------------------------------------------------------------ shifted CG (FP32)
 // base system (A0 + sigma0) on single vectors p, r, ap, t; shifted solutions
 // and directions x_i, p_i batched [Vh][N][3].
+template <class PS>
 __global__ __launch_bounds__(256) HISQ_WAVES(8) void k_ms_ap(Geom g, const char *__restrict__ fat,
                                                           const char *__restrict__ lng,
                                                           const float2 *__restrict__ t, const float2 *__restrict__ p,
@@ -380,7 +384,7 @@ __global__ __launch_bounds__(256) HISQ_WAVES(8) void k_ms_ap(Geom g, const char 
     if (tile < g.ntiles) {
         const int hc = h < g.Vh ? h : g.Vh - 1;
         float acc[6];
-        dslash_site<PF32>(g, fat, lng, t, 0, tile, lane, hc, acc);
+        dslash_site<PS>(g, fat, lng, t, 0, tile, lane, hc, acc);
         if (h < g.Vh) {
             const float m = (float)st->sigma0;
 #pragma unroll
@@ -876,7 +880,19 @@ struct MShape {
 constexpr int N_MSHAPES = 4;
 static const MShape MSHAPES[N_MSHAPES] = { { 1, 256 }, { 2, 256 }, { 4, 256 }, { 1, 128 } };
 
-static int mshape_for(const Geom &g, int N) { return tuned_choice("mdslash", g, HISQ_F32, N, 0); }
+template <class PS> static int mshape_for(const Geom &g, int N) { return tuned_choice("mdslash", g, PS::prec, N, 0); }
+
+// Link storage of the batched solvers: the outer FP64 links (reliable
+// updates, true residuals) and the inner FP32 links, both full or both with
+// two-row long links.
+struct MultiLinks32 {
+    using PH = PF64;
+    using PS = PF32;
+};
+struct MultiLinks32C {
+    using PH = PF64C;
+    using PS = PF32C;
+};
 
 template <class P, int N, int G, int NT, int EPI>
 static hipError_t launch_md(const Geom &g, const void *fat, const void *lng, const void *src, void *dst,
@@ -1075,7 +1091,7 @@ struct MultiOut {
 
 // Batched reliable-update CG, set-up: R64 = B - A X64 for every RHS, RS =
 // float(R64), PS = RS (B.b64 and B.x64 [Vh][N][3] FP64 on entry).
-template <int N>
+template <class M, int N>
 static int multi_rhs_init(int n, const double *masses, double tol, const void *fat, const void *lng, const Geom &g,
                           const hisq_cg_opts &o, MultiBufs &B, MultiState *hs, hipStream_t s)
 {
@@ -1091,9 +1107,9 @@ static int multi_rhs_init(int n, const double *masses, double tol, const void *f
     hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nbm, B.st, (int)FM_BB,
                        (int)GATE_ALWAYS);
     int nb = 0;
-    HISQ_HIP((launch_md_shape<PF64, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
+    HISQ_HIP((launch_md_shape<typename M::PH, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
                                                   B.st, MASK_ALL, GATE_ALWAYS, s, &nb)));
-    HISQ_HIP((launch_md_shape<PF64, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
+    HISQ_HIP((launch_md_shape<typename M::PH, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
                                                   MASK_ALL, GATE_ALWAYS, s, &nb)));
     hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nb, B.st, (int)FM_INIT,
                        (int)GATE_ALWAYS);
@@ -1103,25 +1119,26 @@ static int multi_rhs_init(int n, const double *masses, double tol, const void *f
     return read_mstate(hs, B.st, s);
 }
 
-template <int N>
+template <class M, int N>
 static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, const void *lng_lo, const Geom &g,
                          const hisq_cg_opts &o, MultiBufs &B, MultiState *hs, hipStream_t s, int iter_offset,
                          MultiOut &out);
 
-template <int N>
+template <class PS, int N>
 static int tune_multi_impl(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, void *ws,
                            size_t ws_bytes, int reps, int *best, double *us, hipStream_t s);
 
-// Launch shape of the N-RHS FP32 Dslash on this lattice: the tuned one, or
-// tuned now on the batch's own vectors (scratch state in the partials
-// buffer, which holds nothing live before the iteration starts).
-template <int N>
+// Launch shape of the N-RHS FP32 Dslash on this lattice and inner link
+// storage: the tuned one, or tuned now on the batch's own vectors (scratch
+// state in the partials buffer, which holds nothing live before the
+// iteration starts).
+template <class PS, int N>
 static int md_shape_or_tune(const Geom &g, const void *fat_lo, const void *lng_lo, MultiBufs &B, hipStream_t s)
 {
-    int shape = tuned_choice("mdslash", g, HISQ_F32, N, -1);
+    int shape = tuned_choice("mdslash", g, PS::prec, N, -1);
     if (shape >= 0) return shape;
-    if (tune_multi_impl<N>(g, fat_lo, lng_lo, B.ps, B.ts, B.part, multi_partials(g, N) * sizeof(double), 5, &shape,
-                           nullptr, s) != HISQ_OK)
+    if (tune_multi_impl<PS, N>(g, fat_lo, lng_lo, B.ps, B.ts, B.part, multi_partials(g, N) * sizeof(double), 5, &shape,
+                               nullptr, s) != HISQ_OK)
         return 0;
     return shape;
 }
@@ -1145,7 +1162,7 @@ static void retire(MultiBufs &B, const MultiState *hs, const Geom &g, int c, Mul
 // into [Vh][N2][3] in the same buffers (through the scratch vectors t64 and
 // ts), their per-RHS state moves with them, and the iteration continues
 // with the N2 kernels.  Nothing restarts: x, r, p and every scalar are kept.
-template <int N, int N2>
+template <class M, int N, int N2>
 static int shrink_to(const void *fat, const void *lng, const void *fat_lo, const void *lng_lo, const Geom &g,
                      const hisq_cg_opts &o, MultiBufs &B, MultiState *hs, hipStream_t s, int iter_offset,
                      MultiOut &out, const Cols &live)
@@ -1194,30 +1211,31 @@ static int shrink_to(const void *fat, const void *lng, const void *fat_lo, const
     std::memcpy(out.orig, orig2, sizeof(orig2));
     HISQ_HIP(hipMemcpyAsync(B.st, hs, sizeof(MultiState), hipMemcpyHostToDevice, s));
     HISQ_HIP(hipStreamSynchronize(s));
-    return multi_rhs_run<N2>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out);
+    return multi_rhs_run<M, N2>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out);
 }
 
 // Batched reliable-update CG iterations from the state multi_rhs_init (or a
 // shrink) left; every right-hand side ends in the caller's x and in `out`.
-template <int N>
+template <class M, int N>
 static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, const void *lng_lo, const Geom &g,
                          const hisq_cg_opts &o, MultiBufs &B, MultiState *hs, hipStream_t s, int iter_offset,
                          MultiOut &out)
 {
     const long long np = (long long)g.Vh * N;
     const int nbm = mblocks(np);
-    const int shape = md_shape_or_tune<N>(g, fat_lo, lng_lo, B, s);
+    using PS = typename M::PS;
+    const int shape = md_shape_or_tune<PS, N>(g, fat_lo, lng_lo, B, s);
     auto iter = [&](hipStream_t q) -> hipError_t {
         // t = D_oe p and |t|^2 ; alpha = rr / (m4 |p|^2 + |t|^2)
         int nb1 = 0;
-        hipError_t e = launch_md_shape<PF32, N, EPI_STORE_NORM>(shape, g, fat_lo, lng_lo, B.ps, B.ts, nullptr,
+        hipError_t e = launch_md_shape<PS, N, EPI_STORE_NORM>(shape, g, fat_lo, lng_lo, B.ps, B.ts, nullptr,
                                                                 nullptr, nullptr, 1, B.part, B.st, MASK_ACTIVE,
                                                                 GATE_PAUSE, q, &nb1);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mfinalize_pap<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb1,
                            (const double *)B.part_p, nbm, B.st);
         // x += alpha p ; r -= alpha (m4 p - D_eo t) ; |r|^2
-        e = launch_md_shape<PF32, N, EPI_UPD>(shape, g, fat_lo, lng_lo, B.ts, B.xs, B.ps, nullptr, B.rs, 0, B.part,
+        e = launch_md_shape<PS, N, EPI_UPD>(shape, g, fat_lo, lng_lo, B.ts, B.xs, B.ps, nullptr, B.rs, 0, B.part,
                                               B.st, MASK_ACTIVE, GATE_PAUSE, q, &nb1);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb1, B.st,
@@ -1233,10 +1251,10 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
                            (int)MASK_RELIABLE, (int)GATE_RELIABLE);
         hipError_t e;
         int nb2 = 0;
-        e = launch_md_shape<PF64, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
+        e = launch_md_shape<typename M::PH, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
                                                 B.st, MASK_RELIABLE, GATE_RELIABLE, q, &nb2);
         if (e != hipSuccess) return e;
-        e = launch_md_shape<PF64, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
+        e = launch_md_shape<typename M::PH, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
                                                 MASK_RELIABLE, GATE_RELIABLE, q, &nb2);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb2, B.st,
@@ -1265,10 +1283,10 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
             }
             HISQ_HIP(hipGetLastError());
             const int n2 = pad_n(live.n);
-            if (n2 == 1) return shrink_to<N, 1>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
-            if constexpr (N > 2) if (n2 == 2) return shrink_to<N, 2>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
-            if constexpr (N > 4) if (n2 == 4) return shrink_to<N, 4>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
-            if constexpr (N > 8) if (n2 == 8) return shrink_to<N, 8>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
+            if (n2 == 1) return shrink_to<M, N, 1>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
+            if constexpr (N > 2) if (n2 == 2) return shrink_to<M, N, 2>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
+            if constexpr (N > 4) if (n2 == 4) return shrink_to<M, N, 4>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
+            if constexpr (N > 8) if (n2 == 8) return shrink_to<M, N, 8>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, iter_offset, out, live);
             return fail(HISQ_EINVAL, "cg_solve_multi: internal batch size error");
         }
     }
@@ -1277,9 +1295,9 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
     hipLaunchKernelGGL((k_maccum<N>), dim3(nbm), dim3(MB_NT), 0, s, B.x64, B.xs, np, (const MultiState *)B.st,
                        (int)MASK_ALL, (int)GATE_ALWAYS);
     int nb = 0;
-    HISQ_HIP((launch_md_shape<PF64, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
+    HISQ_HIP((launch_md_shape<typename M::PH, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
                                                   B.st, MASK_ALL, GATE_ALWAYS, s, &nb)));
-    HISQ_HIP((launch_md_shape<PF64, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
+    HISQ_HIP((launch_md_shape<typename M::PH, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
                                                   MASK_ALL, GATE_ALWAYS, s, &nb)));
     hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nb, B.st, (int)FM_FINAL,
                        (int)GATE_ALWAYS);
@@ -1293,7 +1311,7 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
 
 // Shifted CG for one source and n shifts in FP32 (stage 1 of MULTI_SHIFT);
 // leaves the shifted solutions in B.xs.
-template <int N>
+template <class M, int N>
 static int multi_shift_core(int n, const double *masses, double tol_ms, const void *fat_lo, const void *lng_lo,
                             const void *b, const Geom &g, const hisq_cg_opts &o, MultiBufs &B, MultiState *hs,
                             hipStream_t s)
@@ -1316,9 +1334,9 @@ static int multi_shift_core(int n, const double *masses, double tol_ms, const vo
     if (rc0) return rc0;
     if (hs->bb0 == 0.0) return HISQ_OK;  // zero source: every x_i = 0 (already in B.xs)
     auto iter = [&](hipStream_t q) -> hipError_t {
-        hipError_t e = launch_dslash<PF32>(g, fat_lo, lng_lo, B.p1, B.t1, 1, q, &B.st->flags, GATE_NOT_DONE);
+        hipError_t e = launch_dslash<typename M::PS>(g, fat_lo, lng_lo, B.p1, B.t1, 1, q, &B.st->flags, GATE_NOT_DONE);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_ms_ap, dim3(xcd_grid(nbd)), dim3(256), 0, q, g, (const char *)fat_lo,
+        hipLaunchKernelGGL(k_ms_ap<typename M::PS>, dim3(xcd_grid(nbd)), dim3(256), 0, q, g, (const char *)fat_lo,
                            (const char *)lng_lo, (const float2 *)B.t1, (const float2 *)B.p1, B.ap1, nbd, B.part,
                            (const MultiState *)B.st);
         hipLaunchKernelGGL(k_msfinalize, dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nbd, B.st,
@@ -1338,7 +1356,7 @@ static int multi_shift_core(int n, const double *masses, double tol_ms, const vo
     return hs->ms_status;
 }
 
-template <int N>
+template <class M, int N>
 static int cg_multi_impl(int n, const double *masses, double tol, int mode, const void *fat, const void *lng,
                          const void *fat_lo, const void *lng_lo, const void *b, void *x, const Geom &g,
                          const hisq_cg_opts &o, void *ws, size_t ws_bytes, hisq_cg_stats *stats, hipStream_t s)
@@ -1355,7 +1373,7 @@ static int cg_multi_impl(int n, const double *masses, double tol, int mode, cons
     int offset = 0;
     if (mode == HISQ_MULTI_SHIFT) {
         const double tol_ms = std::max(tol, 1e-5);
-        int rc = multi_shift_core<N>(n, masses, tol_ms, fat_lo, lng_lo, b, g, o, B, H.h, s);
+        int rc = multi_shift_core<M, N>(n, masses, tol_ms, fat_lo, lng_lo, b, g, o, B, H.h, s);
         if (rc) return fail(rc, "cg_solve_multi: shifted CG broke down");
         for (int i = 0; i < n; ++i) ms_iters[i] = H.h->iters[i];
         offset = H.h->iter;
@@ -1369,13 +1387,13 @@ static int cg_multi_impl(int n, const double *masses, double tol, int mode, cons
                            n, 0);
     }
     HISQ_HIP(hipGetLastError());
-    int rc = multi_rhs_init<N>(n, masses, tol, fat, lng, g, o, B, H.h, s);
+    int rc = multi_rhs_init<M, N>(n, masses, tol, fat, lng, g, o, B, H.h, s);
     if (rc) return rc;
     MultiOut out;
     std::memset(&out, 0, sizeof(out));
     out.x = (double2 *)x;
     for (int c = 0; c < MAXR; ++c) out.orig[c] = c < n ? c : -1;
-    rc = multi_rhs_run<N>(fat, lng, fat_lo, lng_lo, g, o, B, H.h, s, offset, out);
+    rc = multi_rhs_run<M, N>(fat, lng, fat_lo, lng_lo, g, o, B, H.h, s, offset, out);
     if (rc) return rc;
     HISQ_HIP(hipStreamSynchronize(s));
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1400,7 +1418,7 @@ static int cg_multi_impl(int n, const double *masses, double tol, int mode, cons
 }
 
 // ------------------------------------------------------------------ autotuner of the multi-RHS Dslash
-template <int N>
+template <class PS, int N>
 static int tune_multi_impl(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, void *ws,
                            size_t ws_bytes, int reps, int *best, double *us, hipStream_t s)
 {
@@ -1415,8 +1433,8 @@ static int tune_multi_impl(const Geom &g, const void *fat, const void *lng, cons
     for (int i = 0; i < N_MSHAPES && !rc; ++i) {
         if (N / MSHAPES[i].gdiv < 1 || (N % MSHAPES[i].gdiv)) { if (us) us[i] = -1; continue; }
         auto go = [&]() {
-            return launch_md_shape<PF32, N, EPI_STORE>(i, g, fat, lng, src, dst, nullptr, nullptr, nullptr, 1, nullptr,
-                                                      st, MASK_ACTIVE, GATE_ALWAYS, s, nullptr);
+            return launch_md_shape<PS, N, EPI_STORE>(i, g, fat, lng, src, dst, nullptr, nullptr, nullptr, 1, nullptr,
+                                                    st, MASK_ACTIVE, GATE_ALWAYS, s, nullptr);
         };
         for (int w = 0; w < 2; ++w) if (go() != hipSuccess) rc = HISQ_EHIP;
         hipEventRecord(e0, s);
@@ -1432,7 +1450,7 @@ static int tune_multi_impl(const Geom &g, const void *fat, const void *lng, cons
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return fail(rc, "hisq_tune_multi: launch failed");
-    set_tuned_choice("mdslash", g, HISQ_F32, N, best_i);
+    set_tuned_choice("mdslash", g, PS::prec, N, best_i);
     if (best) *best = best_i;
     return HISQ_OK;
 }
@@ -1444,9 +1462,23 @@ static int mdslash_apply_impl(const Geom &g, const void *fat, const void *lng, c
 {
     MultiState *st = (MultiState *)ws;
     hipLaunchKernelGGL(k_mstate_all, dim3(1), dim3(1), 0, s, st, N);
-    HISQ_HIP((launch_md_shape<PF32, N, EPI_STORE>(mshape_for(g, N), g, fat, lng, src, dst, nullptr, nullptr, nullptr,
+    HISQ_HIP((launch_md_shape<PF32, N, EPI_STORE>(mshape_for<PF32>(g, N), g, fat, lng, src, dst, nullptr, nullptr, nullptr,
                                                   parity, nullptr, st, MASK_ACTIVE, GATE_ALWAYS, s, nullptr)));
     return HISQ_OK;
+}
+
+template <class M>
+static int cg_multi_dispatch(int nrhs, const double *masses, double tol, int mode, const void *fat, const void *lng,
+                             const void *fat_lo, const void *lng_lo, const void *b, void *x, const Geom &g,
+                             const hisq_cg_opts &o, void *ws, size_t ws_bytes, hisq_cg_stats *stats, hipStream_t s)
+{
+    switch (pad_n(nrhs)) {
+    case 1: return cg_multi_impl<M, 1>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, ws, ws_bytes, stats, s);
+    case 2: return cg_multi_impl<M, 2>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, ws, ws_bytes, stats, s);
+    case 4: return cg_multi_impl<M, 4>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, ws, ws_bytes, stats, s);
+    case 8: return cg_multi_impl<M, 8>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, ws, ws_bytes, stats, s);
+    default: return cg_multi_impl<M, 16>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, ws, ws_bytes, stats, s);
+    }
 }
 
 }  // namespace hisq
@@ -1474,13 +1506,8 @@ extern "C" int cg_solve_multi(int nrhs, const double *masses, double tol, int mo
     hisq_cg_opts o = resolve_opts(opts, g);
     hipStream_t s = (hipStream_t)stream;
     HISQ_HIP(hipStreamSynchronize(s));
-    switch (pad_n(nrhs)) {
-    case 1: return cg_multi_impl<1>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
-    case 2: return cg_multi_impl<2>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
-    case 4: return cg_multi_impl<4>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
-    case 8: return cg_multi_impl<8>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
-    default: return cg_multi_impl<16>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
-    }
+    if (o.mode == HISQ_CG_MIXED_F32C) return cg_multi_dispatch<MultiLinks32C>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
+    return cg_multi_dispatch<MultiLinks32>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
 }
 
 extern "C" int hisq_tune_multi(const void *fat, const void *lng, const void *src, void *dst, const int dims[4], int nrhs,
@@ -1496,11 +1523,11 @@ extern "C" int hisq_tune_multi(const void *fat, const void *lng, const void *src
     if (reps <= 0) reps = 10;
     hipStream_t s = (hipStream_t)stream;
     switch (nrhs) {
-    case 1: return tune_multi_impl<1>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
-    case 2: return tune_multi_impl<2>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
-    case 4: return tune_multi_impl<4>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
-    case 8: return tune_multi_impl<8>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
-    default: return tune_multi_impl<16>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
+    case 1: return tune_multi_impl<PF32, 1>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
+    case 2: return tune_multi_impl<PF32, 2>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
+    case 4: return tune_multi_impl<PF32, 4>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
+    case 8: return tune_multi_impl<PF32, 8>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
+    default: return tune_multi_impl<PF32, 16>(g, fat, lng, src, dst, workspace, ws_bytes, reps, best_shape, us_per_shape, s);
     }
 }
 
@@ -1537,5 +1564,5 @@ extern "C" int hisq_multi_shape(const int dims[4], int nrhs, int shape)
         if (nrhs % MSHAPES[shape].gdiv) return fail(HISQ_EINVAL, "hisq_multi_shape: shape does not divide nrhs");
         set_tuned_choice("mdslash", g, HISQ_F32, nrhs, shape);
     }
-    return mshape_for(g, nrhs);
+    return mshape_for<PF32>(g, nrhs);
 }

@@ -49,33 +49,35 @@ def test_dslash_multi_parity(hq, dims, nrhs):
     say(f"dslash_multi dims={dims} nrhs={nrhs}: shapes {len(outs)}, tuned {best} {['%.1f' % u for u in us]} us")
 
 
-def _solve_multi(hq, dims, fat, lng, bs, masses, mode, max_iter=0):
+def _solve_multi(hq, dims, fat, lng, bs, masses, mode, max_iter=0, compressed=False):
+    """compressed: two-row long links on both levels (F64C outer, F32C inner)."""
     import torch
-    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
-    L32 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32)
+    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64C if compressed else hq.HISQ_F64)
+    L32 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32C if compressed else hq.HISQ_F32)
     n = len(masses)
     b = torch.from_numpy(np.ascontiguousarray(bs)).cuda()
     vh = int(np.prod(dims)) // 2
     x = torch.zeros((n, vh, 3), dtype=torch.complex128, device="cuda")
     ws = hq.fields.workspace("cg_multi", dims, n, mode)
-    opts = hq.CGOpts(mode=0, max_iter=max_iter, check_every=0, use_graph=1, delta=0.1)
+    opts = hq.CGOpts(mode=hq.HISQ_CG_MIXED_F32C if compressed else 0, max_iter=max_iter, check_every=0, use_graph=1,
+                     delta=0.1)
     st = hq.cg_solve_multi(n, masses, CG_TOL, mode, L64.fat, L64.lng, L32.fat, L32.lng, b, x, dims, opts, ws)
     return x.cpu().numpy(), st
 
 
-@pytest.mark.parametrize("n", [3, 8, 16])
-def test_cg_multi_rhs(hq, n):
+@pytest.mark.parametrize("n,compressed", [(3, False), (8, False), (16, False), (8, True)])
+def test_cg_multi_rhs(hq, n, compressed):
     dims = (8, 8, 8, 8)
     fat, lng = fields(dims, synth.gauge_seed(4))
     masses = synth.log_masses(n, 0.002, 0.2) if n > 1 else np.array([0.05])
     bs = np.stack([synth.source(dims, synth.source_seed(4, r)) for r in range(n)])
     if n == 3:
         bs[1] = 0.0  # a zero source inside the batch
-    x, st = _solve_multi(hq, dims, fat, lng, bs, masses, hq.HISQ_MULTI_RHS)
+    x, st = _solve_multi(hq, dims, fat, lng, bs, masses, hq.HISQ_MULTI_RHS, compressed=compressed)
     for r in range(n):
         tr = oracle.true_residual(dims, masses[r], fat, lng, bs[r], x[r]) if bs[r].any() else 0.0
-        say(f"multi-rhs n={n} r={r} m={masses[r]:.4f}: iters={st[r]['iters']} updates={st[r]['reliable_updates']} "
-            f"gpu={st[r]['true_resid']:.2e} oracle={tr:.2e}")
+        say(f"multi-rhs n={n} compressed={compressed} r={r} m={masses[r]:.4f}: iters={st[r]['iters']} "
+            f"updates={st[r]['reliable_updates']} gpu={st[r]['true_resid']:.2e} oracle={tr:.2e}")
         assert st[r]["status"] == 0 and tr <= CG_TOL
         if not bs[r].any():
             assert not x[r].any()
@@ -84,17 +86,17 @@ def test_cg_multi_rhs(hq, n):
     assert np.linalg.norm(x[0] - xo) / np.linalg.norm(xo) < 1e-6
 
 
-@pytest.mark.parametrize("n", [4, 8])
-def test_cg_multi_shift(hq, n):
+@pytest.mark.parametrize("n,compressed", [(4, False), (8, False), (4, True)])
+def test_cg_multi_shift(hq, n, compressed):
     dims = (8, 8, 8, 8)
     fat, lng = fields(dims, synth.gauge_seed(4))
     masses = synth.log_masses(n, 0.002, 0.2)
     b = synth.source(dims, synth.source_seed(4))
-    x, st = _solve_multi(hq, dims, fat, lng, b, masses, hq.HISQ_MULTI_SHIFT)
+    x, st = _solve_multi(hq, dims, fat, lng, b, masses, hq.HISQ_MULTI_SHIFT, compressed=compressed)
     for r in range(n):
         tr = oracle.true_residual(dims, masses[r], fat, lng, b, x[r])
-        say(f"multi-shift n={n} m={masses[r]:.4f}: iters={st[r]['iters']} updates={st[r]['reliable_updates']} "
-            f"oracle={tr:.2e}")
+        say(f"multi-shift n={n} compressed={compressed} m={masses[r]:.4f}: iters={st[r]['iters']} "
+            f"updates={st[r]['reliable_updates']} oracle={tr:.2e}")
         assert st[r]["status"] == 0 and tr <= CG_TOL
     xo, _ = oracle.cg(dims, masses[-1], fat, lng, b, tol=1e-12)
     assert np.linalg.norm(x[-1] - xo) / np.linalg.norm(xo) < 1e-6
