@@ -211,10 +211,11 @@ int cg_solve(double mass, double tol, const void *fat, const void *lng, const vo
  * [nrhs][Vh][3] (MULTI_RHS) or [Vh][3] (MULTI_SHIFT); x: complex128
  * [nrhs][Vh][3], solved from x0 = 0 to |b_i - A(m_i) x_i| <= tol |b_i| for
  * every i.  fat/lng: F64 packed links (reliable updates, final residuals);
- * fat_lo/lng_lo: F32 packed links (inner iterations); with opts->mode ==
- * HISQ_CG_MIXED_F32C, F64C and F32C packed links instead (two-row long
- * links, Sec. 4), any other mode: F64 and F32.  opts: max_iter,
- * check_every, use_graph and delta as for cg_solve.
+ * fat_lo/lng_lo: F32 packed links (inner iterations) for opts->mode
+ * HISQ_CG_PLAIN_F64 or HISQ_CG_MIXED_F32; for HISQ_CG_MIXED_F32C, F64C and
+ * F32C packed links (two-row long links, Sec. 4); any other mode is
+ * HISQ_EINVAL.  opts: max_iter, check_every, use_graph and delta as for
+ * cg_solve.
  * stats: host array [nrhs] (may be NULL), per right-hand side; iters counts
  * the shifted-CG iterations plus the refinement iterations.  Returns
  * HISQ_ENOCONV / HISQ_EBREAKDOWN if any right-hand side failed; x then holds

@@ -111,6 +111,17 @@ def test_cg_multi_zero_source_and_limits(hq):
     bs = np.stack([synth.source(dims, 1), synth.source(dims, 2)])
     x, st = _solve_multi(hq, dims, fat, lng, bs, [0.01, 0.2], hq.HISQ_MULTI_RHS, max_iter=3)
     assert st[0]["rc"] == -5
+    # 16-bit inner links are refused (argument check, before any launch)
+    import torch
+    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
+    LI = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_I16S)
+    b = torch.from_numpy(bs).cuda()
+    xg = torch.zeros_like(b)
+    ws = hq.fields.workspace("cg_multi", dims, 2, hq.HISQ_MULTI_RHS)
+    opts = hq.CGOpts(mode=hq.HISQ_CG_MIXED_I16S, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    with pytest.raises(hq.HisqError, match="HISQ_EINVAL"):
+        hq.cg_solve_multi(2, [0.01, 0.2], 1e-10, hq.HISQ_MULTI_RHS, L64.fat, L64.lng, LI.fat, LI.lng, b, xg, dims,
+                          opts, ws)
 
 
 def test_cg_multi_16_4_timing(hq):
