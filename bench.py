@@ -247,7 +247,7 @@ def run_large(args):
     fat, lng = synth.links(dims, synth.gauge_seed(3))
     b_np = synth.source(dims, synth.source_seed(3))
     fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
-    precs = (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S, hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_F16S)
+    precs = (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S, hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_I16SC, hq.HISQ_F16S)
     L = {p: hq.fields.Links.pack(fd, ld, dims, p) for p in precs}
     del fd, ld
     b = torch.from_numpy(b_np).cuda()
@@ -266,8 +266,10 @@ def run_large(args):
                            ("mixed_f32", hq.HISQ_CG_MIXED_F32, hq.HISQ_F32),
                            ("mixed_i16s", hq.HISQ_CG_MIXED_I16S, hq.HISQ_I16S),
                            ("mixed_f32c", hq.HISQ_CG_MIXED_F32C, hq.HISQ_F32C),
+                           ("mixed_i16sc", hq.HISQ_CG_MIXED_I16SC, hq.HISQ_I16SC),
                            ("mixed_f16s", hq.HISQ_CG_MIXED_F16S, hq.HISQ_F16S)):
-        hi = L[hq.HISQ_F64C] if mode in (hq.HISQ_CG_PLAIN_F64C, hq.HISQ_CG_MIXED_F32C) else L[hq.HISQ_F64]
+        hi = L[hq.HISQ_F64C] if mode in (hq.HISQ_CG_PLAIN_F64C, hq.HISQ_CG_MIXED_F32C,
+                                         hq.HISQ_CG_MIXED_I16SC) else L[hq.HISQ_F64]
         ws = hq.fields.workspace("cg", dims, 1, mode)
         x = torch.zeros_like(b)
         o = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
@@ -371,7 +373,7 @@ def run_paper_grids(args):
     import paper_1411_2087_amd as hq
     import synth
     names = {hq.HISQ_F64: "f64", hq.HISQ_F32: "f32", hq.HISQ_F16S: "f16s", hq.HISQ_I16S: "i16s",
-             hq.HISQ_F64C: "f64c", hq.HISQ_F32C: "f32c"}
+             hq.HISQ_F64C: "f64c", hq.HISQ_F32C: "f32c", hq.HISQ_I16SC: "i16sc"}
     grids = {}
     for dims in PAPER_GRIDS:
         vh = int(np.prod(dims)) // 2
@@ -458,6 +460,7 @@ def main():
     LI16 = hq.fields.Links.pack(fat_d, lng_d, DIMS, hq.HISQ_I16S)
     L64C = hq.fields.Links.pack(fat_d, lng_d, DIMS, hq.HISQ_F64C)
     L32C = hq.fields.Links.pack(fat_d, lng_d, DIMS, hq.HISQ_F32C)
+    LI16C = hq.fields.Links.pack(fat_d, lng_d, DIMS, hq.HISQ_I16SC)
     del fat_d, lng_d
     torch.cuda.synchronize()
     b = torch.from_numpy(b_np).to(dev)
@@ -482,7 +485,8 @@ def main():
     tuned = {}
     tmp = torch.empty_like(b)
     for name, prec, L in (("f64", hq.HISQ_F64, L64), ("f32", hq.HISQ_F32, L32), ("f16s", hq.HISQ_F16S, L16),
-                          ("i16s", hq.HISQ_I16S, LI16), ("f64c", hq.HISQ_F64C, L64C), ("f32c", hq.HISQ_F32C, L32C)):
+                          ("i16s", hq.HISQ_I16S, LI16), ("f64c", hq.HISQ_F64C, L64C), ("f32c", hq.HISQ_F32C, L32C),
+                          ("i16sc", hq.HISQ_I16SC, LI16C)):
         dt = hq.fields.VEC_DTYPE[prec]
         s_, d_ = b.to(dt), torch.empty(b.shape, dtype=dt, device=dev)
         best, us = hq.hisq_tune_dslash(L.fat, L.lng, s_, d_, DIMS, prec, reps=20)
@@ -551,7 +555,8 @@ def main():
                                      ("mixed_f16s", hq.HISQ_CG_MIXED_F16S, L64, L16),
                                      ("mixed_i16s", hq.HISQ_CG_MIXED_I16S, L64, LI16),
                                      ("plain_f64c", hq.HISQ_CG_PLAIN_F64C, L64C, None),
-                                     ("mixed_f32c", hq.HISQ_CG_MIXED_F32C, L64C, L32C)):
+                                     ("mixed_f32c", hq.HISQ_CG_MIXED_F32C, L64C, L32C),
+                                     ("mixed_i16sc", hq.HISQ_CG_MIXED_I16SC, L64C, LI16C)):
             wsm = hq.fields.workspace("cg", DIMS, 1, mode)
             om = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
             xm = torch.zeros_like(b)
@@ -579,7 +584,7 @@ def main():
         forms["multi_shift_8_f32c"] = form_batched(hq, DIMS, L64C, L32C, hq.HISQ_MULTI_SHIFT, 8, log,
                                                    hq.HISQ_CG_MIXED_F32C, forms["multi_shift_8"])
     if not args.no_forms and not args.no_learned:
-        del L16, LI16, L64C, L32C
+        del L16, LI16, L64C, L32C, LI16C
         forms["learned"] = form_learned(hq, log)
 
     cpu = None

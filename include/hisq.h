@@ -73,8 +73,19 @@ typedef enum {
  *             fat links stay full).  Packing checks that every long link is
  *             +-SU(3) to 1e-6 and fails with HISQ_EINVAL otherwise.
  * HISQ_F32C : FP32 with two-row long links.
- * HISQ_F32, HISQ_F16S, HISQ_I16S and HISQ_F32C have FP32 (complex64) vectors. */
-typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16S = 2, HISQ_I16S = 3, HISQ_F64C = 4, HISQ_F32C = 5 } hisq_prec;
+ * HISQ_I16SC: HISQ_I16S fat links and two-row long links in the same 16-bit
+ *             fixed point (rows 0 and 1 with one FP32 scale per matrix).
+ * HISQ_F32, HISQ_F16S, HISQ_I16S, HISQ_F32C and HISQ_I16SC have FP32
+ * (complex64) vectors. */
+typedef enum {
+    HISQ_F64 = 0,
+    HISQ_F32 = 1,
+    HISQ_F16S = 2,
+    HISQ_I16S = 3,
+    HISQ_F64C = 4,
+    HISQ_F32C = 5,
+    HISQ_I16SC = 6
+} hisq_prec;
 
 /* CG modes.
  * PLAIN_F64  : every step in FP64.
@@ -85,6 +96,7 @@ typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16S = 2, HISQ_I16S = 3, HISQ_F6
  * MIXED_I16S : as MIXED_F32 with HISQ_I16S links in the inner Dslash.
  * PLAIN_F64C : PLAIN_F64 with HISQ_F64C links.
  * MIXED_F32C : MIXED_F32 with HISQ_F64C outer and HISQ_F32C inner links.
+ * MIXED_I16SC: MIXED_F32 with HISQ_F64C outer and HISQ_I16SC inner links.
  * Every mixed mode watches for stagnation: two reliable updates in a row
  * that do not halve the true residual, or an inner solve that runs ten times
  * as long as its first cycle (plus 1000 iterations) without triggering an
@@ -96,7 +108,8 @@ enum {
     HISQ_CG_MIXED_F16S = 2,
     HISQ_CG_MIXED_I16S = 3,
     HISQ_CG_PLAIN_F64C = 4,
-    HISQ_CG_MIXED_F32C = 5
+    HISQ_CG_MIXED_F32C = 5,
+    HISQ_CG_MIXED_I16SC = 6
 };
 
 /* cg_solve_multi modes.
@@ -197,11 +210,13 @@ int hisq_dslash_shape(const int dims[4], int prec, int shape);
 size_t hisq_workspace_bytes(const char *solver, const int dims[4], int nrhs, int mode, int channels);
 
 /* Solve A(mass) x = b on the even sites to |b - A x| <= tol |b| (Sec. 3 CG;
- * Sec. 4 even-odd).  fat/lng: HISQ_F64 packed links (HISQ_F64C for the *C
- * modes).  fat_lo/lng_lo: HISQ_F32, HISQ_F16S, HISQ_I16S or HISQ_F32C packed
- * links matching the mode, NULL for the plain modes.  b, x: complex128 Vh x 3; x holds x0 on entry and the solution
- * on exit (also on HISQ_ENOCONV).  opts NULL = plain FP64 defaults.  stats
- * (may be NULL) is always written.  Returns when the solve has finished. */
+ * Sec. 4 even-odd).  fat/lng: HISQ_F64 packed links (HISQ_F64C for the
+ * PLAIN_F64C, MIXED_F32C and MIXED_I16SC modes).  fat_lo/lng_lo: HISQ_F32,
+ * HISQ_F16S, HISQ_I16S, HISQ_F32C or HISQ_I16SC packed links matching the
+ * mode, NULL for the plain modes.  b, x: complex128 Vh x 3; x holds x0 on
+ * entry and the solution on exit (also on HISQ_ENOCONV).  opts NULL = plain
+ * FP64 defaults.  stats (may be NULL) is always written.  Returns when the
+ * solve has finished. */
 int cg_solve(double mass, double tol, const void *fat, const void *lng, const void *fat_lo, const void *lng_lo,
              const void *b, void *x, const int dims[4], const hisq_cg_opts *opts, void *workspace,
              size_t ws_bytes, hisq_cg_stats *stats, void *stream);

@@ -20,9 +20,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhisq.so")
 
-HISQ_F64, HISQ_F32, HISQ_F16S, HISQ_I16S, HISQ_F64C, HISQ_F32C = 0, 1, 2, 3, 4, 5
+HISQ_F64, HISQ_F32, HISQ_F16S, HISQ_I16S, HISQ_F64C, HISQ_F32C, HISQ_I16SC = 0, 1, 2, 3, 4, 5, 6
 HISQ_CG_PLAIN_F64, HISQ_CG_MIXED_F32, HISQ_CG_MIXED_F16S, HISQ_CG_MIXED_I16S = 0, 1, 2, 3
-HISQ_CG_PLAIN_F64C, HISQ_CG_MIXED_F32C = 4, 5
+HISQ_CG_PLAIN_F64C, HISQ_CG_MIXED_F32C, HISQ_CG_MIXED_I16SC = 4, 5, 6
 HISQ_MULTI_RHS, HISQ_MULTI_SHIFT = 0, 1
 HISQ_OK, HISQ_EINVAL, HISQ_EDIMS, HISQ_EALIAS, HISQ_EHIP = 0, -1, -2, -3, -4
 HISQ_ENOCONV, HISQ_EBREAKDOWN, HISQ_EWORKSPACE = -5, -6, -7
@@ -34,7 +34,7 @@ STATUS = {0: "HISQ_OK", -1: "HISQ_EINVAL", -2: "HISQ_EDIMS", -3: "HISQ_EALIAS", 
 # the paper's flop count.
 DSLASH_BYTES_PER_SITE = {HISQ_F64: 16 * 144 + 48 + 48, HISQ_F32: 16 * 72 + 24 + 24, HISQ_F16S: 16 * 40 + 24 + 24,
                          HISQ_I16S: 16 * 40 + 24 + 24, HISQ_F64C: 8 * 144 + 8 * 96 + 48 + 48,
-                         HISQ_F32C: 8 * 72 + 8 * 48 + 24 + 24}
+                         HISQ_F32C: 8 * 72 + 8 * 48 + 24 + 24, HISQ_I16SC: 8 * 40 + 8 * 28 + 24 + 24}
 DSLASH_FLOPS_PER_SITE = 1146
 
 

@@ -298,7 +298,7 @@ __global__ void k_clear_done(CGState *st)
 //   FP32, FP16S       8 waves, 1 term
 template <class P> constexpr bool cg_wide()
 {
-    return P::prec == HISQ_I16S || P::prec == HISQ_F32C;
+    return P::prec == HISQ_I16S || P::prec == HISQ_F32C || P::prec == HISQ_I16SC;
 }
 template <class P> constexpr int cg_waves()
 {
@@ -881,7 +881,7 @@ extern "C" size_t hisq_workspace_bytes(const char *solver, const int dims[4], in
     Geom g;
     if (!solver || make_geom(dims, g)) return 0;
     if (!std::strcmp(solver, "cg")) {
-        if (mode < HISQ_CG_PLAIN_F64 || mode > HISQ_CG_MIXED_F32C) return 0;
+        if (mode < HISQ_CG_PLAIN_F64 || mode > HISQ_CG_MIXED_I16SC) return 0;
         return cg_workspace_bytes(g, mode);
     }
     if (!std::strcmp(solver, "cg_multi")) return cg_multi_workspace_bytes(g, nrhs, mode);
@@ -910,7 +910,7 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
     if (!(tol > 0) || !(mass >= 0)) return st.status = fail(HISQ_EINVAL, "cg_solve: need tol > 0 and mass >= 0");
     if (o.mode != HISQ_CG_PLAIN_F64 && o.mode != HISQ_CG_PLAIN_F64C && (!fat_lo || !lng_lo))
         return st.status = fail(HISQ_EINVAL, "cg_solve: mixed mode needs fat_lo and lng_lo");
-    if (o.mode < HISQ_CG_PLAIN_F64 || o.mode > HISQ_CG_MIXED_F32C)
+    if (o.mode < HISQ_CG_PLAIN_F64 || o.mode > HISQ_CG_MIXED_I16SC)
         return st.status = fail(HISQ_EINVAL, "cg_solve: unknown mode");
     if (!workspace || ws_bytes < cg_workspace_bytes(g, o.mode))
         return st.status = fail(HISQ_EWORKSPACE, "cg_solve: workspace NULL or smaller than hisq_workspace_bytes()");
@@ -931,8 +931,11 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
     case HISQ_CG_MIXED_I16S:
         rc = cg_mixed<PF64, PI16S>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
         break;
-    default:
+    case HISQ_CG_MIXED_F32C:
         rc = cg_mixed<PF64C, PF32C>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
+        break;
+    default:
+        rc = cg_mixed<PF64C, PI16SC>(mass, tol, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, st, s);
     }
     st.status = rc;
     return rc;
@@ -941,7 +944,7 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
 extern "C" int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *stream)
 {
     if (!x || !y || !out_host || n < 0) return fail(HISQ_EINVAL, "hisq_dot: bad argument");
-    if (prec < HISQ_F64 || prec > HISQ_F32C) return fail(HISQ_EINVAL, "hisq_dot: bad precision");
+    if (prec < HISQ_F64 || prec > HISQ_I16SC) return fail(HISQ_EINVAL, "hisq_dot: bad precision");
     // small scratch (partials and the result), allocated once per thread
     static thread_local char *scratch = nullptr;
     const size_t part_bytes = 2 * sizeof(double) * BLAS_MAX_BLOCKS;

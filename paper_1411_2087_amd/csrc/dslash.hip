@@ -134,6 +134,7 @@ HISQ_INST(PF16S)
 HISQ_INST(PI16S)
 HISQ_INST(PF64C)
 HISQ_INST(PF32C)
+HISQ_INST(PI16SC)
 #undef HISQ_INST
 
 constexpr int AXMY_NT = 256;
@@ -173,6 +174,7 @@ extern "C" int dslash_apply(const void *fat, const void *lng, const void *src, v
     case HISQ_I16S: e = launch_dslash<PI16S>(g, fat, lng, src, dst, parity, s); break;
     case HISQ_F64C: e = launch_dslash<PF64C>(g, fat, lng, src, dst, parity, s); break;
     case HISQ_F32C: e = launch_dslash<PF32C>(g, fat, lng, src, dst, parity, s); break;
+    case HISQ_I16SC: e = launch_dslash<PI16SC>(g, fat, lng, src, dst, parity, s); break;
     default: return fail(HISQ_EINVAL, "dslash_apply: unknown precision");
     }
     if (e != hipSuccess) return hip_fail(e, "dslash_apply launch");
@@ -196,6 +198,7 @@ extern "C" int hisq_apply_A(double mass, const void *fat, const void *lng, const
     case HISQ_I16S: e = launch_apply_A<PI16S>(g, mass, fat, lng, x, y, tmp, s); break;
     case HISQ_F64C: e = launch_apply_A<PF64C>(g, mass, fat, lng, x, y, tmp, s); break;
     case HISQ_F32C: e = launch_apply_A<PF32C>(g, mass, fat, lng, x, y, tmp, s); break;
+    case HISQ_I16SC: e = launch_apply_A<PI16SC>(g, mass, fat, lng, x, y, tmp, s); break;
     default: return fail(HISQ_EINVAL, "hisq_apply_A: unknown precision");
     }
     if (e != hipSuccess) return hip_fail(e, "hisq_apply_A launch");

@@ -227,6 +227,7 @@ __device__ __forceinline__ uint4 ntload(const uint4 *p)
     nu4 v = __builtin_nontemporal_load(reinterpret_cast<const nu4 *>(p));
     return make_uint4(v.x, v.y, v.z, v.w);
 }
+__device__ __forceinline__ float ntload(const float *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void ntstore(double2 v, double2 *p)
 {
     nd2 w = { v.x, v.y };
@@ -438,8 +439,39 @@ struct PF32R {
     }
 };
 
-// FP64 / FP32 with two-row long links (the fat field stays full: smeared
-// links are not SU(3)).
+// 16-bit fixed-point two-row form: rows 0 and 1 as 6 words of two int16
+// (re, im) scaled by a per-matrix FP32 scale (the largest |re|, |im| of the
+// two rows), in a plane of uint4 (words 0-3), one of uint2 (words 4-5) and
+// one of the scale: 28 bytes per matrix, and the sign word as above.
+struct PI16R {
+    using real = float;
+    using cvec = float2;
+    static constexpr size_t block_bytes = TILE * 28;
+    static constexpr bool two_row = true;
+    static constexpr size_t tile_bytes = 8 * block_bytes + 64;
+    __device__ __forceinline__ static float load_rows(const char *tile, int d, int lane, float m[12])
+    {
+        const char *blk = tile + (size_t)d * block_bytes;
+        const uint4 a = ntload(reinterpret_cast<const uint4 *>(blk) + lane);
+        const uint2 b = ntload(reinterpret_cast<const uint2 *>(blk + TILE * 16) + lane);
+        const float s = ntload(reinterpret_cast<const float *>(blk + TILE * 24) + lane) * (1.0f / 32767.0f);
+        const unsigned w[6] = { a.x, a.y, a.z, a.w, b.x, b.y };
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            m[2 * e] = (float)(short)(w[e] & 0xFFFFu) * s;
+            m[2 * e + 1] = (float)(short)(w[e] >> 16) * s;
+        }
+        return ((sign_word(tile, block_bytes, d) >> lane) & 1ull) ? -1.0f : 1.0f;
+    }
+    __device__ __forceinline__ static void load_dir(const char *tile, int d, int lane, float m[18])
+    {
+        const float c = load_rows(tile, d, lane, m);
+        third_row<float>(m, c);
+    }
+};
+
+// FP64 / FP32 / 16-bit fixed point with two-row long links (the fat field
+// stays full: smeared links are not SU(3)).
 struct PF64C {
     using real = double;
     using cvec = double2;
@@ -453,6 +485,13 @@ struct PF32C {
     static constexpr int prec = HISQ_F32C;
     using Fat = PF32;
     using Long = PF32R;
+};
+struct PI16SC {
+    using real = float;
+    using cvec = float2;
+    static constexpr int prec = HISQ_I16SC;
+    using Fat = PI16S;
+    using Long = PI16R;
 };
 
 }  // namespace hisq

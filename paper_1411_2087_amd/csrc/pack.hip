@@ -188,6 +188,25 @@ __global__ __launch_bounds__(256) void k_pack_rows(const double2 *__restrict__ c
         double2 *q = reinterpret_cast<double2 *>(tile_base + (size_t)d * BB) + lane;
 #pragma unroll
         for (int e = 0; e < 6; ++e) q[e * TILE] = make_double2(m[2 * e], m[2 * e + 1]);
+    } else if (PREC == HISQ_I16SC) {
+        // rows 0 and 1 in 16-bit fixed point against their largest |re|, |im|
+        double mx = 0.0;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) mx = fmax(mx, fabs(m[i]));
+        const float scale = (float)mx;
+        const double inv = scale > 0.0f ? 32767.0 / (double)scale : 0.0;
+        unsigned w[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            int qr = (int)rint(m[2 * e] * inv), qi = (int)rint(m[2 * e + 1] * inv);
+            qr = qr > 32767 ? 32767 : (qr < -32767 ? -32767 : qr);
+            qi = qi > 32767 ? 32767 : (qi < -32767 ? -32767 : qi);
+            w[e] = ((unsigned)qr & 0xFFFFu) | (((unsigned)qi & 0xFFFFu) << 16);
+        }
+        char *blk = tile_base + (size_t)d * BB;
+        reinterpret_cast<uint4 *>(blk)[lane] = make_uint4(w[0], w[1], w[2], w[3]);
+        reinterpret_cast<uint2 *>(blk + TILE * 16)[lane] = make_uint2(w[4], w[5]);
+        reinterpret_cast<float *>(blk + TILE * 24)[lane] = scale;
     } else {
         float4 *q = reinterpret_cast<float4 *>(tile_base + (size_t)d * BB) + lane;
 #pragma unroll
@@ -205,6 +224,7 @@ size_t dir_block_bytes(int prec)
     case HISQ_I16S: return PI16S::block_bytes;
     case HISQ_F64C: return PF64::block_bytes;  // the fat field
     case HISQ_F32C: return PF32::block_bytes;
+    case HISQ_I16SC: return PI16S::block_bytes;
     default: return 0;
     }
 }
@@ -215,6 +235,7 @@ static size_t long_field_bytes(const Geom &g, int prec)
 {
     if (prec == HISQ_F64C) return 2ull * g.ntiles * PF64R::tile_bytes + 256;
     if (prec == HISQ_F32C) return 2ull * g.ntiles * PF32R::tile_bytes + 256;
+    if (prec == HISQ_I16SC) return 2ull * g.ntiles * PI16R::tile_bytes + 256;
     return 2ull * g.ntiles * 8 * dir_block_bytes(prec);
 }
 
@@ -248,20 +269,25 @@ extern "C" int hisq_pack_links(const void *fat_canon, const void *long_canon, co
     hipStream_t s = (hipStream_t)stream;
     const long long total = 2LL * g.ntiles * 8 * TILE;
     const dim3 grid((unsigned)((total + 255) / 256)), block(256);
-    if (prec == HISQ_F64C || prec == HISQ_F32C) {
-        const int fp = prec == HISQ_F64C ? HISQ_F64 : HISQ_F32;
+    if (prec == HISQ_F64C || prec == HISQ_F32C || prec == HISQ_I16SC) {
+        const int fp = prec == HISQ_F64C ? HISQ_F64 : (prec == HISQ_F32C ? HISQ_F32 : HISQ_I16S);
         const size_t fbb = dir_block_bytes(fp);
         if (fp == HISQ_F64)
             hipLaunchKernelGGL(k_pack<HISQ_F64>, grid, block, 0, s, (const double2 *)fat_canon, (char *)fat_out, g, 1, fbb);
-        else
+        else if (fp == HISQ_F32)
             hipLaunchKernelGGL(k_pack<HISQ_F32>, grid, block, 0, s, (const double2 *)fat_canon, (char *)fat_out, g, 1, fbb);
+        else
+            hipLaunchKernelGGL(k_pack<HISQ_I16S>, grid, block, 0, s, (const double2 *)fat_canon, (char *)fat_out, g, 1, fbb);
         int *status = reinterpret_cast<int *>((char *)long_out + long_field_bytes(g, prec) - 256);
         HISQ_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
         if (prec == HISQ_F64C)
             hipLaunchKernelGGL((k_pack_rows<HISQ_F64C, PF64R>), grid, block, 0, s, (const double2 *)long_canon,
                                (char *)long_out, g, 3, status);
-        else
+        else if (prec == HISQ_F32C)
             hipLaunchKernelGGL((k_pack_rows<HISQ_F32C, PF32R>), grid, block, 0, s, (const double2 *)long_canon,
+                               (char *)long_out, g, 3, status);
+        else
+            hipLaunchKernelGGL((k_pack_rows<HISQ_I16SC, PI16R>), grid, block, 0, s, (const double2 *)long_canon,
                                (char *)long_out, g, 3, status);
         HISQ_HIP(hipGetLastError());
         int h_status = 0;

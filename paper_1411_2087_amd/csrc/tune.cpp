@@ -153,6 +153,7 @@ extern "C" int hisq_tune_dslash(const void *fat, const void *lng, const void *sr
     case HISQ_I16S: return tune_dslash_impl<PI16S>(g, fat, lng, src, dst, reps, best_shape, us_per_shape, s);
     case HISQ_F64C: return tune_dslash_impl<PF64C>(g, fat, lng, src, dst, reps, best_shape, us_per_shape, s);
     case HISQ_F32C: return tune_dslash_impl<PF32C>(g, fat, lng, src, dst, reps, best_shape, us_per_shape, s);
+    case HISQ_I16SC: return tune_dslash_impl<PI16SC>(g, fat, lng, src, dst, reps, best_shape, us_per_shape, s);
     default: return fail(HISQ_EINVAL, "hisq_tune_dslash: unknown precision");
     }
 }
@@ -162,7 +163,7 @@ extern "C" int hisq_dslash_shape(const int dims[4], int prec, int shape)
     Geom g;
     int rc = make_geom(dims, g);
     if (rc) return rc;
-    if (prec < HISQ_F64 || prec > HISQ_F32C) return fail(HISQ_EINVAL, "hisq_dslash_shape: unknown precision");
+    if (prec < HISQ_F64 || prec > HISQ_I16SC) return fail(HISQ_EINVAL, "hisq_dslash_shape: unknown precision");
     if (shape == -2) return N_DSLASH_SHAPES;
     if (shape < -2 || shape >= N_DSLASH_SHAPES) return fail(HISQ_EINVAL, "hisq_dslash_shape: no such shape");
     if (shape >= 0) set_tuned_dslash_shape(g, prec, shape);

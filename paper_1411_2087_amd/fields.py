@@ -7,11 +7,12 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (HISQ_F16S, HISQ_F32, HISQ_F32C, HISQ_F64, HISQ_F64C, HISQ_I16S, hisq_pack_links,
+from . import (HISQ_F16S, HISQ_F32, HISQ_F32C, HISQ_F64, HISQ_F64C, HISQ_I16S, HISQ_I16SC, hisq_pack_links,
                hisq_packed_link_bytes, hisq_workspace_bytes)
 
 VEC_DTYPE = {HISQ_F64: torch.complex128, HISQ_F32: torch.complex64, HISQ_F16S: torch.complex64,
-             HISQ_I16S: torch.complex64, HISQ_F64C: torch.complex128, HISQ_F32C: torch.complex64}
+             HISQ_I16S: torch.complex64, HISQ_F64C: torch.complex128, HISQ_F32C: torch.complex64,
+             HISQ_I16SC: torch.complex64}
 
 
 def to_device(a: np.ndarray, device="cuda"):

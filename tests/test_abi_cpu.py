@@ -56,9 +56,11 @@ def test_packed_sizes(dims):
     import paper_1411_2087_amd as hq
     vh = int(np.prod(dims)) // 2
     ntiles = -(-vh // 64)
-    for prec, per_matrix in ((0, 144), (1, 72), (2, 40), (3, 40), (4, 144), (5, 72)):
+    # the fat field is the larger one for the two-row forms (their long field is smaller)
+    for prec, per_matrix in ((0, 144), (1, 72), (2, 40), (3, 40), (4, 144), (5, 72), (6, 40)):
         assert hq.hisq_packed_link_bytes(dims, prec) == 2 * ntiles * 64 * 8 * per_matrix
     assert hq.hisq_packed_link_bytes((4, 4, 4, 3), 0) == 0
+    assert hq.hisq_packed_link_bytes(dims, 7) == 0
 
 
 def test_workspace_sizes():
@@ -71,3 +73,5 @@ def test_workspace_sizes():
     assert hq.hisq_workspace_bytes("fat_paths", dims, 0, 0) >= 3 * 4096 * 144
     assert hq.hisq_workspace_bytes("nope", dims, 1, 0) == 0
     assert hq.hisq_workspace_bytes("cg", (4, 4, 4, 5), 1, 0) == 0
+    assert hq.hisq_workspace_bytes("cg", dims, 1, 6) == hq.hisq_workspace_bytes("cg", dims, 1, 1)
+    assert hq.hisq_workspace_bytes("cg", dims, 1, 7) == 0

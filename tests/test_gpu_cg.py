@@ -20,7 +20,7 @@ def hq():
 
 def _solve(hq, dims, fat, lng, b, mass, mode, tol=CG_TOL, max_iter=0, use_graph=1, check_every=0, x0=None):
     import torch
-    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64C if mode in (4, 5) else hq.HISQ_F64)
+    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64C if mode in (4, 5, 6) else hq.HISQ_F64)
     Llo = None
     if mode == 1:
         Llo = hq.fields.Links.pack(fat, lng, dims, 1)
@@ -28,6 +28,8 @@ def _solve(hq, dims, fat, lng, b, mass, mode, tol=CG_TOL, max_iter=0, use_graph=
         Llo = hq.fields.Links.pack(fat, lng, dims, mode)
     elif mode == 5:
         Llo = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32C)
+    elif mode == 6:
+        Llo = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_I16SC)
     bd = torch.from_numpy(b).cuda()
     xd = torch.zeros_like(bd) if x0 is None else torch.from_numpy(x0).cuda()
     ws = hq.fields.workspace("cg", dims, 1, mode)
@@ -64,7 +66,7 @@ def test_cg_graph_and_direct_agree(hq, use_graph):
     assert oracle.true_residual(dims, mass, fat, lng, b, x1) <= CG_TOL
 
 
-@pytest.mark.parametrize("mode", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("mode", [1, 2, 3, 4, 5, 6])
 def test_cg_mixed(hq, mode):
     dims, mass = (8, 8, 8, 8), 0.05
     fat, lng = fields(dims, synth.gauge_seed(1))
@@ -137,7 +139,7 @@ def test_cg_32_4(hq):
     tr = oracle.true_residual(dims, mass, fat, lng, b, x)
     say(f"cg 32^4: iters={st['iters']} gpu_resid={st['true_resid']:.3e} oracle_resid={tr:.3e} time={st['time_s']:.3f}s")
     assert st["rc"] == 0 and tr <= CG_TOL
-    for mode in (1, 3, 4, 5):
+    for mode in (1, 3, 4, 5, 6):
         xm, sm = _solve(hq, dims, fat, lng, b, mass, mode)
         trm = oracle.true_residual(dims, mass, fat, lng, b, xm)
         say(f"cg 32^4 mode {mode}: iters={sm['iters']} updates={sm['reliable_updates']} oracle_resid={trm:.3e} "

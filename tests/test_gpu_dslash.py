@@ -33,7 +33,7 @@ def _dslash_gpu(hq, dims, fat, lng, src, parity, prec):
 
 @pytest.mark.parametrize("dims", DIMS)
 @pytest.mark.parametrize("prec,tol", [(0, TOL_F64), (1, TOL_F32), (2, TOL_F16S), (3, TOL_I16S), (4, TOL_F64),
-                                      (5, TOL_F32)])
+                                      (5, TOL_F32), (6, TOL_I16S)])
 def test_dslash_parity(hq, dims, prec, tol):
     fat, lng = fields(dims, 1000 + sum(dims))
     r = np.random.default_rng(7)
@@ -152,7 +152,7 @@ def test_all_launch_shapes_bitwise_identical(hq, dims):
     import torch
     fat, lng = fields(dims)
     src = synth.source(dims, 9)
-    for prec in (0, 1, 2, 3, 4, 5):
+    for prec in (0, 1, 2, 3, 4, 5, 6):
         L = hq.fields.Links.pack(fat, lng, dims, prec)
         dt = hq.fields.VEC_DTYPE[prec]
         s = torch.from_numpy(src).to(dt).cuda()
@@ -178,10 +178,11 @@ def test_compressed_pack_rejects_non_su3_long_links(hq):
     """Two-row packing needs +-SU(3) long links; the smeared fat field is not, and is refused."""
     dims = (4, 4, 4, 6)
     fat, lng = fields(dims)
-    with pytest.raises(hq.HisqError) as e:
-        hq.fields.Links.pack(fat, fat, dims, hq.HISQ_F64C)
-    assert e.value.code == -1
-    hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32C)  # Haar long links with folded signs pack
+    for prec in (hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_I16SC):
+        with pytest.raises(hq.HisqError) as e:
+            hq.fields.Links.pack(fat, fat, dims, prec)
+        assert e.value.code == -1
+        hq.fields.Links.pack(fat, lng, dims, prec)  # Haar long links with folded signs pack
 
 
 def test_dslash_32_4_compressed(hq):
