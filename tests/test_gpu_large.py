@@ -73,7 +73,7 @@ def test_dslash_paper_grids(dims):
     scale = oracle.dslash_scale(dims, fat, lng, b, 1)
     fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
     tols = {hq.HISQ_F64: TOL_F64, hq.HISQ_F32: TOL_F32, hq.HISQ_F16S: TOL_F16S, hq.HISQ_I16S: TOL_I16S,
-            hq.HISQ_F64C: TOL_F64, hq.HISQ_F32C: TOL_F32}
+            hq.HISQ_F64C: TOL_F64, hq.HISQ_F32C: TOL_F32, hq.HISQ_I16SC: TOL_I16S}
     for p, tol in tols.items():
         L = hq.fields.Links.pack(fd, ld, dims, p)
         dt = hq.fields.VEC_DTYPE[p]
