@@ -184,11 +184,11 @@ __global__ __launch_bounds__(256) void k_pack_rows(const double2 *__restrict__ c
     const unsigned long long word = __ballot(neg);
     char *tile_base = out + (size_t)pt * TB;
     if (lane == 0) *reinterpret_cast<unsigned long long *>(tile_base + 8 * BB + 8 * (size_t)d) = word;
-    if (PREC == HISQ_F64C) {
+    if constexpr (PREC == HISQ_F64C) {
         double2 *q = reinterpret_cast<double2 *>(tile_base + (size_t)d * BB) + lane;
 #pragma unroll
         for (int e = 0; e < 6; ++e) q[e * TILE] = make_double2(m[2 * e], m[2 * e + 1]);
-    } else if (PREC == HISQ_I16SC) {
+    } else if constexpr (PREC == HISQ_I16SC) {
         // rows 0 and 1 in 16-bit fixed point against their largest |re|, |im|
         double mx = 0.0;
 #pragma unroll
