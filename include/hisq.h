@@ -160,9 +160,9 @@ size_t hisq_packed_link_bytes(const int dims[4], int prec);
 /* Pack canonical links (device, complex128, layout above) into the packed
  * form of `prec` at fat_out / long_out (device, hisq_packed_link_bytes()
  * each).  `hop` of the fat field is 1 and of the long field 3 (Sec. 3: one-
- * and three-link terms).  Asynchronous on `stream`, except for HISQ_F64C and
- * HISQ_F32C, which synchronise to report HISQ_EINVAL when a long link is not
- * +-SU(3). */
+ * and three-link terms).  Asynchronous on `stream`, except for the two-row
+ * forms HISQ_F64C, HISQ_F32C and HISQ_I16SC, which synchronise to report
+ * HISQ_EINVAL when a long link is not +-SU(3). */
 int hisq_pack_links(const void *fat_canon, const void *long_canon, const int dims[4], int prec, void *fat_out,
                     void *long_out, void *stream);
 
