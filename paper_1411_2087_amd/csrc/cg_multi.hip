@@ -56,7 +56,8 @@ __device__ __forceinline__ unsigned pick_mask(const MultiState *st, int which)
 }
 
 // Right-hand sides whose neighbour vectors a thread loads together before
-// multiplying any of them (FP64 path): 2, i.e. 12 double registers.
+// multiplying any of them, where the vectors do not go through LDS: 2 in
+// FP64 (12 double registers), up to 4 in FP32.
 template <class P> constexpr int md_chunk() { return sizeof(typename P::real) == 4 ? 4 : 2; }
 
 // Orders LDS writes by some lanes of a wavefront before reads by others
