@@ -295,8 +295,9 @@ def run_large(args):
 
 
 def traffic_probe_at(workload):
-    """A 1 GiB copy (counter calibration) and 5 FP64 Dslash launches in each of launch shapes 6 and 8 (plain
-    and blocked tile order) on the lattice `workload` ("LxxLyxLzxLt"), for rocprofv3 counter runs."""
+    """A 1 GiB copy (counter calibration) and 5 FP64 Dslash launches in each of launch shapes 6, 8 and 10 (plain
+    and blocked tile order at one term and 6 waves/SIMD, and the FP64 default: two terms at 5 waves/SIMD) on the
+    lattice `workload` ("LxxLyxLzxLt"), for rocprofv3 counter runs."""
     import torch
     import paper_1411_2087_amd as hq
     import synth
@@ -311,13 +312,14 @@ def traffic_probe_at(workload):
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
-    for shape in (6, 8):  # plain and blocked tile order, 5 launches each
+    shapes = (6, 8, 10)
+    for shape in shapes:  # 5 launches each
         hq.hisq_dslash_shape(dims, hq.HISQ_F64, shape)
         for _ in range(5):
             hq.dslash_apply(L.fat, L.lng, b, t, 1, dims, hq.HISQ_F64)
     torch.cuda.synchronize()
     print(json.dumps({"traffic_probe": True, "copy_bytes": n, "dslash_launches": 5, "vh": int(b.shape[0]),
-                      "shapes": [6, 8], "workload": workload}))
+                      "shapes": list(shapes), "workload": workload}))
 
 
 PAPER_GRIDS = ((32, 32, 32, 128), (32, 40, 24, 96))
