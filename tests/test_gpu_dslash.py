@@ -185,15 +185,19 @@ def test_compressed_pack_rejects_non_su3_long_links(hq):
         hq.fields.Links.pack(fat, lng, dims, prec)  # Haar long links with folded signs pack
 
 
-def test_dslash_32_4_compressed(hq):
+@pytest.mark.parametrize("prec,tol", [(4, TOL_F64), (5, TOL_F32), (6, TOL_I16S)], ids=["f64c", "f32c", "i16sc"])
+def test_dslash_32_4_compressed(hq, prec, tol):
+    """Full 32^4 lattice, two-row long links in every storage form, against the oracle."""
     dims = (32, 32, 32, 32)
     fat, lng = fields(dims, 1002)
     src = synth.source(dims, 2129)
+    if prec != 4:
+        src = src.astype(np.complex64).astype(np.complex128)  # the FP32 kernels see FP32 vectors
     ref = oracle.dslash(dims, fat, lng, src, 1)
-    got = _dslash_gpu(hq, dims, fat, lng, src, 1, hq.HISQ_F64C)
+    got = _dslash_gpu(hq, dims, fat, lng, src, 1, prec)
     err = oracle.componentwise_error(got, ref, oracle.dslash_scale(dims, fat, lng, src, 1))
-    say(f"dslash 32^4 f64 two-row long links: componentwise {err:.3e}")
-    assert err <= TOL_F64
+    say(f"dslash 32^4 prec={prec} two-row long links: componentwise {err:.3e}")
+    assert err <= tol
 
 
 def test_read_probe_reads_every_byte_once(hq):
