@@ -322,6 +322,26 @@ def traffic_probe_at(workload):
                       "shapes": list(shapes), "workload": workload}))
 
 
+def run_batched16(args):
+    """16 masses log-spaced 0.002 - 0.2 on 32^4: batched multi-RHS (16 sources) and multi-shift (one source), on
+    FP32 and on two-row links, against 16 sequential plain FP64 solves of the same systems (a report line)."""
+    import torch
+    import paper_1411_2087_amd as hq
+    import synth
+    fat, lng = synth.links(DIMS, synth.gauge_seed(CONFIG))
+    fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
+    del fat, lng
+    L = {p: hq.fields.Links.pack(fd, ld, DIMS, p) for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_F64C, hq.HISQ_F32C)}
+    del fd, ld
+    forms = {}
+    for mode, name in ((hq.HISQ_MULTI_RHS, "multi_rhs_16"), (hq.HISQ_MULTI_SHIFT, "multi_shift_16")):
+        forms[name] = form_batched(hq, DIMS, L[hq.HISQ_F64], L[hq.HISQ_F32], mode, 16, log)
+        forms[name + "_f32c"] = form_batched(hq, DIMS, L[hq.HISQ_F64C], L[hq.HISQ_F32C], mode, 16, log,
+                                             hq.HISQ_CG_MIXED_F32C, forms[name])
+    print(json.dumps({"workload": "batched solves of 16 masses 0.002-0.2, 32^4, tol 1e-10", "n_gpus": 1,
+                      "forms": forms}))
+
+
 PAPER_GRIDS = ((32, 32, 32, 128), (32, 40, 24, 96))
 MATMUL_FLOPS = 198        # 3x3 complex product: 27 complex multiplies (6) + 18 complex adds (2)
 
@@ -424,7 +444,8 @@ def main():
     ap.add_argument("--workload", default="32x32x32x32",
                     help="32x32x32x32 (default: plain FP64 CG, the metric's workload), 48x48x48x96 "
                          "(mixed precision against plain FP64 on the large lattice), paper-grids (the Dslash "
-                         "on 32^3x128 and 32x40x24x96) or learned (512 training pairs on 16^4, C = 8 and 16); "
+                         "on 32^3x128 and 32x40x24x96), learned (512 training pairs on 16^4, C = 8 and 16) or "
+                         "batched-16 (16 masses, batched against sequential plain FP64 solves); "
                          "all but the first are report lines, not the metric")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a 1 GiB copy and the FP64 Dslash (for rocprofv3 counter runs); with --workload "
@@ -449,6 +470,8 @@ def main():
         return run_paper_grids(args)
     if args.workload == "learned":
         return run_learned(args)
+    if args.workload == "batched-16":
+        return run_batched16(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     vh = int(np.prod(DIMS)) // 2
