@@ -169,10 +169,12 @@ def form_learned(hq, log, dims=(16, 16, 16, 16), mass=0.005, C=16, npairs=64, st
             "fcg_true_resid": sf["true_resid"], "speedup_vs_plain": round(sp["time_s"] / sf["time_s"], 3)}
 
 
-def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, steps=600):
+def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, steps=600, channels=(8, 16),
+                nsolve=4):
     """The learned-preconditioner workload: 512 training pairs per gauge field (448 to train, 64 held out), the
-    network trained on the GPU for C = 8 and 16 channels with the residual objective, and flexible CG with the
-    trained network against plain FP64 CG and against flexible CG with K = identity on held-out sources."""
+    network trained on the GPU for each of `channels` with the residual objective, and flexible CG with the
+    trained network against plain FP64 CG and against flexible CG with K = identity on `nsolve` held-out
+    sources."""
     import numpy as np
     import torch
 
@@ -184,11 +186,12 @@ def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, s
     L32 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32)
     src = np.stack([synth.source(dims, synth.source_seed(5, i)) for i in range(npairs)])
     t0 = time.perf_counter()
-    b, x, _, _ = train.make_pairs(dims, mass, L64, L32, src)
+    b, x, _, _ = train.make_pairs(dims, mass, L64, L32, src, log=log if dims[0] > 16 else None)
     t_pairs = time.perf_counter() - t0
     log(f"[learned] {npairs} pairs in {t_pairs:.1f}s")
     ntrain = npairs - nheld
-    held = [torch.from_numpy(src[ntrain + i]).cuda() for i in range(4)]
+    held = [torch.from_numpy(src[ntrain + i]).cuda() for i in range(nsolve)]
+    del src
 
     def solve_all(fn):
         its, secs = [], []
@@ -204,12 +207,14 @@ def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, s
     out = {"workload": f"{'x'.join(map(str, dims))}, m {mass}, {npairs} pairs ({ntrain} train / {nheld} held out), "
                        f"residual objective, {steps} Adam steps, batch 16",
            "pair_s": round(t_pairs, 2), "plain_f64": {"iters": p_its, "s": [round(v, 4) for v in p_s]}, "nets": {}}
-    for C in (8, 16):
+    log(f"[learned] plain FP64 CG on {nsolve} held-out sources: {p_its} iterations, {sum(p_s):.3f}s")
+    for C in channels:
         w0 = train.initial_weights(C, train.residual_scale(b[:16], L32, mass, dims), 0.05, 99)
         tr = train.Trainer(dims, C, L32.fat, w0, batch=16, objective="residual", links32=L32, mass=mass)
         l0 = tr.evaluate(b[ntrain:], x[ntrain:])
         t0 = time.perf_counter()
-        hist = tr.fit(b[:ntrain], x[:ntrain], steps=steps, lr=2e-3, log_every=200)
+        hist = tr.fit(b[:ntrain], x[:ntrain], steps=steps, lr=2e-3, log_every=200 if dims[0] <= 16 else 50,
+                      log=log if dims[0] > 16 else None)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
         l1 = tr.evaluate(b[ntrain:], x[ntrain:])
@@ -229,7 +234,8 @@ def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, s
         log(f"[learned C={C}] held-out loss {l0:.4f} -> {l1:.4f}, train {t_train:.1f}s; fcg {f_its} "
             f"(fallback {last['fallback_used']}) {sum(f_s):.3f}s, identity {i_its}, plain {p_its} {sum(p_s):.3f}s")
     print(json.dumps({"metric": "CG s to 1e-10 resid, flexible CG with the trained network vs plain FP64 (report line)",
-                      "unit": "s", "value": round(sum(out["nets"]["C16"]["fcg_trained"]["s"]), 4), "n_gpus": 1,
+                      "unit": "s", "value": round(sum(out["nets"][f"C{channels[-1]}"]["fcg_trained"]["s"]), 4),
+                      "n_gpus": 1,
                       "higher_is_better": False, "data": "synthetic", "config": {"workload": out["workload"]},
                       "learned": out}))
 
@@ -444,7 +450,8 @@ def main():
     ap.add_argument("--workload", default="32x32x32x32",
                     help="32x32x32x32 (default: plain FP64 CG, the metric's workload), 48x48x48x96 "
                          "(mixed precision against plain FP64 on the large lattice), paper-grids (the Dslash "
-                         "on 32^3x128 and 32x40x24x96), learned (512 training pairs on 16^4, C = 8 and 16) or "
+                         "on 32^3x128 and 32x40x24x96), learned (512 training pairs on 16^4, C = 8 and 16), "
+                         "learned-32 (the same on 32^4, C = 16, two held-out solves) or "
                          "batched-16 (16 masses, batched against sequential plain FP64 solves); "
                          "all but the first are report lines, not the metric")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -470,6 +477,8 @@ def main():
         return run_paper_grids(args)
     if args.workload == "learned":
         return run_learned(args)
+    if args.workload == "learned-32":
+        return run_learned(args, dims=(32, 32, 32, 32), channels=(16,), nsolve=2)
     if args.workload == "batched-16":
         return run_batched16(args)
     dev = torch.device("cuda:0")

@@ -54,9 +54,10 @@ def initial_weights(C, scale, noise, noise_seed):
     return w + noise * z
 
 
-def make_pairs(dims, mass, links64: Links, links32: Links, sources: np.ndarray, tol=1e-8, device="cuda"):
+def make_pairs(dims, mass, links64: Links, links32: Links, sources: np.ndarray, tol=1e-8, device="cuda", log=None):
     """x_i = A(mass)^-1 b_i for every source, by the batched reliable-update CG, 16 at a time.
-    Returns (b, x) as device complex64 tensors [n][Vh][3], the total solve time and x in complex128."""
+    Returns (b, x) as device complex64 tensors [n][Vh][3], the total solve time and x in complex128.
+    log (optional): called with a progress line after each batch."""
     n = sources.shape[0]
     vh = sources.shape[1]
     bs = torch.from_numpy(np.ascontiguousarray(sources)).to(device)
@@ -72,6 +73,8 @@ def make_pairs(dims, mass, links64: Links, links32: Links, sources: np.ndarray, 
                             x, dims, opts, ws, raise_on_noconv=True)
         seconds += st[0]["time_s"]
         xs[s:s + k] = x
+        if log is not None:
+            log(f"[pairs] {s + k}/{n}: {max(r['iters'] for r in st)} iterations, {st[0]['time_s']:.2f}s")
     return bs.to(torch.complex64), xs.to(torch.complex64), seconds, xs
 
 
