@@ -89,8 +89,8 @@ def cpu_baseline(fat, lng, b, vh, budget_s=15.0):
 
 def form_batched(hq, dims, L64, L32, mode, n, log, cg_mode=0, seq_from=None):
     """Batched solve of n masses (log-spaced 0.002 - 0.2) against n sequential plain FP64 solves.
-    cg_mode HISQ_CG_MIXED_F32C: L64 / L32 hold two-row long links (F64C / F32C).  seq_from: a previous
-    result of the same systems whose sequential plain FP64 time is reused."""
+    cg_mode HISQ_CG_MIXED_F32C / HISQ_CG_MIXED_I16SC: L64 / L32 hold F64C / F32C or F64C / I16SC links.
+    seq_from: a previous result of the same systems whose sequential plain FP64 time is reused."""
     import numpy as np
     import torch
     import synth
@@ -103,7 +103,7 @@ def form_batched(hq, dims, L64, L32, mode, n, log, cg_mode=0, seq_from=None):
     b = torch.from_numpy(bs).cuda()
     x = torch.zeros((n, vh, 3), dtype=torch.complex128, device="cuda")
     ws = hq.fields.workspace("cg_multi", dims, n, mode)
-    opts = hq.CGOpts(mode=cg_mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    opts = hq.CGOpts(mode=cg_mode, max_iter=0, check_every=0, use_graph=1, delta=0.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = hq.cg_solve_multi(n, masses, TOL, mode, L64.fat, L64.lng, L32.fat, L32.lng, b, x, dims, opts, ws)
@@ -126,8 +126,7 @@ def form_batched(hq, dims, L64, L32, mode, n, log, cg_mode=0, seq_from=None):
             seq += time.perf_counter() - t1
             seq_iters.append(s1["iters"])
     name = ("multi_rhs" if mode == hq.HISQ_MULTI_RHS else "multi_shift") + f"_{n}"
-    if cg_mode == hq.HISQ_CG_MIXED_F32C:
-        name += "_f32c"
+    name += {hq.HISQ_CG_MIXED_F32C: "_f32c", hq.HISQ_CG_MIXED_I16SC: "_i16sc"}.get(cg_mode, "")
     log(f"[form {name}] {dt:.2f}s vs sequential plain FP64 {seq:.2f}s")
     return {"s": round(dt, 3), "n": n, "masses": "log-spaced 0.002-0.2", "iters": [s_["iters"] for s_ in st],
             "worst_true_resid": max(s_["true_resid"] for s_ in st), "sequential_plain_f64_s": round(seq, 3),
@@ -278,7 +277,7 @@ def run_large(args):
                                          hq.HISQ_CG_MIXED_I16SC) else L[hq.HISQ_F64]
         ws = hq.fields.workspace("cg", dims, 1, mode)
         x = torch.zeros_like(b)
-        o = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+        o = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = hq.cg_solve(mass, TOL, hi.fat, hi.lng, L[lo].fat if lo is not None else None,
@@ -330,20 +329,23 @@ def traffic_probe_at(workload):
 
 def run_batched16(args):
     """16 masses log-spaced 0.002 - 0.2 on 32^4: batched multi-RHS (16 sources) and multi-shift (one source), on
-    FP32 and on two-row links, against 16 sequential plain FP64 solves of the same systems (a report line)."""
+    FP32, two-row FP32 and two-row 16-bit inner links, against 16 sequential plain FP64 solves of the same systems (a report line)."""
     import torch
     import paper_1411_2087_amd as hq
     import synth
     fat, lng = synth.links(DIMS, synth.gauge_seed(CONFIG))
     fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
     del fat, lng
-    L = {p: hq.fields.Links.pack(fd, ld, DIMS, p) for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_F64C, hq.HISQ_F32C)}
+    L = {p: hq.fields.Links.pack(fd, ld, DIMS, p)
+         for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_I16SC)}
     del fd, ld
     forms = {}
     for mode, name in ((hq.HISQ_MULTI_RHS, "multi_rhs_16"), (hq.HISQ_MULTI_SHIFT, "multi_shift_16")):
         forms[name] = form_batched(hq, DIMS, L[hq.HISQ_F64], L[hq.HISQ_F32], mode, 16, log)
         forms[name + "_f32c"] = form_batched(hq, DIMS, L[hq.HISQ_F64C], L[hq.HISQ_F32C], mode, 16, log,
                                              hq.HISQ_CG_MIXED_F32C, forms[name])
+        forms[name + "_i16sc"] = form_batched(hq, DIMS, L[hq.HISQ_F64C], L[hq.HISQ_I16SC], mode, 16, log,
+                                              hq.HISQ_CG_MIXED_I16SC, forms[name])
     print(json.dumps({"workload": "batched solves of 16 masses 0.002-0.2, 32^4, tol 1e-10", "n_gpus": 1,
                       "forms": forms}))
 
@@ -530,7 +532,7 @@ def main():
         del s_, d_
 
     ws = hq.fields.workspace("cg", DIMS, 1, hq.HISQ_CG_PLAIN_F64)
-    opts = hq.CGOpts(mode=hq.HISQ_CG_PLAIN_F64, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    opts = hq.CGOpts(mode=hq.HISQ_CG_PLAIN_F64, max_iter=0, check_every=0, use_graph=1, delta=0.0)
 
     def step():
         x.zero_()
@@ -592,7 +594,7 @@ def main():
                                      ("mixed_f32c", hq.HISQ_CG_MIXED_F32C, L64C, L32C),
                                      ("mixed_i16sc", hq.HISQ_CG_MIXED_I16SC, L64C, LI16C)):
             wsm = hq.fields.workspace("cg", DIMS, 1, mode)
-            om = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+            om = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.0)
             xm = torch.zeros_like(b)
             lo_f, lo_l = (Llo.fat, Llo.lng) if Llo is not None else (None, None)
             hq.cg_solve(MASS, TOL, Lhi.fat, Lhi.lng, lo_f, lo_l, b, xm, DIMS, om, wsm)  # warm
@@ -617,6 +619,11 @@ def main():
                                                  hq.HISQ_CG_MIXED_F32C, forms["multi_rhs_8"])
         forms["multi_shift_8_f32c"] = form_batched(hq, DIMS, L64C, L32C, hq.HISQ_MULTI_SHIFT, 8, log,
                                                    hq.HISQ_CG_MIXED_F32C, forms["multi_shift_8"])
+        # and with 16-bit fixed-point inner links (two-row long links)
+        forms["multi_rhs_8_i16sc"] = form_batched(hq, DIMS, L64C, LI16C, hq.HISQ_MULTI_RHS, 8, log,
+                                                  hq.HISQ_CG_MIXED_I16SC, forms["multi_rhs_8"])
+        forms["multi_shift_8_i16sc"] = form_batched(hq, DIMS, L64C, LI16C, hq.HISQ_MULTI_SHIFT, 8, log,
+                                                    hq.HISQ_CG_MIXED_I16SC, forms["multi_shift_8"])
     if not args.no_forms and not args.no_learned:
         del L16, LI16, L64C, L32C, LI16C
         forms["learned"] = form_learned(hq, log)

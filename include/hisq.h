@@ -98,7 +98,8 @@ typedef enum {
  * MIXED_F32C : MIXED_F32 with HISQ_F64C outer and HISQ_F32C inner links.
  * MIXED_I16SC: MIXED_F32 with HISQ_F64C outer and HISQ_I16SC inner links.
  * Every mixed mode watches for stagnation: two reliable updates in a row
- * that do not halve the true residual, or an inner solve that runs ten times
+ * that do not reduce the true residual by a factor sqrt(delta) (by half when
+ * delta < 0.25), or an inner solve that runs ten times
  * as long as its first cycle (plus 1000 iterations) without triggering an
  * update, end the mixed iteration; x then absorbs the inner solution and
  * plain CG on the outer links finishes the solve (stats.fallback_used = 1). */
@@ -126,7 +127,8 @@ typedef struct {
     int max_iter;      /* iteration cap over the whole solve (default 100000 if <= 0) */
     int check_every;   /* iterations between host convergence checks (<= 0: automatic) */
     int use_graph;     /* 1: replay check_every iterations as one captured HIP graph */
-    double delta;      /* reliable-update trigger |r| < delta * max|r| (<= 0: 0.1) */
+    double delta;      /* reliable-update trigger |r| < delta * max|r| (<= 0: 0.7 for the
+                          16-bit inner links F16S, I16S, I16SC; 0.1 otherwise) */
 } hisq_cg_opts;
 
 typedef struct {
@@ -227,10 +229,12 @@ int cg_solve(double mass, double tol, const void *fat, const void *lng, const vo
  * [nrhs][Vh][3], solved from x0 = 0 to |b_i - A(m_i) x_i| <= tol |b_i| for
  * every i.  fat/lng: F64 packed links (reliable updates, final residuals);
  * fat_lo/lng_lo: F32 packed links (inner iterations) for opts->mode
- * HISQ_CG_PLAIN_F64 or HISQ_CG_MIXED_F32; for HISQ_CG_MIXED_F32C, F64C and
- * F32C packed links (two-row long links, Sec. 4); any other mode is
- * HISQ_EINVAL.  opts: max_iter, check_every, use_graph and delta as for
- * cg_solve.
+ * HISQ_CG_PLAIN_F64 or HISQ_CG_MIXED_F32; I16S for HISQ_CG_MIXED_I16S; for
+ * HISQ_CG_MIXED_F32C and HISQ_CG_MIXED_I16SC, fat/lng are F64C and
+ * fat_lo/lng_lo F32C or I16SC packed links (two-row long links, Sec. 4);
+ * MIXED_F16S is HISQ_EINVAL.  opts: max_iter, check_every, use_graph and
+ * delta as for cg_solve (default 0.7 for the 16-bit inner links, 0.1
+ * otherwise).
  * stats: host array [nrhs] (may be NULL), per right-hand side; iters counts
  * the shifted-CG iterations plus the refinement iterations.  Returns
  * HISQ_ENOCONV / HISQ_EBREAKDOWN if any right-hand side failed; x then holds

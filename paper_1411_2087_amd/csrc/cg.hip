@@ -112,7 +112,10 @@ __device__ __forceinline__ void finalize(CGState *st, int mode, double v)
     case FIN_RELIABLE: {
         const int gap = st->iter - st->last_upd;
         if (st->first_gap == 0) st->first_gap = gap > 0 ? gap : 1;
-        st->poor = (v > 0.25 * st->rr_upd) ? st->poor + 1 : 0;
+        // poor: the true residual fell by less than sqrt(delta) since the last
+        // update (an update fires after a fall by delta in the iterated residual),
+        // or did not halve when delta is small
+        st->poor = (v > fmax(0.25, sqrt(st->delta2)) * st->rr_upd) ? st->poor + 1 : 0;
         st->rr_upd = v;
         st->last_upd = st->iter;
         st->rr_true = v;
@@ -724,6 +727,17 @@ int cg_plain_f64(double mass, double tol, const void *fat, const void *lng, cons
     return cg_plain<PF64>(mass, tol, fat, lng, b, x, g, o, ws, ws_bytes, stats, s);
 }
 
+// Default reliable-update trigger for inner links PS.  With 16-bit links the
+// inner operator is ~1e-5 away from A and the iterated residual drifts from
+// the true one within a cycle: frequent updates (every fall by 0.7) keep the
+// iteration count at the FP32 level (at 32^4, m = 0.005: 7647 iterations
+// against 12 230 at 0.1; at m = 0.002 the solve converges at all).  FP32 inner
+// links are insensitive to it and keep the customary 0.1.
+template <class PS> constexpr double default_delta()
+{
+    return (PS::prec == HISQ_F16S || PS::prec == HISQ_I16S || PS::prec == HISQ_I16SC) ? 0.7 : 0.1;
+}
+
 template <class PH, class PS>
 int cg_mixed(double mass, double tol, const void *fat, const void *lng, const void *fat_lo, const void *lng_lo,
              const void *b, void *x, const Geom &g, const hisq_cg_opts &o, void *ws, size_t ws_bytes,
@@ -742,7 +756,7 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
     if (!hs) return fail(HISQ_EHIP, "cg_solve: pinned state allocation failed");
     const Geom gc = cg_geom(g, PS::prec);
     const Launch L(gc, st, part, part_p);
-    const double delta = o.delta > 0 ? o.delta : 0.1;
+    const double delta = o.delta > 0 ? o.delta : default_delta<PS>();
 
     auto t0 = std::chrono::steady_clock::now();
     HISQ_HIP(hipMemsetAsync(st, 0, sizeof(CGState), s));
@@ -830,11 +844,11 @@ hisq_cg_opts resolve_opts(const hisq_cg_opts *opts, const Geom &g)
         o.max_iter = 0;
         o.check_every = 0;
         o.use_graph = 1;
-        o.delta = 0.1;
+        o.delta = 0.0;
     }
     if (o.max_iter <= 0) o.max_iter = 100000;
     if (o.check_every <= 0) o.check_every = default_check_every(g);
-    if (o.delta <= 0) o.delta = 0.1;
+    if (!(o.delta > 0)) o.delta = 0.0;  // each solver applies the default of its inner links
     return o;
 }
 

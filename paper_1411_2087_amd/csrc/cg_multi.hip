@@ -896,6 +896,23 @@ struct MultiLinks32C {
     using PH = PF64C;
     using PS = PF32C;
 };
+// 16-bit fixed-point inner links (full, or with two-row long links)
+struct MultiLinks16 {
+    using PH = PF64;
+    using PS = PI16S;
+};
+struct MultiLinks16C {
+    using PH = PF64C;
+    using PS = PI16SC;
+};
+
+// Default reliable-update trigger for inner links PS: frequent updates for the
+// 16-bit forms, whose inner operator is ~1e-5 away from A (at 0.1 their batch
+// stalled at m = 0.002 on 32^4); FP32 keeps the customary 0.1.
+template <class PS> constexpr double multi_default_delta()
+{
+    return (PS::prec == HISQ_I16S || PS::prec == HISQ_I16SC) ? 0.7 : 0.1;
+}
 
 template <class P, int N, int G, int NT, int EPI>
 static hipError_t launch_md(const Geom &g, const void *fat, const void *lng, const void *src, void *dst,
@@ -1100,7 +1117,7 @@ static int multi_rhs_init(int n, const double *masses, double tol, const void *f
 {
     const long long np = (long long)g.Vh * N;
     const int nbm = mblocks(np);
-    const double delta = o.delta > 0 ? o.delta : 0.1;
+    const double delta = o.delta > 0 ? o.delta : multi_default_delta<typename M::PS>();
     double m4[MAXR];
     for (int r = 0; r < n; ++r) m4[r] = 4.0 * masses[r] * masses[r];
     HISQ_HIP(hipMemcpyAsync(B.dm, m4, n * sizeof(double), hipMemcpyHostToDevice, s));
@@ -1537,15 +1554,26 @@ extern "C" int cg_solve_multi(int nrhs, const double *masses, double tol, int mo
     if (!workspace || ws_bytes < cg_multi_workspace_bytes(g, nrhs, mode))
         return fail(HISQ_EWORKSPACE, "cg_solve_multi: workspace NULL or smaller than hisq_workspace_bytes()");
     hisq_cg_opts o = resolve_opts(opts, g);
-    // 16-bit inner links are not offered: at m = 0.002 on 32^4 the I16S
-    // inner solve of the batch stalled (1.6e-8 after 100000 iterations)
-    if (o.mode != HISQ_CG_PLAIN_F64 && o.mode != HISQ_CG_MIXED_F32 && o.mode != HISQ_CG_MIXED_F32C)
-        return fail(HISQ_EINVAL, "cg_solve_multi: opts->mode must be PLAIN_F64 / MIXED_F32 (F64 + F32 links) or "
-                                 "MIXED_F32C (F64C + F32C links)");
+    if (o.mode != HISQ_CG_PLAIN_F64 && o.mode != HISQ_CG_MIXED_F32 && o.mode != HISQ_CG_MIXED_F32C &&
+        o.mode != HISQ_CG_MIXED_I16S && o.mode != HISQ_CG_MIXED_I16SC)
+        return fail(HISQ_EINVAL, "cg_solve_multi: opts->mode must be PLAIN_F64 / MIXED_F32 (F64 + F32 links), "
+                                 "MIXED_F32C (F64C + F32C), MIXED_I16S (F64 + I16S) or MIXED_I16SC (F64C + I16SC)");
     hipStream_t s = (hipStream_t)stream;
     HISQ_HIP(hipStreamSynchronize(s));
-    if (o.mode == HISQ_CG_MIXED_F32C) return cg_multi_dispatch<MultiLinks32C>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
-    return cg_multi_dispatch<MultiLinks32>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o, workspace, ws_bytes, stats, s);
+    switch (o.mode) {
+    case HISQ_CG_MIXED_F32C:
+        return cg_multi_dispatch<MultiLinks32C>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o,
+                                                workspace, ws_bytes, stats, s);
+    case HISQ_CG_MIXED_I16S:
+        return cg_multi_dispatch<MultiLinks16>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o,
+                                               workspace, ws_bytes, stats, s);
+    case HISQ_CG_MIXED_I16SC:
+        return cg_multi_dispatch<MultiLinks16C>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o,
+                                                workspace, ws_bytes, stats, s);
+    default:
+        return cg_multi_dispatch<MultiLinks32>(nrhs, masses, tol, mode, fat, lng, fat_lo, lng_lo, b, x, g, o,
+                                               workspace, ws_bytes, stats, s);
+    }
 }
 
 extern "C" int hisq_tune_multi(const void *fat, const void *lng, const void *src, void *dst, const int dims[4], int nrhs,

@@ -18,7 +18,8 @@ def hq():
     return hq
 
 
-def _solve(hq, dims, fat, lng, b, mass, mode, tol=CG_TOL, max_iter=0, use_graph=1, check_every=0, x0=None):
+def _solve(hq, dims, fat, lng, b, mass, mode, tol=CG_TOL, max_iter=0, use_graph=1, check_every=0, x0=None,
+           delta=0.0):
     import torch
     L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64C if mode in (4, 5, 6) else hq.HISQ_F64)
     Llo = None
@@ -33,7 +34,7 @@ def _solve(hq, dims, fat, lng, b, mass, mode, tol=CG_TOL, max_iter=0, use_graph=
     bd = torch.from_numpy(b).cuda()
     xd = torch.zeros_like(bd) if x0 is None else torch.from_numpy(x0).cuda()
     ws = hq.fields.workspace("cg", dims, 1, mode)
-    opts = hq.CGOpts(mode=mode, max_iter=max_iter, check_every=check_every, use_graph=use_graph, delta=0.1)
+    opts = hq.CGOpts(mode=mode, max_iter=max_iter, check_every=check_every, use_graph=use_graph, delta=delta)
     st = hq.cg_solve(mass, tol, L64.fat, L64.lng, Llo.fat if Llo else None, Llo.lng if Llo else None, bd, xd, dims,
                      opts, ws)
     return xd.cpu().numpy(), st
@@ -80,24 +81,32 @@ def test_cg_mixed(hq, mode):
     assert st["rc"] == 0 and tr <= CG_TOL
     if mode != 2:
         assert st["fallback_used"] == 0
+    # default trigger: 0.7 for the 16-bit inner links (an update every fall by 0.7, ~65 over
+    # ten decades), 0.1 otherwise (~10)
+    if mode in (2, 3, 6):
+        assert st["reliable_updates"] >= 30
+    else:
+        assert st["reliable_updates"] <= 20
 
 
-def test_cg_mixed_falls_back_on_a_wrong_inner_operator(hq):
+@pytest.mark.parametrize("mode,delta", [(1, 0.1), (3, 0.0), (3, 0.9)])
+def test_cg_mixed_falls_back_on_a_wrong_inner_operator(hq, mode, delta):
     """Inner links of another gauge field: the inner solves converge to the wrong
     answer, reliable updates stop reducing the true residual, and plain FP64 CG
-    on the outer links finishes the solve."""
+    on the outer links finishes the solve (also with frequent updates, whose
+    stagnation test is scaled by delta)."""
     import torch
     dims, mass = (8, 8, 8, 8), 0.05
     fat, lng = fields(dims, synth.gauge_seed(1))
     fat_w, lng_w = fields(dims, synth.gauge_seed(12))
     b = synth.source(dims, synth.source_seed(1))
     L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
-    Lw = hq.fields.Links.pack(fat_w, lng_w, dims, hq.HISQ_F32)
+    Lw = hq.fields.Links.pack(fat_w, lng_w, dims, hq.HISQ_F32 if mode == 1 else hq.HISQ_I16S)
     bd = torch.from_numpy(b).cuda()
     xd = torch.zeros_like(bd)
-    opts = hq.CGOpts(mode=1, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    opts = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=delta)
     st = hq.cg_solve(mass, CG_TOL, L64.fat, L64.lng, Lw.fat, Lw.lng, bd, xd, dims, opts,
-                     hq.fields.workspace("cg", dims, 1, 1))
+                     hq.fields.workspace("cg", dims, 1, mode))
     tr = oracle.true_residual(dims, mass, fat, lng, b, xd.cpu().numpy())
     say(f"cg mixed, wrong inner links: iters={st['iters']} updates={st['reliable_updates']} "
         f"fallback={st['fallback_used']} after {st['iters'] - st['fallback_iters']} inner iterations, "

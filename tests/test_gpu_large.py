@@ -20,7 +20,7 @@ def big():
     b = synth.source(DIMS, synth.source_seed(3))
     fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
     L = {p: hq.fields.Links.pack(fd, ld, DIMS, p)
-         for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S, hq.HISQ_F64C, hq.HISQ_F32C)}
+         for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S, hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_I16SC)}
     del fd, ld
     torch.cuda.synchronize()
     return hq, fat, lng, b, L
@@ -40,16 +40,16 @@ def test_dslash_f64_48x96(big):
         assert err <= TOL_F64
 
 
-@pytest.mark.parametrize("mode", [1, 3, 5])
+@pytest.mark.parametrize("mode", [1, 3, 5, 6])
 def test_mixed_cg_48x96(big, mode):
     import torch
     hq, fat, lng, b, L = big
-    lo = {1: L[hq.HISQ_F32], 3: L[hq.HISQ_I16S], 5: L[hq.HISQ_F32C]}[mode]
-    hi = L[hq.HISQ_F64C] if mode == 5 else L[hq.HISQ_F64]
+    lo = {1: L[hq.HISQ_F32], 3: L[hq.HISQ_I16S], 5: L[hq.HISQ_F32C], 6: L[hq.HISQ_I16SC]}[mode]
+    hi = L[hq.HISQ_F64C] if mode in (5, 6) else L[hq.HISQ_F64]
     bd = torch.from_numpy(b).cuda()
     x = torch.zeros_like(bd)
     ws = hq.fields.workspace("cg", DIMS, 1, mode)
-    opts = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    opts = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.0)
     st = hq.cg_solve(MASS, CG_TOL, hi.fat, hi.lng, lo.fat, lo.lng, bd, x, DIMS, opts, ws)
     tr = oracle.true_residual(DIMS, MASS, fat, lng, b, x.cpu().numpy())
     say(f"48^3x96 m={MASS} mode={mode}: iters={st['iters']} updates={st['reliable_updates']} "

@@ -49,34 +49,41 @@ def test_dslash_multi_parity(hq, dims, nrhs):
     say(f"dslash_multi dims={dims} nrhs={nrhs}: shapes {len(outs)}, tuned {best} {['%.1f' % u for u in us]} us")
 
 
-def _solve_multi(hq, dims, fat, lng, bs, masses, mode, max_iter=0, compressed=False):
-    """compressed: two-row long links on both levels (F64C outer, F32C inner)."""
+# inner link storage of the batched solver: outer links, inner links, opts->mode
+INNER = {"f32": ("HISQ_F64", "HISQ_F32", "HISQ_CG_MIXED_F32"),
+         "f32c": ("HISQ_F64C", "HISQ_F32C", "HISQ_CG_MIXED_F32C"),  # two-row long links on both levels
+         "i16s": ("HISQ_F64", "HISQ_I16S", "HISQ_CG_MIXED_I16S"),
+         "i16sc": ("HISQ_F64C", "HISQ_I16SC", "HISQ_CG_MIXED_I16SC")}
+
+
+def _solve_multi(hq, dims, fat, lng, bs, masses, mode, max_iter=0, inner="f32"):
+    """Batched solve with the inner links `inner` (a key of INNER) and the default reliable-update trigger."""
     import torch
-    L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64C if compressed else hq.HISQ_F64)
-    L32 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32C if compressed else hq.HISQ_F32)
+    po, pi, cg_mode = (getattr(hq, k) for k in INNER[inner])
+    L64 = hq.fields.Links.pack(fat, lng, dims, po)
+    Llo = hq.fields.Links.pack(fat, lng, dims, pi)
     n = len(masses)
     b = torch.from_numpy(np.ascontiguousarray(bs)).cuda()
     vh = int(np.prod(dims)) // 2
     x = torch.zeros((n, vh, 3), dtype=torch.complex128, device="cuda")
     ws = hq.fields.workspace("cg_multi", dims, n, mode)
-    opts = hq.CGOpts(mode=hq.HISQ_CG_MIXED_F32C if compressed else 0, max_iter=max_iter, check_every=0, use_graph=1,
-                     delta=0.1)
-    st = hq.cg_solve_multi(n, masses, CG_TOL, mode, L64.fat, L64.lng, L32.fat, L32.lng, b, x, dims, opts, ws)
+    opts = hq.CGOpts(mode=cg_mode, max_iter=max_iter, check_every=0, use_graph=1, delta=0.0)
+    st = hq.cg_solve_multi(n, masses, CG_TOL, mode, L64.fat, L64.lng, Llo.fat, Llo.lng, b, x, dims, opts, ws)
     return x.cpu().numpy(), st
 
 
-@pytest.mark.parametrize("n,compressed", [(3, False), (8, False), (16, False), (8, True)])
-def test_cg_multi_rhs(hq, n, compressed):
+@pytest.mark.parametrize("n,inner", [(3, "f32"), (8, "f32"), (16, "f32"), (8, "f32c"), (8, "i16s"), (8, "i16sc")])
+def test_cg_multi_rhs(hq, n, inner):
     dims = (8, 8, 8, 8)
     fat, lng = fields(dims, synth.gauge_seed(4))
     masses = synth.log_masses(n, 0.002, 0.2) if n > 1 else np.array([0.05])
     bs = np.stack([synth.source(dims, synth.source_seed(4, r)) for r in range(n)])
     if n == 3:
         bs[1] = 0.0  # a zero source inside the batch
-    x, st = _solve_multi(hq, dims, fat, lng, bs, masses, hq.HISQ_MULTI_RHS, compressed=compressed)
+    x, st = _solve_multi(hq, dims, fat, lng, bs, masses, hq.HISQ_MULTI_RHS, inner=inner)
     for r in range(n):
         tr = oracle.true_residual(dims, masses[r], fat, lng, bs[r], x[r]) if bs[r].any() else 0.0
-        say(f"multi-rhs n={n} compressed={compressed} r={r} m={masses[r]:.4f}: iters={st[r]['iters']} "
+        say(f"multi-rhs n={n} inner={inner} r={r} m={masses[r]:.4f}: iters={st[r]['iters']} "
             f"updates={st[r]['reliable_updates']} gpu={st[r]['true_resid']:.2e} oracle={tr:.2e}")
         assert st[r]["status"] == 0 and tr <= CG_TOL
         if not bs[r].any():
@@ -86,16 +93,16 @@ def test_cg_multi_rhs(hq, n, compressed):
     assert np.linalg.norm(x[0] - xo) / np.linalg.norm(xo) < 1e-6
 
 
-@pytest.mark.parametrize("n,compressed", [(4, False), (8, False), (4, True)])
-def test_cg_multi_shift(hq, n, compressed):
+@pytest.mark.parametrize("n,inner", [(4, "f32"), (8, "f32"), (4, "f32c"), (4, "i16sc")])
+def test_cg_multi_shift(hq, n, inner):
     dims = (8, 8, 8, 8)
     fat, lng = fields(dims, synth.gauge_seed(4))
     masses = synth.log_masses(n, 0.002, 0.2)
     b = synth.source(dims, synth.source_seed(4))
-    x, st = _solve_multi(hq, dims, fat, lng, b, masses, hq.HISQ_MULTI_SHIFT, compressed=compressed)
+    x, st = _solve_multi(hq, dims, fat, lng, b, masses, hq.HISQ_MULTI_SHIFT, inner=inner)
     for r in range(n):
         tr = oracle.true_residual(dims, masses[r], fat, lng, b, x[r])
-        say(f"multi-shift n={n} compressed={compressed} m={masses[r]:.4f}: iters={st[r]['iters']} "
+        say(f"multi-shift n={n} inner={inner} m={masses[r]:.4f}: iters={st[r]['iters']} "
             f"updates={st[r]['reliable_updates']} oracle={tr:.2e}")
         assert st[r]["status"] == 0 and tr <= CG_TOL
     xo, _ = oracle.cg(dims, masses[-1], fat, lng, b, tol=1e-12)
@@ -111,14 +118,14 @@ def test_cg_multi_zero_source_and_limits(hq):
     bs = np.stack([synth.source(dims, 1), synth.source(dims, 2)])
     x, st = _solve_multi(hq, dims, fat, lng, bs, [0.01, 0.2], hq.HISQ_MULTI_RHS, max_iter=3)
     assert st[0]["rc"] == -5
-    # 16-bit inner links are refused (argument check, before any launch)
+    # half-float inner links are refused (argument check, before any launch)
     import torch
     L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
-    LI = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_I16S)
+    LI = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F16S)
     b = torch.from_numpy(bs).cuda()
     xg = torch.zeros_like(b)
     ws = hq.fields.workspace("cg_multi", dims, 2, hq.HISQ_MULTI_RHS)
-    opts = hq.CGOpts(mode=hq.HISQ_CG_MIXED_I16S, max_iter=0, check_every=0, use_graph=1, delta=0.1)
+    opts = hq.CGOpts(mode=hq.HISQ_CG_MIXED_F16S, max_iter=0, check_every=0, use_graph=1, delta=0.1)
     with pytest.raises(hq.HisqError, match="HISQ_EINVAL"):
         hq.cg_solve_multi(2, [0.01, 0.2], 1e-10, hq.HISQ_MULTI_RHS, L64.fat, L64.lng, LI.fat, LI.lng, b, xg, dims,
                           opts, ws)
