@@ -331,6 +331,72 @@ __global__ __launch_bounds__(MB_NT) void k_mnorm32(const float2 *__restrict__ v,
     mblock_partials<N>(acc, partials);
 }
 
+// Reliable update of the RHS in relmask at the end of the captured iterations.
+// Their inner iteration ran on past the trigger, so p = r_in + beta p_old was
+// built from the iterated residual; the update replaces r_in by r_true and p by
+// r_true + beta p_old, i.e. p += r_true - r_in.  Before the FP64 residual:
+// X64 += XS, XS = 0, PS -= RS (and flags.reliable opens the update's gates).
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_mrel_pre(double2 *__restrict__ x, float2 *__restrict__ xs,
+                                                   float2 *__restrict__ ps, const float2 *__restrict__ rs,
+                                                   long long npairs, const MultiState *st)
+{
+    if (st->flags.done) return;
+    const int r = threadIdx.x % N;
+    if (!((st->relmask >> r) & 1u)) return;
+    for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long long i = j * 3 + c;
+            const float2 v = xs[i], rv = rs[i];
+            double2 a = x[i];
+            a.x += (double)v.x;
+            a.y += (double)v.y;
+            x[i] = a;
+            xs[i] = make_float2(0.f, 0.f);
+            float2 pv = ps[i];
+            pv.x -= rv.x;
+            pv.y -= rv.y;
+            ps[i] = pv;
+        }
+    }
+}
+
+// After the FP64 residual (RS = float(r_true) for the RHS in relmask): PS += RS
+// for those, and the |p|^2 partials of every active RHS for the next <p, A p>.
+template <int N>
+__global__ __launch_bounds__(MB_NT) void k_mrel_post(float2 *__restrict__ ps, const float2 *__restrict__ rs,
+                                                    long long npairs, double *partials, const MultiState *st)
+{
+    if (st->flags.done) return;
+    const int r = threadIdx.x % N;
+    const bool on = (st->active >> r) & 1u, upd = (st->relmask >> r) & 1u;
+    double acc = 0.0;
+    if (on) {
+        for (long long j = (long long)blockIdx.x * MB_NT + threadIdx.x; j < npairs; j += (long long)gridDim.x * MB_NT) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long long i = j * 3 + c;
+                float2 pv = ps[i];
+                if (upd) {
+                    const float2 rv = rs[i];
+                    pv.x += rv.x;
+                    pv.y += rv.y;
+                    ps[i] = pv;
+                }
+                acc = fma((double)pv.x, (double)pv.x, fma((double)pv.y, (double)pv.y, acc));
+            }
+        }
+    }
+    mblock_partials<N>(acc, partials);
+}
+
+__global__ void k_mrel_open(MultiState *st)
+{
+    if (threadIdx.x || blockIdx.x) return;
+    st->flags.reliable = st->relmask != 0;
+}
+
 // X64 += XS ; XS = 0 for the RHS in `which_mask`
 template <int N>
 __global__ __launch_bounds__(MB_NT) void k_maccum(double2 *__restrict__ x, float2 *__restrict__ xs, long long npairs,
@@ -708,15 +774,15 @@ __device__ void mfinalize(MultiState *st, int mode, const double *v)
             if (!isfinite(x)) {
                 st->status[r] = HISQ_EBREAKDOWN;
                 st->active &= ~(1u << r);
-            } else if (x <= st->stop2[r] || x < st->delta2 * st->maxrr[r]) {
-                st->relmask |= 1u << r;
             } else {
+                // a reliable update is due: flag it for the end of the captured
+                // iterations and keep iterating (the batch is not paused)
+                if (x <= st->stop2[r] || x < st->delta2 * st->maxrr[r]) st->relmask |= 1u << r;
                 st->maxrr[r] = fmax(st->maxrr[r], x);
                 st->beta[r] = x / st->rr[r];
                 st->rr[r] = x;
             }
         }
-        st->flags.reliable = st->relmask != 0;
         if (!st->active) st->flags.done = 1;
         break;
     case FM_RELIABLE:
@@ -1079,7 +1145,7 @@ static int run_multi(F iter_fn, hipStream_t s, MultiState *dst, MultiState *hst,
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { rc = hip_fail(e, "batched CG state read-back"); break; }
         if (hst->flags.done) break;
-        if (hst->flags.reliable) {
+        if (hst->flags.reliable || hst->relmask) {
             e = pause_fn(s);
             if (e != hipSuccess) { rc = hip_fail(e, "reliable update launch"); break; }
             e = hipMemcpyAsync(hst, dst, sizeof(MultiState), hipMemcpyDeviceToHost, s);
@@ -1295,10 +1361,12 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
                            (const MultiState *)B.st);
         return hipGetLastError();
     };
-    // reliable updates of the RHS that asked for one, outside the captured iterations
+    // reliable updates of the RHS that asked for one during the last captured
+    // iterations (they kept iterating; see k_mrel_pre), all at once
     auto reliable = [&](hipStream_t q) -> hipError_t {
-        hipLaunchKernelGGL((k_maccum<N>), dim3(nbm), dim3(MB_NT), 0, q, B.x64, B.xs, np, (const MultiState *)B.st,
-                           (int)MASK_RELIABLE, (int)GATE_RELIABLE);
+        hipLaunchKernelGGL(k_mrel_open, dim3(1), dim3(1), 0, q, B.st);
+        hipLaunchKernelGGL((k_mrel_pre<N>), dim3(nbm), dim3(MB_NT), 0, q, B.x64, B.xs, B.ps, (const float2 *)B.rs, np,
+                           (const MultiState *)B.st);
         hipError_t e;
         int nb2 = 0;
         e = launch_md_shape<typename M::PH, N, EPI_STORE>(0, g, fat, lng, B.x64, B.t64, nullptr, nullptr, nullptr, 1, B.part,
@@ -1307,10 +1375,10 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
         e = launch_md_shape<typename M::PH, N, EPI_RESID>(0, g, fat, lng, B.t64, B.r64, B.x64, B.b64, B.rs, 0, B.part, B.st,
                                                 MASK_RELIABLE, GATE_RELIABLE, q, &nb2);
         if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mrel_post<N>), dim3(nbm), dim3(MB_NT), 0, q, B.ps, (const float2 *)B.rs, np, B.part_p,
+                           (const MultiState *)B.st);
         hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, q, (const double *)B.part, nb2, B.st,
                            (int)FM_RELIABLE, (int)GATE_RELIABLE);
-        hipLaunchKernelGGL((k_mp_norm<N>), dim3(nbm), dim3(MB_NT), 0, q, B.ps, (const float2 *)B.rs, np, B.part_p,
-                           (const MultiState *)B.st);
         return hipGetLastError();
     };
     int rc = HISQ_OK;
