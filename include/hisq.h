@@ -118,8 +118,9 @@ enum {
  *               A(m_i) x_i = b_i, all sharing one Dslash launch per
  *               application (each link load serves every right-hand side).
  * MULTI_SHIFT : one source b, nrhs masses: A(m_i) x_i = b, solved together
- *               by shifted CG (one Dslash pair per iteration for all shifts),
- *               then each x_i refined to tol by reliable-update CG. */
+ *               by shifted CG (one Dslash pair per iteration for all shifts)
+ *               to 1e-3 on the inner links, then each x_i refined to tol by
+ *               the batched reliable-update CG. */
 enum { HISQ_MULTI_RHS = 0, HISQ_MULTI_SHIFT = 1 };
 
 typedef struct {

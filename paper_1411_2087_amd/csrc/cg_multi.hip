@@ -1490,7 +1490,12 @@ static int cg_multi_impl(int n, const double *masses, double tol, int mode, cons
     int ms_iters[MAXR] = { 0 };
     int offset = 0;
     if (mode == HISQ_MULTI_SHIFT) {
-        const double tol_ms = std::max(tol, 1e-5);
+        // The shifted phase has no reliable updates: its iterated residuals
+        // drift from the true ones, and the refinement restarts the Krylov
+        // space.  Stopping it at 1e-3 rather than 1e-5 cut the lightest of 8
+        // masses at 32^4 from 19 854 to 19 238 total iterations (FP32 inner
+        // links) and from 23 529 to 20 288 (16-bit inner links).
+        const double tol_ms = std::max(tol, 1e-3);
         int rc = multi_shift_core<M, N>(n, masses, tol_ms, fat_lo, lng_lo, b, g, o, B, H.h, s);
         if (rc) return fail(rc, "cg_solve_multi: shifted CG broke down");
         for (int i = 0; i < n; ++i) ms_iters[i] = H.h->iters[i];
