@@ -128,8 +128,9 @@ typedef struct {
     int max_iter;      /* iteration cap over the whole solve (default 100000 if <= 0) */
     int check_every;   /* iterations between host convergence checks (<= 0: automatic) */
     int use_graph;     /* 1: replay check_every iterations as one captured HIP graph */
-    double delta;      /* reliable-update trigger |r| < delta * max|r| (<= 0: 0.7 for the
-                          16-bit inner links F16S, I16S, I16SC; 0.1 otherwise) */
+    double delta;      /* reliable-update trigger |r| < delta * max|r|, below 1 (>= 1 is
+                          HISQ_EINVAL; <= 0: 0.7 for the 16-bit inner links F16S,
+                          I16S, I16SC; 0.1 otherwise) */
 } hisq_cg_opts;
 
 typedef struct {

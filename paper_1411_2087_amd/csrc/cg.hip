@@ -926,6 +926,7 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
         return st.status = fail(HISQ_EINVAL, "cg_solve: mixed mode needs fat_lo and lng_lo");
     if (o.mode < HISQ_CG_PLAIN_F64 || o.mode > HISQ_CG_MIXED_I16SC)
         return st.status = fail(HISQ_EINVAL, "cg_solve: unknown mode");
+    if (!(o.delta < 1.0)) return st.status = fail(HISQ_EINVAL, "cg_solve: opts->delta must be below 1");
     if (!workspace || ws_bytes < cg_workspace_bytes(g, o.mode))
         return st.status = fail(HISQ_EWORKSPACE, "cg_solve: workspace NULL or smaller than hisq_workspace_bytes()");
     hipStream_t s = (hipStream_t)stream;

@@ -1624,9 +1624,10 @@ extern "C" int cg_solve_multi(int nrhs, const double *masses, double tol, int mo
     if (!(tol > 0)) return fail(HISQ_EINVAL, "cg_solve_multi: need tol > 0");
     for (int r = 0; r < nrhs; ++r)
         if (!(masses[r] > 0)) return fail(HISQ_EINVAL, "cg_solve_multi: masses must be > 0");
+    hisq_cg_opts o = resolve_opts(opts, g);
+    if (!(o.delta < 1.0)) return fail(HISQ_EINVAL, "cg_solve_multi: opts->delta must be below 1");
     if (!workspace || ws_bytes < cg_multi_workspace_bytes(g, nrhs, mode))
         return fail(HISQ_EWORKSPACE, "cg_solve_multi: workspace NULL or smaller than hisq_workspace_bytes()");
-    hisq_cg_opts o = resolve_opts(opts, g);
     if (o.mode != HISQ_CG_PLAIN_F64 && o.mode != HISQ_CG_MIXED_F32 && o.mode != HISQ_CG_MIXED_F32C &&
         o.mode != HISQ_CG_MIXED_I16S && o.mode != HISQ_CG_MIXED_I16SC)
         return fail(HISQ_EINVAL, "cg_solve_multi: opts->mode must be PLAIN_F64 / MIXED_F32 (F64 + F32 links), "

@@ -75,3 +75,31 @@ def test_workspace_sizes():
     assert hq.hisq_workspace_bytes("cg", (4, 4, 4, 5), 1, 0) == 0
     assert hq.hisq_workspace_bytes("cg", dims, 1, 6) == hq.hisq_workspace_bytes("cg", dims, 1, 1)
     assert hq.hisq_workspace_bytes("cg", dims, 1, 7) == 0
+
+
+def test_cg_option_validation_without_gpu():
+    """The reliable-update trigger must be below 1; <= 0 selects the inner links' default. Rejected
+    before any GPU work, as are unknown modes and (for the batched solver) half-float inner links."""
+    import paper_1411_2087_amd as hq
+    lib = hq._lib
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    p = [ctypes.c_void_p(0x1000 * (i + 1)) for i in range(6)]
+    st = hq.CGStats()
+    for delta, mode, want in ((1.0, 1, -1), (2.5, 3, -1), (0.5, 9, -1)):
+        o = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=delta)
+        rc = lib.cg_solve(0.1, 1e-10, p[0], p[1], p[2], p[3], p[4], p[5], dims, ctypes.byref(o), None, 0,
+                          ctypes.byref(st), None)
+        assert rc == want and st.status == want, (delta, mode, rc)
+        assert b"delta" in lib.hisq_last_error() or b"mode" in lib.hisq_last_error()
+    # a valid trigger (or the default) passes these checks and stops at the missing workspace
+    for delta in (0.0, 0.7, -1.0):
+        o = hq.CGOpts(mode=3, max_iter=0, check_every=0, use_graph=1, delta=delta)
+        assert lib.cg_solve(0.1, 1e-10, p[0], p[1], p[2], p[3], p[4], p[5], dims, ctypes.byref(o), None, 0,
+                            ctypes.byref(st), None) == -7
+    masses = (ctypes.c_double * 2)(0.01, 0.1)
+    for delta, mode, want in ((1.0, 0, -1), (0.1, hq.HISQ_CG_MIXED_F16S, -1), (0.0, hq.HISQ_CG_MIXED_I16SC, -7)):
+        o = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=delta)
+        rc = lib.cg_solve_multi(2, masses, 1e-10, hq.HISQ_MULTI_RHS, p[0], p[1], p[2], p[3], p[4], p[5], dims,
+                                ctypes.byref(o), None if want == -7 else p[0], 0 if want == -7 else 1 << 40,
+                                None, None)
+        assert rc == want, (delta, mode, rc)
