@@ -56,8 +56,9 @@ INNER = {"f32": ("HISQ_F64", "HISQ_F32", "HISQ_CG_MIXED_F32"),
          "i16sc": ("HISQ_F64C", "HISQ_I16SC", "HISQ_CG_MIXED_I16SC")}
 
 
-def _solve_multi(hq, dims, fat, lng, bs, masses, mode, max_iter=0, inner="f32"):
-    """Batched solve with the inner links `inner` (a key of INNER) and the default reliable-update trigger."""
+def _solve_multi(hq, dims, fat, lng, bs, masses, mode, max_iter=0, inner="f32", delta=0.0):
+    """Batched solve with the inner links `inner` (a key of INNER) and the reliable-update trigger `delta`
+    (0: the default of the inner links)."""
     import torch
     po, pi, cg_mode = (getattr(hq, k) for k in INNER[inner])
     L64 = hq.fields.Links.pack(fat, lng, dims, po)
@@ -67,7 +68,7 @@ def _solve_multi(hq, dims, fat, lng, bs, masses, mode, max_iter=0, inner="f32"):
     vh = int(np.prod(dims)) // 2
     x = torch.zeros((n, vh, 3), dtype=torch.complex128, device="cuda")
     ws = hq.fields.workspace("cg_multi", dims, n, mode)
-    opts = hq.CGOpts(mode=cg_mode, max_iter=max_iter, check_every=0, use_graph=1, delta=0.0)
+    opts = hq.CGOpts(mode=cg_mode, max_iter=max_iter, check_every=0, use_graph=1, delta=delta)
     st = hq.cg_solve_multi(n, masses, CG_TOL, mode, L64.fat, L64.lng, Llo.fat, Llo.lng, b, x, dims, opts, ws)
     return x.cpu().numpy(), st
 
@@ -107,6 +108,29 @@ def test_cg_multi_shift(hq, n, inner):
         assert st[r]["status"] == 0 and tr <= CG_TOL
     xo, _ = oracle.cg(dims, masses[-1], fat, lng, b, tol=1e-12)
     assert np.linalg.norm(x[-1] - xo) / np.linalg.norm(xo) < 1e-6
+
+
+@pytest.mark.parametrize("inner,mode", [("f32", 0), ("i16sc", 0), ("f32", 1)])
+def test_cg_multi_frequent_updates(hq, inner, mode):
+    """delta = 0.9: reliable updates are due every few iterations for every RHS, so most
+    captured runs end with several deferred updates at once (the direction of each updated
+    RHS corrected by r_true - r_in); every solution is still certified by the oracle."""
+    dims = (8, 8, 8, 8)
+    fat, lng = fields(dims, synth.gauge_seed(4))
+    n = 4
+    masses = synth.log_masses(n, 0.002, 0.2)
+    if mode == 0:
+        bs = np.stack([synth.source(dims, synth.source_seed(4, r)) for r in range(n)])
+    else:
+        bs = synth.source(dims, synth.source_seed(4))
+    x, st = _solve_multi(hq, dims, fat, lng, bs, masses, mode, inner=inner, delta=0.9)
+    for r in range(n):
+        b = bs[r] if mode == 0 else bs
+        tr = oracle.true_residual(dims, masses[r], fat, lng, b, x[r])
+        say(f"frequent updates inner={inner} mode={mode} m={masses[r]:.4f}: iters={st[r]['iters']} "
+            f"updates={st[r]['reliable_updates']} oracle={tr:.2e}")
+        assert st[r]["status"] == 0 and tr <= CG_TOL
+    assert max(s_["reliable_updates"] for s_ in st) >= 20
 
 
 def test_cg_multi_zero_source_and_limits(hq):
