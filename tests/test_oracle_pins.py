@@ -270,6 +270,82 @@ def test_pins_reject_planted_mistakes(dense44):
     assert np.abs(Dw @ psi.reshape(-1) - want.reshape(-1)).max() < 1e-13
 
 
+# ---------------------------------------------------------------- the componentwise error scale
+def _walk_scale(dims, fat, lng, src, p, h, dagger=True):
+    """Error scale of the output components at site (parity p, index h), by an
+    explicit walk over the 16 terms of the operator (Sec. 3): each term is the
+    matrix T that multiplies a neighbour vector -- F_mu(n) at n+mu,
+    -F_mu(n-mu)^dag at n-mu, L_mu(n) at n+3mu, -L_mu(n-3mu)^dag at n-3mu --
+    and contributes sum_b |T_ab| |psi_b| to component a.  The backward
+    matrices are formed as explicit conjugate transposes; dagger=False plants
+    the mistake of using the untransposed matrix there."""
+    c = lattice.coords(dims)
+    n = int(lattice.parity_sites(dims, p)[h])
+    out = np.zeros(3)
+    for mu in range(4):
+        for hop, U in ((1, fat), (3, lng)):
+            for sgn in (+1, -1):
+                d = c[n].copy()
+                d[mu] = (d[mu] + sgn * hop) % dims[mu]
+                m = int(lattice.lex_of(d, dims))
+                if sgn > 0:
+                    T = U[mu, n]
+                else:
+                    T = -(U[mu, m].conj().T if dagger else U[mu, m])
+                psi = src[m >> 1]
+                out += np.abs(T) @ np.abs(psi)
+    return out
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 4, 8), (8, 8, 8, 8)])
+def test_scale_bounds_the_output(dims):
+    """|(D psi)_i| <= a_i: the scale sums the moduli of the very products that D adds."""
+    fat, lng = synth.links(dims, 1200)
+    src = synth.source(dims, 1201)
+    for p in (0, 1):
+        y = oracle.dslash(dims, fat, lng, src, p)
+        a = oracle.dslash_scale(dims, fat, lng, src, p)
+        assert np.all(np.abs(y) <= a * (1 + 1e-14))
+        assert np.all(a > 0)
+
+
+def test_scale_free_field_closed_form():
+    """Unit links c1*1 and c3*1 (phases folded, so each term is +-|c| times the
+    identity): a(n)_a = 8 (|c1| + |c3|) |psi_a| summed over the 8 one-hop and
+    the 8 three-hop neighbours' a-th components."""
+    dims = (8, 8, 8, 8)
+    c1, c3 = 0.7, -0.3
+    fat, lng = synth.unit_links(dims, c1, c3)
+    # a source of unit modulus in every component: the neighbours' moduli are all 1
+    r = rng(5)
+    src = np.exp(2j * np.pi * r.random((int(np.prod(dims)) // 2, 3)))
+    for p in (0, 1):
+        a = oracle.dslash_scale(dims, fat, lng, src, p)
+        assert np.abs(a - 8 * (abs(c1) + abs(c3))).max() < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (8, 10, 8, 12)])
+def test_scale_matches_an_explicit_walk(dims):
+    """Every extent >= 8 (and not 6), so the 16 neighbours of a site are distinct
+    and no two terms alias; the oracle's scale equals the walk at sampled sites,
+    and the two planted mistakes (untransposed backward matrices, every term
+    counted twice) are far from it."""
+    fat, lng = synth.links(dims, 1300)
+    src = synth.source(dims, 1301)
+    vh = int(np.prod(dims)) // 2
+    r = rng(9)
+    worst_planted = 0.0
+    for p in (0, 1):
+        a = oracle.dslash_scale(dims, fat, lng, src, p)
+        for h in r.choice(vh, 24, replace=False):
+            want = _walk_scale(dims, fat, lng, src, p, h)
+            assert np.abs(a[h] - want).max() <= 1e-13 * want.max(), (p, h)
+            planted = _walk_scale(dims, fat, lng, src, p, h, dagger=False)
+            worst_planted = max(worst_planted, np.abs(a[h] - planted).max() / want.max())
+            assert np.abs(2 * want - a[h]).max() > 0.5 * want.max()
+    assert worst_planted > 1e-2
+
+
 # ---------------------------------------------------------------- golden: the paper's printed counts
 def test_golden_paper_counts():
     """The counts and sizes printed in Sec. 3-5 (tests/golden/paper_counts.json),
