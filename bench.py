@@ -39,18 +39,41 @@ HBM_PEAK_GBS = 8000.0
 DSLASH_SOURCES = ["paper_1411_2087_amd/csrc/hisq_common.hpp", "paper_1411_2087_amd/csrc/dslash_core.hpp",
                   "paper_1411_2087_amd/csrc/dslash.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_f64_32x32x32x32_traffic.json")
+# the plain CG's kernels: the Dslash core plus the fused CG epilogues
+CG_SOURCES = DSLASH_SOURCES + ["paper_1411_2087_amd/csrc/cg_internal.hpp", "paper_1411_2087_amd/csrc/cg.hip"]
+CG_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_f64_32x32x32x32_traffic.json")
+# algorithmic bytes per even site of the CG's dominant kernel, k_cg_Ap_upd: the parity-0 Dslash of t
+# (16 FP64 matrices, t gathered once: 2304 + 48 B), p read at the site (48 B), x and r read and written
+# (4 x 48 B); A p stays in registers
+AP_UPD_BYTES = 2304 + 48 + 48 + 4 * 48
+DP_BYTES = 2400  # k_cg_Dp: the parity-1 Dslash of p, t written
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def dslash_source_sha():
+def dslash_source_sha(sources=None):
     h = hashlib.sha256()
-    for p in DSLASH_SOURCES:
+    for p in sources or DSLASH_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def cg_traffic_from_profile(vh, kernel):
+    """HBM bytes per launch of the plain CG kernel `kernel` (k_cg_Dp / k_cg_Ap_upd) from committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs of the traffic probe, calibrated against a plain copy, or None if absent or
+    taken on other kernel sources or another lattice."""
+    try:
+        with open(CG_TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != dslash_source_sha(CG_SOURCES) or t.get("vh") != vh:
+        return None
+    row = t.get("kernels", {}).get(kernel)
+    return round(row["bytes_per_launch"]) if row else None
 
 
 def traffic_from_profile(vh, shape):
@@ -237,6 +260,105 @@ def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, s
                       "n_gpus": 1,
                       "higher_is_better": False, "data": "synthetic", "config": {"workload": out["workload"]},
                       "learned": out}))
+
+
+def run_shift_depth(args, n=8):
+    """How deep the multi-shift CG's shifted phase should run before the batched refinement: 8 masses
+    (log-spaced 0.002-0.2) at 32^4, one source, MULTI_SHIFT at several shift_tol against MULTI_RHS on the
+    same systems, FP32 and two-row 16-bit inner links (report line)."""
+    import numpy as np
+    import torch
+
+    import paper_1411_2087_amd as hq
+    import synth
+    fat, lng = synth.links(DIMS, synth.gauge_seed(4))
+    fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
+    del fat, lng
+    links = {p: hq.fields.Links.pack(fd, ld, DIMS, p)
+             for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_F64C, hq.HISQ_I16SC)}
+    del fd, ld
+    masses = synth.log_masses(n, 0.002, 0.2)
+    b1 = torch.from_numpy(synth.source(DIMS, synth.source_seed(4))).cuda()
+    bn = b1.unsqueeze(0).repeat(n, 1, 1).contiguous()
+    vh = int(np.prod(DIMS)) // 2
+    rows = {}
+    for inner, mode, hi, lo in (("f32", hq.HISQ_CG_MIXED_F32, hq.HISQ_F64, hq.HISQ_F32),
+                                ("i16sc", hq.HISQ_CG_MIXED_I16SC, hq.HISQ_F64C, hq.HISQ_I16SC)):
+        H, L = links[hi], links[lo]
+        for label, mmode, stol, b in [("multi_rhs", hq.HISQ_MULTI_RHS, 0.0, bn)] + \
+                [(f"multi_shift_{t:.0e}", hq.HISQ_MULTI_SHIFT, t, b1) for t in (1e-3, 1e-4, 1e-5, 1e-6)]:
+            ws = hq.fields.workspace("cg_multi", DIMS, n, mmode)
+            x = torch.zeros((n, vh, 3), dtype=torch.complex128, device="cuda")
+            o = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.0, shift_tol=stol)
+            st = hq.cg_solve_multi(n, masses, TOL, mmode, H.fat, H.lng, L.fat, L.lng, b, x, DIMS, o, ws)
+            r = {"s": round(st[0]["time_s"], 3), "iters": [s_["iters"] for s_ in st],
+                 "worst_true_resid": max(s_["true_resid"] for s_ in st), "rc": st[0]["rc"]}
+            if mmode == hq.HISQ_MULTI_SHIFT:
+                # the shifted phase alone: its iterations and the FP64 true residuals it leaves
+                x.zero_()
+                o.shift_only = 1
+                sp = hq.cg_solve_multi(n, masses, TOL, mmode, H.fat, H.lng, L.fat, L.lng, b, x, DIMS, o, ws)
+                r["shifted_phase"] = {"s": round(sp[0]["time_s"], 3), "iters": [s_["iters"] for s_ in sp],
+                                      "true_resid": [float(f"{s_['true_resid']:.2e}") for s_ in sp]}
+            rows[f"{inner}/{label}"] = r
+            log(f"[shift-depth] {inner} {label}: {r}")
+            del ws, x
+    print(json.dumps({"metric": "multi-shift CG s to 1e-10 by shifted-phase depth (report line)", "unit": "s",
+                      "value": rows["f32/multi_shift_1e-03"]["s"], "n_gpus": 1, "higher_is_better": False,
+                      "data": "synthetic",
+                      "config": {"workload": "32^4, 8 masses 0.002-0.2, one source, tol 1e-10"}, "shift_depth": rows}))
+
+
+def run_net_kernels(args, dims=(16, 16, 16, 16), C=16, batch=16, reps=5):
+    """The network's kernels alone on the training shape: forward (4 layers) and backward (4 weight
+    gradients, 3 input gradients) of a batch of 16 sources at 16^4, C = 16, timed with HIP events on the
+    stream they run on.  Algorithmic bytes per full-lattice site of a C_in -> C_out layer: the fat links
+    (four FP32 matrices, each serving two sites) and the input and output features (24 bytes per
+    channel); of a weight gradient the links, the input features and the upstream gradient."""
+    import numpy as np
+    import torch
+
+    import paper_1411_2087_amd as hq
+    import synth
+    from paper_1411_2087_amd import train
+    fat, lng = synth.links(dims, synth.gauge_seed(5))
+    L32 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32)
+    del fat, lng
+    V = int(np.prod(dims))
+    r = np.random.default_rng(7)
+    w = torch.from_numpy(train.flatten(train.initial_weights(C, 1.0, 0.2, 7))).cuda()
+    src = np.stack([synth.source(dims, synth.source_seed(5, i)) for i in range(batch)]).astype(np.complex64)
+    b = torch.from_numpy(src).cuda()
+    y = torch.empty_like(b)
+    gout = torch.from_numpy((r.standard_normal(src.shape) + 1j * r.standard_normal(src.shape)).astype(np.complex64)).cuda()
+    gin = torch.empty_like(b)
+    gw = torch.empty(hq.net_weight_count(C), dtype=torch.complex64, device="cuda")
+    acts = torch.empty(hq.net_act_bytes(dims, C, batch), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(hq.net_backward_ws_bytes(dims, C, batch), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def fwd():
+        hq.net_forward(L32.fat, w, C, b, y, acts, batch, dims)
+
+    def bwd():
+        hq.net_backward(L32.fat, w, C, acts, gout, gw, gin, batch, dims, ws)
+    fwd()
+    bwd()
+    t_f = timed(fwd, reps, stream) * 1e-6  # seconds per call
+    t_b = timed(bwd, reps, stream) * 1e-6
+    layer_bytes = lambda ci, co: (4 * 72 + (ci + co) * 24) * V * batch
+    fwd_bytes = layer_bytes(1, C) + 2 * layer_bytes(C, C) + layer_bytes(C, 1)
+    # backward: weight gradients (links, input, upstream gradient) and the three input gradients it needs
+    bwd_bytes = fwd_bytes + layer_bytes(1, C) + 2 * layer_bytes(C, C)
+    out = {"workload": f"network forward / backward, {'x'.join(map(str, dims))}, C {C}, batch {batch}",
+           "forward_ms": round(t_f * 1e3, 3), "backward_ms": round(t_b * 1e3, 3),
+           "forward_gbs": round(fwd_bytes / t_f / 1e9, 1), "backward_gbs": round(bwd_bytes / t_b / 1e9, 1),
+           "cc_layer_bytes": layer_bytes(C, C)}
+    log(f"[net] forward {t_f * 1e3:.3f} ms ({out['forward_gbs']} GB/s), backward {t_b * 1e3:.3f} ms "
+        f"({out['backward_gbs']} GB/s)")
+    print(json.dumps({"metric": "network forward / backward time (report line)", "unit": "ms",
+                      "value": out["forward_ms"] + out["backward_ms"], "n_gpus": 1, "higher_is_better": False,
+                      "data": "synthetic", "config": {"workload": out["workload"]}, "net": out}))
 
 
 def run_large(args):
@@ -454,7 +576,9 @@ def main():
                          "(mixed precision against plain FP64 on the large lattice), paper-grids (the Dslash "
                          "on 32^3x128 and 32x40x24x96), learned (512 training pairs on 16^4, C = 8 and 16), "
                          "learned-32 (the same on 32^4, C = 16, two held-out solves) or "
-                         "batched-16 (16 masses, batched against sequential plain FP64 solves); "
+                         "batched-16 (16 masses, batched against sequential plain FP64 solves) or net-kernels "
+                         "(the network's forward and backward kernels at 16^4, batch 16, C = 16) or shift-depth "
+                         "(the multi-shift CG's shifted phase run to several depths); "
                          "all but the first are report lines, not the metric")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a 1 GiB copy and the FP64 Dslash (for rocprofv3 counter runs); with --workload "
@@ -483,6 +607,10 @@ def main():
         return run_learned(args, dims=(32, 32, 32, 32), channels=(16,), nsolve=2)
     if args.workload == "batched-16":
         return run_batched16(args)
+    if args.workload == "net-kernels":
+        return run_net_kernels(args)
+    if args.workload == "shift-depth":
+        return run_shift_depth(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     vh = int(np.prod(DIMS)) // 2
@@ -513,8 +641,14 @@ def main():
         shape, _ = hq.hisq_tune_dslash(L64.fat, L64.lng, b, tmp, DIMS, hq.HISQ_F64, reps=5)
         for i in range(5):  # the last 5 FP64 Dslash dispatches are the measured ones
             hq.dslash_apply(L64.fat, L64.lng, b, tmp, 1, DIMS, hq.HISQ_F64)
+        # and 6 iterations of the plain CG, launched directly (the kernels of the timed solve)
+        wsp = hq.fields.workspace("cg", DIMS)
+        xp = torch.zeros_like(b)
+        op = hq.CGOpts(mode=hq.HISQ_CG_PLAIN_F64, max_iter=6, check_every=6, use_graph=0, delta=0.0)
+        hq.cg_solve(MASS, TOL, L64.fat, L64.lng, None, None, b, xp, DIMS, op, wsp)
         torch.cuda.synchronize()
-        print(json.dumps({"traffic_probe": True, "copy_bytes": n, "dslash_launches": 5, "vh": vh, "shape": shape}))
+        print(json.dumps({"traffic_probe": True, "copy_bytes": n, "dslash_launches": 5, "cg_iterations": 6, "vh": vh,
+                          "shape": shape}))
         return
 
     # autotune the Dslash launch shape of each precision on this lattice
@@ -552,6 +686,17 @@ def main():
     value = n_dslash * 2400.0 * vh / wall / 1e9
     ms_per_step = wall / args.steps * 1e3
     x_np = x.cpu().numpy()
+
+    # the solve's kernels timed one by one: the same solve with direct launches and HIP events around
+    # its three main kernels, on the stream they run on
+    x.zero_()
+    st_k = hq.cg_solve(MASS, TOL, L64.fat, L64.lng, None, None, b, x,
+                       DIMS, hq.CGOpts(mode=hq.HISQ_CG_PLAIN_F64, max_iter=0, check_every=0, use_graph=2, delta=0.0),
+                       ws, raise_on_noconv=True)
+    t_dp, t_ap, t_pn = (u * 1e-6 for u in st_k["kernel_us"])
+    ap_achieved = AP_UPD_BYTES * vh / t_ap / 1e9
+    log(f"[cg kernels] k_cg_Dp {t_dp * 1e6:.1f} us, k_cg_Ap_upd {t_ap * 1e6:.1f} us "
+        f"({ap_achieved:.0f} GB/s), k_cg_p_norm {t_pn * 1e6:.1f} us over {st_k['iters']} iterations")
 
     # the FP64 Dslash kernel alone: HIP events on the stream it runs on
     for i in range(10):
@@ -637,7 +782,7 @@ def main():
         log(f"[cpu] oracle-recomputed residual of the GPU solution: {tr:.3e}")
         cpu = cpu_baseline(fat, lng, b_np, vh)
 
-    traffic = traffic_from_profile(vh, tuned["f64"]["shape"])
+    traffic = cg_traffic_from_profile(vh, "k_cg_Ap_upd")
     out = {
         "metric": "Dslash GB/s (% HBM peak); CG s to 1e-10 resid, FP64 plain vs chosen form",
         "value": round(value, 2),
@@ -657,11 +802,23 @@ def main():
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "cg_s_to_1e-10": round(ms_per_step / 1e3, 4),
         "cg_iters": stats[-1]["iters"],
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_dslash<PF64> (parity 1, 32^4, tuned shape)", "avg_us": round(t_dslash * 1e6, 2),
-                     "bytes_per_launch": 2400 * vh, "copy_probe_gbs": round(copy_gbs, 1), "read_probe_gbs": round(read_gbs, 1),
-                     "gflops": round(1146.0 * vh / t_dslash / 1e9, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(ap_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ap_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_cg_Ap_upd<PF64> (the CG's dominant kernel: parity-0 Dslash, A p in registers, "
+                               "x and r updates; 32^4)",
+                     "avg_us": round(t_ap * 1e6, 2), "bytes_per_launch": AP_UPD_BYTES * vh,
+                     "bytes_per_site": AP_UPD_BYTES,
+                     "other_kernels": {
+                         "k_cg_Dp": {"avg_us": round(t_dp * 1e6, 2), "bytes_per_site": DP_BYTES,
+                                     "gbs": round(DP_BYTES * vh / t_dp / 1e9, 1),
+                                     "traffic": cg_traffic_from_profile(vh, "k_cg_Dp")},
+                         "k_cg_p_norm": {"avg_us": round(t_pn * 1e6, 2), "bytes_per_site": 3 * 48,
+                                         "gbs": round(3 * 48 * vh / t_pn / 1e9, 1)},
+                         "k_dslash_bare": {"avg_us": round(t_dslash * 1e6, 2), "bytes_per_site": 2400,
+                                           "gbs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                           "traffic": traffic_from_profile(vh, tuned["f64"]["shape"]),
+                                           "gflops": round(1146.0 * vh / t_dslash / 1e9, 1)}},
+                     "copy_probe_gbs": round(copy_gbs, 1), "read_probe_gbs": round(read_gbs, 1)},
         "cpu_baseline": cpu,
         "forms": forms,
         "tuned_dslash_shapes": tuned,

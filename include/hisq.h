@@ -114,23 +114,36 @@ enum {
 };
 
 /* cg_solve_multi modes.
- * MULTI_RHS   : nrhs independent systems (A + 4 m_i^2 - 4 m_0^2 ...) i.e.
- *               A(m_i) x_i = b_i, all sharing one Dslash launch per
- *               application (each link load serves every right-hand side).
+ * MULTI_RHS   : nrhs independent systems A(m_i) x_i = b_i, one source and
+ *               one mass each, advancing together: every Dslash application
+ *               is one launch for all of them (each link load serves every
+ *               right-hand side).
  * MULTI_SHIFT : one source b, nrhs masses: A(m_i) x_i = b, solved together
  *               by shifted CG (one Dslash pair per iteration for all shifts)
- *               to 1e-3 on the inner links, then each x_i refined to tol by
- *               the batched reliable-update CG. */
+ *               on the inner links to opts->shift_tol (default max(tol, 1e-3)),
+ *               then each x_i refined to tol by the batched reliable-update CG
+ *               (skipped when opts->shift_only is set). */
 enum { HISQ_MULTI_RHS = 0, HISQ_MULTI_SHIFT = 1 };
 
 typedef struct {
     int mode;          /* HISQ_CG_* */
     int max_iter;      /* iteration cap over the whole solve (default 100000 if <= 0) */
     int check_every;   /* iterations between host convergence checks (<= 0: automatic) */
-    int use_graph;     /* 1: replay check_every iterations as one captured HIP graph */
+    int use_graph;     /* 1: replay check_every iterations as one captured HIP graph;
+                          0: launch every kernel directly; 2 (cg_solve, plain modes):
+                          direct launches timed with HIP events, see stats.kernel_us */
     double delta;      /* reliable-update trigger |r| < delta * max|r|, below 1 (>= 1 is
                           HISQ_EINVAL; <= 0: 0.7 for the 16-bit inner links F16S,
                           I16S, I16SC; 0.1 otherwise) */
+    double shift_tol;  /* cg_solve_multi, MULTI_SHIFT: shift i leaves the shifted-CG phase
+                          when its recursive residual |zeta_i r| / |b| <= shift_tol
+                          (<= 0: max(tol, 1e-3); >= 1 is HISQ_EINVAL).  Ignored elsewhere */
+    int shift_only;    /* cg_solve_multi, MULTI_SHIFT: 1 = return the shifted-CG solutions
+                          as they are, without the batched refinement; stats[i] then
+                          holds shift i's shifted-CG iterations, its recursive residual
+                          (iter_resid) and the FP64 true residual of x_i, and status
+                          HISQ_OK when the recursion reached shift_tol within max_iter
+                          (HISQ_ENOCONV otherwise).  0 = refine to tol.  Ignored elsewhere */
 } hisq_cg_opts;
 
 typedef struct {
@@ -144,6 +157,17 @@ typedef struct {
                                3 recursion converged but the true residual did not.
                                cg_solve mixed modes: 0 none; 1 stagnation, finished by plain CG */
     int fallback_iters;     /* plain CG iterations after the fallback (included in iters) */
+    double iter_resid;      /* |r| / |b| of the solver's own recursion when it stopped (the
+                               inner residual of a mixed solve; |zeta_i r| / |b| of a shift) */
+    double bytes_moved;     /* algorithmic HBM bytes of the solve: every Dslash at its bytes per
+                               site (links once, source once, output once) and every vector
+                               stream once, summed over iterations and reliable updates
+                               (cg_solve_multi: the whole batched solve, in every stats[i]) */
+    double kernel_us[3];    /* cg_solve plain modes with opts->use_graph == 2: mean duration in
+                               microseconds of the iteration's three main kernels, timed with
+                               HIP events on the solve's stream: [0] t = D_oe p with the |t|^2
+                               partials, [1] the parity-0 Dslash with A p in registers and the
+                               x, r updates, [2] p = r + beta p with |p|^2; 0 otherwise */
 } hisq_cg_stats;
 
 /* Library version string. */
@@ -185,10 +209,14 @@ int hisq_apply_A(double mass, const void *fat, const void *lng, const void *x, v
                  const int dims[4], int prec, void *stream);
 
 /* Deterministic FP64 reductions over n complex entries of precision `prec`
- * vectors: out_host[0] = Re <x, y>, out_host[1] = Im <x, y> (y == x gives
- * |x|^2).  Fixed order: wave64 tree, per-workgroup partials, one fixed final
- * sum; results are bitwise reproducible.  Synchronises `stream`. */
-int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *stream);
+ * vectors (Sec. 3: the dot products of CG): out_host[0] = Re <x, y>,
+ * out_host[1] = Im <x, y> (y == x gives |x|^2).  Fixed order: wave64 tree,
+ * per-workgroup partials (at most 1024 workgroups, striding over the
+ * vectors), one fixed final sum; results are bitwise reproducible.
+ * workspace: device scratch of hisq_workspace_bytes("dot", ...) bytes
+ * (16.25 KB whatever n is), else HISQ_EWORKSPACE.  Synchronises `stream`. */
+int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *workspace,
+             size_t ws_bytes, void *stream);
 
 /* Autotuner of the single-RHS Dslash launch shape (threads per workgroup,
  * occupancy target): times every shape with HIP events on the caller's
@@ -207,10 +235,10 @@ int hisq_tune_dslash(const void *fat, const void *lng, const void *src, void *ds
  * hisq_status.  shape == -2 returns the number of shapes. */
 int hisq_dslash_shape(const int dims[4], int prec, int shape);
 
-/* Workspace bytes for `solver` = "cg", "cg_multi", "fcg" or "fat_paths" on
- * `dims` with `nrhs` right-hand sides (1 for cg), `mode` (HISQ_CG_* for
- * cg/fcg, HISQ_MULTI_* for cg_multi) and `channels` (fcg only); fat_paths
- * ignores the last three.  0 on bad arguments. */
+/* Workspace bytes for `solver` = "cg", "cg_multi", "fcg", "fat_paths" or
+ * "dot" on `dims` with `nrhs` right-hand sides (1 for cg), `mode` (HISQ_CG_*
+ * for cg/fcg, HISQ_MULTI_* for cg_multi) and `channels` (fcg only);
+ * fat_paths and dot ignore the last three.  0 on bad arguments. */
 size_t hisq_workspace_bytes(const char *solver, const int dims[4], int nrhs, int mode, int channels);
 
 /* Solve A(mass) x = b on the even sites to |b - A x| <= tol |b| (Sec. 3 CG;
@@ -292,10 +320,23 @@ int net_forward(const void *fat, const void *weights, int channels, const void *
                 size_t act_bytes, int batch, const int dims[4], void *stream);
 /* grad_out: dl/d out [batch][Vh][3]; grad_w: dl/dW summed over the batch
  * (complex, dl/dRe + i dl/dIm); grad_in (may be NULL): dl/d in.  acts: the
- * buffer filled by the net_forward of the same batch. */
+ * buffer filled by the net_forward of the same batch.  On return the
+ * workspace starts with the gradients with respect to the input of layers 4,
+ * 3 and 2 ([batch][channels][parity][Vh][3] complex64 each), then the
+ * embedded grad_out and the gradient with respect to the input of layer 1
+ * ([batch][1][parity][Vh][3] each, the latter written only when grad_in is
+ * given), every block at a multiple of 256 bytes; the rest is scratch. */
 int net_backward(const void *fat, const void *weights, int channels, const void *acts, size_t act_bytes,
                  const void *grad_out, void *grad_w, void *grad_in, int batch, const int dims[4], void *workspace,
                  size_t ws_bytes, void *stream);
+/* The transported fields that the layers mix: out[b][k][c] = T_k in[b][c]
+ * on the full lattice for k = 0..8 (k = 0 the identity, 1..4 the hops along
+ * +x, +y, +z, +t, 5..8 along -x, -y, -z, -t), in FP32 from the same device
+ * code as the layer kernels, which round exactly these values to BF16 for the
+ * MFMA.  in: [batch][channels][parity][Vh][3] complex64 (channels 1, 4, 8 or
+ * 16); out: [batch][9][channels][parity][Vh][3] complex64.  Asynchronous. */
+int net_transport(const void *fat, const void *in, void *out, int channels, int batch, const int dims[4],
+                  void *stream);
 /* l = mean_b |y_b - x_b|^2 / |x_b|^2 (FP64 accumulation) into *loss_host
  * (may be NULL: no synchronisation) and dl/dy into grad_y (may be NULL).
  * workspace >= 2048 * (batch + 1) bytes. */

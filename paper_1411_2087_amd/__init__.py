@@ -46,16 +46,21 @@ class HisqError(RuntimeError):
 
 class CGOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("delta", ctypes.c_double)]
+                ("use_graph", ctypes.c_int), ("delta", ctypes.c_double), ("shift_tol", ctypes.c_double),
+                ("shift_only", ctypes.c_int)]
 
 
 class CGStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("status", ctypes.c_int), ("true_resid", ctypes.c_double), ("time_s", ctypes.c_double),
-                ("fallback_used", ctypes.c_int), ("fallback_iters", ctypes.c_int)]
+                ("fallback_used", ctypes.c_int), ("fallback_iters", ctypes.c_int),
+                ("iter_resid", ctypes.c_double), ("bytes_moved", ctypes.c_double),
+                ("kernel_us", ctypes.c_double * 3)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["kernel_us"] = list(self.kernel_us)
+        return d
 
 
 def _load():
@@ -70,7 +75,7 @@ def _load():
     lib.hisq_pack_links.argtypes = [vp, vp, ip, ctypes.c_int, vp, vp, vp]
     lib.dslash_apply.argtypes = [vp, vp, vp, vp, ctypes.c_int, ip, ctypes.c_int, vp]
     lib.hisq_apply_A.argtypes = [d, vp, vp, vp, vp, vp, ip, ctypes.c_int, vp]
-    lib.hisq_dot.argtypes = [vp, vp, ctypes.c_longlong, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
+    lib.hisq_dot.argtypes = [vp, vp, ctypes.c_longlong, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     lib.hisq_workspace_bytes.argtypes = [ctypes.c_char_p, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.hisq_workspace_bytes.restype = sz
     lib.cg_solve.argtypes = [d, d, vp, vp, vp, vp, vp, vp, ip, ctypes.POINTER(CGOpts), vp, sz,
@@ -92,6 +97,7 @@ def _load():
     lib.net_backward_ws_bytes.restype = sz
     lib.net_forward.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp, sz, ctypes.c_int, ip, vp]
     lib.net_backward.argtypes = [vp, vp, ctypes.c_int, vp, sz, vp, vp, vp, ctypes.c_int, ip, vp, sz, vp]
+    lib.net_transport.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ip, vp]
     lib.net_loss.argtypes = [vp, vp, ctypes.c_int, ip, ctypes.POINTER(ctypes.c_double), vp, vp, sz, vp]
     lib.net_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_longlong, d, ctypes.c_int, vp]
     lib.fcg_solve.argtypes = [d, d, vp, vp, vp, vp, ctypes.c_int, vp, vp, ip, ctypes.POINTER(CGOpts), vp, sz,
@@ -103,7 +109,7 @@ def _load():
     for name in ("hisq_three_link", "hisq_fat_paths", "hisq_fold_links", "hisq_read_probe", "hisq_pack_links",
                  "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi",
                  "hisq_tune_dslash", "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape",
-                 "net_forward", "net_backward", "net_loss", "net_adam_step", "fcg_solve"):
+                 "net_forward", "net_backward", "net_transport", "net_loss", "net_adam_step", "fcg_solve"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -113,7 +119,8 @@ _lib = _load()
 EXPORTED = ["hisq_version", "hisq_last_error", "hisq_packed_link_bytes", "hisq_pack_links", "dslash_apply",
             "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi", "hisq_tune_dslash",
             "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape", "net_weight_count",
-            "net_act_bytes", "net_backward_ws_bytes", "net_forward", "net_backward", "net_loss", "net_adam_step",
+            "net_act_bytes", "net_backward_ws_bytes", "net_forward", "net_backward", "net_transport", "net_loss",
+            "net_adam_step",
             "fcg_solve", "hisq_three_link", "hisq_fat_paths", "hisq_fold_links", "hisq_read_probe"]
 
 
@@ -195,9 +202,14 @@ def hisq_apply_A(mass, fat, lng, x, y, tmp, dims, prec, stream=None):
                              _stream(stream)), "hisq_apply_A")
 
 
-def hisq_dot(x, y, n, prec, stream=None) -> complex:
+def hisq_dot(x, y, n, prec, workspace=None, stream=None) -> complex:
+    """<x, y> over n complex entries; `workspace` (a device tensor of at least
+    hisq_workspace_bytes("dot", ...) bytes) is made here when not given."""
+    if workspace is None:
+        workspace = torch.empty(hisq_workspace_bytes("dot", (4, 4, 4, 4)), dtype=torch.uint8, device=x.device)
     out = (ctypes.c_double * 2)()
-    _check(_lib.hisq_dot(_ptr(x), _ptr(y), int(n), int(prec), out, _stream(stream)), "hisq_dot")
+    _check(_lib.hisq_dot(_ptr(x), _ptr(y), int(n), int(prec), out, _ptr(workspace), _nbytes(workspace),
+                         _stream(stream)), "hisq_dot")
     return complex(out[0], out[1])
 
 
@@ -298,6 +310,11 @@ def net_backward(fat, weights, channels, acts, grad_out, grad_w, grad_in, batch,
     _check(_lib.net_backward(_ptr(fat), _ptr(weights), int(channels), _ptr(acts), _nbytes(acts), _ptr(grad_out),
                              _ptr(grad_w), _ptr(grad_in), int(batch), _dims(dims), _ptr(workspace),
                              _nbytes(workspace), _stream(stream)), "net_backward")
+
+
+def net_transport(fat, inp, out, channels, batch, dims, stream=None):
+    _check(_lib.net_transport(_ptr(fat), _ptr(inp), _ptr(out), int(channels), int(batch), _dims(dims),
+                              _stream(stream)), "net_transport")
 
 
 def net_loss(y, x, batch, dims, grad_y, workspace, sync=True, stream=None):

@@ -4,8 +4,9 @@
 //
 // Everything stays on the GPU: alpha, beta and the residual norms live in a
 // device-resident state block, every dot product is a deterministic
-// two-stage reduction (wave64 butterfly -> per-workgroup partial -> the last
-// workgroup sums the partials in a fixed order), and kernels read the
+// two-stage reduction (wave64 butterfly -> per-workgroup partial -> a
+// one-workgroup finaliser kernel sums the partials in a fixed order and
+// updates the scalars), and kernels read the
 // state's `done` flag so iterations queued past convergence cost one launch
 // each and change nothing.  The host only looks at the state every
 // `check_every` iterations; those iterations are replayed as one captured
@@ -459,15 +460,16 @@ size_t cg_workspace_bytes(const Geom &g, int mode)
     return bytes;
 }
 
-// Pinned host mirror of a solver state (one per thread; allocated once).
-CGState *pinned_state()
+void *pinned_slot(int slot)
 {
-    static thread_local CGState *h = nullptr;
+    static thread_local char *h = nullptr;
+    if (slot < 0 || slot >= PIN_SLOTS) return nullptr;
     if (!h) {
-        if (hipHostMalloc((void **)&h, sizeof(CGState) * 64, hipHostMallocDefault) != hipSuccess) h = nullptr;
+        if (hipHostMalloc((void **)&h, PIN_SLOT_BYTES * PIN_SLOTS, hipHostMallocDefault) != hipSuccess) h = nullptr;
     }
-    return h;
+    return h ? h + (size_t)slot * PIN_SLOT_BYTES : nullptr;
 }
+static_assert(sizeof(CGState) <= PIN_SLOT_BYTES, "CGState does not fit its pinned slot");
 
 hipStream_t capture_stream()
 {
@@ -488,9 +490,15 @@ struct NoPause {
 
 // pause_fn (mixed solvers): enqueues the reliable update when a state check
 // finds one pending; the iterations then resume.
-template <class IterFn, class PauseFn = NoPause>
+struct NoCheck {
+    void operator()(int) const {}
+};
+
+// on_check(n): called after every state read-back with the number of
+// iterations that ran (were not gated off) since the previous one.
+template <class IterFn, class PauseFn = NoPause, class CheckFn = NoCheck>
 static int run_iterations(IterFn iter_fn, hipStream_t s, CGState *dstate, CGState *hstate, int K, int max_iter,
-                          bool use_graph, int already, PauseFn pause_fn = PauseFn())
+                          bool use_graph, int already, PauseFn pause_fn = PauseFn(), CheckFn on_check = CheckFn())
 {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -525,9 +533,11 @@ static int run_iterations(IterFn iter_fn, hipStream_t s, CGState *dstate, CGStat
             if (rc) break;
         }
         queued += k;
+        const int before = hstate->iter;
         hipError_t e = hipMemcpyAsync(hstate, dstate, sizeof(CGState), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { rc = hip_fail(e, "CG state read-back"); break; }
+        on_check(hstate->iter - before);
         if (hstate->flags.done) break;
         if (hstate->flags.reliable) {
             e = pause_fn(s);
@@ -599,29 +609,38 @@ struct Launch {
         hipLaunchKernelGGL((k_dot_state<T>), gb, dim3(BL_NT), 0, q, p, p, n, part_p);
     }
     // t = D_oe p ; alpha = rr / (m4 |p|^2 + |t|^2)
-    template <class P> void dp(hipStream_t q, const void *fat, const void *lng, const void *p, void *t) const
+    // e0 / e1 (may be NULL): events recorded right before and after the main kernel
+    template <class P>
+    void dp(hipStream_t q, const void *fat, const void *lng, const void *p, void *t, hipEvent_t e0 = nullptr,
+            hipEvent_t e1 = nullptr) const
     {
         using V = typename P::cvec;
+        if (e0) hipEventRecord(e0, q);
         hipLaunchKernelGGL((k_cg_Dp<P, CG_NT, cg_waves<P>()>), gd, dim3(CG_NT), 0, q, g, (const char *)fat,
                            (const char *)lng, (const V *)p, (V *)t, nbd, part, (const CGState *)st);
+        if (e1) hipEventRecord(e1, q);
         hipLaunchKernelGGL(k_finalize_pap, dim3(1), dim3(FIN_NT), 0, q, (const double *)part_p, nbl,
                            (const double *)part, nbd, st);
     }
     // x += alpha p ; r -= alpha (m4 p - D_eo t) ; |r|^2 -> mode
     template <class P>
     void ap_update(hipStream_t q, const void *fat, const void *lng, const void *t, const void *p, void *x, void *r,
-                   int mode) const
+                   int mode, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) const
     {
         using V = typename P::cvec;
+        if (e0) hipEventRecord(e0, q);
         hipLaunchKernelGGL((k_cg_Ap_upd<P, CG_NT, cg_waves<P>()>), gd, dim3(CG_NT), 0, q, g, (const char *)fat,
                            (const char *)lng, (const V *)t, (const V *)p, (V *)x, (V *)r, nbd, part,
                            (const CGState *)st);
+        if (e1) hipEventRecord(e1, q);
         fin(q, nbd, mode, GATE_PAUSE);
     }
     // p = r + beta p ; |p|^2 partials into part_p
-    template <class T> void pupd(hipStream_t q, T *p, const T *r) const
+    template <class T> void pupd(hipStream_t q, T *p, const T *r, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) const
     {
+        if (e0) hipEventRecord(e0, q);
         hipLaunchKernelGGL((k_cg_p_norm<T>), gb, dim3(BL_NT), 0, q, p, r, n, part_p, (const CGState *)st);
+        if (e1) hipEventRecord(e1, q);
     }
 };
 
@@ -634,16 +653,27 @@ static Geom cg_geom(const Geom &g, int prec)
     return c;
 }
 
-static void finish_stats(hisq_cg_stats &stats, const CGState *hs, int status, int restarts,
+static void finish_stats(hisq_cg_stats &stats, const CGState *hs, int status, int restarts, double bytes,
                          std::chrono::steady_clock::time_point t0)
 {
     stats.iters = hs->iter;
     stats.restarts = restarts;
     stats.reliable_updates = hs->nupdates;
     stats.true_resid = hs->bb > 0 ? std::sqrt(hs->rr_true / hs->bb) : 0.0;
+    stats.iter_resid = hs->bb > 0 ? std::sqrt(hs->rr / hs->bb) : 0.0;
+    stats.bytes_moved = bytes;
     stats.status = status;
     stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
+
+// Byte model of a CG iteration per even site: the two Dslash link streams and
+// seven vector streams (p read and t written by the first Dslash; t, p read,
+// x and r read and written by the update epilogue, where A p stays in
+// registers; r, p read and p written by the direction update).  A true
+// residual (x read, t written; t, x, b read, r written) moves the links
+// twice and six vectors.
+static double cg_iter_bytes(int prec) { return 2 * link_bytes_site(prec) + 7 * vec_bytes(prec); }
+static double cg_resid_bytes(int prec) { return 2 * link_bytes_site(prec) + 6 * vec_bytes(prec); }
 
 static int zero_source_exit(void *x, size_t v64, hipStream_t s, hisq_cg_stats &stats,
                             std::chrono::steady_clock::time_point t0)
@@ -656,6 +686,44 @@ static int zero_source_exit(void *x, size_t v64, hipStream_t s, hisq_cg_stats &s
     stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return HISQ_OK;
 }
+
+// Kernel timing of the plain solver (opts->use_graph == 2): the iterations
+// launch directly, with HIP events right before and after each of the three
+// main kernels, slot i % K of K slots per state check; after each check the
+// slots of the iterations that ran are read and summed.
+struct IterTimer {
+    int K = 0;
+    std::vector<hipEvent_t> ev;
+    double sum[3] = { 0.0, 0.0, 0.0 };
+    long long n = 0;
+    int slot = 0;
+    bool start(int k)
+    {
+        ev.assign(6 * (size_t)k, nullptr);
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return false;
+        K = k;
+        return true;
+    }
+    hipEvent_t at(int i) const { return K ? ev[6 * (size_t)(slot % K) + i] : nullptr; }
+    void next() { if (K) ++slot; }
+    void collect(int ran)
+    {
+        for (int j = 0; j < std::min(ran, K); ++j)
+            for (int c = 0; c < 3; ++c) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[6 * (size_t)j + 2 * c], ev[6 * (size_t)j + 2 * c + 1]) == hipSuccess)
+                    sum[c] += 1e3 * ms;
+            }
+        n += std::min(ran, K);
+        slot = 0;
+    }
+    ~IterTimer()
+    {
+        for (auto &e : ev)
+            if (e) hipEventDestroy(e);
+    }
+};
 
 template <class PH>
 int cg_plain(double mass, double tol, const void *fat, const void *lng, const void *b, void *x, const Geom &g,
@@ -685,18 +753,23 @@ int cg_plain(double mass, double tol, const void *fat, const void *lng, const vo
     if (rc) return rc;
     if (hs->bb == 0.0) return zero_source_exit(x, v64, s, stats, t0);
 
+    IterTimer tm;
+    if (o.use_graph == 2 && !tm.start(o.check_every)) return fail(HISQ_EHIP, "cg_solve: event creation failed");
     auto iter = [&](hipStream_t q) -> hipError_t {
-        L.dp<PH>(q, fat, lng, p, t);
-        L.ap_update<PH>(q, fat, lng, t, p, x, r, FIN_UPD_PLAIN);
-        L.pupd<double2>(q, p, r);
+        L.dp<PH>(q, fat, lng, p, t, tm.at(0), tm.at(1));
+        L.ap_update<PH>(q, fat, lng, t, p, x, r, FIN_UPD_PLAIN, tm.at(2), tm.at(3));
+        L.pupd<double2>(q, p, r, tm.at(4), tm.at(5));
+        tm.next();
         return hipGetLastError();
     };
+    auto on_check = [&](int ran) { if (tm.K) tm.collect(ran); };
 
     int restarts = 0;
     int status = HISQ_OK;
     while (true) {
         if (!hs->flags.done) {
-            rc = run_iterations(iter, s, st, hs, o.check_every, o.max_iter, o.use_graph != 0, hs->iter);
+            rc = run_iterations(iter, s, st, hs, o.check_every, o.max_iter, o.use_graph != 0 && o.use_graph != 2, hs->iter, NoPause(),
+                                on_check);
             if (rc) return rc;
         }
         if (hs->flags.done == CG_BREAKDOWN) { status = HISQ_EBREAKDOWN; break; }
@@ -715,7 +788,9 @@ int cg_plain(double mass, double tol, const void *fat, const void *lng, const vo
         rc = read_state(hs, st, s);
         if (rc) return rc;
     }
-    finish_stats(stats, hs, status, restarts, t0);
+    const double bytes = ((double)hs->iter * cg_iter_bytes(PH::prec) + (2 + 2 * restarts) * cg_resid_bytes(PH::prec)) * g.Vh;
+    finish_stats(stats, hs, status, restarts, bytes, t0);
+    for (int c = 0; c < 3; ++c) stats.kernel_us[c] = tm.n ? tm.sum[c] / tm.n : 0.0;
     if (status == HISQ_EBREAKDOWN) return fail(status, "cg_solve: breakdown (<p,Ap> <= 0 or not finite)");
     if (status == HISQ_ENOCONV) return fail(status, "cg_solve: not converged within max_iter");
     return HISQ_OK;
@@ -810,6 +885,7 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
         stats.reliable_updates = nupd;
         stats.fallback_used = 1;
         stats.fallback_iters = s2.iters;
+        stats.bytes_moved += ((double)used * cg_iter_bytes(PS::prec) + (nupd + 1) * cg_resid_bytes(PH::prec)) * g.Vh;
         stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return rc;
     }
@@ -827,7 +903,10 @@ int cg_mixed(double mass, double tol, const void *fat, const void *lng, const vo
         if (rc) return rc;
         status = hs->rr_true <= hs->stop2 ? HISQ_OK : HISQ_ENOCONV;
     }
-    finish_stats(stats, hs, status, 0, t0);
+    // inner iterations on PS, every reliable update (and the start) one FP64 true residual
+    const double bytes =
+        ((double)hs->iter * cg_iter_bytes(PS::prec) + (hs->nupdates + 1) * cg_resid_bytes(PH::prec)) * g.Vh;
+    finish_stats(stats, hs, status, 0, bytes, t0);
     if (status == HISQ_EBREAKDOWN) return fail(status, "cg_solve: breakdown (<p,Ap> <= 0 or not finite)");
     if (status == HISQ_ENOCONV) return fail(status, "cg_solve: not converged within max_iter");
     return HISQ_OK;
@@ -845,10 +924,13 @@ hisq_cg_opts resolve_opts(const hisq_cg_opts *opts, const Geom &g)
         o.check_every = 0;
         o.use_graph = 1;
         o.delta = 0.0;
+        o.shift_tol = 0.0;
+        o.shift_only = 0;
     }
     if (o.max_iter <= 0) o.max_iter = 100000;
     if (o.check_every <= 0) o.check_every = default_check_every(g);
     if (!(o.delta > 0)) o.delta = 0.0;  // each solver applies the default of its inner links
+    if (!(o.shift_tol > 0)) o.shift_tol = 0.0;
     return o;
 }
 
@@ -890,6 +972,12 @@ __global__ __launch_bounds__(FIN_NT) void k_dot2_fin(const double *__restrict__ 
 
 using namespace hisq;
 
+namespace hisq {
+// scratch of the standalone dot product: the per-workgroup partials, then the result
+constexpr size_t DOT_PART_BYTES = 2 * sizeof(double) * BLAS_MAX_BLOCKS;
+constexpr size_t DOT_WS_BYTES = DOT_PART_BYTES + 256;
+}  // namespace hisq
+
 extern "C" size_t hisq_workspace_bytes(const char *solver, const int dims[4], int nrhs, int mode, int channels)
 {
     Geom g;
@@ -900,6 +988,7 @@ extern "C" size_t hisq_workspace_bytes(const char *solver, const int dims[4], in
     }
     if (!std::strcmp(solver, "cg_multi")) return cg_multi_workspace_bytes(g, nrhs, mode);
     if (!std::strcmp(solver, "fat_paths")) return fat_paths_ws_bytes(dims);
+    if (!std::strcmp(solver, "dot")) return DOT_WS_BYTES;
     if (!std::strcmp(solver, "fcg")) {
         if (channels != 4 && channels != 8 && channels != 16) return 0;
         return fcg_ws_bytes(g, channels);
@@ -956,21 +1045,15 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
     return rc;
 }
 
-extern "C" int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *stream)
+// Deterministic dot product on scratch `ws` (>= DOT_WS_BYTES of device memory).
+static int dot_on(const void *x, const void *y, long long n, int prec, double out_host[2], char *ws, hipStream_t s)
 {
-    if (!x || !y || !out_host || n < 0) return fail(HISQ_EINVAL, "hisq_dot: bad argument");
-    if (prec < HISQ_F64 || prec > HISQ_I16SC) return fail(HISQ_EINVAL, "hisq_dot: bad precision");
-    // small scratch (partials and the result), allocated once per thread
-    static thread_local char *scratch = nullptr;
-    const size_t part_bytes = 2 * sizeof(double) * BLAS_MAX_BLOCKS;
-    if (!scratch) HISQ_HIP(hipMalloc((void **)&scratch, part_bytes + 256));
-    double *part = (double *)scratch;
-    double *out = (double *)(scratch + part_bytes);
-    hipStream_t s = (hipStream_t)stream;
     if (n == 0) {
         out_host[0] = out_host[1] = 0.0;
         return HISQ_OK;
     }
+    double *part = (double *)ws;
+    double *out = (double *)(ws + DOT_PART_BYTES);
     const int nb = (int)std::min<long long>((n + 255) / 256, BLAS_MAX_BLOCKS);
     if (prec == HISQ_F64 || prec == HISQ_F64C)
         hipLaunchKernelGGL((k_dot2<double2>), dim3(nb), dim3(BL_NT), 0, s, (const double2 *)x, (const double2 *)y, n,
@@ -983,4 +1066,14 @@ extern "C" int hisq_dot(const void *x, const void *y, long long n, int prec, dou
     HISQ_HIP(hipMemcpyAsync(out_host, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HISQ_HIP(hipStreamSynchronize(s));
     return HISQ_OK;
+}
+
+extern "C" int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *workspace,
+                        size_t ws_bytes, void *stream)
+{
+    if (!x || !y || !out_host || n < 0) return fail(HISQ_EINVAL, "hisq_dot: bad argument");
+    if (prec < HISQ_F64 || prec > HISQ_I16SC) return fail(HISQ_EINVAL, "hisq_dot: bad precision");
+    if (!workspace || ws_bytes < DOT_WS_BYTES)
+        return fail(HISQ_EWORKSPACE, "hisq_dot: workspace NULL or smaller than hisq_workspace_bytes(\"dot\")");
+    return dot_on(x, y, n, prec, out_host, (char *)workspace, (hipStream_t)stream);
 }

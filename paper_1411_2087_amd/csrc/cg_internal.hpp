@@ -43,12 +43,36 @@ struct CGState {
     int pad_;
 };
 
+// Algorithmic bytes per site of the byte model of every solver's bytes_moved:
+// the 16 link matrices of one Dslash in precision `prec` (a two-row long
+// matrix is 96, 48 or 28 bytes) and one colour vector of its vector type.
+inline double link_bytes_site(int prec)
+{
+    switch (prec) {
+    case HISQ_F64: return 16 * 144.0;
+    case HISQ_F32: return 16 * 72.0;
+    case HISQ_F16S:
+    case HISQ_I16S: return 16 * 40.0;
+    case HISQ_F64C: return 8 * 144.0 + 8 * 96.0;
+    case HISQ_F32C: return 8 * 72.0 + 8 * 48.0;
+    default: return 8 * 40.0 + 8 * 28.0;  // HISQ_I16SC
+    }
+}
+inline double vec_bytes(int prec) { return (prec == HISQ_F64 || prec == HISQ_F64C) ? 48.0 : 24.0; }
+
 int blas_blocks(long long n);
 size_t cg_partials_count(const Geom &g);
 size_t cg_multi_workspace_bytes(const Geom &g, int nrhs, int mode);
 size_t fcg_ws_bytes(const Geom &g, int channels);
 size_t fat_paths_ws_bytes(const int dims[4]);  // links.hip
-CGState *pinned_state();
+// Pinned host mirrors of the solvers' device states: one block per thread,
+// allocated by the first solve on the thread and kept, so no solve allocates
+// or frees pinned memory (hipHostFree would synchronise the device).  Slots:
+// fcg_solve keeps its state live while its plain-CG fallback uses PIN_CG.
+enum { PIN_CG = 0, PIN_MULTI = 1, PIN_FCG = 2, PIN_SLOTS = 3 };
+constexpr size_t PIN_SLOT_BYTES = 16384;
+void *pinned_slot(int slot);
+inline CGState *pinned_state() { return (CGState *)pinned_slot(PIN_CG); }
 hipStream_t capture_stream();
 hisq_cg_opts resolve_opts(const hisq_cg_opts *opts, const Geom &g);
 

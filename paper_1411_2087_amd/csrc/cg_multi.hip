@@ -44,6 +44,7 @@ struct MultiState {
     // shifted CG
     double sigma0, rr0, bb0, stop0, alpha0, beta0, a_prev, b_prev;
     double dsig[MAXR], zeta[MAXR], zeta_prev[MAXR], zeta_next[MAXR], alpha_s[MAXR], beta_s[MAXR];
+    double rr_s[MAXR];  // |zeta_i r|^2: shift i's recursive residual after its last iteration
     int ms_status;
 };
 
@@ -555,6 +556,7 @@ __global__ __launch_bounds__(FIN_NT_M) void k_msfinalize(const double *__restric
         st->bb0 = v;
         st->rr0 = v;
         st->stop0 = st->tol2 * v;
+        for (int i = 0; i < n; ++i) st->rr_s[i] = v;
         break;
     case FS_PAP: {
         if (!(v > 0.0) || !isfinite(v)) {
@@ -590,7 +592,8 @@ __global__ __launch_bounds__(FIN_NT_M) void k_msfinalize(const double *__restric
             st->beta_s[i] = be * q * q;
             st->zeta_prev[i] = st->zeta[i];
             st->zeta[i] = st->zeta_next[i];
-            if (st->zeta[i] * st->zeta[i] * v <= st->stop0) st->active &= ~(1u << i);
+            st->rr_s[i] = st->zeta[i] * st->zeta[i] * v;
+            if (st->rr_s[i] <= st->stop0) st->active &= ~(1u << i);
         }
         st->a_prev = st->alpha0;
         st->b_prev = be;
@@ -619,6 +622,7 @@ __global__ void k_ms_init(MultiState *st, int n, double tol2, double sigma0, con
         st->dsig[i] = i < n ? dsig[i] : 0.0;
         st->zeta[i] = st->zeta_prev[i] = st->zeta_next[i] = 1.0;
         st->alpha_s[i] = st->beta_s[i] = 0.0;
+        st->rr_s[i] = 0.0;
         st->iters[i] = 0;
     }
 }
@@ -1044,6 +1048,7 @@ size_t cg_multi_ws_for(const Geom &g, int N)
     b += 4 * (al256(vp * 16) + MSKEW) + 4 * (al256(vp * 8) + MSKEW) + 4 * (al256((size_t)g.Vh * 3 * 8) + MSKEW);
     return b + 4096;
 }
+static_assert(sizeof(MultiState) <= PIN_SLOT_BYTES, "MultiState does not fit its pinned slot");
 
 static int pad_n(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : 16; }
 
@@ -1084,18 +1089,6 @@ static bool carve(MultiBufs &B, void *ws, size_t bytes, const Geom &g, int N)
     B.t1 = (float2 *)take(v1 * 8);
     return B.t1 != nullptr;
 }
-
-struct MultiHost {
-    MultiState *h = nullptr;
-    MultiHost()
-    {
-        if (hipHostMalloc((void **)&h, sizeof(MultiState), hipHostMallocDefault) != hipSuccess) h = nullptr;
-    }
-    ~MultiHost()
-    {
-        if (h) hipHostFree(h);
-    }
-};
 
 // run_multi returns MULTI_SHRINK (> 0) when at a state check no more than
 // `shrink_at` right-hand sides are still iterating.
@@ -1172,8 +1165,24 @@ struct MultiOut {
     double2 *x;        // caller's x [n][Vh][3]
     int orig[MAXR];    // batch column -> caller index
     int iters[MAXR], nupd[MAXR], status[MAXR];
-    double rr_true[MAXR], bb[MAXR];
+    double rr_true[MAXR], bb[MAXR], rr[MAXR];
+    double bytes;      // algorithmic bytes moved so far (the whole batched solve)
 };
+
+// Byte model of the batched iteration with N columns of inner links PS, per
+// site: two Dslash link streams, then the vector streams of the three
+// kernels (norm epilogue: p read, t written; update epilogue: t read, p
+// read, x and r read and written; direction update: r read, p read and
+// written), 11 FP32 vectors per column.
+template <class PS> static double multi_iter_bytes(int N) { return 2 * link_bytes_site(PS::prec) + 11 * 24.0 * N; }
+// One deferred reliable-update pass for k flagged columns: the two FP64
+// Dslash link streams, then per column x64 read and written, x, p read and
+// written, r read (k_mrel_pre), x64 read, t64 written, t64 read, x64 and b
+// read, r64 and r written (the two Dslashes), p read and written, r read.
+template <class PH> static double multi_rel_bytes(int k)
+{
+    return 2 * link_bytes_site(PH::prec) + k * (2 * 48.0 + 4 * 24.0 + 24 + 48 * 6 + 24 + 3 * 24);
+}
 
 // Batched reliable-update CG, set-up: R64 = B - A X64 for every RHS, RS =
 // float(R64), PS = RS (B.b64 and B.x64 [Vh][N][3] FP64 on entry).
@@ -1271,6 +1280,7 @@ static void retire(MultiBufs &B, const MultiState *hs, const Geom &g, int c, Mul
     out.status[r] = hs->status[c];
     out.rr_true[r] = hs->rr_true[c];
     out.bb[r] = hs->bb[c];
+    out.rr[r] = hs->rr[c];
 }
 
 // The batch shrinks to the next power of two that holds the right-hand
@@ -1364,6 +1374,7 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
     // reliable updates of the RHS that asked for one during the last captured
     // iterations (they kept iterating; see k_mrel_pre), all at once
     auto reliable = [&](hipStream_t q) -> hipError_t {
+        out.bytes += multi_rel_bytes<typename M::PH>(__builtin_popcount(hs->relmask)) * g.Vh;
         hipLaunchKernelGGL(k_mrel_open, dim3(1), dim3(1), 0, q, B.st);
         hipLaunchKernelGGL((k_mrel_pre<N>), dim3(nbm), dim3(MB_NT), 0, q, B.x64, B.xs, B.ps, (const float2 *)B.rs, np,
                            (const MultiState *)B.st);
@@ -1384,8 +1395,10 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
     int rc = HISQ_OK;
     if (!hs->flags.done) {
         const int budget = std::max(1, o.max_iter - iter_offset - hs->iter);
+        const int it0 = hs->iter;
         rc = run_multi(iter, s, B.st, hs, o.check_every, budget, o.use_graph != 0, N > 1 ? N / 2 : -1, reliable);
         if (rc < 0) return rc;
+        out.bytes += (double)(hs->iter - it0) * multi_iter_bytes<PS>(N) * g.Vh;
     }
     if constexpr (N > 1) {
         if (rc == MULTI_SHRINK) {
@@ -1420,6 +1433,7 @@ static int multi_rhs_run(const void *fat, const void *lng, const void *fat_lo, c
     hipLaunchKernelGGL((k_mfinalize<N>), dim3(1), dim3(FIN_NT_M), 0, s, (const double *)B.part, nb, B.st, (int)FM_FINAL,
                        (int)GATE_ALWAYS);
     HISQ_HIP(hipGetLastError());
+    out.bytes += multi_rel_bytes<typename M::PH>(N) * g.Vh;
     rc = read_mstate(hs, B.st, s);
     if (rc) return rc;
     for (int c = 0; c < hs->n; ++c) retire<N>(B, hs, g, c, out, s);
@@ -1481,25 +1495,40 @@ static int cg_multi_impl(int n, const double *masses, double tol, int mode, cons
 {
     MultiBufs B;
     if (!carve(B, ws, ws_bytes, g, N)) return fail(HISQ_EWORKSPACE, "cg_solve_multi: workspace too small");
-    MultiHost H;
-    if (!H.h) return fail(HISQ_EHIP, "cg_solve_multi: pinned state allocation failed");
+    MultiState *hs = (MultiState *)pinned_slot(PIN_MULTI);
+    if (!hs) return fail(HISQ_EHIP, "cg_solve_multi: pinned state allocation failed");
     const long long np = (long long)g.Vh * N;
     const int nbm = mblocks(np);
     auto t0 = std::chrono::steady_clock::now();
     HISQ_HIP(hipMemsetAsync(B.st, 0, sizeof(MultiState), s));
     int ms_iters[MAXR] = { 0 };
+    double ms_resid[MAXR] = { 0.0 };
+    bool ms_conv[MAXR] = { false };
     int offset = 0;
+    MultiOut out;
+    std::memset(&out, 0, sizeof(out));
+    out.x = (double2 *)x;
+    for (int c = 0; c < MAXR; ++c) out.orig[c] = c < n ? c : -1;
+    const bool shift_only = mode == HISQ_MULTI_SHIFT && o.shift_only;
     if (mode == HISQ_MULTI_SHIFT) {
         // The shifted phase has no reliable updates: its iterated residuals
         // drift from the true ones, and the refinement restarts the Krylov
-        // space.  Stopping it at 1e-3 rather than 1e-5 cut the lightest of 8
+        // space.  By default it stops at 1e-3: that cut the lightest of 8
         // masses at 32^4 from 19 854 to 19 238 total iterations (FP32 inner
-        // links) and from 23 529 to 20 288 (16-bit inner links).
-        const double tol_ms = std::max(tol, 1e-3);
-        int rc = multi_shift_core<M, N>(n, masses, tol_ms, fat_lo, lng_lo, b, g, o, B, H.h, s);
+        // links) and from 23 529 to 20 288 (16-bit inner links) against 1e-5.
+        const double tol_ms = o.shift_tol > 0 ? o.shift_tol : std::max(tol, 1e-3);
+        int rc = multi_shift_core<M, N>(n, masses, tol_ms, fat_lo, lng_lo, b, g, o, B, hs, s);
         if (rc) return fail(rc, "cg_solve_multi: shifted CG broke down");
-        for (int i = 0; i < n; ++i) ms_iters[i] = H.h->iters[i];
-        offset = H.h->iter;
+        for (int i = 0; i < n; ++i) {
+            ms_iters[i] = hs->iters[i];
+            ms_resid[i] = hs->bb0 > 0 ? std::sqrt(hs->rr_s[i] / hs->bb0) : 0.0;
+            ms_conv[i] = hs->bb0 == 0.0 || !((hs->active >> i) & 1u);
+        }
+        offset = hs->iter;
+        // per iteration: two Dslash link streams; base vectors p, t (first
+        // Dslash), t, p, A p (second), r, r, A p (residual update), r, p, p
+        // (direction): 11; per shift x, x, p (solution) and p, p (direction)
+        out.bytes += (double)hs->iter * (2 * link_bytes_site(M::PS::prec) + 11 * 24.0 + 5 * 24.0 * N) * g.Vh;
         const long long nv = np * 3;
         hipLaunchKernelGGL(k_to_double, dim3(nbm), dim3(MB_NT), 0, s, (const float2 *)B.xs, B.x64, nv);
         hipLaunchKernelGGL((k_to_batched<N>), dim3(nbm), dim3(MB_NT), 0, s, (const double2 *)b, B.b64, (long long)g.Vh,
@@ -1510,33 +1539,42 @@ static int cg_multi_impl(int n, const double *masses, double tol, int mode, cons
                            n, 0);
     }
     HISQ_HIP(hipGetLastError());
-    int rc = multi_rhs_init<M, N>(n, masses, tol, fat, lng, g, o, B, H.h, s);
+    // FP64 true residuals of the starting x (the shifted solutions, or 0)
+    int rc = multi_rhs_init<M, N>(n, masses, tol, fat, lng, g, o, B, hs, s);
     if (rc) return rc;
-    MultiOut out;
-    std::memset(&out, 0, sizeof(out));
-    out.x = (double2 *)x;
-    for (int c = 0; c < MAXR; ++c) out.orig[c] = c < n ? c : -1;
-    rc = multi_rhs_run<M, N>(fat, lng, fat_lo, lng_lo, g, o, B, H.h, s, offset, out);
-    if (rc) return rc;
+    out.bytes += multi_rel_bytes<typename M::PH>(N) * g.Vh;
+    if (shift_only) {
+        for (int c = 0; c < n; ++c) retire<N>(B, hs, g, c, out, s);
+        HISQ_HIP(hipGetLastError());
+    } else {
+        rc = multi_rhs_run<M, N>(fat, lng, fat_lo, lng_lo, g, o, B, hs, s, offset, out);
+        if (rc) return rc;
+    }
     HISQ_HIP(hipStreamSynchronize(s));
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     int worst = HISQ_OK;
     for (int r = 0; r < n; ++r) {
         const double tr = out.bb[r] > 0 ? std::sqrt(out.rr_true[r] / out.bb[r]) : 0.0;
-        int st = out.bb[r] == 0.0 ? HISQ_OK
-                                  : (tr <= tol ? HISQ_OK : (out.status[r] == HISQ_EBREAKDOWN ? HISQ_EBREAKDOWN : HISQ_ENOCONV));
+        int st;
+        if (shift_only) st = ms_conv[r] ? HISQ_OK : HISQ_ENOCONV;
+        else st = out.bb[r] == 0.0 ? HISQ_OK
+                                   : (tr <= tol ? HISQ_OK : (out.status[r] == HISQ_EBREAKDOWN ? HISQ_EBREAKDOWN : HISQ_ENOCONV));
         if (st != HISQ_OK && worst == HISQ_OK) worst = st;
         if (stats) {
-            stats[r].iters = out.iters[r] + ms_iters[r];
-            stats[r].reliable_updates = out.nupd[r];
+            stats[r].iters = shift_only ? ms_iters[r] : out.iters[r] + ms_iters[r];
+            stats[r].reliable_updates = shift_only ? 0 : out.nupd[r];
             stats[r].restarts = 0;
             stats[r].status = st;
             stats[r].true_resid = tr;
             stats[r].time_s = dt;
+            stats[r].iter_resid = shift_only ? ms_resid[r] : (out.bb[r] > 0 ? std::sqrt(out.rr[r] / out.bb[r]) : 0.0);
+            stats[r].bytes_moved = out.bytes;
         }
     }
     if (worst == HISQ_EBREAKDOWN) return fail(worst, "cg_solve_multi: breakdown in some right-hand side");
-    if (worst == HISQ_ENOCONV) return fail(worst, "cg_solve_multi: some right-hand side not converged");
+    if (worst == HISQ_ENOCONV)
+        return fail(worst, shift_only ? "cg_solve_multi: some shift did not reach shift_tol within max_iter"
+                                      : "cg_solve_multi: some right-hand side not converged");
     return HISQ_OK;
 }
 
@@ -1626,6 +1664,7 @@ extern "C" int cg_solve_multi(int nrhs, const double *masses, double tol, int mo
         if (!(masses[r] > 0)) return fail(HISQ_EINVAL, "cg_solve_multi: masses must be > 0");
     hisq_cg_opts o = resolve_opts(opts, g);
     if (!(o.delta < 1.0)) return fail(HISQ_EINVAL, "cg_solve_multi: opts->delta must be below 1");
+    if (!(o.shift_tol < 1.0)) return fail(HISQ_EINVAL, "cg_solve_multi: opts->shift_tol must be below 1");
     if (!workspace || ws_bytes < cg_multi_workspace_bytes(g, nrhs, mode))
         return fail(HISQ_EWORKSPACE, "cg_solve_multi: workspace NULL or smaller than hisq_workspace_bytes()");
     if (o.mode != HISQ_CG_PLAIN_F64 && o.mode != HISQ_CG_MIXED_F32 && o.mode != HISQ_CG_MIXED_F32C &&

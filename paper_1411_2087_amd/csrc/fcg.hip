@@ -278,6 +278,21 @@ __global__ __launch_bounds__(F_NT) void k_f_norm(const double2 *__restrict__ b, 
 }
 
 static size_t a256f(size_t v) { return (v + 255) & ~(size_t)255; }
+static_assert(sizeof(FState) <= PIN_SLOT_BYTES, "FState does not fit its pinned slot");
+
+// Byte model of one flexible-CG iteration.  The network on the full lattice
+// (V = 2 Vh sites): per layer the fat links (each matrix serves two sites, so
+// four per site at 72 bytes) and the input and output features (24 bytes per
+// channel); the embedding and extraction of the even vector.  Per even site:
+// two FP64 Dslash link streams and 20 FP64-vector equivalents of streams
+// (r to FP32, z from FP32 with the two dot products, p, the two Dslash
+// sources and outputs, A p, x, r, r_prev).
+static double fcg_iter_bytes(const Geom &g, int C)
+{
+    const double layers = 4 * 4 * 72.0 + 24.0 * ((1 + C) + 2 * (C + C) + (C + 1));
+    const double net = layers * 2 * g.Vh + (24.0 + 2 * 24.0 + 2 * 24.0 + 24.0) * g.Vh;
+    return net + (2 * link_bytes_site(HISQ_F64) + 20 * 48.0) * g.Vh;
+}
 
 size_t fcg_ws_bytes(const Geom &g, int C)
 {
@@ -305,9 +320,8 @@ static int fcg_impl(double mass, double tol, const void *fat, const void *lng, c
     take(v64);
     float2 *r32 = (float2 *)take(v32), *z32 = (float2 *)take(v32);
     void *acts = take(net_act_bytes_g(g, C, 1));
-    FState *hs = nullptr;
-    HISQ_HIP(hipHostMalloc((void **)&hs, sizeof(FState), hipHostMallocDefault));
-    struct Free { FState *h; ~Free() { if (h) hipHostFree(h); } } guard{ hs };
+    FState *hs = (FState *)pinned_slot(PIN_FCG);
+    if (!hs) return fail(HISQ_EHIP, "fcg_solve: pinned state allocation failed");
     const dim3 gb(nbf), gd(xcd_grid(nbd));
     auto t0 = std::chrono::steady_clock::now();
     hipLaunchKernelGGL(k_f_init, dim3(1), dim3(1), 0, s, st, tol * tol, 4.0 * mass * mass, 50);
@@ -387,6 +401,8 @@ static int fcg_impl(double mass, double tol, const void *fat, const void *lng, c
     const int fcg_iters = hs->iter;
     const int fell_back = hs->fallback;
     stats.iters = fcg_iters;
+    stats.iter_resid = std::sqrt(hs->rr / hs->bb);
+    stats.bytes_moved = (fcg_iters * fcg_iter_bytes(g, C) + 2 * (2 * link_bytes_site(HISQ_F64) + 6 * 48.0) * g.Vh);
     stats.fallback_used = 0;
     stats.fallback_iters = 0;
     if (fell_back || !(hs->rr <= hs->stop2)) {
@@ -407,6 +423,8 @@ static int fcg_impl(double mass, double tol, const void *fat, const void *lng, c
             stats.fallback_iters = s2.iters;
             stats.iters = fcg_iters + s2.iters;
             stats.true_resid = s2.true_resid;
+            stats.iter_resid = s2.iter_resid;
+            stats.bytes_moved += s2.bytes_moved;
             stats.status = rc2;
             stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             return rc2;
@@ -429,6 +447,8 @@ static int fcg_impl(double mass, double tol, const void *fat, const void *lng, c
             stats.fallback_iters = s2.iters;
             stats.iters = fcg_iters + s2.iters;
             stats.true_resid = s2.true_resid;
+            stats.iter_resid = s2.iter_resid;
+            stats.bytes_moved += s2.bytes_moved;
             stats.status = rc2;
             stats.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             return rc2;

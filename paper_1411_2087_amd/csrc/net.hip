@@ -9,16 +9,21 @@
 // transformations.  An even-site input is embedded on the full lattice (odd
 // sites zero); the output's even part is the preconditioned vector.
 //
-// Each layer is one kernel per 32-site tile of one parity: the 9*C_in
-// transported fields of the tile are computed in FP32 and written to LDS as
-// BF16 (the real embedding [Re; Im]), then the channel mixing is a real GEMM
-//     [Re out; Im out] (2 C_out x 96) = [[Wr, -Wi], [Wi, Wr]] (2 C_out x 18 C_in)
-//                                       x [Re F; Im F] (18 C_in x 96)
-// on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  The gradient with
-// respect to the input is the same kernel with W'_{k'}^{ba} = conj(W_{k}^{ab}),
-// k' the adjoint transport of k (T_{+mu}^dag = T_{-mu}); the weight gradient
-// G_k^{ab} = sum_x <T_k in^b, g^a> is a split-K MFMA over sites followed by a
-// fixed-order sum of the per-workgroup partials.
+// A layer kernel takes one 64-site tile (one wavefront of sites, the tile of
+// the packed links) of one parity.  The 9 C_in transported fields are taken
+// in slices of 16 (transport, channel) pairs: each thread computes one site's
+// transport of four channels along one direction in FP32 (one link load for
+// the four), the slice goes to LDS as BF16 in the real embedding, and the
+// channel mixing accumulates
+//     [Re out; Im out] (2 C_out x 192) += [[Wr, -Wi], [Wi, Wr]] (2 C_out x 32)
+//                                         x [Re T; Im T] (32 x 192)
+// on v_mfma_f32_16x16x32_bf16 with FP32 accumulation, so the LDS holds one
+// slice (15 KB) and the transports are computed once per site and channel.
+// The gradient with respect to the input is the same kernel with
+// W'_{k'}^{ba} = conj(W_{k}^{ab}), k' the adjoint transport of k
+// (T_{+mu}^dag = T_{-mu}); the weight gradient G_k^{ab} = sum_x <T_k in^b, g^a>
+// reuses the slice transport, with the sites (and Re/Im) as the K dimension,
+// and a fixed-order FP64 sum of the per-workgroup partials.
 //
 // Feature layout: [batch][channel][parity][h][colour] complex64.
 #include <hip/hip_runtime.h>
@@ -32,241 +37,388 @@
 namespace hisq {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int NET_SW = 32;              // sites per workgroup tile (forward)
-constexpr int NET_COLS = 3 * NET_SW;    // GEMM columns per tile
-constexpr int NET_NT = 128;             // two wavefronts
-constexpr int WG_SW = 16;               // sites per unit (weight gradient)
-constexpr int WG_COLS = 3 * WG_SW;
-constexpr int MPAD = 32;                // GEMM rows (2 C_out <= 32)
+constexpr int NET_NT = 256;     // four wavefronts; wave q transports the pairs 4q..4q+3 of a slice
+constexpr int MPAD = 32;        // GEMM rows: Re and Im of up to 16 output channels
+constexpr int SK = 32;          // K of one slice: 16 (transport, channel) pairs, Re parts then Im parts
+constexpr int NCOL = 3 * TILE;  // GEMM columns of a 64-site tile: (site, colour)
 constexpr int WG_MAX_BLOCKS = 1024;
 
-__host__ __device__ constexpr int kpad_of(int cin) { return (18 * cin + 15) / 16 * 16; }
-__host__ __device__ constexpr int npad_of(int cin) { return (9 * cin + 31) / 32 * 32; }
+// The 9 transports of a layer with CIN input channels in slices of 16
+// (transport, channel) pairs: KG transports per slice, pair pi -> transport
+// kg = pi / CIN of the slice, channel pi % CIN.  Pairs past transport 8 are zero.
+template <int CIN> struct Slices {
+    static constexpr int KG = CIN >= 16 ? 1 : 16 / CIN;
+    static constexpr int N = (9 + KG - 1) / KG;
+};
+__host__ __device__ constexpr int slices_of(int cin) { return cin >= 16 ? 9 : (9 + 16 / cin - 1) / (16 / cin); }
+__host__ __device__ constexpr int kg_of(int cin) { return cin >= 16 ? 1 : 16 / cin; }
 constexpr int ADJ[9] = { 0, 5, 6, 7, 8, 1, 2, 3, 4 };
-
-__device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }  // round to nearest even
 
 __device__ __forceinline__ size_t feat_idx(int b, int C, int c, int p, int Vh, int h)
 {
     return ((((size_t)b * C + c) * 2 + p) * Vh + h) * 3;
 }
 
-// (T_k phi^c)(x)_a for all channels c of `in`, for the site h of parity p:
-// calls emit(k, c, re, im).  Rows of the packed fat links: +mu holds
-// U_mu(x), -mu holds -U_mu(x-mu)^dag.
-template <int CIN, class Emit>
-__device__ __forceinline__ void transport_site(const Geom &g, const char *__restrict__ fat,
-                                               const float2 *__restrict__ in, int b, int p, int h, int a, Emit emit)
+// One packed FP32 link (18 floats) with plain loads: the four pair groups of
+// a slice read the same matrix, so it should stay in the caches.
+__device__ __forceinline__ void load_link32(const char *__restrict__ blk, int lane, float m[18])
 {
-    int x, y, z, t;
-    site_coords(g, h, p, x, y, z, t);
-    // k = 0
-#pragma unroll 4
-    for (int c = 0; c < CIN; ++c) {
-        float2 v = in[feat_idx(b, CIN, c, p, g.Vh, h) + a];
-        emit(0, c, v.x, v.y);
+    const float4 *p4 = reinterpret_cast<const float4 *>(blk) + lane;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float4 v = p4[q * TILE];
+        m[4 * q] = v.x; m[4 * q + 1] = v.y; m[4 * q + 2] = v.z; m[4 * q + 3] = v.w;
     }
-    const int tile = h / TILE, lane = h % TILE;
-    const size_t tile_off = ((size_t)p * g.ntiles + tile) * 8 * PF32::block_bytes;
-#pragma unroll 1
-    for (int d = 0; d < 8; ++d) {
-        const int mu = d & 3;
-        const bool bwd = d >= 4;
-        const int nh = nbr_h(g, h, x, y, z, t, mu, bwd ? -1 : 1);
-        float m[18];
-        PF32::load(fat + tile_off + (size_t)d * PF32::block_bytes, lane, m);
-        const float sg = bwd ? -1.0f : 1.0f;  // packed backward link is -U^dag
-        const float m0r = sg * m[6 * a], m0i = sg * m[6 * a + 1], m1r = sg * m[6 * a + 2], m1i = sg * m[6 * a + 3],
-                    m2r = sg * m[6 * a + 4], m2i = sg * m[6 * a + 5];
-#pragma unroll 4
-        for (int c = 0; c < CIN; ++c) {
-            const float2 *s = in + feat_idx(b, CIN, c, 1 - p, g.Vh, nh);
-            const float2 s0 = s[0], s1 = s[1], s2 = s[2];
-            float re = m0r * s0.x - m0i * s0.y;
-            float im = m0r * s0.y + m0i * s0.x;
-            re = fmaf(m1r, s1.x, re); re = fmaf(-m1i, s1.y, re);
-            im = fmaf(m1r, s1.y, im); im = fmaf(m1i, s1.x, im);
-            re = fmaf(m2r, s2.x, re); re = fmaf(-m2i, s2.y, re);
-            im = fmaf(m2r, s2.y, im); im = fmaf(m2i, s2.x, im);
-            emit(1 + d, c, re, im);
+    const float2 v = reinterpret_cast<const float2 *>(blk + 4 * TILE * 16)[lane];
+    m[16] = v.x;
+    m[17] = v.y;
+}
+
+// o = sg M phi for a row-major complex 3x3 M (18 floats) and sg = +-1, as
+// explicit fmaf chains: every kernel that transports gets the same bits.
+__device__ __forceinline__ void matvec32(const float m[18], float sg, float2 s0, float2 s1, float2 s2, float o[6])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float *r = m + 6 * a;
+        float re = r[4] * s2.x;
+        re = fmaf(-r[5], s2.y, re);
+        re = fmaf(r[2], s1.x, re);
+        re = fmaf(-r[3], s1.y, re);
+        re = fmaf(r[0], s0.x, re);
+        re = fmaf(-r[1], s0.y, re);
+        float im = r[4] * s2.y;
+        im = fmaf(r[5], s2.x, im);
+        im = fmaf(r[2], s1.y, im);
+        im = fmaf(r[3], s1.x, im);
+        im = fmaf(r[0], s0.y, im);
+        im = fmaf(r[1], s0.x, im);
+        o[2 * a] = sg * re;
+        o[2 * a + 1] = sg * im;
+    }
+}
+
+// The four (transport, channel) pairs 4q..4q+3 of slice j at site h of
+// parity p (lane `lane` of `tile`): tv[i] = (T_k phi^c)(x) for pair 4q + i,
+// colours (re, im) x 3; zero for padding pairs and sites past Vh.
+// T_0 = 1; T_{1+d}: packed direction d (0..3 = +x..+t holds F_mu(x), 4..7 =
+// -x..-t holds -F_mu(x-mu)^dag) times the neighbour one hop along d.
+// in: the channels of one batch entry, [c][parity][Vh][3].
+template <int CIN>
+__device__ __forceinline__ void slice_transport(const Geom &g, const char *__restrict__ fat,
+                                                const float2 *__restrict__ in, int p, int tile, int lane, int j,
+                                                int q, float tv[4][6])
+{
+    constexpr int KG = Slices<CIN>::KG;
+    const int h = tile * TILE + lane;
+    const bool valid = h < g.Vh;
+    const int hc = valid ? h : g.Vh - 1;
+    int x, y, z, t;
+    site_coords(g, hc, p, x, y, z, t);
+    const size_t ch_stride = (size_t)2 * g.Vh * 3;
+    const char *tb = fat + ((size_t)p * g.ntiles + tile) * 8 * PF32::block_bytes;
+    if constexpr (CIN >= 4) {
+        // the four pairs share one transport
+        const int k = j * KG + (4 * q) / CIN, c0 = (4 * q) % CIN;
+        if (k == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float2 *v = in + (c0 + i) * ch_stride + (size_t)p * g.Vh * 3 + (size_t)hc * 3;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float2 e = v[a];
+                    tv[i][2 * a] = e.x;
+                    tv[i][2 * a + 1] = e.y;
+                }
+            }
+        } else if (k < 9) {
+            const int d = k - 1;
+            const int nh = nbr_h(g, hc, x, y, z, t, d & 3, d >= 4 ? -1 : 1);
+            float m[18];
+            load_link32(tb + (size_t)d * PF32::block_bytes, lane, m);
+            const float sg = d >= 4 ? -1.0f : 1.0f;  // packed backward link is -F^dag
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float2 *v = in + (c0 + i) * ch_stride + (size_t)(1 - p) * g.Vh * 3 + (size_t)nh * 3;
+                matvec32(m, sg, v[0], v[1], v[2], tv[i]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int e = 0; e < 6; ++e) tv[i][e] = 0.f;
         }
+    } else {
+        // CIN == 1: one slice holds every transport; pair i of group q is transport 4q + i
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * q + i;
+            if (k == 0) {
+                const float2 *v = in + (size_t)p * g.Vh * 3 + (size_t)hc * 3;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float2 e = v[a];
+                    tv[i][2 * a] = e.x;
+                    tv[i][2 * a + 1] = e.y;
+                }
+            } else if (k < 9) {
+                const int d = k - 1;
+                const int nh = nbr_h(g, hc, x, y, z, t, d & 3, d >= 4 ? -1 : 1);
+                float m[18];
+                load_link32(tb + (size_t)d * PF32::block_bytes, lane, m);
+                const float2 *v = in + (size_t)(1 - p) * g.Vh * 3 + (size_t)nh * 3;
+                matvec32(m, d >= 4 ? -1.0f : 1.0f, v[0], v[1], v[2], tv[i]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 6; ++e) tv[i][e] = 0.f;
+            }
+        }
+    }
+    if (!valid) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 6; ++e) tv[i][e] = 0.f;
     }
 }
 
 // ------------------------------------------------------------------ weights -> BF16 GEMM operand
-// A[m][kk] (MPAD x kpad) for out = sum_k W_k T_k in.  transposed_adjoint:
-// the matrix of the input-gradient layer (C_in' = COUT, C_out' = CIN).
+// A[j][m][kk] (slices x 32 x 32) for out = sum_k W_k T_k in: row m < COUT'
+// is Re out^m, row COUT' + a is Im out^a; column kk < 16 takes the real
+// part of pair kk of slice j, kk >= 16 the imaginary part of pair kk - 16;
+// the real embedding [[Wr, -Wi], [Wi, Wr]].  adjoint: the matrix of the
+// input-gradient layer (C_in' = COUT, C_out' = CIN, W'_k^{ac} =
+// conj(W_{adj k}^{ca}), T_{+mu}^dag = T_{-mu}).
 template <int CIN, int COUT>
 __global__ void k_net_prep(const float2 *__restrict__ W, __bf16 *__restrict__ A, int adjoint)
 {
-    // the GEMM layer has (ci, co) = (CIN, COUT), or (COUT, CIN) for the adjoint
     const int ci = adjoint ? COUT : CIN, co = adjoint ? CIN : COUT;
-    const int kp = kpad_of(ci);
-    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < MPAD * kp; i += blockDim.x * gridDim.x) {
-        const int m = i / kp, kk = i % kp;
+    const int ns = slices_of(ci), kgs = kg_of(ci);
+    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < ns * MPAD * SK; i += blockDim.x * gridDim.x) {
+        const int j = i / (MPAD * SK), m = (i / SK) % MPAD, kk = i % SK;
+        const int pi = kk % 16;
+        const bool im_col = kk >= 16, im_row = m >= co;
+        const int k = j * kgs + pi / ci, c = pi % ci;
         float v = 0.f;
-        if (m < 2 * co && kk < 18 * ci) {
-            const bool im_row = m >= co, im_col = kk >= 9 * ci;
-            const int a = im_row ? m - co : m;   // output channel of the GEMM layer
-            const int q = im_col ? kk - 9 * ci : kk;
-            const int k = q / ci, c = q % ci;   // transport, input channel of the GEMM layer
+        if (m < 2 * co && k < 9) {
+            const int a = im_row ? m - co : m;
             float2 w;
             if (!adjoint) {
                 w = W[((size_t)k * COUT + a) * CIN + c];
-            } else {  // W'_{k}^{a c} = conj(W_{adj k}^{c a})
-                float2 u = W[((size_t)ADJ[k] * COUT + c) * CIN + a];
+            } else {
+                const float2 u = W[((size_t)ADJ[k] * COUT + c) * CIN + a];
                 w = make_float2(u.x, -u.y);
             }
-            // [[Wr, -Wi], [Wi, Wr]]
             v = !im_row ? (!im_col ? w.x : -w.y) : (!im_col ? w.y : w.x);
         }
-        A[i] = to_bf16(v);
+        A[i] = (__bf16)v;
     }
 }
 
 // ------------------------------------------------------------------ layer (forward and input gradient)
+// One 64-site tile of parity blockIdx.y, batch entry blockIdx.z.  Per slice:
+// the tile's 16 x 192 transported values go to LDS as BF16 (B[column][K]),
+// then the four waves run v_mfma_f32_16x16x32_bf16 on 16-column tiles
+// 3q..3q+2 for every 16-row tile of the output (FP32 accumulation).
 template <int CIN, int COUT>
 __global__ __launch_bounds__(NET_NT) void k_net_layer(Geom g, const char *__restrict__ fat,
                                                       const float2 *__restrict__ in, float2 *__restrict__ out,
                                                       const __bf16 *__restrict__ A)
 {
-    constexpr int KP = kpad_of(CIN);
-    constexpr int PITCH = KP + 8;  // bf16 per LDS row (padding spreads the banks)
-    __shared__ __align__(16) __bf16 F[NET_COLS * PITCH];
-    const int p = blockIdx.y, b = blockIdx.z;
-    const int h0 = blockIdx.x * NET_SW;
-    // phase 1: transported fields of the tile -> F[col][kk] (BF16), col = site*3 + colour
-    if (threadIdx.x < NET_COLS) {
-        const int col = threadIdx.x, s = col / 3, a = col % 3, h = h0 + s;
-        __bf16 *row = F + col * PITCH;
-        if (h < g.Vh) {
-            transport_site<CIN>(g, fat, in, b, p, h, a, [&](int k, int c, float re, float im) {
-                row[k * CIN + c] = to_bf16(re);
-                row[9 * CIN + k * CIN + c] = to_bf16(im);
-            });
-        } else {
-            for (int q = 0; q < 18 * CIN; ++q) row[q] = to_bf16(0.f);
+    using S = Slices<CIN>;
+    constexpr int MT = (2 * COUT + 15) / 16;  // 16-row tiles of the output
+    constexpr int PB = SK + 8;                // LDS pitch of a column (bf16)
+    __shared__ __align__(16) __bf16 F[NCOL * PB];
+    const int tile = blockIdx.x, p = blockIdx.y, b = blockIdx.z;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
+    floatx4 acc[3][MT];
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[n][mt] = floatx4{ 0.f, 0.f, 0.f, 0.f };
+    const int r16 = lane & 15, k8 = 8 * (lane >> 4);
+#pragma unroll 1
+    for (int j = 0; j < S::N; ++j) {
+        float tv[4][6];
+        slice_transport<CIN>(g, fat, inb, p, tile, lane, j, q, tv);
+        if (j) __syncthreads();  // the previous slice's operands have been read
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            __bf16 *col = F + (3 * lane + a) * PB;
+            const bf16x4 re = { (__bf16)tv[0][2 * a], (__bf16)tv[1][2 * a], (__bf16)tv[2][2 * a], (__bf16)tv[3][2 * a] };
+            const bf16x4 im = { (__bf16)tv[0][2 * a + 1], (__bf16)tv[1][2 * a + 1], (__bf16)tv[2][2 * a + 1],
+                                (__bf16)tv[3][2 * a + 1] };
+            *reinterpret_cast<bf16x4 *>(col + 4 * q) = re;
+            *reinterpret_cast<bf16x4 *>(col + 16 + 4 * q) = im;
         }
-        for (int q = 18 * CIN; q < KP; ++q) row[q] = to_bf16(0.f);
+        __syncthreads();
+        bf16x8 av[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            av[mt] = *reinterpret_cast<const bf16x8 *>(A + ((size_t)j * MPAD + mt * 16 + r16) * SK + k8);
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(F + ((3 * q + n) * 16 + r16) * PB + k8);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[n][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[n][mt], 0, 0, 0);
+        }
     }
-    __syncthreads();
-    // phase 2: MFMA, wave w takes column tiles w, w + 2
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    for (int j = w; j < NET_COLS / 32; j += 2) {
-        floatx16 acc = {};
+    // D[row][col]: lane holds column r16 of its tile and rows 4 (lane >> 4) + 0..3
+    float *o = reinterpret_cast<float *>(out);
 #pragma unroll
-        for (int kb = 0; kb < KP / 16; ++kb) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(A + (l % 32) * KP + kb * 16 + 8 * (l / 32));
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(F + (j * 32 + l % 32) * PITCH + kb * 16 + 8 * (l / 32));
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-        }
-        const int col = j * 32 + l % 32, s = col / 3, a = col % 3, h = h0 + s;
-        if (h < g.Vh) {
-            float *o = reinterpret_cast<float *>(out);
+    for (int n = 0; n < 3; ++n) {
+        const int col = (3 * q + n) * 16 + r16, s = col / 3, a = col % 3, h = tile * TILE + s;
+        if (h >= g.Vh) continue;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int m = 8 * (r / 4) + 4 * (l / 32) + (r % 4);
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = mt * 16 + 4 * (lane >> 4) + i;
                 if (m < 2 * COUT) {
                     const int ch = m < COUT ? m : m - COUT;
-                    o[2 * (feat_idx(b, COUT, ch, p, g.Vh, h) + a) + (m < COUT ? 0 : 1)] = acc[r];
+                    o[2 * (feat_idx(b, COUT, ch, p, g.Vh, h) + a) + (m < COUT ? 0 : 1)] = acc[n][mt][i];
                 }
             }
+    }
+}
+
+// ------------------------------------------------------------------ transports (inspection of the operands)
+// out[b][k][c][parity][Vh][3] = (T_k in^c) for k = 0..8, the FP32 values the
+// layer kernels round to BF16 (same device function, same bits).
+template <int CIN>
+__global__ __launch_bounds__(NET_NT) void k_net_transport(Geom g, const char *__restrict__ fat,
+                                                          const float2 *__restrict__ in, float2 *__restrict__ out)
+{
+    using S = Slices<CIN>;
+    const int tile = blockIdx.x, p = blockIdx.y, b = blockIdx.z;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int h = tile * TILE + lane;
+    const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
+    for (int j = 0; j < S::N; ++j) {
+        float tv[4][6];
+        slice_transport<CIN>(g, fat, inb, p, tile, lane, j, q, tv);
+        if (h >= g.Vh) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int pi = 4 * q + i, k = j * S::KG + pi / CIN, c = pi % CIN;
+            if (k >= 9) continue;
+            float2 *dst = out + feat_idx(b * 9 + k, CIN, c, p, g.Vh, h);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) dst[a] = make_float2(tv[i][2 * a], tv[i][2 * a + 1]);
         }
     }
 }
 
-// ------------------------------------------------------------------ weight gradient (split-K over sites)
-// partials[block][MPAD][NP] (float): rows m < COUT -> Re G, COUT <= m < 2COUT -> Im G; column q = k*CIN + c.
+// ------------------------------------------------------------------ weight gradient
+// G_k^{ac} = sum_x <T_k in^c, g^a>: per 64-site tile the real GEMM
+//   [Re G; Im G] (2 COUT x 16 pairs) += [[gr, gi], [gi, -gr]] (2 COUT x 384) x [Re T; Im T] (384 x 16)
+// with K = (column, re/im) interleaved.  g goes to LDS once per tile, each
+// slice's transports once per slice; wave q takes the 16-row tile q % MT and
+// a quarter (MT = 1) or half (MT = 2) of the 12 K steps, and keeps that
+// tile's accumulators of every slice.  Blocks stride over (batch, parity, tile)
+// units; the four waves are summed in a fixed order at the end and each block
+// writes its partial [slice][row][pair] (FP32), summed in FP64 by
+// k_net_wgrad_reduce.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(NET_NT) void k_net_wgrad(Geom g, const char *__restrict__ fat,
                                                       const float2 *__restrict__ in, const float2 *__restrict__ gout,
                                                       int batch, float *__restrict__ partials)
 {
-    constexpr int NP = npad_of(CIN);
-    constexpr int FP = 2 * WG_COLS + 8;      // F2 row pitch (bf16)
-    constexpr int GP = 2 * WG_COLS + 8;      // G row pitch
-    constexpr int NTILES = NP / 32;
-    __shared__ __align__(16) __bf16 F2[NP * FP];
-    __shared__ __align__(16) __bf16 G2[MPAD * GP];
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    floatx16 acc[(NTILES + 1) / 2];
+    using S = Slices<CIN>;
+    constexpr int MT = (2 * COUT + 15) / 16;
+    constexpr int KT = 2 * NCOL;  // K per tile
+    constexpr int PK = KT + 8;    // LDS pitch (bf16)
+    constexpr int PART = S::N * MT * 256;
+    __shared__ __align__(16) __bf16 lds[(16 + MT * 16) * PK];
+    __bf16 *Fb = lds;            // B: [pair][K]
+    __bf16 *Ga = lds + 16 * PK;  // A: [row][K]
+    static_assert(PART * 4 <= (16 + MT * 16) * PK * 2, "partial reduction does not fit the LDS operands");
+    constexpr int KSW = 3 * MT;  // K steps of a wave
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int r16 = lane & 15, k8 = 8 * (lane >> 4);
+    const int wmt = q % MT, ks0 = (q / MT) * KSW;
+    floatx4 acc[S::N];
 #pragma unroll
-    for (int i = 0; i < (NTILES + 1) / 2; ++i) acc[i] = floatx16{};
-    const int tiles_per_par = (g.Vh + WG_SW - 1) / WG_SW;
-    const int nunits = batch * 2 * tiles_per_par;
-    for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
-        const int b = u / (2 * tiles_per_par), rem = u % (2 * tiles_per_par);
-        const int p = rem / tiles_per_par, h0 = (rem % tiles_per_par) * WG_SW;
-        __syncthreads();  // previous unit's LDS reads are done
-        // zero the padding rows of F2 and all of G2's unused rows
-        for (int i = threadIdx.x; i < (NP - 9 * CIN) * FP; i += NET_NT) F2[9 * CIN * FP + i] = to_bf16(0.f);
-        if (threadIdx.x < WG_COLS) {
-            const int col = threadIdx.x, s = col / 3, a = col % 3, h = h0 + s;
-            if (h < g.Vh) {
-                transport_site<CIN>(g, fat, in, b, p, h, a, [&](int k, int c, float re, float im) {
-                    F2[(k * CIN + c) * FP + col] = to_bf16(re);
-                    F2[(k * CIN + c) * FP + WG_COLS + col] = to_bf16(im);
-                });
-            } else {
-                for (int q = 0; q < 9 * CIN; ++q) {
-                    F2[q * FP + col] = to_bf16(0.f);
-                    F2[q * FP + WG_COLS + col] = to_bf16(0.f);
-                }
+    for (int j = 0; j < S::N; ++j) acc[j] = floatx4{ 0.f, 0.f, 0.f, 0.f };
+    // rows 2 COUT .. 16 MT - 1 of the g operand stay zero
+    for (int i = threadIdx.x; i < (MT * 16 - 2 * COUT) * PK; i += NET_NT) Ga[2 * COUT * PK + i] = (__bf16)0.f;
+    const int units = batch * 2 * g.ntiles;
+#pragma unroll 1
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int b = u / (2 * g.ntiles), p = (u / g.ntiles) % 2, tile = u % g.ntiles;
+        const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
+        __syncthreads();  // the previous unit's operands have been read
+        for (int i = threadIdx.x; i < COUT * NCOL; i += NET_NT) {
+            const int a = i / NCOL, jc = i % NCOL, h = tile * TILE + jc / 3;
+            float2 v = make_float2(0.f, 0.f);
+            if (h < g.Vh) v = gout[feat_idx(b, COUT, a, p, g.Vh, h) + jc % 3];
+            *reinterpret_cast<bf16x2 *>(Ga + a * PK + 2 * jc) = bf16x2{ (__bf16)v.x, (__bf16)v.y };
+            *reinterpret_cast<bf16x2 *>(Ga + (COUT + a) * PK + 2 * jc) = bf16x2{ (__bf16)v.y, (__bf16)(-v.x) };
+        }
+        // unrolled: acc[j] must stay in registers
+#pragma unroll
+        for (int j = 0; j < S::N; ++j) {
+            float tv[4][6];
+            slice_transport<CIN>(g, fat, inb, p, tile, lane, j, q, tv);
+            if (j) __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                __bf16 *row = Fb + (4 * q + i) * PK + 6 * lane;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    *reinterpret_cast<bf16x2 *>(row + 2 * a) = bf16x2{ (__bf16)tv[i][2 * a], (__bf16)tv[i][2 * a + 1] };
             }
-            // G2 rows: [gr, gi] (Re G) and [gi, -gr] (Im G)
-            for (int m = 0; m < MPAD; ++m) {
-                float v1 = 0.f, v2 = 0.f;
-                if (m < 2 * COUT && h < g.Vh) {
-                    const int ch = m < COUT ? m : m - COUT;
-                    const float2 gv = gout[feat_idx(b, COUT, ch, p, g.Vh, h) + a];
-                    if (m < COUT) { v1 = gv.x; v2 = gv.y; } else { v1 = gv.y; v2 = -gv.x; }
-                }
-                G2[m * GP + col] = to_bf16(v1);
-                G2[m * GP + WG_COLS + col] = to_bf16(v2);
+            __syncthreads();
+#pragma unroll
+            for (int ks = ks0; ks < ks0 + KSW; ++ks) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Fb + r16 * PK + SK * ks + k8);
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Ga + (wmt * 16 + r16) * PK + SK * ks + k8);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
             }
+        }
+    }
+    // the waves' accumulators of each row tile, summed in wave order through LDS
+    float *red = reinterpret_cast<float *>(lds);
+    __syncthreads();
+#pragma unroll 1
+    for (int w = 0; w < 4; ++w) {
+        if (q == w) {
+#pragma unroll
+            for (int j = 0; j < S::N; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int idx = ((j * MT + wmt) * 16 + 4 * (lane >> 4) + i) * 16 + r16;
+                    red[idx] = (w < MT ? 0.f : red[idx]) + acc[j][i];
+                }
         }
         __syncthreads();
-#pragma unroll
-        for (int i = 0; i < (NTILES + 1) / 2; ++i) {
-            const int j = w + 2 * i;
-            if (j >= NTILES) break;
-#pragma unroll
-            for (int kb = 0; kb < 2 * WG_COLS / 16; ++kb) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(G2 + (l % 32) * GP + kb * 16 + 8 * (l / 32));
-                const bf16x8 bv =
-                    *reinterpret_cast<const bf16x8 *>(F2 + (j * 32 + l % 32) * FP + kb * 16 + 8 * (l / 32));
-                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[i], 0, 0, 0);
-            }
-        }
     }
-    float *dst = partials + (size_t)blockIdx.x * MPAD * NP;
-#pragma unroll
-    for (int i = 0; i < (NTILES + 1) / 2; ++i) {
-        const int j = w + 2 * i;
-        if (j >= NTILES) break;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int m = 8 * (r / 4) + 4 * (l / 32) + (r % 4);
-            dst[m * NP + j * 32 + l % 32] = acc[i][r];
-        }
-    }
+    float *dst = partials + (size_t)blockIdx.x * PART;
+    for (int i = threadIdx.x; i < PART; i += NET_NT) dst[i] = red[i];
 }
 
-// grad_w[k][a][c] = sum over blocks, fixed order
+// grad_w[k][a][c] = sum over blocks (FP64, fixed order) of the partial at
+// slice k / KG, rows a (Re) and COUT + a (Im), pair (k % KG) CIN + c
 template <int CIN, int COUT>
 __global__ void k_net_wgrad_reduce(const float *__restrict__ partials, int nblocks, float2 *__restrict__ gw)
 {
-    constexpr int NP = npad_of(CIN);
+    using S = Slices<CIN>;
+    constexpr int MT = (2 * COUT + 15) / 16;
+    constexpr int PART = S::N * MT * 256;
     const int n = 9 * COUT * CIN;
     for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) {
         const int k = i / (COUT * CIN), a = (i / CIN) % COUT, c = i % CIN;
-        const int q = k * CIN + c;
+        const int j = k / S::KG, pi = (k % S::KG) * CIN + c;
+        const int ore = (j * MT * 16 + a) * 16 + pi, oim = (j * MT * 16 + COUT + a) * 16 + pi;
         double re = 0.0, im = 0.0;
         for (int bl = 0; bl < nblocks; ++bl) {
-            re += partials[((size_t)bl * MPAD + a) * NP + q];
-            im += partials[((size_t)bl * MPAD + COUT + a) * NP + q];
+            re += partials[(size_t)bl * PART + ore];
+            im += partials[(size_t)bl * PART + oim];
         }
         gw[i] = make_float2((float)re, (float)im);
     }
@@ -381,7 +533,7 @@ static size_t w_off(int C, int layer)
 
 static size_t feat_bytes(const Geom &g, int batch, int C) { return (size_t)batch * C * 2 * g.Vh * 3 * 8; }
 static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
-constexpr size_t ABF_SLOT = (size_t)MPAD * 288 * 2;  // one layer's BF16 operand (C <= 16)
+constexpr size_t ABF_SLOT = (size_t)9 * MPAD * SK * 2;  // one layer's BF16 operand: up to 9 slices
 
 size_t net_act_bytes_g(const Geom &g, int C, int batch)
 {
@@ -409,7 +561,7 @@ template <int CIN, int COUT>
 static void layer_launch(const Geom &g, const void *fat, const float2 *in, float2 *out, const __bf16 *A, int batch,
                          hipStream_t s)
 {
-    const dim3 grid((g.Vh + NET_SW - 1) / NET_SW, 2, batch);
+    const dim3 grid(g.ntiles, 2, batch);
     hipLaunchKernelGGL((k_net_layer<CIN, COUT>), grid, dim3(NET_NT), 0, s, g, (const char *)fat, in, out, A);
 }
 
@@ -440,19 +592,47 @@ static int net_forward_t(const Geom &g, const void *fat, const float2 *W, const 
     return HISQ_OK;
 }
 
-static int wgrad_blocks() { return 512; }
+constexpr size_t WG_PART_FLOATS = (size_t)9 * 2 * 256;  // the largest per-block partial (9 slices, 32 rows)
+
+static int wgrad_blocks(const Geom &g, int batch)
+{
+    return (int)std::min<long long>((long long)batch * 2 * g.ntiles, WG_MAX_BLOCKS);
+}
+
+// Backward workspace: dl/d in4, dl/d in3, dl/d in2 (C channels each), dl/d out
+// (the embedded gradient) and dl/d in1 (one channel each), every block at a
+// multiple of 256 bytes; then the weight-gradient partials and the four BF16
+// operands of the adjoint layers.
+struct NetGrads {
+    float2 *gin[4];  // gin[l] = dl/d (input of layer l + 1)
+    float2 *gout;    // dl/d (output of layer 4), full lattice
+    float *part;
+    __bf16 *A[4];
+};
+
+static NetGrads net_grads(void *ws, const Geom &g, int C, int batch)
+{
+    NetGrads r;
+    char *p = (char *)ws;
+    for (int l = 3; l >= 1; --l) { r.gin[l] = (float2 *)p; p += a256(feat_bytes(g, batch, C)); }
+    r.gout = (float2 *)p; p += a256(feat_bytes(g, batch, 1));
+    r.gin[0] = (float2 *)p; p += a256(feat_bytes(g, batch, 1));
+    r.part = (float *)p; p += a256((size_t)WG_MAX_BLOCKS * WG_PART_FLOATS * sizeof(float));
+    for (int i = 0; i < 4; ++i) { r.A[i] = (__bf16 *)p; p += a256(ABF_SLOT); }
+    return r;
+}
 
 size_t net_bwd_ws_bytes_g(const Geom &g, int C, int batch)
 {
-    return 2 * a256(feat_bytes(g, batch, C)) + a256(feat_bytes(g, batch, 1)) +
-           a256((size_t)wgrad_blocks() * MPAD * 160 * sizeof(float)) + 4 * a256(ABF_SLOT);
+    return 3 * a256(feat_bytes(g, batch, C)) + 2 * a256(feat_bytes(g, batch, 1)) +
+           a256((size_t)WG_MAX_BLOCKS * WG_PART_FLOATS * sizeof(float)) + 4 * a256(ABF_SLOT);
 }
 
 template <int CIN, int COUT>
 static void wgrad_launch(const Geom &g, const void *fat, const float2 *in, const float2 *gout, int batch, float *part,
                          float2 *gw, hipStream_t s)
 {
-    const int nb = wgrad_blocks();
+    const int nb = wgrad_blocks(g, batch);
     hipLaunchKernelGGL((k_net_wgrad<CIN, COUT>), dim3(nb), dim3(NET_NT), 0, s, g, (const char *)fat, in, gout, batch,
                        part);
     hipLaunchKernelGGL((k_net_wgrad_reduce<CIN, COUT>), dim3(16), dim3(256), 0, s, (const float *)part, nb, gw);
@@ -463,32 +643,25 @@ static int net_backward_t(const Geom &g, const void *fat, const float2 *W, const
                           float2 *gw, float2 *gin_even, int batch, void *ws, hipStream_t s)
 {
     NetActs a = net_acts(const_cast<void *>(acts), g, C, batch);
-    char *p = (char *)ws;
-    float2 *g1 = (float2 *)p; p += a256(feat_bytes(g, batch, C));
-    float2 *g2 = (float2 *)p; p += a256(feat_bytes(g, batch, C));
-    float2 *gl = (float2 *)p; p += a256(feat_bytes(g, batch, 1));
-    float *part = (float *)p; p += a256((size_t)wgrad_blocks() * MPAD * 160 * sizeof(float));
-    __bf16 *Ab[4];
-    for (int i = 0; i < 4; ++i) { Ab[i] = (__bf16 *)p; p += a256(ABF_SLOT); }
+    NetGrads d = net_grads(ws, g, C, batch);
     const long long ne = (long long)batch * 2 * g.Vh * 3;
     const int nb = (int)std::min<long long>((ne + 255) / 256, 4096);
     // gradient of the last layer's output: even part given, odd part zero
-    hipLaunchKernelGGL(k_net_embed, dim3(nb), dim3(256), 0, s, gout_even, gl, batch, g.Vh);
-    prep_launch<C, 1>(W + w_off(C, 3), Ab[3], 1, s);
-    prep_launch<C, C>(W + w_off(C, 2), Ab[2], 1, s);
-    prep_launch<C, C>(W + w_off(C, 1), Ab[1], 1, s);
-    prep_launch<1, C>(W + w_off(C, 0), Ab[0], 1, s);
-    // layer 4: C -> 1
-    wgrad_launch<C, 1>(g, fat, a.in[3], gl, batch, part, gw + w_off(C, 3), s);
-    layer_launch<1, C>(g, fat, gl, g1, Ab[3], batch, s);       // dl/d in4 (adjoint layer: 1 -> C)
-    wgrad_launch<C, C>(g, fat, a.in[2], g1, batch, part, gw + w_off(C, 2), s);
-    layer_launch<C, C>(g, fat, g1, g2, Ab[2], batch, s);       // dl/d in3
-    wgrad_launch<C, C>(g, fat, a.in[1], g2, batch, part, gw + w_off(C, 1), s);
-    layer_launch<C, C>(g, fat, g2, g1, Ab[1], batch, s);       // dl/d in2
-    wgrad_launch<1, C>(g, fat, a.in[0], g1, batch, part, gw + w_off(C, 0), s);
+    hipLaunchKernelGGL(k_net_embed, dim3(nb), dim3(256), 0, s, gout_even, d.gout, batch, g.Vh);
+    prep_launch<C, 1>(W + w_off(C, 3), d.A[3], 1, s);
+    prep_launch<C, C>(W + w_off(C, 2), d.A[2], 1, s);
+    prep_launch<C, C>(W + w_off(C, 1), d.A[1], 1, s);
+    prep_launch<1, C>(W + w_off(C, 0), d.A[0], 1, s);
+    wgrad_launch<C, 1>(g, fat, a.in[3], d.gout, batch, d.part, gw + w_off(C, 3), s);
+    layer_launch<1, C>(g, fat, d.gout, d.gin[3], d.A[3], batch, s);   // dl/d in4 (adjoint layer: 1 -> C)
+    wgrad_launch<C, C>(g, fat, a.in[2], d.gin[3], batch, d.part, gw + w_off(C, 2), s);
+    layer_launch<C, C>(g, fat, d.gin[3], d.gin[2], d.A[2], batch, s);  // dl/d in3
+    wgrad_launch<C, C>(g, fat, a.in[1], d.gin[2], batch, d.part, gw + w_off(C, 1), s);
+    layer_launch<C, C>(g, fat, d.gin[2], d.gin[1], d.A[1], batch, s);  // dl/d in2
+    wgrad_launch<1, C>(g, fat, a.in[0], d.gin[1], batch, d.part, gw + w_off(C, 0), s);
     if (gin_even) {
-        layer_launch<C, 1>(g, fat, g1, gl, Ab[0], batch, s);   // dl/d in1 (C -> 1)
-        hipLaunchKernelGGL(k_net_extract, dim3(nb), dim3(256), 0, s, (const float2 *)gl, gin_even, batch, g.Vh);
+        layer_launch<C, 1>(g, fat, d.gin[1], d.gin[0], d.A[0], batch, s);  // dl/d in1 (C -> 1)
+        hipLaunchKernelGGL(k_net_extract, dim3(nb), dim3(256), 0, s, (const float2 *)d.gin[0], gin_even, batch, g.Vh);
     }
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
@@ -556,6 +729,28 @@ extern "C" int net_backward(const void *fat, const void *weights, int channels, 
     case 8: return net_backward_t<8>(g, fat, (const float2 *)weights, acts, (const float2 *)grad_out, (float2 *)grad_w, (float2 *)grad_in, batch, workspace, s);
     default: return net_backward_t<16>(g, fat, (const float2 *)weights, acts, (const float2 *)grad_out, (float2 *)grad_w, (float2 *)grad_in, batch, workspace, s);
     }
+}
+
+extern "C" int net_transport(const void *fat, const void *in, void *out, int channels, int batch, const int dims[4],
+                             void *stream)
+{
+    Geom g;
+    int rc = make_geom(dims, g);
+    if (rc) return rc;
+    if (channels != 1 && !net_channels_ok(channels)) return fail(HISQ_EINVAL, "net_transport: channels must be 1, 4, 8 or 16");
+    if (batch < 1) return fail(HISQ_EINVAL, "net_transport: batch must be >= 1");
+    if (!fat || !in || !out) return fail(HISQ_EINVAL, "net_transport: NULL pointer");
+    if (in == out) return fail(HISQ_EALIAS, "net_transport: in and out alias");
+    const dim3 grid(g.ntiles, 2, batch);
+    hipStream_t s = (hipStream_t)stream;
+    switch (channels) {
+    case 1: hipLaunchKernelGGL((k_net_transport<1>), grid, dim3(NET_NT), 0, s, g, (const char *)fat, (const float2 *)in, (float2 *)out); break;
+    case 4: hipLaunchKernelGGL((k_net_transport<4>), grid, dim3(NET_NT), 0, s, g, (const char *)fat, (const float2 *)in, (float2 *)out); break;
+    case 8: hipLaunchKernelGGL((k_net_transport<8>), grid, dim3(NET_NT), 0, s, g, (const char *)fat, (const float2 *)in, (float2 *)out); break;
+    default: hipLaunchKernelGGL((k_net_transport<16>), grid, dim3(NET_NT), 0, s, g, (const char *)fat, (const float2 *)in, (float2 *)out);
+    }
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
 }
 
 extern "C" int net_loss(const void *y, const void *x, int batch, const int dims[4], double *loss_host, void *grad_y,

@@ -1,5 +1,6 @@
 // Autotuner: times the launch shapes of a kernel on the caller's buffers and
-// remembers the fastest per (kernel, lattice, precision, batch).  Choices live
+// remembers the fastest per (GPU architecture, kernel, lattice, precision,
+// batch).  Choices live
 // in a process-wide table; when HISQ_TUNE_CACHE names a file they are also
 // loaded from and saved to it (a flat JSON object of integers).
 #include <hip/hip_runtime.h>
@@ -19,10 +20,24 @@ static std::mutex g_mu;
 static std::map<std::string, int> g_table;
 static bool g_loaded = false;
 
+// Architecture of the current device (e.g. "gfx950"), part of every key, so
+// that a cache file written on one GPU model is not applied to another.
+static std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');  // drop feature suffixes such as ":sramecc+:xnack-"
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
 static std::string key_of(const char *kind, const Geom &g, int prec, int n)
 {
-    char buf[128];
-    std::snprintf(buf, sizeof buf, "%s:p%d:n%d:%dx%dx%dx%d", kind, prec, n, g.L[0], g.L[1], g.L[2], g.L[3]);
+    static const std::string arch = device_arch();
+    char buf[192];
+    std::snprintf(buf, sizeof buf, "%s:%s:p%d:n%d:%dx%dx%dx%d", arch.c_str(), kind, prec, n, g.L[0], g.L[1], g.L[2],
+                  g.L[3]);
     return buf;
 }
 

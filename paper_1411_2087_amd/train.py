@@ -14,7 +14,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (HISQ_F32, HISQ_F64, HISQ_MULTI_RHS, CGOpts, cg_solve_multi, hisq_apply_A, hisq_dot, net_act_bytes,
+from . import (HISQ_F32, HISQ_F64, HISQ_MULTI_RHS, CGOpts, cg_solve_multi, hisq_apply_A, hisq_dot,
+               hisq_workspace_bytes, net_act_bytes,
                net_adam_step, net_backward, net_backward_ws_bytes, net_forward, net_loss, net_weight_count)
 from .fields import Links, workspace
 
@@ -168,11 +169,16 @@ class Trainer:
         return float(np.sum(losses) / b.shape[0])
 
 
+def _dot_workspace(like):
+    return torch.empty(hisq_workspace_bytes("dot", (4, 4, 4, 4)), dtype=torch.uint8, device=like.device)
+
+
 def least_squares_scale(b, x):
     """The scalar s minimising sum |s b - x|^2 (starting point of K = s 1 for the error objective)."""
     n = b.shape[1] * 3
-    num = sum(hisq_dot(b[i], x[i], n, HISQ_F32).real for i in range(b.shape[0]))
-    den = sum(hisq_dot(b[i], b[i], n, HISQ_F32).real for i in range(b.shape[0]))
+    ws = _dot_workspace(b)
+    num = sum(hisq_dot(b[i], x[i], n, HISQ_F32, ws).real for i in range(b.shape[0]))
+    den = sum(hisq_dot(b[i], b[i], n, HISQ_F32, ws).real for i in range(b.shape[0]))
     return num / den
 
 
@@ -181,9 +187,10 @@ def residual_scale(b, links32: Links, mass, dims):
     n = b.shape[1] * 3
     ab = torch.empty_like(b[0])
     tmp = torch.empty_like(b[0])
+    ws = _dot_workspace(b)
     num = den = 0.0
     for i in range(b.shape[0]):
         hisq_apply_A(mass, links32.fat, links32.lng, b[i].contiguous(), ab, tmp, dims, HISQ_F32)
-        num += hisq_dot(ab, b[i].contiguous(), n, HISQ_F32).real
-        den += hisq_dot(ab, ab, n, HISQ_F32).real
+        num += hisq_dot(ab, b[i].contiguous(), n, HISQ_F32, ws).real
+        den += hisq_dot(ab, ab, n, HISQ_F32, ws).real
     return num / den

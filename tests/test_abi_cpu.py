@@ -103,3 +103,27 @@ def test_cg_option_validation_without_gpu():
                                 ctypes.byref(o), None if want == -7 else p[0], 0 if want == -7 else 1 << 40,
                                 None, None)
         assert rc == want, (delta, mode, rc)
+
+
+def test_shift_and_dot_validation_without_gpu():
+    """shift_tol must be below 1 (MULTI_SHIFT's shifted-phase stop); the dot product needs its
+    fixed-size workspace.  Both are refused before any GPU work."""
+    import paper_1411_2087_amd as hq
+    lib = hq._lib
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    p = [ctypes.c_void_p(0x1000 * (i + 1)) for i in range(6)]
+    masses = (ctypes.c_double * 2)(0.01, 0.1)
+    o = hq.CGOpts(mode=1, max_iter=0, check_every=0, use_graph=1, delta=0.0, shift_tol=1.0, shift_only=1)
+    rc = lib.cg_solve_multi(2, masses, 1e-10, hq.HISQ_MULTI_SHIFT, p[0], p[1], p[2], p[3], p[4], p[5], dims,
+                            ctypes.byref(o), p[0], 1 << 40, None, None)
+    assert rc == -1 and b"shift_tol" in lib.hisq_last_error()
+    o.shift_tol = 1e-4
+    rc = lib.cg_solve_multi(2, masses, 1e-10, hq.HISQ_MULTI_SHIFT, p[0], p[1], p[2], p[3], p[4], p[5], dims,
+                            ctypes.byref(o), None, 0, None, None)
+    assert rc == -7
+    need = hq.hisq_workspace_bytes("dot", (4, 4, 4, 4))
+    assert need == 2 * 8 * 1024 + 256
+    out = (ctypes.c_double * 2)()
+    assert lib.hisq_dot(p[0], p[1], 10, 0, out, None, 0, None) == -7
+    assert lib.hisq_dot(p[0], p[1], 10, 0, out, p[2], need - 1, None) == -7
+    assert lib.hisq_dot(p[0], p[1], -1, 0, out, p[2], need, None) == -1

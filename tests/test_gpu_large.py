@@ -20,7 +20,7 @@ def big():
     b = synth.source(DIMS, synth.source_seed(3))
     fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
     L = {p: hq.fields.Links.pack(fd, ld, DIMS, p)
-         for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S, hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_I16SC)}
+         for p in (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_F16S, hq.HISQ_I16S, hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_I16SC)}
     del fd, ld
     torch.cuda.synchronize()
     return hq, fat, lng, b, L
@@ -40,11 +40,14 @@ def test_dslash_f64_48x96(big):
         assert err <= TOL_F64
 
 
-@pytest.mark.parametrize("mode", [1, 3, 5, 6])
+@pytest.mark.parametrize("mode", [1, 2, 3, 5, 6])
 def test_mixed_cg_48x96(big, mode):
+    """Every mixed form on the largest workload, FP16-links-with-per-matrix-scale (mode 2) included;
+    none may need the plain-CG fallback."""
     import torch
     hq, fat, lng, b, L = big
-    lo = {1: L[hq.HISQ_F32], 3: L[hq.HISQ_I16S], 5: L[hq.HISQ_F32C], 6: L[hq.HISQ_I16SC]}[mode]
+    lo = {1: L[hq.HISQ_F32], 2: L[hq.HISQ_F16S], 3: L[hq.HISQ_I16S], 5: L[hq.HISQ_F32C],
+          6: L[hq.HISQ_I16SC]}[mode]
     hi = L[hq.HISQ_F64C] if mode in (5, 6) else L[hq.HISQ_F64]
     bd = torch.from_numpy(b).cuda()
     x = torch.zeros_like(bd)
@@ -53,8 +56,9 @@ def test_mixed_cg_48x96(big, mode):
     st = hq.cg_solve(MASS, CG_TOL, hi.fat, hi.lng, lo.fat, lo.lng, bd, x, DIMS, opts, ws)
     tr = oracle.true_residual(DIMS, MASS, fat, lng, b, x.cpu().numpy())
     say(f"48^3x96 m={MASS} mode={mode}: iters={st['iters']} updates={st['reliable_updates']} "
-        f"time={st['time_s']:.2f}s gpu={st['true_resid']:.2e} oracle={tr:.2e}")
+        f"time={st['time_s']:.2f}s gpu={st['true_resid']:.2e} oracle={tr:.2e} fallback={st['fallback_used']}")
     assert st["rc"] == 0 and tr <= CG_TOL
+    assert st["fallback_used"] == 0
 
 
 # The two lattices of the paper's single-coprocessor Dslash runs (Sec. 4,

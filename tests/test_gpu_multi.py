@@ -56,9 +56,11 @@ INNER = {"f32": ("HISQ_F64", "HISQ_F32", "HISQ_CG_MIXED_F32"),
          "i16sc": ("HISQ_F64C", "HISQ_I16SC", "HISQ_CG_MIXED_I16SC")}
 
 
-def _solve_multi(hq, dims, fat, lng, bs, masses, mode, max_iter=0, inner="f32", delta=0.0):
+def _solve_multi(hq, dims, fat, lng, bs, masses, mode, max_iter=0, inner="f32", delta=0.0, shift_tol=0.0,
+                 shift_only=0):
     """Batched solve with the inner links `inner` (a key of INNER) and the reliable-update trigger `delta`
-    (0: the default of the inner links)."""
+    (0: the default of the inner links); for MULTI_SHIFT the shifted phase's stop `shift_tol` and,
+    with shift_only, its solutions without the refinement."""
     import torch
     po, pi, cg_mode = (getattr(hq, k) for k in INNER[inner])
     L64 = hq.fields.Links.pack(fat, lng, dims, po)
@@ -68,7 +70,8 @@ def _solve_multi(hq, dims, fat, lng, bs, masses, mode, max_iter=0, inner="f32", 
     vh = int(np.prod(dims)) // 2
     x = torch.zeros((n, vh, 3), dtype=torch.complex128, device="cuda")
     ws = hq.fields.workspace("cg_multi", dims, n, mode)
-    opts = hq.CGOpts(mode=cg_mode, max_iter=max_iter, check_every=0, use_graph=1, delta=delta)
+    opts = hq.CGOpts(mode=cg_mode, max_iter=max_iter, check_every=0, use_graph=1, delta=delta, shift_tol=shift_tol,
+                     shift_only=shift_only)
     st = hq.cg_solve_multi(n, masses, CG_TOL, mode, L64.fat, L64.lng, Llo.fat, Llo.lng, b, x, dims, opts, ws)
     return x.cpu().numpy(), st
 
@@ -108,6 +111,83 @@ def test_cg_multi_shift(hq, n, inner):
         assert st[r]["status"] == 0 and tr <= CG_TOL
     xo, _ = oracle.cg(dims, masses[-1], fat, lng, b, tol=1e-12)
     assert np.linalg.norm(x[-1] - xo) / np.linalg.norm(xo) < 1e-6
+
+
+# (lattice, shifts, inner links, lightest mass): the oracle runs one FP64 CG per shift, so the lightest
+# mass (the base system) is chosen to keep that to seconds (about 1600 iterations at 8^4, m = 0.01)
+SHIFT_CASES = [((8, 8, 8, 8), 4, "f32", 0.01), ((8, 8, 8, 8), 8, "f32", 0.01), ((8, 8, 8, 8), 16, "f32", 0.01),
+               ((8, 8, 8, 8), 8, "f32c", 0.01), ((16, 16, 16, 16), 4, "f32", 0.02),
+               ((16, 16, 16, 16), 8, "f32", 0.03), ((16, 16, 16, 16), 16, "f32", 0.05)]
+
+
+def _lambda_max(dims, fat, lng, iters=40):
+    """Largest eigenvalue of A0 = -D_eo D_oe (mass 0) by power iteration with the oracle's operator,
+    raised by 5 % (the iteration approaches it from below)."""
+    v = synth.source(dims, 999)
+    lam = 0.0
+    for _ in range(iters):
+        w = oracle.apply_A(dims, 0.0, fat, lng, v)
+        lam = np.linalg.norm(w) / np.linalg.norm(v)
+        v = w / np.linalg.norm(w)
+    return 1.05 * lam
+
+
+U32 = 2.0 ** -24  # FP32 unit roundoff
+
+
+@pytest.mark.parametrize("dims,n,inner,m_lo", SHIFT_CASES)
+def test_shifted_cg_phase(hq, dims, n, inner, m_lo):
+    """The shifted-CG recurrences alone (Sec. 3: multishift CG over several masses), without the
+    batched refinement.  The Krylov spaces of all shifted systems coincide, so after k iterations
+    shift i holds the k-th CG iterate of A(m_i) x = b from x = 0, and its residual is zeta_i times
+    the base residual.  For every shift the oracle runs exactly as many CG iterations in FP64 at
+    m_i as the shift did (k), and:
+      (1) the oracle's recursive residual has reached shift_tol at k (within 10 %) but not 2 % of
+          the iterations earlier: the shift left the phase where plain CG would;
+      (2) the GPU's recursive residual |zeta_i r| / |b| equals the oracle's at k within 10 % of
+          shift_tol (the zeta, alpha, beta recurrences in FP64 scalars over FP32 vectors);
+      (3) the FP64 true residual of the GPU's x_i (recomputed by the oracle), and its distance to
+          the oracle's k-th iterate, stay within the FP32 recursion's drift: a residual gap of
+          order u32 * kappa_i, kappa_i = lambda_max / (4 m_i^2), grows over the iterations
+          (Greenbaum 1997); at m = 0.002 on 8^4 it reaches ~6e-2, which is why the phase is
+          followed by the FP64 reliable-update refinement.
+    A wrong zeta, alpha or beta recurrence breaks (1) and (2) for every shift but the base one."""
+    tol_s = 1e-4
+    fat, lng = fields(dims, synth.gauge_seed(4))
+    masses = synth.log_masses(n, m_lo, 0.2)
+    b = synth.source(dims, synth.source_seed(4))
+    x, st = _solve_multi(hq, dims, fat, lng, b, masses, hq.HISQ_MULTI_SHIFT, inner=inner, shift_tol=tol_s,
+                         shift_only=1)
+    lmax = _lambda_max(dims, fat, lng)
+    say(f"shifted CG dims={dims} n={n}: GPU done, iterations {[s_['iters'] for s_ in st]}; lambda_max {lmax:.2f}")
+    rows = []
+    import time
+    for i in range(n):
+        m = masses[i]
+        k = st[i]["iters"]
+        t0 = time.perf_counter()
+        tr = oracle.true_residual(dims, m, fat, lng, b, x[i])
+        xk, info = oracle.cg(dims, m, fat, lng, b, tol=0.0, max_iter=k, history=True)
+        say(f"  shift {i} m={m:.4f}: oracle CG of {k} iterations in {time.perf_counter() - t0:.1f}s")
+        hist = info["history"]
+        slack = max(2, int(np.ceil(0.02 * k)))
+        dx = np.linalg.norm(x[i] - xk) / np.linalg.norm(xk)
+        drift = 2 * U32 * (lmax + 4 * m * m) / (4 * m * m)
+        rows.append((round(m, 5), k, f"{hist[k]:.3e}", f"{st[i]['iter_resid']:.3e}", f"{tr:.2e}", f"{dx:.1e}",
+                     f"{drift:.1e}"))
+        assert st[i]["status"] == 0 and st[i]["rc"] == 0 and info["iters"] == k
+        assert hist[k] <= 1.1 * tol_s, (m, k, hist[k])
+        if k > slack:
+            assert hist[:k - slack + 1].min() > tol_s, (m, k, hist[:k - slack + 1].min())
+        assert abs(st[i]["iter_resid"] - hist[k]) <= 0.1 * tol_s, (m, st[i]["iter_resid"], hist[k])
+        assert tr <= tol_s + drift, (m, tr, drift)
+        assert dx <= tol_s + drift, (m, dx, drift)
+    say(f"shifted CG dims={dims} n={n} inner={inner} shift_tol={tol_s} lambda_max={lmax:.2f}: (m, iters, oracle "
+        f"recursive residual at iters, GPU recursive residual, oracle true residual of x, |x - x_k|/|x_k|, "
+        f"drift bound) = {rows}")
+    # shifts converge in mass order: a heavier mass never needs more iterations
+    ks = [s_["iters"] for s_ in st]
+    assert all(ks[i] >= ks[i + 1] for i in range(n - 1)), ks
 
 
 @pytest.mark.parametrize("inner,mode", [("f32", 0), ("i16sc", 0), ("f32", 1)])
