@@ -91,23 +91,96 @@ def traffic_from_profile(vh, shape):
     return round(row["bytes_per_launch"]) if row else None
 
 
-def cpu_baseline(fat, lng, b, vh, budget_s=15.0):
-    """Oracle CG on the host cores for a bounded number of iterations."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(fat, lng, b, vh, budget_s=15.0, cg_budget_s=45.0):
+    """The CPU oracle on the host cores: its build for this machine (-O3 -march=native, compiled here), and
+      - the value: CG iterations of the same 32^4 FP64 CG for about budget_s, as sustained Dslash GB/s;
+      - the oracle Dslash on 8^4, 16^4, 32^4 and 48^3x96 (median of 5; of 3 single-threaded on the
+        largest), with every thread and with one, as algorithmic GB/s and GFLOP/s (1146 flops per site);
+      - the oracle CG to completion (1e-10) on 8^4 (m = 0.05) and 16^4 (m = 0.005)."""
+    import tempfile
+
     import numpy as np
     import oracle
+    import synth
+    from oracle import build as obuild
+    lib = oracle.load_library(obuild.build_timing(os.path.join(tempfile.gettempdir(), "hisq_oracle_timing")))
+    nthreads = oracle.num_threads(lib)
     t0 = time.perf_counter()
     oracle.apply_A(DIMS, MASS, fat, lng, b)
     t_A = time.perf_counter() - t0
     n_it = int(max(2, min(2000, (budget_s - 2 * t_A) / max(t_A, 1e-3))))
     log(f"[cpu] one A application {t_A:.2f}s -> {n_it} CG iterations")
     t0 = time.perf_counter()
-    _, info = oracle.cg(DIMS, MASS, fat, lng, b, tol=1e-30, max_iter=n_it)
+    _, info = oracle.cg(DIMS, MASS, fat, lng, b, tol=1e-30, max_iter=n_it, lib=lib)
     dt = time.perf_counter() - t0
     n_dslash = 2 * info["iters"] + 4  # initial residual, 2 per iteration, final residual
     gbs = n_dslash * 2400.0 * vh / dt / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{info['iters']} iterations of the same 32^4 FP64 CG ({n_dslash} Dslash applications "
-                      f"+ BLAS-1) in {dt:.1f} s; sustained algorithmic Dslash GB/s"}
+    out = {"value": round(gbs, 3), "unit": "GB/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"{info['iters']} iterations of the same 32^4 FP64 CG ({n_dslash} Dslash applications "
+                     f"+ BLAS-1) in {dt:.1f} s; sustained algorithmic Dslash GB/s",
+           "cpu_model": cpu_model(), "build": "gcc -O3 -march=native -fopenmp (plain loops, no intrinsics)"}
+    # the oracle Dslash on every lattice of the workloads
+    dsl = {}
+    for dims in ((8, 8, 8, 8), (16, 16, 16, 16), (32, 32, 32, 32), (48, 48, 48, 96)):
+        if dims == DIMS:
+            f_, l_, s_ = fat, lng, b
+        else:
+            f_, l_ = synth.links(dims, synth.gauge_seed(3 if dims[3] == 96 else 1))
+            s_ = synth.source(dims, synth.source_seed(1))
+        vh_d = int(np.prod(dims)) // 2
+        row = {}
+        for th in (nthreads, 1):
+            oracle.set_num_threads(th, lib)
+            reps = 3 if (th == 1 and vh_d > 10 ** 6) else 5
+            oracle.dslash(dims, f_, l_, s_, 1, lib=lib)
+            ts = []
+            for _ in range(reps):
+                t1 = time.perf_counter()
+                oracle.dslash(dims, f_, l_, s_, 1, lib=lib)
+                ts.append(time.perf_counter() - t1)
+            t = float(np.median(ts))
+            row[f"threads_{th}"] = {"s": round(t, 5), "gbs": round(2400.0 * vh_d / t / 1e9, 2),
+                                    "gflops": round(1146.0 * vh_d / t / 1e9, 2), "reps": reps}
+        oracle.set_num_threads(nthreads, lib)
+        dsl["x".join(map(str, dims))] = row
+        log(f"[cpu] oracle dslash {'x'.join(map(str, dims))}: {row}")
+        if dims != DIMS:
+            del f_, l_, s_
+    out["dslash"] = dsl
+    # the oracle CG to completion on the two small workloads (16^4 at m = 0.005 needs ~7600 iterations: run
+    # to completion when the oracle's measured Dslash rate says it fits cg_budget_s, else 200 iterations,
+    # extrapolated to the GPU solve's iteration count and marked so)
+    cgs = {}
+    for dims, mass, cfg, gpu_iters in (((8, 8, 8, 8), 0.05, 1, 753), ((16, 16, 16, 16), 0.005, 5, 7582)):
+        f_, l_ = synth.links(dims, synth.gauge_seed(cfg))
+        s_ = synth.source(dims, synth.source_seed(cfg))
+        est = 2.2 * gpu_iters * dsl["x".join(map(str, dims))][f"threads_{nthreads}"]["s"]
+        full = est <= cg_budget_s
+        t1 = time.perf_counter()
+        _, ci = oracle.cg(dims, mass, f_, l_, s_, tol=TOL if full else 1e-30, max_iter=100000 if full else 200,
+                         lib=lib)
+        t = time.perf_counter() - t1
+        row = {"mass": mass, "iters": ci["iters"]}
+        if full:
+            row.update({"s": round(t, 3), "true_resid": ci["true_rel"], "converged": ci["converged"]})
+        else:
+            row.update({"s": round(t / ci["iters"] * gpu_iters, 3), "extrapolated": True,
+                        "from": f"{ci['iters']} iterations in {t:.2f} s, scaled to {gpu_iters} iterations"})
+        cgs["x".join(map(str, dims))] = row
+        log(f"[cpu] oracle CG {'x'.join(map(str, dims))} m={mass}: {row}")
+    out["cg_to_1e-10"] = cgs
+    return out
 
 
 def form_batched(hq, dims, L64, L32, mode, n, log, cg_mode=0, seq_from=None):
@@ -156,8 +229,45 @@ def form_batched(hq, dims, L64, L32, mode, n, log, cg_mode=0, seq_from=None):
             "sequential_plain_iters": seq_iters, "speedup_vs_sequential_plain": round(seq / dt, 3)}
 
 
-def form_learned(hq, log, dims=(16, 16, 16, 16), mass=0.005, C=16, npairs=64, steps=300):
-    """Learned preconditioner: pairs from the batched CG, GPU training, flexible CG vs plain FP64 CG."""
+def polynomial_reference(hq, log, dims, mass, fat, lng, sources, C=4):
+    """The network built, not trained, as K = p(A), p the Chebyshev-optimal quadratic on [4 m^2, lambda_max]
+    (train.chebyshev_weights): exact on the naive operator (long links zero), where it shows what four fat-link
+    layers can reach; on the HISQ operator the same weights miss the three-hop terms.  Flexible CG with it
+    against plain FP64 CG on each operator and source."""
+    import numpy as np
+    import torch
+    from paper_1411_2087_amd import train
+    rows = {}
+    for name, L in (("naive", np.zeros_like(lng)), ("hisq", lng)):
+        L64 = hq.fields.Links.pack(fat, L, dims, hq.HISQ_F64)
+        L32 = hq.fields.Links.pack(fat, L, dims, hq.HISQ_F32)
+        lmax = train.lambda_max_estimate(L64, mass, dims)
+        w, coef = train.chebyshev_weights(C, mass, lmax)
+        wd = torch.from_numpy(w).cuda()
+        wsc, wsf = hq.fields.workspace("cg", dims), hq.fields.workspace("fcg", dims, 1, 0, C)
+        r = {"lambda_max": round(lmax, 3), "p_coeffs": [round(float(c), 6) for c in coef], "plain_iters": [],
+             "plain_s": [], "fcg_iters": [], "fcg_s": [], "fallback_used": []}
+        for src in sources:
+            bd = torch.from_numpy(np.ascontiguousarray(src)).cuda()
+            xp, xf = torch.zeros_like(bd), torch.zeros_like(bd)
+            sp = hq.cg_solve(mass, TOL, L64.fat, L64.lng, None, None, bd, xp, dims, None, wsc)
+            sf = hq.fcg_solve(mass, TOL, L64.fat, L64.lng, L32.fat, wd, C, bd, xf, dims, None, wsf)
+            r["plain_iters"].append(sp["iters"])
+            r["plain_s"].append(round(sp["time_s"], 4))
+            r["fcg_iters"].append(sf["iters"])
+            r["fcg_s"].append(round(sf["time_s"], 4))
+            r["fallback_used"].append(sf["fallback_used"])
+        r["iteration_ratio_vs_plain"] = round(sum(r["fcg_iters"]) / sum(r["plain_iters"]), 3)
+        log(f"[polynomial K, {name} operator] lambda_max {lmax:.3f}: plain {r['plain_iters']} {r['plain_s']}s, "
+            f"fcg {r['fcg_iters']} {r['fcg_s']}s (fallback {r['fallback_used']})")
+        rows[name] = r
+    return rows
+
+
+def form_learned(hq, log, dims=(16, 16, 16, 16), mass=0.005, C=16, npairs=512, nheld=64, steps=600):
+    """Learned preconditioner: 512 pairs from the batched CG (448 to train, 64 held out), GPU training with the
+    residual objective, then flexible CG with the trained network, and with K = identity, against plain FP64 CG on
+    a held-out source."""
     import numpy as np
     import torch
     import synth
@@ -165,30 +275,41 @@ def form_learned(hq, log, dims=(16, 16, 16, 16), mass=0.005, C=16, npairs=64, st
     fat, lng = synth.links(dims, synth.gauge_seed(5))
     L64 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F64)
     L32 = hq.fields.Links.pack(fat, lng, dims, hq.HISQ_F32)
-    src = np.stack([synth.source(dims, synth.source_seed(5, i)) for i in range(npairs + 1)])
+    src = np.stack([synth.source(dims, synth.source_seed(5, i)) for i in range(npairs)])
     t0 = time.perf_counter()
-    b, x, _, _ = train.make_pairs(dims, mass, L64, L32, src[:npairs])
+    b, x, _, _ = train.make_pairs(dims, mass, L64, L32, src)
     t_pairs = time.perf_counter() - t0
+    ntr = npairs - nheld
     tr = train.Trainer(dims, C, L32.fat, train.initial_weights(C, train.residual_scale(b[:16], L32, mass, dims), 0.05,
                                                                99), batch=16, objective="residual", links32=L32,
                        mass=mass)
+    l0 = tr.evaluate(b[ntr:], x[ntr:])
     t0 = time.perf_counter()
-    hist = tr.fit(b, x, steps=steps, lr=2e-3, log_every=100)
+    hist = tr.fit(b[:ntr], x[:ntr], steps=steps, lr=2e-3, log_every=200)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    bd = torch.from_numpy(src[npairs]).cuda()
+    l1 = tr.evaluate(b[ntr:], x[ntr:])
+    bd = torch.from_numpy(src[ntr]).cuda()
     xp = torch.zeros_like(bd)
     sp = hq.cg_solve(mass, TOL, L64.fat, L64.lng, None, None, bd, xp, dims, None, hq.fields.workspace("cg", dims))
+    wsf = hq.fields.workspace("fcg", dims, 1, 0, C)
     xf = torch.zeros_like(bd)
-    sf = hq.fcg_solve(mass, TOL, L64.fat, L64.lng, L32.fat, tr.w, C, bd, xf, dims, None,
-                      hq.fields.workspace("fcg", dims, 1, 0, C))
-    log(f"[form learned] pairs {t_pairs:.1f}s train {t_train:.1f}s; plain {sp['iters']} it {sp['time_s']:.3f}s; "
-        f"fcg {sf['iters']} it (fallback {sf['fallback_used']}) {sf['time_s']:.3f}s")
-    return {"workload": "16^4, m 0.005, C 16, residual objective", "pairs": npairs, "pair_s": round(t_pairs, 2),
-            "train_steps": steps, "train_s": round(t_train, 2), "loss_log": [(s_, round(l, 4)) for s_, l in hist],
+    sf = hq.fcg_solve(mass, TOL, L64.fat, L64.lng, L32.fat, tr.w, C, bd, xf, dims, None, wsf)
+    xi = torch.zeros_like(bd)
+    wid = torch.from_numpy(train.flatten(train.identity_weights(C))).cuda()
+    si = hq.fcg_solve(mass, TOL, L64.fat, L64.lng, L32.fat, wid, C, bd, xi, dims, None, wsf)
+    log(f"[form learned] pairs {t_pairs:.1f}s train {t_train:.1f}s (held-out loss {l0:.4f} -> {l1:.4f}); plain "
+        f"{sp['iters']} it {sp['time_s']:.3f}s; fcg {sf['iters']} it (fallback {sf['fallback_used']}) "
+        f"{sf['time_s']:.3f}s; fcg with K = 1 {si['iters']} it {si['time_s']:.3f}s")
+    poly = polynomial_reference(hq, log, dims, mass, fat, lng, src[ntr:ntr + 1])
+    return {"workload": f"16^4, m {mass}, C {C}, residual objective, {npairs} pairs ({ntr} train / {nheld} held out)",
+            "pairs": npairs, "pair_s": round(t_pairs, 2), "train_steps": steps, "train_s": round(t_train, 2),
+            "held_out_loss": [round(l0, 4), round(l1, 4)], "loss_log": [(s_, round(l, 4)) for s_, l in hist],
             "plain_f64_s": round(sp["time_s"], 4), "plain_iters": sp["iters"], "fcg_s": round(sf["time_s"], 4),
             "fcg_iters": sf["iters"], "fallback_used": sf["fallback_used"], "fallback_iters": sf["fallback_iters"],
-            "fcg_true_resid": sf["true_resid"], "speedup_vs_plain": round(sp["time_s"] / sf["time_s"], 3)}
+            "fcg_true_resid": sf["true_resid"], "fcg_identity_iters": si["iters"], "fcg_identity_s": round(si["time_s"], 4),
+            "speedup_vs_plain": round(sp["time_s"] / sf["time_s"], 3),
+            "iteration_ratio_vs_plain": round(sf["iters"] / sp["iters"], 3), "polynomial_K_C4": poly}
 
 
 def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, steps=600, channels=(8, 16),
@@ -213,6 +334,7 @@ def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, s
     log(f"[learned] {npairs} pairs in {t_pairs:.1f}s")
     ntrain = npairs - nheld
     held = [torch.from_numpy(src[ntrain + i]).cuda() for i in range(nsolve)]
+    poly_src = src[ntrain:ntrain + 2].copy()
     del src
 
     def solve_all(fn):
@@ -255,6 +377,7 @@ def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, s
                                 "speedup_vs_plain": round(sum(p_s) / sum(f_s), 3)}
         log(f"[learned C={C}] held-out loss {l0:.4f} -> {l1:.4f}, train {t_train:.1f}s; fcg {f_its} "
             f"(fallback {last['fallback_used']}) {sum(f_s):.3f}s, identity {i_its}, plain {p_its} {sum(p_s):.3f}s")
+    out["polynomial_K_C4"] = polynomial_reference(hq, log, dims, mass, fat, lng, poly_src)
     print(json.dumps({"metric": "CG s to 1e-10 resid, flexible CG with the trained network vs plain FP64 (report line)",
                       "unit": "s", "value": round(sum(out["nets"][f"C{channels[-1]}"]["fcg_trained"]["s"]), 4),
                       "n_gpus": 1,
@@ -309,6 +432,38 @@ def run_shift_depth(args, n=8):
                       "config": {"workload": "32^4, 8 masses 0.002-0.2, one source, tol 1e-10"}, "shift_depth": rows}))
 
 
+def run_mdslash(args, nrhs=(8, 16), reps=20):
+    """The multi-RHS FP32 Dslash alone at 32^4 (the kernel of the batched solves): every launch shape
+    tuned, then the chosen one timed with HIP events; algorithmic bytes per site 1152 (16 FP32 links)
+    + 48 N (N sources and N outputs of 24 bytes) (report line; the command of its counter profiles)."""
+    import numpy as np
+    import torch
+
+    import paper_1411_2087_amd as hq
+    import synth
+    fat, lng = synth.links(DIMS, synth.gauge_seed(CONFIG))
+    L = hq.fields.Links.pack(fat, lng, DIMS, hq.HISQ_F32)
+    vh = int(np.prod(DIMS)) // 2
+    ws = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    rows = {}
+    for n in nrhs:
+        src = np.stack([synth.source(DIMS, synth.source_seed(CONFIG, r)) for r in range(n)], axis=1)
+        s_ = torch.from_numpy(src.astype(np.complex64)).cuda().contiguous()
+        d_ = torch.empty_like(s_)
+        best, us = hq.hisq_tune_multi(L.fat, L.lng, s_, d_, DIMS, n, ws, reps=5)
+        t = timed(lambda: hq.hisq_dslash_multi(L.fat, L.lng, s_, d_, 1, n, DIMS, ws), reps, stream)
+        bps = 1152 + 48 * n
+        rows[f"N{n}"] = {"shape": best, "shape_us": [round(u, 1) for u in us], "us": round(t, 1),
+                         "bytes_per_site": bps, "gbs": round(bps * vh / t / 1e3, 1),
+                         "frac": round(bps * vh / t / 1e3 / HBM_PEAK_GBS, 4)}
+        log(f"[mdslash] N={n}: shape {best} {t:.1f} us {rows[f'N{n}']['gbs']} GB/s")
+        del s_, d_
+    print(json.dumps({"metric": "multi-RHS FP32 Dslash GB/s at 32^4 (report line)", "unit": "GB/s",
+                      "value": rows[f"N{nrhs[0]}"]["gbs"], "n_gpus": 1, "higher_is_better": True,
+                      "data": "synthetic", "config": {"workload": "32^4 multi-RHS FP32 Dslash"}, "mdslash": rows}))
+
+
 def run_net_kernels(args, dims=(16, 16, 16, 16), C=16, batch=16, reps=5):
     """The network's kernels alone on the training shape: forward (4 layers) and backward (4 weight
     gradients, 3 input gradients) of a batch of 16 sources at 16^4, C = 16, timed with HIP events on the
@@ -361,20 +516,25 @@ def run_net_kernels(args, dims=(16, 16, 16, 16), C=16, batch=16, reps=5):
                       "data": "synthetic", "config": {"workload": out["workload"]}, "net": out}))
 
 
-def run_large(args):
-    """48^3 x 96, m = 0.005: seconds to 1e-10 of plain FP64 CG and of the mixed-precision forms."""
+LARGE_DIMS, LARGE_MASS = (48, 48, 48, 96), 0.005
+# 48^3x96 CG kernels: k_cg_Dp moves the Dslash bytes, k_cg_Ap_upd those of AP_UPD_BYTES
+
+
+def large_lattice(hq, log, precs, forms_list):
+    """48^3 x 96, m = 0.005: each storage form's tuned Dslash (HIP events), then seconds to 1e-10 of the listed
+    CG forms.  The plain FP64 solve runs with its kernels timed one by one (direct launches, HIP events), which
+    gives the CG kernels' durations on the largest lattice."""
     import numpy as np
     import torch
 
-    import paper_1411_2087_amd as hq
     import synth
-    dims, mass = (48, 48, 48, 96), 0.005
+    dims, mass = LARGE_DIMS, LARGE_MASS
     vh = int(np.prod(dims)) // 2
     log("[setup] generating 48^3x96 links and source")
     fat, lng = synth.links(dims, synth.gauge_seed(3))
     b_np = synth.source(dims, synth.source_seed(3))
     fd, ld = torch.from_numpy(fat).cuda(), torch.from_numpy(lng).cuda()
-    precs = (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S, hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_I16SC, hq.HISQ_F16S)
+    del fat, lng
     L = {p: hq.fields.Links.pack(fd, ld, dims, p) for p in precs}
     del fd, ld
     b = torch.from_numpy(b_np).cuda()
@@ -384,41 +544,64 @@ def run_large(args):
         s_, d_ = b.to(dt), torch.empty(b.shape, dtype=dt, device="cuda")
         best, us = hq.hisq_tune_dslash(L[p].fat, L[p].lng, s_, d_, dims, p, reps=10)
         t = min(us) * 1e-6
-        dsl[p] = {"us": round(t * 1e6, 1), "gbs": round(hq.DSLASH_BYTES_PER_SITE[p] * vh / t / 1e9, 1), "shape": best,
+        gbs = hq.DSLASH_BYTES_PER_SITE[p] * vh / t / 1e9
+        dsl[p] = {"us": round(t * 1e6, 1), "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "shape": best,
                   "us_per_shape": [round(u, 1) for u in us]}
         log(f"[dslash 48^3x96] prec {p}: {dsl[p]}")
         del s_, d_
+    lo_of = {hq.HISQ_CG_MIXED_F32: hq.HISQ_F32, hq.HISQ_CG_MIXED_I16S: hq.HISQ_I16S,
+             hq.HISQ_CG_MIXED_F32C: hq.HISQ_F32C, hq.HISQ_CG_MIXED_I16SC: hq.HISQ_I16SC,
+             hq.HISQ_CG_MIXED_F16S: hq.HISQ_F16S}
     forms = {}
-    for name, mode, lo in (("plain_f64", hq.HISQ_CG_PLAIN_F64, None), ("plain_f64c", hq.HISQ_CG_PLAIN_F64C, None),
-                           ("mixed_f32", hq.HISQ_CG_MIXED_F32, hq.HISQ_F32),
-                           ("mixed_i16s", hq.HISQ_CG_MIXED_I16S, hq.HISQ_I16S),
-                           ("mixed_f32c", hq.HISQ_CG_MIXED_F32C, hq.HISQ_F32C),
-                           ("mixed_i16sc", hq.HISQ_CG_MIXED_I16SC, hq.HISQ_I16SC),
-                           ("mixed_f16s", hq.HISQ_CG_MIXED_F16S, hq.HISQ_F16S)):
+    for name, mode in forms_list:
         hi = L[hq.HISQ_F64C] if mode in (hq.HISQ_CG_PLAIN_F64C, hq.HISQ_CG_MIXED_F32C,
                                          hq.HISQ_CG_MIXED_I16SC) else L[hq.HISQ_F64]
+        lo = L[lo_of[mode]] if mode in lo_of else None
         ws = hq.fields.workspace("cg", dims, 1, mode)
         x = torch.zeros_like(b)
-        o = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=1, delta=0.0)
+        timing = mode == hq.HISQ_CG_PLAIN_F64
+        o = hq.CGOpts(mode=mode, max_iter=0, check_every=0, use_graph=2 if timing else 1, delta=0.0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = hq.cg_solve(mass, TOL, hi.fat, hi.lng, L[lo].fat if lo is not None else None,
-                         L[lo].lng if lo is not None else None, b, x, dims, o, ws)
+        st = hq.cg_solve(mass, TOL, hi.fat, hi.lng, lo.fat if lo is not None else None,
+                         lo.lng if lo is not None else None, b, x, dims, o, ws)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         forms[name] = {"s": round(dt, 3), "iters": st["iters"], "reliable_updates": st["reliable_updates"],
                        "true_resid": st["true_resid"], "rc": st["rc"], "fallback_used": st["fallback_used"],
                        "fallback_iters": st["fallback_iters"]}
+        if timing:
+            t_dp, t_ap, t_pn = (u * 1e-6 for u in st["kernel_us"])
+            forms[name]["kernels"] = {
+                "k_cg_Dp": {"avg_us": round(t_dp * 1e6, 1), "gbs": round(DP_BYTES * vh / t_dp / 1e9, 1),
+                            "frac": round(DP_BYTES * vh / t_dp / 1e9 / HBM_PEAK_GBS, 4)},
+                "k_cg_Ap_upd": {"avg_us": round(t_ap * 1e6, 1), "gbs": round(AP_UPD_BYTES * vh / t_ap / 1e9, 1),
+                                "frac": round(AP_UPD_BYTES * vh / t_ap / 1e9 / HBM_PEAK_GBS, 4)},
+                "k_cg_p_norm": {"avg_us": round(t_pn * 1e6, 1)}}
         log(f"[48^3x96 {name}] {dt:.2f}s iters={st['iters']} resid={st['true_resid']:.2e} "
-            f"fallback={st['fallback_used']} ({st['fallback_iters']} plain iterations)")
+            f"fallback={st['fallback_used']} ({st['fallback_iters']} plain iterations) {forms[name].get('kernels', '')}")
         del ws, x
     base = forms["plain_f64"]["s"]
     for k in forms:
         forms[k]["speedup_vs_plain"] = round(base / forms[k]["s"], 3)
+    del L
+    torch.cuda.empty_cache()
+    return {"dslash": {str(k): v for k, v in dsl.items()}, "forms": forms}
+
+
+def run_large(args):
+    """48^3 x 96, m = 0.005: seconds to 1e-10 of plain FP64 CG and of every mixed-precision form."""
+    import paper_1411_2087_amd as hq
+    precs = (hq.HISQ_F64, hq.HISQ_F32, hq.HISQ_I16S, hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_I16SC, hq.HISQ_F16S)
+    forms_list = (("plain_f64", hq.HISQ_CG_PLAIN_F64), ("plain_f64c", hq.HISQ_CG_PLAIN_F64C),
+                  ("mixed_f32", hq.HISQ_CG_MIXED_F32), ("mixed_i16s", hq.HISQ_CG_MIXED_I16S),
+                  ("mixed_f32c", hq.HISQ_CG_MIXED_F32C), ("mixed_i16sc", hq.HISQ_CG_MIXED_I16SC),
+                  ("mixed_f16s", hq.HISQ_CG_MIXED_F16S))
+    r = large_lattice(hq, log, precs, forms_list)
     print(json.dumps({"metric": "CG s to 1e-10 resid, FP64 plain vs chosen form (report line)", "unit": "s",
-                      "value": base, "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
-                      "config": {"workload": "HISQ even-odd CG, 48^3x96, mass 0.005, tol 1e-10"},
-                      "dslash": {str(k): v for k, v in dsl.items()}, "forms": forms}))
+                      "value": r["forms"]["plain_f64"]["s"], "n_gpus": 1, "higher_is_better": False,
+                      "data": "synthetic", "config": {"workload": "HISQ even-odd CG, 48^3x96, mass 0.005, tol 1e-10"},
+                      "dslash": r["dslash"], "forms": r["forms"]}))
 
 
 def traffic_probe_at(workload):
@@ -571,6 +754,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (multi-RHS / multi-shift) forms")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
+    ap.add_argument("--no-large", action="store_true", help="skip the 48^3x96 entries of the default line")
     ap.add_argument("--workload", default="32x32x32x32",
                     help="32x32x32x32 (default: plain FP64 CG, the metric's workload), 48x48x48x96 "
                          "(mixed precision against plain FP64 on the large lattice), paper-grids (the Dslash "
@@ -578,7 +762,8 @@ def main():
                          "learned-32 (the same on 32^4, C = 16, two held-out solves) or "
                          "batched-16 (16 masses, batched against sequential plain FP64 solves) or net-kernels "
                          "(the network's forward and backward kernels at 16^4, batch 16, C = 16) or shift-depth "
-                         "(the multi-shift CG's shifted phase run to several depths); "
+                         "(the multi-shift CG's shifted phase run to several depths) or mdslash (the multi-RHS "
+                         "Dslash alone at 32^4, N = 8 and 16); "
                          "all but the first are report lines, not the metric")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a 1 GiB copy and the FP64 Dslash (for rocprofv3 counter runs); with --workload "
@@ -611,6 +796,8 @@ def main():
         return run_net_kernels(args)
     if args.workload == "shift-depth":
         return run_shift_depth(args)
+    if args.workload == "mdslash":
+        return run_mdslash(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     vh = int(np.prod(DIMS)) // 2
@@ -769,9 +956,17 @@ def main():
                                                   hq.HISQ_CG_MIXED_I16SC, forms["multi_rhs_8"])
         forms["multi_shift_8_i16sc"] = form_batched(hq, DIMS, L64C, LI16C, hq.HISQ_MULTI_SHIFT, 8, log,
                                                     hq.HISQ_CG_MIXED_I16SC, forms["multi_shift_8"])
+    del L16, LI16, L64C, L32C, LI16C
+    torch.cuda.empty_cache()
     if not args.no_forms and not args.no_learned:
-        del L16, LI16, L64C, L32C, LI16C
         forms["learned"] = form_learned(hq, log)
+    large = None
+    if not args.no_large:
+        # the largest workload: its FP64 Dslash and CG kernels against the roofline, and the time to 1e-10 of
+        # plain FP64 CG against the two-row FP32 and 16-bit forms
+        large = large_lattice(hq, log, (hq.HISQ_F64, hq.HISQ_F64C, hq.HISQ_F32C, hq.HISQ_I16SC),
+                              (("plain_f64", hq.HISQ_CG_PLAIN_F64), ("mixed_f32c", hq.HISQ_CG_MIXED_F32C),
+                               ("mixed_i16sc", hq.HISQ_CG_MIXED_I16SC)))
 
     cpu = None
     if not args.no_cpu:
@@ -821,6 +1016,7 @@ def main():
                      "copy_probe_gbs": round(copy_gbs, 1), "read_probe_gbs": round(read_gbs, 1)},
         "cpu_baseline": cpu,
         "forms": forms,
+        "large_48x48x48x96": large,
         "tuned_dslash_shapes": tuned,
     }
     print(json.dumps(out))

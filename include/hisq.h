@@ -153,7 +153,7 @@ typedef struct {
     int status;             /* hisq_status of this solve */
     double true_resid;      /* |b - A x| / |b| recomputed in FP64 on the GPU */
     double time_s;          /* wall time of the solve, first kernel to final check */
-    int fallback_used;      /* fcg_solve: 0 none; 1 K not positive on r or <p,Ap> <= 0; 2 stall or slow;
+    int fallback_used;      /* fcg_solve: 0 none; 1 K not positive on r or <p,Ap> <= 0; 2 too slow;
                                3 recursion converged but the true residual did not.
                                cg_solve mixed modes: 0 none; 1 stagnation, finished by plain CG */
     int fallback_iters;     /* plain CG iterations after the fallback (included in iters) */
@@ -350,8 +350,8 @@ int net_adam_step(void *weights, const void *grad_w, void *m, void *v, long long
 /* Flexible CG (Notay 2000, one stored direction, Polak-Ribiere update)
  * preconditioned by the network, on A(mass) x = b to tol; plain FP64 CG from
  * the current x is the fallback when K is not positive on the residual, when
- * <p, A p> <= 0, after 50 iterations without a new lowest residual, or when
- * |r| has not halved over a window of 200 iterations (stats.fallback_used
+ * <p, A p> <= 0, or when the lowest |r| reached over a window of 1000
+ * iterations is not below half the lowest before it (stats.fallback_used
  * says which).  fat/lng: HISQ_F64 packed links; fat32:
  * HISQ_F32 packed fat links for the network.  Workspace from
  * hisq_workspace_bytes("fcg", dims, 1, 0, channels). */

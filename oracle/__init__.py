@@ -44,7 +44,14 @@ def _load():
     if not os.path.exists(_LIB_PATH):
         from . import build as _b
         _b.build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    _lib = load_library(_LIB_PATH)
+    return _lib
+
+
+def load_library(path):
+    """ctypes handle of an oracle build at `path` (the checker, or the benchmark's timing build), with the
+    prototypes set; every function below takes it as `lib` (default: the checker)."""
+    lib = ctypes.CDLL(path)
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
     lib.or_dslash.argtypes = [ip, dp, dp, dp, dp, ctypes.c_int]
@@ -64,7 +71,8 @@ def _load():
     lib.or_cg.restype = ctypes.c_int
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = ctypes.c_int
-    _lib = lib
+    lib.or_set_num_threads.argtypes = [ctypes.c_int]
+    lib.or_set_num_threads.restype = None
     return lib
 
 
@@ -88,14 +96,14 @@ def _check(dims, fat, lng):
     assert fat.shape == (4, V, 3, 3) and lng.shape == (4, V, 3, 3), (fat.shape, dims)
 
 
-def dslash(dims, fat, lng, src, parity: int):
+def dslash(dims, fat, lng, src, parity: int, lib=None):
     """(D src) on the sites of `parity`; src lives on parity 1 - parity (Sec. 3)."""
     fat, lng, src = _c128(fat), _c128(lng), _c128(src)
     _check(dims, fat, lng)
     Vh = int(np.prod(dims)) // 2
     assert src.shape == (Vh, 3)
     out = np.empty((Vh, 3), np.complex128)
-    _load().or_dslash(_L(dims), _dp(fat), _dp(lng), _dp(src), _dp(out), int(parity))
+    (lib or _load()).or_dslash(_L(dims), _dp(fat), _dp(lng), _dp(src), _dp(out), int(parity))
     return out
 
 
@@ -123,7 +131,7 @@ def true_residual(dims, mass, fat, lng, b, x) -> float:
     return float(_load().or_true_residual(_L(dims), float(mass), _dp(fat), _dp(lng), _dp(b), _dp(x)))
 
 
-def cg(dims, mass, fat, lng, b, tol=1e-10, max_iter=100000, x0=None, history=False):
+def cg(dims, mass, fat, lng, b, tol=1e-10, max_iter=100000, x0=None, history=False, lib=None):
     """Conjugate gradient on A x = b (even sites) from x0 (default 0).
 
     Returns (x, info) with info = {converged, iters, true_rel[, history]}.
@@ -133,7 +141,7 @@ def cg(dims, mass, fat, lng, b, tol=1e-10, max_iter=100000, x0=None, history=Fal
     it = ctypes.c_int(0)
     tr = np.zeros(1)
     hist = np.zeros(max_iter + 1) if history else None
-    st = _load().or_cg(_L(dims), float(mass), float(tol), int(max_iter), _dp(fat), _dp(lng), _dp(b), _dp(x),
+    st = (lib or _load()).or_cg(_L(dims), float(mass), float(tol), int(max_iter), _dp(fat), _dp(lng), _dp(b), _dp(x),
                        ctypes.byref(it), _dp(tr), _dp(hist))
     info = {"converged": st == 0, "iters": it.value, "true_rel": float(tr[0])}
     if history:
@@ -141,9 +149,13 @@ def cg(dims, mass, fat, lng, b, tol=1e-10, max_iter=100000, x0=None, history=Fal
     return x, info
 
 
-def num_threads() -> int:
+def num_threads(lib=None) -> int:
     """OpenMP threads the oracle's loops use."""
-    return int(_load().or_num_threads())
+    return int((lib or _load()).or_num_threads())
+
+
+def set_num_threads(n: int, lib=None):
+    (lib or _load()).or_set_num_threads(int(n))
 
 
 def norm2(x) -> float:

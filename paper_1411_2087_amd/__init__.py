@@ -117,7 +117,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["hisq_version", "hisq_last_error", "hisq_packed_link_bytes", "hisq_pack_links", "dslash_apply",
-            "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi", "hisq_tune_dslash",
+            "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi",
+            "hisq_tune_dslash",
             "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape", "net_weight_count",
             "net_act_bytes", "net_backward_ws_bytes", "net_forward", "net_backward", "net_transport", "net_loss",
             "net_adam_step",

@@ -972,11 +972,6 @@ __global__ __launch_bounds__(FIN_NT) void k_dot2_fin(const double *__restrict__ 
 
 using namespace hisq;
 
-namespace hisq {
-// scratch of the standalone dot product: the per-workgroup partials, then the result
-constexpr size_t DOT_PART_BYTES = 2 * sizeof(double) * BLAS_MAX_BLOCKS;
-constexpr size_t DOT_WS_BYTES = DOT_PART_BYTES + 256;
-}  // namespace hisq
 
 extern "C" size_t hisq_workspace_bytes(const char *solver, const int dims[4], int nrhs, int mode, int channels)
 {
@@ -1045,8 +1040,9 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
     return rc;
 }
 
+namespace hisq {
 // Deterministic dot product on scratch `ws` (>= DOT_WS_BYTES of device memory).
-static int dot_on(const void *x, const void *y, long long n, int prec, double out_host[2], char *ws, hipStream_t s)
+int dot_on(const void *x, const void *y, long long n, int prec, double out_host[2], char *ws, hipStream_t s)
 {
     if (n == 0) {
         out_host[0] = out_host[1] = 0.0;
@@ -1055,6 +1051,7 @@ static int dot_on(const void *x, const void *y, long long n, int prec, double ou
     double *part = (double *)ws;
     double *out = (double *)(ws + DOT_PART_BYTES);
     const int nb = (int)std::min<long long>((n + 255) / 256, BLAS_MAX_BLOCKS);
+    if ((size_t)nb * 2 * sizeof(double) > DOT_PART_BYTES) return fail(HISQ_EWORKSPACE, "dot: partials exceed the scratch");
     if (prec == HISQ_F64 || prec == HISQ_F64C)
         hipLaunchKernelGGL((k_dot2<double2>), dim3(nb), dim3(BL_NT), 0, s, (const double2 *)x, (const double2 *)y, n,
                            part);
@@ -1067,6 +1064,7 @@ static int dot_on(const void *x, const void *y, long long n, int prec, double ou
     HISQ_HIP(hipStreamSynchronize(s));
     return HISQ_OK;
 }
+}  // namespace hisq
 
 extern "C" int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *workspace,
                         size_t ws_bytes, void *stream)

@@ -17,8 +17,6 @@ __device__ __forceinline__ bool solver_gate_closed(const SolverFlags *f, int gat
 {
     return gate == GATE_PAUSE ? paused(*f) : gate_closed(f, gate);
 }
-constexpr int BLAS_MAX_BLOCKS = 1024;
-
 // Device-resident scalars of one solve.  `flags` comes first: kernels gate on it.
 struct CGState {
     SolverFlags flags;
@@ -59,6 +57,15 @@ inline double link_bytes_site(int prec)
     }
 }
 inline double vec_bytes(int prec) { return (prec == HISQ_F64 || prec == HISQ_F64C) ? 48.0 : 24.0; }
+
+// Scratch of the standalone dot product: the per-workgroup partials of the
+// first stage (at most BLAS_MAX_BLOCKS workgroups, striding over the vectors)
+// and the result.  dot_on launches the two stages on `s` and copies the
+// result to out_host (synchronises `s`).
+constexpr int BLAS_MAX_BLOCKS = 1024;
+constexpr size_t DOT_PART_BYTES = 2 * sizeof(double) * BLAS_MAX_BLOCKS;
+constexpr size_t DOT_WS_BYTES = DOT_PART_BYTES + 256;
+int dot_on(const void *x, const void *y, long long n, int prec, double out_host[2], char *ws, hipStream_t s);
 
 int blas_blocks(long long n);
 size_t cg_partials_count(const Geom &g);

@@ -102,56 +102,99 @@ __device__ __forceinline__ void matvec32(const float m[18], float sg, float2 s0,
     }
 }
 
-// The four (transport, channel) pairs 4q..4q+3 of slice j at site h of
-// parity p (lane `lane` of `tile`): tv[i] = (T_k phi^c)(x) for pair 4q + i,
-// colours (re, im) x 3; zero for padding pairs and sites past Vh.
+// The site a thread transports at: its h (clamped to the last site for the
+// ragged tail of the last tile) and coordinates, computed once per tile.
+struct NetSite {
+    int hc, x, y, z, t;
+    bool valid;
+};
+__device__ __forceinline__ NetSite net_site(const Geom &g, int p, int tile, int lane)
+{
+    NetSite s;
+    const int h = tile * TILE + lane;
+    s.valid = h < g.Vh;
+    s.hc = s.valid ? h : g.Vh - 1;
+    site_coords(g, s.hc, p, s.x, s.y, s.z, s.t);
+    return s;
+}
+
+// The loads of a thread's four pairs of one slice when they share one
+// transport (C_in >= 4): the link and the four neighbour (or own) vectors,
+// kept raw so that the MFMA of the previous slice can run while they arrive.
+struct SliceRaw {
+    float m[18];
+    float2 v[4][3];
+    float sg;  // sign of the packed link (backward slots hold -F^dag)
+    int kind;  // 0: T_0 (v is the result), 1: transport, 2: padding (zero)
+};
+
+template <int CIN>
+__device__ __forceinline__ void slice_load(const Geom &g, const char *__restrict__ fat, const float2 *__restrict__ in,
+                                           int p, int tile, int lane, const NetSite &st, int j, int q, SliceRaw &r)
+{
+    static_assert(CIN >= 4, "one transport per thread and slice");
+    constexpr int KG = Slices<CIN>::KG;
+    const size_t ch_stride = (size_t)2 * g.Vh * 3;
+    const int k = j * KG + (4 * q) / CIN, c0 = (4 * q) % CIN;
+    r.kind = k == 0 ? 0 : (k < 9 ? 1 : 2);
+    r.sg = 1.0f;
+    if (r.kind == 2) return;
+    int hn = st.hc, pn = p;
+    if (k > 0) {
+        const int d = k - 1;
+        hn = nbr_h(g, st.hc, st.x, st.y, st.z, st.t, d & 3, d >= 4 ? -1 : 1);
+        pn = 1 - p;
+        load_link32(fat + (((size_t)p * g.ntiles + tile) * 8 + d) * PF32::block_bytes, lane, r.m);
+        r.sg = d >= 4 ? -1.0f : 1.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float2 *v = in + (c0 + i) * ch_stride + (size_t)pn * g.Vh * 3 + (size_t)hn * 3;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) r.v[i][a] = v[a];
+    }
+}
+
+__device__ __forceinline__ void slice_finish(const SliceRaw &r, bool valid, float tv[4][6])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (r.kind == 1) {
+            matvec32(r.m, r.sg, r.v[i][0], r.v[i][1], r.v[i][2], tv[i]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                tv[i][2 * a] = r.kind == 0 ? r.v[i][a].x : 0.f;
+                tv[i][2 * a + 1] = r.kind == 0 ? r.v[i][a].y : 0.f;
+            }
+        }
+        if (!valid)
+#pragma unroll
+            for (int e = 0; e < 6; ++e) tv[i][e] = 0.f;
+    }
+}
+
+// The four (transport, channel) pairs 4q..4q+3 of slice j at the thread's
+// site of parity p (lane `lane` of `tile`): tv[i] = (T_k phi^c)(x) for pair
+// 4q + i, colours (re, im) x 3; zero for padding pairs and sites past Vh.
 // T_0 = 1; T_{1+d}: packed direction d (0..3 = +x..+t holds F_mu(x), 4..7 =
 // -x..-t holds -F_mu(x-mu)^dag) times the neighbour one hop along d.
 // in: the channels of one batch entry, [c][parity][Vh][3].
 template <int CIN>
 __device__ __forceinline__ void slice_transport(const Geom &g, const char *__restrict__ fat,
-                                                const float2 *__restrict__ in, int p, int tile, int lane, int j,
-                                                int q, float tv[4][6])
+                                                const float2 *__restrict__ in, int p, int tile, int lane,
+                                                const NetSite &st, int j, int q, float tv[4][6])
 {
     constexpr int KG = Slices<CIN>::KG;
-    const int h = tile * TILE + lane;
-    const bool valid = h < g.Vh;
-    const int hc = valid ? h : g.Vh - 1;
-    int x, y, z, t;
-    site_coords(g, hc, p, x, y, z, t);
+    const bool valid = st.valid;
+    const int hc = st.hc, x = st.x, y = st.y, z = st.z, t = st.t;
     const size_t ch_stride = (size_t)2 * g.Vh * 3;
     const char *tb = fat + ((size_t)p * g.ntiles + tile) * 8 * PF32::block_bytes;
     if constexpr (CIN >= 4) {
-        // the four pairs share one transport
-        const int k = j * KG + (4 * q) / CIN, c0 = (4 * q) % CIN;
-        if (k == 0) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float2 *v = in + (c0 + i) * ch_stride + (size_t)p * g.Vh * 3 + (size_t)hc * 3;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float2 e = v[a];
-                    tv[i][2 * a] = e.x;
-                    tv[i][2 * a + 1] = e.y;
-                }
-            }
-        } else if (k < 9) {
-            const int d = k - 1;
-            const int nh = nbr_h(g, hc, x, y, z, t, d & 3, d >= 4 ? -1 : 1);
-            float m[18];
-            load_link32(tb + (size_t)d * PF32::block_bytes, lane, m);
-            const float sg = d >= 4 ? -1.0f : 1.0f;  // packed backward link is -F^dag
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float2 *v = in + (c0 + i) * ch_stride + (size_t)(1 - p) * g.Vh * 3 + (size_t)nh * 3;
-                matvec32(m, sg, v[0], v[1], v[2], tv[i]);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int e = 0; e < 6; ++e) tv[i][e] = 0.f;
-        }
+        SliceRaw r;
+        slice_load<CIN>(g, fat, in, p, tile, lane, st, j, q, r);
+        slice_finish(r, valid, tv);
+        return;
     } else {
         // CIN == 1: one slice holds every transport; pair i of group q is transport 4q + i
 #pragma unroll
@@ -232,41 +275,69 @@ __global__ __launch_bounds__(NET_NT) void k_net_layer(Geom g, const char *__rest
     using S = Slices<CIN>;
     constexpr int MT = (2 * COUT + 15) / 16;  // 16-row tiles of the output
     constexpr int PB = SK + 8;                // LDS pitch of a column (bf16)
-    __shared__ __align__(16) __bf16 F[NCOL * PB];
+    __shared__ __align__(16) __bf16 F[2][NCOL * PB];  // two slices: one mixed while the next is written
     const int tile = blockIdx.x, p = blockIdx.y, b = blockIdx.z;
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
+    const NetSite site = net_site(g, p, tile, lane);
     floatx4 acc[3][MT];
 #pragma unroll
     for (int n = 0; n < 3; ++n)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) acc[n][mt] = floatx4{ 0.f, 0.f, 0.f, 0.f };
     const int r16 = lane & 15, k8 = 8 * (lane >> 4);
-#pragma unroll 1
-    for (int j = 0; j < S::N; ++j) {
-        float tv[4][6];
-        slice_transport<CIN>(g, fat, inb, p, tile, lane, j, q, tv);
-        if (j) __syncthreads();  // the previous slice's operands have been read
+    auto put = [&](__bf16 *Fs, const float tv[4][6]) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            __bf16 *col = F + (3 * lane + a) * PB;
+            __bf16 *col = Fs + (3 * lane + a) * PB;
             const bf16x4 re = { (__bf16)tv[0][2 * a], (__bf16)tv[1][2 * a], (__bf16)tv[2][2 * a], (__bf16)tv[3][2 * a] };
             const bf16x4 im = { (__bf16)tv[0][2 * a + 1], (__bf16)tv[1][2 * a + 1], (__bf16)tv[2][2 * a + 1],
                                 (__bf16)tv[3][2 * a + 1] };
             *reinterpret_cast<bf16x4 *>(col + 4 * q) = re;
             *reinterpret_cast<bf16x4 *>(col + 16 + 4 * q) = im;
         }
-        __syncthreads();
+    };
+    auto mix = [&](const __bf16 *Fs, int j) {
         bf16x8 av[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
             av[mt] = *reinterpret_cast<const bf16x8 *>(A + ((size_t)j * MPAD + mt * 16 + r16) * SK + k8);
 #pragma unroll
         for (int n = 0; n < 3; ++n) {
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(F + ((3 * q + n) * 16 + r16) * PB + k8);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Fs + ((3 * q + n) * 16 + r16) * PB + k8);
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[n][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[n][mt], 0, 0, 0);
+            for (int mt = 0; mt < MT; ++mt)
+                acc[n][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[n][mt], 0, 0, 0);
         }
+    };
+    {
+        float tv[4][6];
+        slice_transport<CIN>(g, fat, inb, p, tile, lane, site, 0, q, tv);
+        put(F[0], tv);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int j = 0; j < S::N; ++j) {
+        // slice j is in F[j & 1]; F[(j + 1) & 1] was last read before the previous barrier
+        if constexpr (CIN >= 4) {
+            SliceRaw r;
+            const bool more = j + 1 < S::N;
+            if (more) slice_load<CIN>(g, fat, inb, p, tile, lane, site, j + 1, q, r);  // in flight over the MFMA
+            mix(F[j & 1], j);
+            if (more) {
+                float tv[4][6];
+                slice_finish(r, site.valid, tv);
+                put(F[(j + 1) & 1], tv);
+            }
+        } else {
+            mix(F[j & 1], j);
+            if (j + 1 < S::N) {
+                float tv[4][6];
+                slice_transport<CIN>(g, fat, inb, p, tile, lane, site, j + 1, q, tv);
+                put(F[(j + 1) & 1], tv);
+            }
+        }
+        __syncthreads();
     }
     // D[row][col]: lane holds column r16 of its tile and rows 4 (lane >> 4) + 0..3
     float *o = reinterpret_cast<float *>(out);
@@ -274,6 +345,13 @@ __global__ __launch_bounds__(NET_NT) void k_net_layer(Geom g, const char *__rest
     for (int n = 0; n < 3; ++n) {
         const int col = (3 * q + n) * 16 + r16, s = col / 3, a = col % 3, h = tile * TILE + s;
         if (h >= g.Vh) continue;
+        if constexpr (COUT == 16) {
+            // row tile 0 holds Re, row tile 1 Im of the same four channels
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[feat_idx(b, COUT, 4 * (lane >> 4) + i, p, g.Vh, h) + a] = make_float2(acc[n][0][i], acc[n][1][i]);
+            continue;
+        }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -299,9 +377,10 @@ __global__ __launch_bounds__(NET_NT) void k_net_transport(Geom g, const char *__
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int h = tile * TILE + lane;
     const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
+    const NetSite site = net_site(g, p, tile, lane);
     for (int j = 0; j < S::N; ++j) {
         float tv[4][6];
-        slice_transport<CIN>(g, fat, inb, p, tile, lane, j, q, tv);
+        slice_transport<CIN>(g, fat, inb, p, tile, lane, site, j, q, tv);
         if (h >= g.Vh) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -334,10 +413,10 @@ __global__ __launch_bounds__(NET_NT) void k_net_wgrad(Geom g, const char *__rest
     constexpr int KT = 2 * NCOL;  // K per tile
     constexpr int PK = KT + 8;    // LDS pitch (bf16)
     constexpr int PART = S::N * MT * 256;
-    __shared__ __align__(16) __bf16 lds[(16 + MT * 16) * PK];
-    __bf16 *Fb = lds;            // B: [pair][K]
-    __bf16 *Ga = lds + 16 * PK;  // A: [row][K]
-    static_assert(PART * 4 <= (16 + MT * 16) * PK * 2, "partial reduction does not fit the LDS operands");
+    __shared__ __align__(16) __bf16 lds[(32 + MT * 16) * PK];
+    __bf16 *Fbuf[2] = { lds, lds + 16 * PK };  // B: [pair][K], two slices (one mixed while the next is written)
+    __bf16 *Ga = lds + 32 * PK;                // A: [row][K]
+    static_assert(PART * 4 <= (32 + MT * 16) * PK * 2, "partial reduction does not fit the LDS operands");
     constexpr int KSW = 3 * MT;  // K steps of a wave
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int r16 = lane & 15, k8 = 8 * (lane >> 4);
@@ -352,6 +431,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_wgrad(Geom g, const char *__rest
     for (int u = blockIdx.x; u < units; u += gridDim.x) {
         const int b = u / (2 * g.ntiles), p = (u / g.ntiles) % 2, tile = u % g.ntiles;
         const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
+        const NetSite site = net_site(g, p, tile, lane);
         __syncthreads();  // the previous unit's operands have been read
         for (int i = threadIdx.x; i < COUT * NCOL; i += NET_NT) {
             const int a = i / NCOL, jc = i % NCOL, h = tile * TILE + jc / 3;
@@ -360,12 +440,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_wgrad(Geom g, const char *__rest
             *reinterpret_cast<bf16x2 *>(Ga + a * PK + 2 * jc) = bf16x2{ (__bf16)v.x, (__bf16)v.y };
             *reinterpret_cast<bf16x2 *>(Ga + (COUT + a) * PK + 2 * jc) = bf16x2{ (__bf16)v.y, (__bf16)(-v.x) };
         }
-        // unrolled: acc[j] must stay in registers
-#pragma unroll
-        for (int j = 0; j < S::N; ++j) {
-            float tv[4][6];
-            slice_transport<CIN>(g, fat, inb, p, tile, lane, j, q, tv);
-            if (j) __syncthreads();
+        auto put = [&](__bf16 *Fb, const float tv[4][6]) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 __bf16 *row = Fb + (4 * q + i) * PK + 6 * lane;
@@ -373,13 +448,34 @@ __global__ __launch_bounds__(NET_NT) void k_net_wgrad(Geom g, const char *__rest
                 for (int a = 0; a < 3; ++a)
                     *reinterpret_cast<bf16x2 *>(row + 2 * a) = bf16x2{ (__bf16)tv[i][2 * a], (__bf16)tv[i][2 * a + 1] };
             }
-            __syncthreads();
+        };
+        {
+            float tv[4][6];
+            slice_transport<CIN>(g, fat, inb, p, tile, lane, site, 0, q, tv);
+            put(Fbuf[0], tv);
+        }
+        __syncthreads();  // g and slice 0 are in LDS
+        // unrolled: acc[j] must stay in registers; slice j + 1's loads are in flight over slice j's MFMA
+#pragma unroll
+        for (int j = 0; j < S::N; ++j) {
+            const bool more = j + 1 < S::N;
+            SliceRaw r;
+            if constexpr (CIN >= 4)
+                if (more) slice_load<CIN>(g, fat, inb, p, tile, lane, site, j + 1, q, r);
+            const __bf16 *Fb = Fbuf[j & 1];
 #pragma unroll
             for (int ks = ks0; ks < ks0 + KSW; ++ks) {
                 const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Fb + r16 * PK + SK * ks + k8);
                 const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Ga + (wmt * 16 + r16) * PK + SK * ks + k8);
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
             }
+            if (more) {
+                float tv[4][6];
+                if constexpr (CIN >= 4) slice_finish(r, site.valid, tv);
+                else slice_transport<CIN>(g, fat, inb, p, tile, lane, site, j + 1, q, tv);
+                put(Fbuf[(j + 1) & 1], tv);
+            }
+            __syncthreads();
         }
     }
     // the waves' accumulators of each row tile, summed in wave order through LDS
@@ -402,26 +498,43 @@ __global__ __launch_bounds__(NET_NT) void k_net_wgrad(Geom g, const char *__rest
     for (int i = threadIdx.x; i < PART; i += NET_NT) dst[i] = red[i];
 }
 
-// grad_w[k][a][c] = sum over blocks (FP64, fixed order) of the partial at
-// slice k / KG, rows a (Re) and COUT + a (Im), pair (k % KG) CIN + c
+// grad_w from the per-workgroup partials [nblocks][PART] (FP32): each entry
+// summed over the workgroups in FP64 in a fixed order -- a workgroup takes 64
+// consecutive entries (coalesced reads), its four waves the workgroups g,
+// g + 4, ... (four running sums each), the four groups added in order -- then
+// written to its place: entry ((j MT + mt) 16 + r) 16 + pi is row m = 16 mt + r
+// (Re of channel m, or Im of m - COUT) and pair pi (transport j KG + pi / CIN,
+// channel pi % CIN) of slice j.
 template <int CIN, int COUT>
-__global__ void k_net_wgrad_reduce(const float *__restrict__ partials, int nblocks, float2 *__restrict__ gw)
+__global__ __launch_bounds__(256) void k_net_wgrad_reduce(const float *__restrict__ partials, int nblocks,
+                                                          float *__restrict__ gw)
 {
     using S = Slices<CIN>;
     constexpr int MT = (2 * COUT + 15) / 16;
     constexpr int PART = S::N * MT * 256;
-    const int n = 9 * COUT * CIN;
-    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) {
-        const int k = i / (COUT * CIN), a = (i / CIN) % COUT, c = i % CIN;
-        const int j = k / S::KG, pi = (k % S::KG) * CIN + c;
-        const int ore = (j * MT * 16 + a) * 16 + pi, oim = (j * MT * 16 + COUT + a) * 16 + pi;
-        double re = 0.0, im = 0.0;
-        for (int bl = 0; bl < nblocks; ++bl) {
-            re += partials[(size_t)bl * PART + ore];
-            im += partials[(size_t)bl * PART + oim];
+    const int l = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + l;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (e < PART) {
+        int bl = grp;
+        for (; bl + 12 < nblocks; bl += 16) {
+            s0 += partials[(size_t)bl * PART + e];
+            s1 += partials[(size_t)(bl + 4) * PART + e];
+            s2 += partials[(size_t)(bl + 8) * PART + e];
+            s3 += partials[(size_t)(bl + 12) * PART + e];
         }
-        gw[i] = make_float2((float)re, (float)im);
+        for (; bl < nblocks; bl += 4) s0 += partials[(size_t)bl * PART + e];
     }
+    __shared__ double red[4][64];
+    red[grp][l] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (grp || e >= PART) return;
+    const double tot = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
+    const int pi = e % 16, m = (e / 16) % (MT * 16), j = e / (16 * MT * 16);
+    const int k = j * S::KG + pi / CIN, c = pi % CIN;
+    if (m >= 2 * COUT || k >= 9) return;
+    const int a = m < COUT ? m : m - COUT;
+    gw[2 * (((size_t)k * COUT + a) * CIN + c) + (m < COUT ? 0 : 1)] = (float)tot;
 }
 
 // ------------------------------------------------------------------ embedding, loss, Adam
@@ -635,7 +748,9 @@ static void wgrad_launch(const Geom &g, const void *fat, const float2 *in, const
     const int nb = wgrad_blocks(g, batch);
     hipLaunchKernelGGL((k_net_wgrad<CIN, COUT>), dim3(nb), dim3(NET_NT), 0, s, g, (const char *)fat, in, gout, batch,
                        part);
-    hipLaunchKernelGGL((k_net_wgrad_reduce<CIN, COUT>), dim3(16), dim3(256), 0, s, (const float *)part, nb, gw);
+    constexpr int part_entries = Slices<CIN>::N * ((2 * COUT + 15) / 16) * 256;
+    hipLaunchKernelGGL((k_net_wgrad_reduce<CIN, COUT>), dim3((part_entries + 63) / 64), dim3(256), 0, s,
+                       (const float *)part, nb, (float *)gw);
 }
 
 template <int C>

@@ -55,6 +55,56 @@ def initial_weights(C, scale, noise, noise_seed):
     return w + noise * z
 
 
+def lambda_max_estimate(links64: Links, mass, dims, steps=40, seed=999):
+    """The largest eigenvalue of A(mass) by power iteration on the FP64 operator: sqrt(|A^(k+1) v|^2 / |A^k v|^2)
+    after `steps` applications to a Gaussian v (no normalisation needed in FP64 for |lambda| < 1e6), raised by 5 %
+    (the iteration approaches it from below)."""
+    import synth
+    v = torch.from_numpy(synth.source(dims, seed)).cuda()
+    w, tmp = torch.empty_like(v), torch.empty_like(v)
+    ws = torch.empty(hisq_workspace_bytes("dot", dims), dtype=torch.uint8, device=v.device)
+    n = v.shape[0] * 3
+    prev = hisq_dot(v, v, n, HISQ_F64, ws).real
+    lam = 0.0
+    for _ in range(steps):
+        hisq_apply_A(mass, links64.fat, links64.lng, v, w, tmp, dims, HISQ_F64)
+        cur = hisq_dot(w, w, n, HISQ_F64, ws).real
+        lam = float(np.sqrt(cur / prev))
+        prev = cur
+        v, w = w, v
+    return 1.05 * lam
+
+
+def chebyshev_weights(C, mass, lambda_max):
+    """Weights with which the network computes K = p(A) exactly when the operator's long links are zero (its
+    Dslash is then D = sum_mu T_{+mu} - T_{-mu} over the fat-link transports the layers already apply), p the
+    quadratic for which 1 - l p(l) is the degree-3 Chebyshev polynomial shifted to [4 m^2, lambda_max] and
+    normalised to 1 at l = 0: the quadratic that minimises max |1 - l p(l)| on the spectrum's interval, so the
+    condition number of K A is that of A over (d + 1)^2 = 9.  With D^2 = 4 m^2 - A on the even sites the layers
+    carry phi, D phi -> phi, D^2 phi -> phi, D^3 phi, D^2 phi -> alpha phi + beta D^2 phi + gamma D^4 phi (C >= 4).
+    A reference for the trained networks: it is built, not learned."""
+    from numpy.polynomial import Polynomial
+    a, b = 4.0 * mass * mass, float(lambda_max)
+    y = Polynomial([(b + a) / (b - a), -2.0 / (b - a)])   # [a, b] -> [1, -1]
+    t3 = Polynomial([0.0, -3.0, 0.0, 4.0])                 # T_3(y) = 4 y^3 - 3 y
+    q = t3(y) / t3((b + a) / (b - a))                      # q(0) = 1
+    c0, c1, c2 = -q.coef[1], -q.coef[2], -q.coef[3]        # p(l) = (1 - q(l)) / l
+    alpha, beta, gamma = c0 + a * c1 + a * a * c2, -c1 - 2 * a * c2, c2
+    Ws = [np.zeros((9, co, ci), np.complex64) for co, ci in LAYER_SHAPES(C)]
+    sgn = [0.0, 1.0, 1.0, 1.0, 1.0, -1.0, -1.0, -1.0, -1.0]  # D: +1 on the forward hops, -1 on the backward ones
+    Ws[0][0, 0, 0] = 1.0
+    Ws[0][:, 1, 0] = sgn                                   # ch0 = phi, ch1 = D phi
+    Ws[1][0, 0, 0] = 1.0
+    Ws[1][:, 1, 1] = sgn                                   # ch0 = phi, ch1 = D^2 phi
+    Ws[2][0, 0, 0] = 1.0
+    Ws[2][:, 1, 1] = sgn
+    Ws[2][0, 2, 1] = 1.0                                   # ch0 = phi, ch1 = D^3 phi, ch2 = D^2 phi
+    Ws[3][0, 0, 0] = alpha
+    Ws[3][0, 0, 2] = beta
+    Ws[3][:, 0, 1] = np.asarray(sgn) * gamma               # out = alpha phi + beta D^2 phi + gamma D^4 phi
+    return flatten(Ws), (c0, c1, c2)
+
+
 def make_pairs(dims, mass, links64: Links, links32: Links, sources: np.ndarray, tol=1e-8, device="cuda", log=None):
     """x_i = A(mass)^-1 b_i for every source, by the batched reliable-update CG, 16 at a time.
     Returns (b, x) as device complex64 tensors [n][Vh][3], the total solve time and x in complex128.

@@ -127,3 +127,4 @@ def test_shift_and_dot_validation_without_gpu():
     assert lib.hisq_dot(p[0], p[1], 10, 0, out, None, 0, None) == -7
     assert lib.hisq_dot(p[0], p[1], 10, 0, out, p[2], need - 1, None) == -7
     assert lib.hisq_dot(p[0], p[1], -1, 0, out, p[2], need, None) == -1
+

