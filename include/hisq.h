@@ -218,6 +218,16 @@ int hisq_apply_A(double mass, const void *fat, const void *lng, const void *x, v
 int hisq_dot(const void *x, const void *y, long long n, int prec, double out_host[2], void *workspace,
              size_t ws_bytes, void *stream);
 
+/* hisq_dot without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops): the same two
+ * kernels and result, on the library's own scratch, a static device array of
+ * 16.25 KB per GPU (the first stage's at most 1024 partial pairs and the
+ * result) held until the process ends.  Every call on a GPU uses that GPU's
+ * one array: calls that overlap on one GPU race.  Any n from 0 to 2^37
+ * complex entries (larger is HISQ_EINVAL); the scratch never grows with n.
+ * Synchronises `stream`. */
+int hisq_dot_noalloc(const void *x, const void *y, long long n, int prec, double out_host[2], void *stream);
+
 /* Autotuner of the single-RHS Dslash launch shape (threads per workgroup,
  * occupancy target): times every shape with HIP events on the caller's
  * buffers (dst = D src on parity 1, `reps` launches each, 20 if <= 0),

@@ -76,6 +76,7 @@ def _load():
     lib.dslash_apply.argtypes = [vp, vp, vp, vp, ctypes.c_int, ip, ctypes.c_int, vp]
     lib.hisq_apply_A.argtypes = [d, vp, vp, vp, vp, vp, ip, ctypes.c_int, vp]
     lib.hisq_dot.argtypes = [vp, vp, ctypes.c_longlong, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+    lib.hisq_dot_noalloc.argtypes = [vp, vp, ctypes.c_longlong, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
     lib.hisq_workspace_bytes.argtypes = [ctypes.c_char_p, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.hisq_workspace_bytes.restype = sz
     lib.cg_solve.argtypes = [d, d, vp, vp, vp, vp, vp, vp, ip, ctypes.POINTER(CGOpts), vp, sz,
@@ -107,7 +108,7 @@ def _load():
     lib.hisq_fold_links.argtypes = [vp, ip, ctypes.c_int, ctypes.c_int, vp]
     lib.hisq_read_probe.argtypes = [vp, sz, vp, sz, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
     for name in ("hisq_three_link", "hisq_fat_paths", "hisq_fold_links", "hisq_read_probe", "hisq_pack_links",
-                 "dslash_apply", "hisq_apply_A", "hisq_dot", "cg_solve", "cg_solve_multi",
+                 "dslash_apply", "hisq_apply_A", "hisq_dot", "hisq_dot_noalloc", "cg_solve", "cg_solve_multi",
                  "hisq_tune_dslash", "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape",
                  "net_forward", "net_backward", "net_transport", "net_loss", "net_adam_step", "fcg_solve"):
         getattr(lib, name).restype = ctypes.c_int
@@ -117,7 +118,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["hisq_version", "hisq_last_error", "hisq_packed_link_bytes", "hisq_pack_links", "dslash_apply",
-            "hisq_apply_A", "hisq_dot", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi",
+            "hisq_apply_A", "hisq_dot", "hisq_dot_noalloc", "hisq_workspace_bytes", "cg_solve", "cg_solve_multi",
             "hisq_tune_dslash",
             "hisq_dslash_shape", "hisq_dslash_multi", "hisq_tune_multi", "hisq_multi_shape", "net_weight_count",
             "net_act_bytes", "net_backward_ws_bytes", "net_forward", "net_backward", "net_transport", "net_loss",
@@ -211,6 +212,13 @@ def hisq_dot(x, y, n, prec, workspace=None, stream=None) -> complex:
     out = (ctypes.c_double * 2)()
     _check(_lib.hisq_dot(_ptr(x), _ptr(y), int(n), int(prec), out, _ptr(workspace), _nbytes(workspace),
                          _stream(stream)), "hisq_dot")
+    return complex(out[0], out[1])
+
+
+def hisq_dot_noalloc(x, y, n, prec, stream=None) -> complex:
+    """<x, y> over n complex entries on the library's static scratch (no allocation anywhere)."""
+    out = (ctypes.c_double * 2)()
+    _check(_lib.hisq_dot_noalloc(_ptr(x), _ptr(y), int(n), int(prec), out, _stream(stream)), "hisq_dot_noalloc")
     return complex(out[0], out[1])
 
 

@@ -128,3 +128,14 @@ def test_shift_and_dot_validation_without_gpu():
     assert lib.hisq_dot(p[0], p[1], 10, 0, out, p[2], need - 1, None) == -7
     assert lib.hisq_dot(p[0], p[1], -1, 0, out, p[2], need, None) == -1
 
+
+def test_dot_noalloc_validation_without_gpu():
+    """The no-allocation dot product refuses bad sizes before touching a GPU."""
+    import paper_1411_2087_amd as hq
+    lib = hq._lib
+    p = [ctypes.c_void_p(0x1000 * (i + 1)) for i in range(2)]
+    out = (ctypes.c_double * 2)()
+    assert lib.hisq_dot_noalloc(p[0], p[1], -1, 0, out, None) == -1
+    assert lib.hisq_dot_noalloc(p[0], p[1], 1 << 38, 0, out, None) == -1 and b"2^37" in lib.hisq_last_error()
+    assert lib.hisq_dot_noalloc(None, p[1], 10, 0, out, None) == -1
+    assert lib.hisq_dot_noalloc(p[0], p[1], 10, 9, out, None) == -1
