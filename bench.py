@@ -91,6 +91,101 @@ def traffic_from_profile(vh, shape):
     return round(row["bytes_per_launch"]) if row else None
 
 
+NET_SOURCES = ["paper_1411_2087_amd/csrc/net.hip"]
+NET_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "net_16x16x16x16_b16_c16_traffic.json")
+
+
+def net_layer_bytes(cin, cout, sites):
+    """Algorithmic bytes of one network layer (or its weight gradient) over `sites` (sites x batch): per site the
+    four FP32 fat links it owns (each link serves two sites, 4 x 72 B) and the input and output features
+    (24 B per channel: 3 complex64), links counted once per batch element."""
+    return (4 * 72 + (cin + cout) * 24) * sites
+
+
+def summarize_counters(kind, fetch_dir, write_dir):
+    """HBM traffic per launch from a pair of rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, in KiB per
+    dispatch) of a traffic probe, each counter scaled by what it reads for the probe's 1 GiB device copy.
+    kind "cg": the plain CG's k_cg_Dp / k_cg_Ap_upd / k_cg_p_norm on 32^4; kind "net": the network kernels on
+    16^4, batch 16, C = 16.  Writes the JSON summary under profiles/ and prints a markdown table."""
+    import csv
+    import glob
+    import re
+
+    def rows(d, counter):
+        out = []
+        for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+            with open(path) as f:
+                for r in csv.DictReader(f):
+                    if r.get("Counter_Name") == counter:
+                        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+                        out.append((r["Kernel_Name"], float(r["Counter_Value"]), us))
+        if not out:
+            raise SystemExit(f"no {counter} rows under {d}")
+        return out
+    fetch, write = rows(fetch_dir, "FETCH_SIZE"), rows(write_dir, "WRITE_SIZE")
+    copy_bytes = 1 << 30
+
+    def copy_kib(rs):
+        big = sorted(v for k, v, _ in rs if "copyBuffer" in k and v * 1024 > 0.25 * copy_bytes)
+        if not big:
+            raise SystemExit("no 1 GiB copy among the dispatches")
+        return big[len(big) // 2]
+    cf, cw = copy_kib(fetch), copy_kib(write)
+    ff, wf = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    if kind == "cg":
+        vh, sources, out_file = DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3] // 2, CG_SOURCES, CG_TRAFFIC_FILE
+        algo = {"k_cg_Ap_upd": AP_UPD_BYTES * vh, "k_cg_Dp": DP_BYTES * vh, "k_cg_p_norm": 3 * 48 * vh}
+
+        def label(name):
+            m = re.search(r"(k_cg_Ap_upd|k_cg_Dp|k_cg_p_norm)\b", name)
+            return m.group(1) if m else None
+    elif kind == "net":
+        V, batch, sources, out_file = 16 ** 4, 16, NET_SOURCES, NET_TRAFFIC_FILE
+        vh = V // 2
+        algo = {}
+
+        def label(name):
+            m = re.search(r"(k_net_layer|k_net_wgrad)<(\d+), ?(\d+)", name)
+            if not m:
+                return None
+            lab = f"{m.group(1)}<{m.group(2)},{m.group(3)}>"
+            algo[lab] = net_layer_bytes(int(m.group(2)), int(m.group(3)), V * batch)
+            return lab
+    else:
+        raise SystemExit(f"unknown counter summary kind {kind}")
+    groups = {}
+    for rs, key in ((fetch, "fetch"), (write, "write")):
+        for name, v, us in rs:
+            lab = label(name)
+            if lab:
+                groups.setdefault(lab, {"fetch": [], "write": [], "us": []})[key].append(v)
+                if key == "fetch":
+                    groups[lab]["us"].append(us)
+    table = {}
+    for lab, g in sorted(groups.items()):
+        fk, wk = sum(g["fetch"]) / len(g["fetch"]), sum(g["write"]) / len(g["write"])
+        fb, wb = fk * 1024 * ff, wk * 1024 * wf
+        us = sum(g["us"]) / len(g["us"])
+        table[lab] = {"dispatches": [len(g["fetch"]), len(g["write"])], "fetch_kib": fk, "write_kib": wk,
+                      "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                      "algorithmic_bytes": algo[lab], "ratio_to_algorithmic": (fb + wb) / algo[lab],
+                      "avg_us_under_counters": us}
+    res = {"kind": kind, "vh": vh, "source_sha": dslash_source_sha(sources), "copy_bytes": copy_bytes,
+           "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_factor": ff, "write_factor": wf, "kernels": table}
+    with open(out_file, "w") as f:
+        json.dump(res, f, indent=1)
+    print(f"Calibration: a device copy of {copy_bytes} B reads as FETCH_SIZE {cf:.0f} KiB and WRITE_SIZE "
+          f"{cw:.0f} KiB: one counter KiB is {ff:.3f} KiB fetched and {wf:.3f} KiB written.\n")
+    print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read GB | HBM written GB | algorithmic GB "
+          "| traffic / algorithmic | avg us under counters |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for lab, t in table.items():
+        print(f"| `{lab}` | {t['dispatches'][0]} | {t['fetch_kib']:.0f} | {t['write_kib']:.0f} | "
+              f"{t['fetch_bytes'] / 1e9:.4f} | {t['write_bytes'] / 1e9:.4f} | {t['algorithmic_bytes'] / 1e9:.4f} | "
+              f"{t['ratio_to_algorithmic']:.3f} | {t['avg_us_under_counters']:.1f} |")
+    print(f"\nKernel sources hash: `{res['source_sha']}`.")
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -491,6 +586,17 @@ def run_net_kernels(args, dims=(16, 16, 16, 16), C=16, batch=16, reps=5):
     acts = torch.empty(hq.net_act_bytes(dims, C, batch), dtype=torch.uint8, device="cuda")
     ws = torch.empty(hq.net_backward_ws_bytes(dims, C, batch), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
+    if args.traffic_probe:  # counter calibration, then one forward and one backward
+        cs = torch.ones((1 << 30) // 4, dtype=torch.float32, device="cuda")
+        cd = torch.empty_like(cs)
+        for _ in range(3):
+            cd.copy_(cs)
+        del cs, cd
+        hq.net_forward(L32.fat, w, C, b, y, acts, batch, dims)
+        hq.net_backward(L32.fat, w, C, acts, gout, gw, gin, batch, dims, ws)
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": True, "copy_bytes": 1 << 30, "workload": "net-kernels"}))
+        return
 
     def fwd():
         hq.net_forward(L32.fat, w, C, b, y, acts, batch, dims)
@@ -501,7 +607,7 @@ def run_net_kernels(args, dims=(16, 16, 16, 16), C=16, batch=16, reps=5):
     bwd()
     t_f = timed(fwd, reps, stream) * 1e-6  # seconds per call
     t_b = timed(bwd, reps, stream) * 1e-6
-    layer_bytes = lambda ci, co: (4 * 72 + (ci + co) * 24) * V * batch
+    layer_bytes = lambda ci, co: net_layer_bytes(ci, co, V * batch)
     fwd_bytes = layer_bytes(1, C) + 2 * layer_bytes(C, C) + layer_bytes(C, 1)
     # backward: weight gradients (links, input, upstream gradient) and the three input gradients it needs
     bwd_bytes = fwd_bytes + layer_bytes(1, C) + 2 * layer_bytes(C, C)
@@ -755,6 +861,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (multi-RHS / multi-shift) forms")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
     ap.add_argument("--no-large", action="store_true", help="skip the 48^3x96 entries of the default line")
+    ap.add_argument("--counter-summary", nargs=3, metavar=("KIND", "FETCH_DIR", "WRITE_DIR"),
+                    help="on the host, after two rocprofv3 --pmc runs of a traffic probe (FETCH_SIZE, WRITE_SIZE): "
+                         "write the calibrated per-launch HBM traffic of the plain CG kernels (KIND cg) or the "
+                         "network kernels (KIND net) under profiles/ and print a markdown table")
     ap.add_argument("--workload", default="32x32x32x32",
                     help="32x32x32x32 (default: plain FP64 CG, the metric's workload), 48x48x48x96 "
                          "(mixed precision against plain FP64 on the large lattice), paper-grids (the Dslash "
@@ -780,6 +890,10 @@ def main():
     import paper_1411_2087_amd as hq
     import synth
 
+    if args.counter_summary:
+        return summarize_counters(*args.counter_summary)
+    if args.traffic_probe and args.workload == "net-kernels":
+        return run_net_kernels(args)
     if args.traffic_probe and args.workload != "32x32x32x32":
         return traffic_probe_at(args.workload)
     if args.workload == "48x48x48x96":

@@ -299,7 +299,8 @@ int hisq_dslash_multi(const void *fat, const void *lng, const void *src, void *d
  * `reps` launches each) and remembers the fastest for hisq_dslash_multi.
  * cg_solve_multi chooses its own shape once per (dims, inner links, batch
  * size), timing its iteration's two launches, whose update epilogue needs
- * more registers per right-hand side.  us_per_shape (may be NULL) gets 4 entries
+ * more registers per right-hand side.  us_per_shape (may be NULL) gets
+ * hisq_multi_shape(dims, nrhs, -2) entries
  * (-1 for shapes that do not apply to nrhs).  Synchronises `stream`. */
 int hisq_tune_multi(const void *fat, const void *lng, const void *src, void *dst, const int dims[4], int nrhs,
                     void *workspace, size_t ws_bytes, int reps, int *best_shape, double *us_per_shape,

@@ -248,7 +248,7 @@ def hisq_dslash_multi(fat, lng, src, dst, parity, nrhs, dims, workspace, stream=
 def hisq_tune_multi(fat, lng, src, dst, dims, nrhs, workspace, reps=10, stream=None):
     """Time every multi-RHS Dslash shape; returns (best_shape, [microseconds per shape, -1 if n/a])."""
     best = ctypes.c_int(-1)
-    us = (ctypes.c_double * 4)()
+    us = (ctypes.c_double * int(_lib.hisq_multi_shape(_dims(dims), int(nrhs), -2)))()
     _check(_lib.hisq_tune_multi(_ptr(fat), _ptr(lng), _ptr(src), _ptr(dst), _dims(dims), int(nrhs), _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), int(reps), ctypes.byref(best), us,
                                 _stream(stream)), "hisq_tune_multi")

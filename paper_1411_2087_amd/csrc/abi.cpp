@@ -53,15 +53,20 @@ static int block_of(int L)
     return 1;
 }
 
-bool blocked_order(Geom &g)
+bool blocked_order(Geom &g, int tb, int zb)
 {
     if ((g.Lxh * g.L[1]) % TILE) return false;
+    if (tb <= 0) tb = block_of(g.L[3]);
+    if (zb <= 0) zb = block_of(g.L[2]);
+    if (g.L[3] % tb || g.L[2] % zb) return false;
     g.oP = g.Lxh * g.L[1] / TILE;
-    g.otb = block_of(g.L[3]);
-    g.ozb = block_of(g.L[2]);
+    g.otb = tb;
+    g.ozb = zb;
     g.ontb = g.L[3] / g.otb;
     return true;
 }
+
+bool blocked_order(Geom &g) { return blocked_order(g, 0, 0); }
 
 }  // namespace hisq
 

@@ -24,6 +24,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "cg_internal.hpp"
@@ -86,12 +87,18 @@ __device__ __forceinline__ void wave_sync()
 // it), the chunks go to LDS in that order, and each thread reads its G
 // right-hand sides back.  With that and every neighbour load issued ahead of
 // the mask tests, the N = 16 Dslash at 32^4 went from 745 to 431 us.
+// PIPE (FP32 links, LDS staging): the link and neighbour loads of direction
+// d + 1 leave before the products of direction d, so one direction's
+// latency overlaps the previous direction's arithmetic instead of being
+// hidden only by other wavefronts.  Full FP32 matrices only: a two-row or
+// 16-bit link is rebuilt or converted as soon as it arrives, which would
+// wait for the load at the point where it is issued.
 //   EPI_STORE      : dst = D src
 //   EPI_STORE_NORM : dst = D src, partial |dst|^2 per RHS
 //   EPI_UPD        : (FP32) with x = p: a = m4_r p - D src in registers, dst (= xs) += alpha_r p,
 //                    rs -= alpha_r a, partial |rs|^2 per RHS
 //   EPI_RESID      : (FP64) dst = b - (m4_r x - D src), rs = float(dst), partial |dst|^2 per RHS
-template <class P, int N, int G, int NT, int EPI>
+template <class P, int N, int G, int NT, int EPI, bool PIPE = false>
 __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__ fat, const char *__restrict__ lng,
                                                 const typename P::cvec *__restrict__ src,
                                                 typename P::cvec *__restrict__ dst,
@@ -109,6 +116,7 @@ __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__
     constexpr int MD_K4 = 3 * N / 2;                      // 16-byte chunks per site block
     constexpr int MD_C4 = (64 / TPS) * MD_K4;             // chunks per wavefront and direction
     constexpr int MD_RR = (MD_C4 + 63) / 64;              // load rounds
+    constexpr bool MD_PIPE = PIPE && MD_LDS && std::is_same<P, PF32>::value;
     __shared__ float4 stage_all[MD_LDS ? NT / 64 : 1][MD_LDS ? MD_C4 : 1];
     float4 *stage = stage_all[MD_LDS ? (threadIdx.x >> 6) : 0];
     const int wl = threadIdx.x & 63;
@@ -132,7 +140,11 @@ __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__
     for (int u = local; u < units_per_xcd; u += per_xcd) {
         const int unit = xcd * units_per_xcd + u;
         if (unit >= nunits) break;
-        const int site = unit * SPB + threadIdx.x / TPS;
+        // the unit's sites in processing order; with the blocked tile order
+        // (g.oP != 0, tile_of) the t and z neighbours of the sites in flight
+        // were gathered shortly before and are still in L2
+        const int s_ord = unit * SPB + threadIdx.x / TPS;
+        const int site = s_ord < g.Vh ? tile_of(g, s_ord / TILE) * TILE + s_ord % TILE : s_ord;
         const int h = site < g.Vh ? site : g.Vh - 1;
         const int tile = h / TILE, lane = h % TILE;
         int cx, cy, cz, ct;
@@ -145,6 +157,60 @@ __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__
         for (int j = 0; j < G; ++j)
 #pragma unroll
             for (int i = 0; i < 6; ++i) acc[j][i] = 0;
+        if constexpr (MD_PIPE) {
+            // native vectors: copies of HIP's float4 struct go through memory
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            R mn[18];             // the link of the next direction, in flight
+            f4v pre[MD_RR];       // its neighbour chunks, in flight
+            // step d: publish direction d, issue the loads of d + 1, then the products of d
+            // (step -1 only issues direction 0)
+#pragma unroll 1
+            for (int d = -1; d < 16; ++d) {
+                R m[18];
+                if (d >= 0) {
+#pragma unroll
+                    for (int i = 0; i < 18; ++i) m[i] = mn[i];
+                    wave_sync();  // every lane has read the previous direction's blocks
+#pragma unroll
+                    for (int q = 0; q < MD_RR; ++q) {
+                        const int j = q * 64 + wl;
+                        if ((MD_C4 % 64 == 0) || j < MD_C4) reinterpret_cast<f4v *>(stage)[j] = pre[q];
+                    }
+                    wave_sync();
+                }
+                if (d + 1 < 16) {
+                    const int dn = d + 1, mu = dn & 3;
+                    const bool is_long = dn >= 8;
+                    const int k = (is_long ? 3 : 1) * (((dn >> 2) & 1) ? -1 : 1);
+                    const int nh = nbr_h(g, h, cx, cy, cz, ct, mu, k);
+                    if (is_long) P::Long::load_dir(lng_t, dn & 7, lane, mn);
+                    else P::Fat::load_dir(fat_t, dn & 7, lane, mn);
+#pragma unroll
+                    for (int q = 0; q < MD_RR; ++q) {
+                        const int j = q * 64 + wl;
+                        const bool in = (MD_C4 % 64 == 0) || j < MD_C4;
+                        const int sj = (in ? j : 0) / MD_K4, kj = (in ? j : 0) - sj * MD_K4;
+                        const int ns = __shfl(nh, sj * TPS);
+                        pre[q] = reinterpret_cast<const f4v *>(src)[(size_t)ns * MD_K4 + kj];
+                    }
+                }
+                if (d < 0) continue;
+                const float4 *o = stage + (wl / TPS) * MD_K4 + r0 * 3 / 2;
+                float f[6 * G];
+#pragma unroll
+                for (int q = 0; q < 3 * G / 2; ++q) {
+                    const float4 w = o[q];
+                    f[4 * q] = w.x;
+                    f[4 * q + 1] = w.y;
+                    f[4 * q + 2] = w.z;
+                    f[4 * q + 3] = w.w;
+                }
+#pragma unroll
+                for (int j = 0; j < G; ++j)
+                    cmac<P>(acc[j], m, make_float2(f[6 * j], f[6 * j + 1]), make_float2(f[6 * j + 2], f[6 * j + 3]),
+                            make_float2(f[6 * j + 4], f[6 * j + 5]));
+            }
+        } else
 #pragma unroll 1
         for (int d = 0; d < 16; ++d) {
             const int mu = d & 3;
@@ -944,14 +1010,44 @@ static int device_cus()
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 constexpr size_t MSKEW = 4352;
 
-// Launch shapes of the multi-RHS Dslash: RHS per thread G (as a divisor of N)
-// and threads per block.  Chosen per (lattice, N) by hisq_tune_multi.
+// Launch shapes of the multi-RHS Dslash: RHS per thread G (as a divisor of N),
+// threads per block, whether the next direction's loads are issued ahead
+// (FP32 links; elsewhere the pipelined shapes run the plain loop), and the
+// tile order.  Orders: 0 plain; 1 blocked along t and z in the default 8 x 8
+// (z, t) blocks; 2 blocks of 4 t-planes by the whole z extent, 3 of 2
+// t-planes by the whole z extent, 4 of 8 x 16.  The XCDs take contiguous
+// ranges of the order, so with 2 and 3 each XCD holds a few whole t-slabs: the
+// z neighbours of the sites in flight stay in its L2 and only the t faces are
+// fetched twice.  In plain order the N x 24-byte neighbour blocks were fetched
+// ~9 times per launch at N = 16.  An order the lattice does not allow falls
+// back to the plain one.  Chosen per (lattice, N) by hisq_tune_multi.
 struct MShape {
     int gdiv;  // G = N / gdiv
     int nt;
+    int pipe;
+    int order;
 };
-constexpr int N_MSHAPES = 4;
-static const MShape MSHAPES[N_MSHAPES] = { { 1, 256 }, { 2, 256 }, { 4, 256 }, { 1, 128 } };
+constexpr int N_MSHAPES = 16;
+static const MShape MSHAPES[N_MSHAPES] = { { 1, 256, 0, 0 }, { 2, 256, 0, 0 }, { 4, 256, 0, 0 }, { 1, 128, 0, 0 },
+                                           { 4, 256, 1, 0 }, { 2, 256, 1, 0 }, { 1, 256, 0, 1 }, { 2, 256, 0, 1 },
+                                           { 4, 256, 0, 1 }, { 4, 256, 1, 1 }, { 2, 256, 1, 1 }, { 4, 256, 1, 2 },
+                                           { 2, 256, 1, 2 }, { 4, 256, 1, 3 }, { 2, 256, 1, 3 }, { 4, 256, 1, 4 } };
+
+// blocked_order with tb planes along t and zb along z per block (0: the
+// default choice); false (g unchanged) where they do not divide the lattice
+// (abi.cpp)
+bool blocked_order(Geom &g, int tb, int zb);
+
+static void md_order(Geom &g, int order)
+{
+    switch (order) {
+    case 1: blocked_order(g); break;
+    case 2: blocked_order(g, 4, g.L[2]); break;
+    case 3: blocked_order(g, 2, g.L[2]); break;
+    case 4: blocked_order(g, 8, 16); break;
+    default: break;
+    }
+}
 
 template <class PS> static int mshape_for(const Geom &g, int N) { return tuned_choice("mdslash", g, PS::prec, N, 0); }
 
@@ -984,7 +1080,7 @@ template <class PS> constexpr double multi_default_delta()
     return (PS::prec == HISQ_I16S || PS::prec == HISQ_I16SC) ? 0.7 : 0.1;
 }
 
-template <class P, int N, int G, int NT, int EPI>
+template <class P, int N, int G, int NT, int EPI, bool PIPE = false>
 static hipError_t launch_md(const Geom &g, const void *fat, const void *lng, const void *src, void *dst,
                             const void *x, const void *b, float2 *rs, int parity, double *part, const MultiState *st,
                             int which, int gate, hipStream_t s, int *nblk_out)
@@ -994,7 +1090,7 @@ static hipError_t launch_md(const Geom &g, const void *fat, const void *lng, con
     static int occ = -1;
     if (occ < 0) {
         int o = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)k_mdslash<P, N, G, NT, EPI>, NT, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)k_mdslash<P, N, G, NT, EPI, PIPE>, NT, 0) !=
                 hipSuccess || o <= 0)
             o = 1;
         occ = o;
@@ -1002,7 +1098,7 @@ static hipError_t launch_md(const Geom &g, const void *fat, const void *lng, con
     int grid = std::min(nunits, device_cus() * occ);
     grid = std::min(std::max((grid + NXCD - 1) / NXCD * NXCD, NXCD), MULTI_MAX_BLOCKS);
     using V = typename P::cvec;
-    hipLaunchKernelGGL((k_mdslash<P, N, G, NT, EPI>), dim3(grid), dim3(NT), 0, s, g, (const char *)fat,
+    hipLaunchKernelGGL((k_mdslash<P, N, G, NT, EPI, PIPE>), dim3(grid), dim3(NT), 0, s, g, (const char *)fat,
                        (const char *)lng, (const V *)src, (V *)dst, (const V *)x, (const V *)b, rs, parity, nunits,
                        part, st, which, gate);
     if (nblk_out) *nblk_out = grid;
@@ -1011,15 +1107,26 @@ static hipError_t launch_md(const Geom &g, const void *fat, const void *lng, con
 
 // dispatch over the tuned shape (FP32 inner kernels) or a fixed one (FP64)
 template <class P, int N, int EPI>
-static hipError_t launch_md_shape(int shape, const Geom &g, const void *fat, const void *lng, const void *src,
+static hipError_t launch_md_shape(int shape, const Geom &g0, const void *fat, const void *lng, const void *src,
                                   void *dst, const void *x, const void *b, float2 *rs, int parity, double *part,
                                   const MultiState *st, int which, int gate, hipStream_t s, int *nblk)
 {
     constexpr int G1 = N, G2 = N >= 2 ? N / 2 : 1, G4 = N >= 4 ? N / 4 : 1;
+    Geom g = g0;
+    if (shape >= 0 && shape < N_MSHAPES) md_order(g, MSHAPES[shape].order);  // unchanged where it cannot
     switch (shape) {
     case 1: return launch_md<P, N, G2, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
     case 2: return launch_md<P, N, G4, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
     case 3: return launch_md<P, N, G1, 128, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
+    case 4: return launch_md<P, N, G4, 256, EPI, true>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s,
+                                                      nblk);
+    case 5: case 10: case 12: case 14:
+        return launch_md<P, N, G2, 256, EPI, true>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
+    case 6: return launch_md<P, N, G1, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
+    case 7: return launch_md<P, N, G2, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
+    case 8: return launch_md<P, N, G4, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
+    case 9: case 11: case 13: case 15:
+        return launch_md<P, N, G4, 256, EPI, true>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
     default: return launch_md<P, N, G1, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
     }
 }

@@ -45,7 +45,7 @@ constexpr int NET_NT = 256;     // four wavefronts; wave q transports the pairs 
 constexpr int MPAD = 32;        // GEMM rows: Re and Im of up to 16 output channels
 constexpr int SK = 32;          // K of one slice: 16 (transport, channel) pairs, Re parts then Im parts
 constexpr int NCOL = 3 * TILE;  // GEMM columns of a 64-site tile: (site, colour)
-constexpr int WG_MAX_BLOCKS = 1024;
+constexpr int WG_MAX_BLOCKS = 1024;  // a multiple of NXCD
 
 // The 9 transports of a layer with CIN input channels in slices of 16
 // (transport, channel) pairs: KG transports per slice, pair pi -> transport
@@ -263,20 +263,34 @@ __global__ void k_net_prep(const float2 *__restrict__ W, __bf16 *__restrict__ A,
 }
 
 // ------------------------------------------------------------------ layer (forward and input gradient)
-// One 64-site tile of parity blockIdx.y, batch entry blockIdx.z.  Per slice:
+// Work units u = (batch entry, tile, parity), u = (b ntiles + tile) 2 + p, in
+// XCD order: each XCD takes a contiguous range of units (xcd_block), so the
+// neighbour tiles a unit transports from are in flight on the same XCD and
+// are served by its L2 instead of being fetched once per XCD.
+__device__ __forceinline__ void net_unit(int u, int ntiles, int &b, int &tile, int &p)
+{
+    b = u / (2 * ntiles);
+    tile = (u >> 1) % ntiles;
+    p = u & 1;
+}
+
+// One unit per workgroup: a 64-site tile of one parity and batch entry.  Per slice:
 // the tile's 16 x 192 transported values go to LDS as BF16 (B[column][K]),
 // then the four waves run v_mfma_f32_16x16x32_bf16 on 16-column tiles
 // 3q..3q+2 for every 16-row tile of the output (FP32 accumulation).
 template <int CIN, int COUT>
 __global__ __launch_bounds__(NET_NT) void k_net_layer(Geom g, const char *__restrict__ fat,
                                                       const float2 *__restrict__ in, float2 *__restrict__ out,
-                                                      const __bf16 *__restrict__ A)
+                                                      const __bf16 *__restrict__ A, int batch)
 {
     using S = Slices<CIN>;
     constexpr int MT = (2 * COUT + 15) / 16;  // 16-row tiles of the output
     constexpr int PB = SK + 8;                // LDS pitch of a column (bf16)
     __shared__ __align__(16) __bf16 F[2][NCOL * PB];  // two slices: one mixed while the next is written
-    const int tile = blockIdx.x, p = blockIdx.y, b = blockIdx.z;
+    const int u = xcd_block(blockIdx.x, gridDim.x);
+    if (u >= batch * 2 * g.ntiles) return;  // the grid is rounded up to a multiple of the XCD count
+    int b, tile, p;
+    net_unit(u, g.ntiles, b, tile, p);
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
     const NetSite site = net_site(g, p, tile, lane);
@@ -404,7 +418,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_transport(Geom g, const char *__
 // writes its partial [slice][row][pair] (FP32), summed in FP64 by
 // k_net_wgrad_reduce.
 template <int CIN, int COUT>
-__global__ __launch_bounds__(NET_NT) void k_net_wgrad(Geom g, const char *__restrict__ fat,
+__global__ __launch_bounds__(NET_NT, 3) void k_net_wgrad(Geom g, const char *__restrict__ fat,
                                                       const float2 *__restrict__ in, const float2 *__restrict__ gout,
                                                       int batch, float *__restrict__ partials)
 {
@@ -426,10 +440,15 @@ __global__ __launch_bounds__(NET_NT) void k_net_wgrad(Geom g, const char *__rest
     for (int j = 0; j < S::N; ++j) acc[j] = floatx4{ 0.f, 0.f, 0.f, 0.f };
     // rows 2 COUT .. 16 MT - 1 of the g operand stay zero
     for (int i = threadIdx.x; i < (MT * 16 - 2 * COUT) * PK; i += NET_NT) Ga[2 * COUT * PK + i] = (__bf16)0.f;
+    // persistent: XCD k walks the k-th contiguous range of units (gridDim.x is a multiple of NXCD)
     const int units = batch * 2 * g.ntiles;
+    const int xcd = blockIdx.x % NXCD, per_xcd = gridDim.x / NXCD, units_per_xcd = (units + NXCD - 1) / NXCD;
 #pragma unroll 1
-    for (int u = blockIdx.x; u < units; u += gridDim.x) {
-        const int b = u / (2 * g.ntiles), p = (u / g.ntiles) % 2, tile = u % g.ntiles;
+    for (int v = blockIdx.x / NXCD; v < units_per_xcd; v += per_xcd) {
+        const int u = xcd * units_per_xcd + v;
+        if (u >= units) break;
+        int b, tile, p;
+        net_unit(u, g.ntiles, b, tile, p);
         const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
         const NetSite site = net_site(g, p, tile, lane);
         __syncthreads();  // the previous unit's operands have been read
@@ -674,8 +693,9 @@ template <int CIN, int COUT>
 static void layer_launch(const Geom &g, const void *fat, const float2 *in, float2 *out, const __bf16 *A, int batch,
                          hipStream_t s)
 {
-    const dim3 grid(g.ntiles, 2, batch);
-    hipLaunchKernelGGL((k_net_layer<CIN, COUT>), grid, dim3(NET_NT), 0, s, g, (const char *)fat, in, out, A);
+    const int grid = xcd_grid(batch * 2 * g.ntiles);
+    hipLaunchKernelGGL((k_net_layer<CIN, COUT>), dim3(grid), dim3(NET_NT), 0, s, g, (const char *)fat, in, out, A,
+                       batch);
 }
 
 template <int CIN, int COUT>
@@ -705,11 +725,28 @@ static int net_forward_t(const Geom &g, const void *fat, const float2 *W, const 
     return HISQ_OK;
 }
 
+static_assert(WG_MAX_BLOCKS % NXCD == 0, "the weight-gradient grid is a whole number of XCD groups");
 constexpr size_t WG_PART_FLOATS = (size_t)9 * 2 * 256;  // the largest per-block partial (9 slices, 32 rows)
 
+// The persistent weight-gradient grid: the workgroups that are resident at
+// once (occupancy x CUs), at most one per unit and WG_MAX_BLOCKS, rounded up
+// to a whole number of XCD groups.
+template <int CIN, int COUT>
 static int wgrad_blocks(const Geom &g, int batch)
 {
-    return (int)std::min<long long>((long long)batch * 2 * g.ntiles, WG_MAX_BLOCKS);
+    static int resident = 0;
+    if (!resident) {
+        int occ = 0, cus = 0, dev = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_net_wgrad<CIN, COUT>, NET_NT, 0) !=
+                hipSuccess || occ <= 0)
+            occ = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        resident = occ * cus;
+    }
+    const long long units = (long long)batch * 2 * g.ntiles;
+    return xcd_grid((int)std::min<long long>(std::min<long long>(units, resident), WG_MAX_BLOCKS));
 }
 
 // Backward workspace: dl/d in4, dl/d in3, dl/d in2 (C channels each), dl/d out
@@ -745,7 +782,7 @@ template <int CIN, int COUT>
 static void wgrad_launch(const Geom &g, const void *fat, const float2 *in, const float2 *gout, int batch, float *part,
                          float2 *gw, hipStream_t s)
 {
-    const int nb = wgrad_blocks(g, batch);
+    const int nb = wgrad_blocks<CIN, COUT>(g, batch);
     hipLaunchKernelGGL((k_net_wgrad<CIN, COUT>), dim3(nb), dim3(NET_NT), 0, s, g, (const char *)fat, in, gout, batch,
                        part);
     constexpr int part_entries = Slices<CIN>::N * ((2 * COUT + 15) / 16) * 256;

@@ -55,7 +55,7 @@ def initial_weights(C, scale, noise, noise_seed):
     return w + noise * z
 
 
-def lambda_max_estimate(links64: Links, mass, dims, steps=40, seed=999):
+def lambda_max_estimate(links64: Links, mass, dims, steps=60, seed=999):
     """The largest eigenvalue of A(mass) by power iteration on the FP64 operator: sqrt(|A^(k+1) v|^2 / |A^k v|^2)
     after `steps` applications to a Gaussian v (no normalisation needed in FP64 for |lambda| < 1e6), raised by 5 %
     (the iteration approaches it from below)."""
@@ -75,21 +75,27 @@ def lambda_max_estimate(links64: Links, mass, dims, steps=40, seed=999):
     return 1.05 * lam
 
 
-def chebyshev_weights(C, mass, lambda_max):
+def chebyshev_weights(C, mass, lambda_max, lambda_lo=None):
     """Weights with which the network computes K = p(A) exactly when the operator's long links are zero (its
     Dslash is then D = sum_mu T_{+mu} - T_{-mu} over the fat-link transports the layers already apply), p the
-    quadratic for which 1 - l p(l) is the degree-3 Chebyshev polynomial shifted to [4 m^2, lambda_max] and
-    normalised to 1 at l = 0: the quadratic that minimises max |1 - l p(l)| on the spectrum's interval, so the
-    condition number of K A is that of A over (d + 1)^2 = 9.  With D^2 = 4 m^2 - A on the even sites the layers
-    carry phi, D phi -> phi, D^2 phi -> phi, D^3 phi, D^2 phi -> alpha phi + beta D^2 phi + gamma D^4 phi (C >= 4).
-    A reference for the trained networks: it is built, not learned."""
+    quadratic for which 1 - l p(l) is the degree-3 Chebyshev polynomial shifted to [lambda_lo, lambda_max] and
+    normalised to 1 at l = 0, the quadratic that minimises max |1 - l p(l)| on that interval.  On [4 m^2,
+    lambda_max] it would divide the condition number by (d + 1)^2 = 9, but p then nearly vanishes where
+    1 - l p(l) touches its upper bound inside the spectrum (p_min / p_max ~ 1e-5 at m = 0.005), and the BF16
+    rounding of the network (~5e-3 of K) can make K indefinite.  The default lambda_lo = max(4 m^2,
+    lambda_max / 30) keeps p_min / p_max ~ 0.04 and costs ~5 % of the condition-number gain.  With
+    D^2 = 4 m^2 - A on the even sites the layers carry phi, D phi -> phi, D^2 phi -> phi, D^3 phi,
+    D^2 phi -> alpha phi + beta D^2 phi + gamma D^4 phi (C >= 4).  A reference for the trained networks: it is
+    built, not learned."""
     from numpy.polynomial import Polynomial
-    a, b = 4.0 * mass * mass, float(lambda_max)
+    b = float(lambda_max)
+    a = max(4.0 * mass * mass, b / 30.0) if lambda_lo is None else float(lambda_lo)
     y = Polynomial([(b + a) / (b - a), -2.0 / (b - a)])   # [a, b] -> [1, -1]
     t3 = Polynomial([0.0, -3.0, 0.0, 4.0])                 # T_3(y) = 4 y^3 - 3 y
     q = t3(y) / t3((b + a) / (b - a))                      # q(0) = 1
     c0, c1, c2 = -q.coef[1], -q.coef[2], -q.coef[3]        # p(l) = (1 - q(l)) / l
-    alpha, beta, gamma = c0 + a * c1 + a * a * c2, -c1 - 2 * a * c2, c2
+    m4 = 4.0 * mass * mass                                 # K = p(A), A = m4 - D^2 on the even sites
+    alpha, beta, gamma = c0 + m4 * c1 + m4 * m4 * c2, -c1 - 2 * m4 * c2, c2
     Ws = [np.zeros((9, co, ci), np.complex64) for co, ci in LAYER_SHAPES(C)]
     sgn = [0.0, 1.0, 1.0, 1.0, 1.0, -1.0, -1.0, -1.0, -1.0]  # D: +1 on the forward hops, -1 on the backward ones
     Ws[0][0, 0, 0] = 1.0

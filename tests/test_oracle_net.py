@@ -169,3 +169,34 @@ def test_input_gradient_is_the_adjoint_layer():
     g = cvec(r, (3, V, 3))
     gx, _ = N.layer_backward(DIMS, fat, W, x, g)
     assert np.abs(N.layer_forward(DIMS, fat, N.adjoint_weights(W), g) - gx).max() < 1e-12
+
+
+def test_built_polynomial_network():
+    """train.chebyshev_weights, the network built (not trained) as K = p(A) on the naive operator, against the
+    dense operator: the FP64 oracle network with those weights is p(A) b; p is positive on the spectrum with
+    p_min / p_max >= 0.03 (BF16 rounding of K, ~5e-3, cannot make K indefinite); cond(K A) <= cond(A) / 6 (the
+    minimax quadratic on [lambda_max / 30, lambda_max]); the oracle's flexible CG with K converges in at most
+    0.6 times plain CG's iterations."""
+    from paper_1411_2087_amd import train
+    dims, mass, C = (4, 4, 4, 6), 0.02, 4
+    fat, lng = synth.links(dims, 1000)
+    lng0 = np.zeros_like(lng)
+    A = dense.dense_A(dims, dense.dense_D(dims, fat, lng0), mass)
+    ev = np.linalg.eigvalsh(A)
+    lmax = 1.02 * ev[-1]
+    w, (c0, c1, c2) = train.chebyshev_weights(C, mass, lmax)
+    Ws = [W.astype(np.complex128) for W in train.unflatten(w, C)]
+    b = synth.source(dims, 5)
+    y, _ = N.net_forward(dims, fat, Ws, b)
+    bv = b.reshape(-1)
+    want = c0 * bv + c1 * (A @ bv) + c2 * (A @ (A @ bv))
+    assert np.linalg.norm(y.reshape(-1) - want) <= 1e-6 * np.linalg.norm(want)
+    p = c0 + c1 * ev + c2 * ev ** 2
+    assert p.min() > 0 and p.min() / p.max() >= 0.03
+    kap = ev * p
+    assert kap.max() / kap.min() <= ev[-1] / ev[0] / 6
+    x, info = fcg.fcg(dims, mass, fat, lng0, b, lambda r: N.net_forward(dims, fat, Ws, r)[0], tol=1e-10)
+    _, cinfo = oracle.cg(dims, mass, fat, lng0, b, tol=1e-10, history=True)
+    assert not info["fallback"]
+    assert oracle.true_residual(dims, mass, fat, lng0, b, x) <= 1e-10
+    assert info["iters"] <= 0.6 * cinfo["iters"]
