@@ -106,7 +106,9 @@ def summarize_counters(kind, fetch_dir, write_dir):
     """HBM traffic per launch from a pair of rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, in KiB per
     dispatch) of a traffic probe, each counter scaled by what it reads for the probe's 1 GiB device copy.
     kind "cg": the plain CG's k_cg_Dp / k_cg_Ap_upd / k_cg_p_norm on 32^4; kind "net": the network kernels on
-    16^4, batch 16, C = 16.  Writes the JSON summary under profiles/ and prints a markdown table."""
+    16^4, batch 16, C = 16; kind "dslash": the FP64 Dslash in every launch shape on 32^4 (the probe's tuner
+    launches each shape 7 times in shape order; the first of the 7 is left out).  Writes the JSON summary under
+    profiles/ and prints a markdown table."""
     import csv
     import glob
     import re
@@ -118,10 +120,10 @@ def summarize_counters(kind, fetch_dir, write_dir):
                 for r in csv.DictReader(f):
                     if r.get("Counter_Name") == counter:
                         us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
-                        out.append((r["Kernel_Name"], float(r["Counter_Value"]), us))
+                        out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]), us))
         if not out:
             raise SystemExit(f"no {counter} rows under {d}")
-        return out
+        return [o[1:] for o in sorted(out)]  # dispatch order
     fetch, write = rows(fetch_dir, "FETCH_SIZE"), rows(write_dir, "WRITE_SIZE")
     copy_bytes = 1 << 30
 
@@ -139,6 +141,19 @@ def summarize_counters(kind, fetch_dir, write_dir):
         def label(name):
             m = re.search(r"(k_cg_Ap_upd|k_cg_Dp|k_cg_p_norm)\b", name)
             return m.group(1) if m else None
+    elif kind == "dslash":
+        vh, sources, out_file = DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3] // 2, DSLASH_SOURCES, TRAFFIC_FILE
+        seq = {"fetch": [(n, v, us) for n, v, us in fetch if n.startswith("void hisq::k_dslash<hisq::PF64, ")],
+               "write": [(n, v, us) for n, v, us in write if n.startswith("void hisq::k_dslash<hisq::PF64, ")]}
+        import paper_1411_2087_amd as hq
+        per = 7  # the tuner's 2 warm-up and 5 timed launches of each shape, in shape order
+        nshapes = hq.hisq_dslash_shape(DIMS, hq.HISQ_F64, -2)
+        if len(seq["fetch"]) < per * nshapes:
+            raise SystemExit(f"{len(seq['fetch'])} FP64 Dslash dispatches, fewer than the tuner's {per * nshapes}")
+        algo = {}
+
+        def label(name):
+            return None
     elif kind == "net":
         V, batch, sources, out_file = 16 ** 4, 16, NET_SOURCES, NET_TRAFFIC_FILE
         vh = V // 2
@@ -154,6 +169,17 @@ def summarize_counters(kind, fetch_dir, write_dir):
     else:
         raise SystemExit(f"unknown counter summary kind {kind}")
     groups = {}
+    if kind == "dslash":
+        for i in range(nshapes):
+            lab = f"shape {i}"
+            algo[lab] = 2400 * vh
+            g_ = groups.setdefault(lab, {"fetch": [], "write": [], "us": []})
+            for key in ("fetch", "write"):
+                chunk = seq[key][per * i + 1:per * (i + 1)]
+                g_[key] += [v for _, v, _ in chunk]
+                if key == "fetch":
+                    g_["us"] += [us for _, _, us in chunk]
+                    g_["kernel"] = chunk[0][0].split("(")[0].replace("void hisq::", "")
     for rs, key in ((fetch, "fetch"), (write, "write")):
         for name, v, us in rs:
             lab = label(name)
@@ -162,16 +188,18 @@ def summarize_counters(kind, fetch_dir, write_dir):
                 if key == "fetch":
                     groups[lab]["us"].append(us)
     table = {}
-    for lab, g in sorted(groups.items()):
+    for lab, g in sorted(groups.items(), key=lambda kv: (len(kv[0]), kv[0])):
         fk, wk = sum(g["fetch"]) / len(g["fetch"]), sum(g["write"]) / len(g["write"])
         fb, wb = fk * 1024 * ff, wk * 1024 * wf
         us = sum(g["us"]) / len(g["us"])
-        table[lab] = {"dispatches": [len(g["fetch"]), len(g["write"])], "fetch_kib": fk, "write_kib": wk,
+        table[lab] = {"kernel": g.get("kernel", lab), "dispatches": [len(g["fetch"]), len(g["write"])], "fetch_kib": fk, "write_kib": wk,
                       "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
                       "algorithmic_bytes": algo[lab], "ratio_to_algorithmic": (fb + wb) / algo[lab],
                       "avg_us_under_counters": us}
     res = {"kind": kind, "vh": vh, "source_sha": dslash_source_sha(sources), "copy_bytes": copy_bytes,
            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_factor": ff, "write_factor": wf, "kernels": table}
+    if kind == "dslash":  # keyed by launch shape, as traffic_from_profile reads it
+        res["per_shape"] = {lab.split()[1]: t for lab, t in table.items()}
     with open(out_file, "w") as f:
         json.dump(res, f, indent=1)
     print(f"Calibration: a device copy of {copy_bytes} B reads as FETCH_SIZE {cf:.0f} KiB and WRITE_SIZE "
@@ -180,7 +208,7 @@ def summarize_counters(kind, fetch_dir, write_dir):
           "| traffic / algorithmic | avg us under counters |")
     print("|---|---|---|---|---|---|---|---|---|")
     for lab, t in table.items():
-        print(f"| `{lab}` | {t['dispatches'][0]} | {t['fetch_kib']:.0f} | {t['write_kib']:.0f} | "
+        print(f"| `{t['kernel'] if kind == 'dslash' else lab}`{' (' + lab + ')' if kind == 'dslash' else ''} | {t['dispatches'][0]} | {t['fetch_kib']:.0f} | {t['write_kib']:.0f} | "
               f"{t['fetch_bytes'] / 1e9:.4f} | {t['write_bytes'] / 1e9:.4f} | {t['algorithmic_bytes'] / 1e9:.4f} | "
               f"{t['ratio_to_algorithmic']:.3f} | {t['avg_us_under_counters']:.1f} |")
     print(f"\nKernel sources hash: `{res['source_sha']}`.")
@@ -711,9 +739,10 @@ def run_large(args):
 
 
 def traffic_probe_at(workload):
-    """A 1 GiB copy (counter calibration) and 5 FP64 Dslash launches in each of launch shapes 6, 8 and 10 (plain
-    and blocked tile order at one term and 6 waves/SIMD, and the FP64 default: two terms at 5 waves/SIMD) on the
-    lattice `workload` ("LxxLyxLzxLt"), for rocprofv3 counter runs."""
+    """A 1 GiB copy (counter calibration) and 5 FP64 Dslash launches in each of launch shapes 6, 8, 10, 11 and 12
+    (plain and default-blocked tile order at one term and 6 waves/SIMD; the FP64 default, two terms at 5
+    waves/SIMD, in plain order and in blocks of 8 and of 4 t-planes by the whole z extent) on the lattice
+    `workload` ("LxxLyxLzxLt"), for rocprofv3 counter runs."""
     import torch
     import paper_1411_2087_amd as hq
     import synth
@@ -728,7 +757,7 @@ def traffic_probe_at(workload):
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
-    shapes = (6, 8, 10)
+    shapes = (6, 8, 10, 11, 12)
     for shape in shapes:  # 5 launches each
         hq.hisq_dslash_shape(dims, hq.HISQ_F64, shape)
         for _ in range(5):

@@ -344,7 +344,7 @@ int net_backward(const void *fat, const void *weights, int channels, const void 
  * on the full lattice for k = 0..8 (k = 0 the identity, 1..4 the hops along
  * +x, +y, +z, +t, 5..8 along -x, -y, -z, -t), in FP32 from the same device
  * code as the layer kernels, which round exactly these values to BF16 for the
- * MFMA.  in: [batch][channels][parity][Vh][3] complex64 (channels 1, 4, 8 or
+ * MFMA (the backward ones negated, with negated weights: the same products).  in: [batch][channels][parity][Vh][3] complex64 (channels 1, 4, 8 or
  * 16); out: [batch][9][channels][parity][Vh][3] complex64.  Asynchronous. */
 int net_transport(const void *fat, const void *in, void *out, int channels, int batch, const int dims[4],
                   void *stream);

@@ -53,7 +53,7 @@ static int block_of(int L)
     return 1;
 }
 
-bool blocked_order(Geom &g, int tb, int zb)
+static bool blocked_order(Geom &g, int tb, int zb)
 {
     if ((g.Lxh * g.L[1]) % TILE) return false;
     if (tb <= 0) tb = block_of(g.L[3]);
@@ -67,6 +67,18 @@ bool blocked_order(Geom &g, int tb, int zb)
 }
 
 bool blocked_order(Geom &g) { return blocked_order(g, 0, 0); }
+
+void apply_order(Geom &g, int order)
+{
+    switch (order) {
+    case 1: blocked_order(g, 0, 0); break;
+    case 2: blocked_order(g, 8, g.L[2]); break;
+    case 3: blocked_order(g, 4, g.L[2]); break;
+    case 4: blocked_order(g, 2, g.L[2]); break;
+    case 5: blocked_order(g, 8, 16); break;
+    default: break;
+    }
+}
 
 }  // namespace hisq
 

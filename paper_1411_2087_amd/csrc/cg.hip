@@ -649,7 +649,7 @@ struct Launch {
 static Geom cg_geom(const Geom &g, int prec)
 {
     Geom c = g;
-    if (DSLASH_SHAPES[tuned_dslash_shape(g, prec)].order) blocked_order(c);
+    apply_order(c, DSLASH_SHAPES[tuned_dslash_shape(g, prec)].order);
     return c;
 }
 

@@ -1013,14 +1013,11 @@ constexpr size_t MSKEW = 4352;
 // Launch shapes of the multi-RHS Dslash: RHS per thread G (as a divisor of N),
 // threads per block, whether the next direction's loads are issued ahead
 // (FP32 links; elsewhere the pipelined shapes run the plain loop), and the
-// tile order.  Orders: 0 plain; 1 blocked along t and z in the default 8 x 8
-// (z, t) blocks; 2 blocks of 4 t-planes by the whole z extent, 3 of 2
-// t-planes by the whole z extent, 4 of 8 x 16.  The XCDs take contiguous
-// ranges of the order, so with 2 and 3 each XCD holds a few whole t-slabs: the
-// z neighbours of the sites in flight stay in its L2 and only the t faces are
-// fetched twice.  In plain order the N x 24-byte neighbour blocks were fetched
-// ~9 times per launch at N = 16.  An order the lattice does not allow falls
-// back to the plain one.  Chosen per (lattice, N) by hisq_tune_multi.
+// tile order (apply_order codes: 1 the default (z, t) blocks, 3 and 4 blocks
+// of 4 and 2 t-planes by the whole z extent, 5 of 8 x 16), which decides how
+// often the N x 24-byte neighbour blocks are fetched again (~9 times per
+// launch at N = 16 in plain order).  Chosen per (lattice, N) by
+// hisq_tune_multi.
 struct MShape {
     int gdiv;  // G = N / gdiv
     int nt;
@@ -1030,24 +1027,8 @@ struct MShape {
 constexpr int N_MSHAPES = 16;
 static const MShape MSHAPES[N_MSHAPES] = { { 1, 256, 0, 0 }, { 2, 256, 0, 0 }, { 4, 256, 0, 0 }, { 1, 128, 0, 0 },
                                            { 4, 256, 1, 0 }, { 2, 256, 1, 0 }, { 1, 256, 0, 1 }, { 2, 256, 0, 1 },
-                                           { 4, 256, 0, 1 }, { 4, 256, 1, 1 }, { 2, 256, 1, 1 }, { 4, 256, 1, 2 },
-                                           { 2, 256, 1, 2 }, { 4, 256, 1, 3 }, { 2, 256, 1, 3 }, { 4, 256, 1, 4 } };
-
-// blocked_order with tb planes along t and zb along z per block (0: the
-// default choice); false (g unchanged) where they do not divide the lattice
-// (abi.cpp)
-bool blocked_order(Geom &g, int tb, int zb);
-
-static void md_order(Geom &g, int order)
-{
-    switch (order) {
-    case 1: blocked_order(g); break;
-    case 2: blocked_order(g, 4, g.L[2]); break;
-    case 3: blocked_order(g, 2, g.L[2]); break;
-    case 4: blocked_order(g, 8, 16); break;
-    default: break;
-    }
-}
+                                           { 4, 256, 0, 1 }, { 4, 256, 1, 1 }, { 2, 256, 1, 1 }, { 4, 256, 1, 3 },
+                                           { 2, 256, 1, 3 }, { 4, 256, 1, 4 }, { 2, 256, 1, 4 }, { 4, 256, 1, 5 } };
 
 template <class PS> static int mshape_for(const Geom &g, int N) { return tuned_choice("mdslash", g, PS::prec, N, 0); }
 
@@ -1113,7 +1094,7 @@ static hipError_t launch_md_shape(int shape, const Geom &g0, const void *fat, co
 {
     constexpr int G1 = N, G2 = N >= 2 ? N / 2 : 1, G4 = N >= 4 ? N / 4 : 1;
     Geom g = g0;
-    if (shape >= 0 && shape < N_MSHAPES) md_order(g, MSHAPES[shape].order);  // unchanged where it cannot
+    if (shape >= 0 && shape < N_MSHAPES) apply_order(g, MSHAPES[shape].order);  // unchanged where it cannot
     switch (shape) {
     case 1: return launch_md<P, N, G2, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);
     case 2: return launch_md<P, N, G4, 256, EPI>(g, fat, lng, src, dst, x, b, rs, parity, part, st, which, gate, s, nblk);

@@ -77,6 +77,7 @@ __global__ __launch_bounds__(NT) HISQ_WAVES((P::prec == HISQ_F64 || P::prec == H
 const DslashShape DSLASH_SHAPES[N_DSLASH_SHAPES] = {
     { 256, 8, 1, 0 }, { 128, 8, 1, 0 }, { 64, 8, 1, 0 }, { 256, 1, 16, 0 }, { 256, 4, 4, 0 },
     { 512, 8, 1, 0 }, { 256, 6, 1, 0 }, { 256, 8, 1, 1 }, { 256, 6, 1, 1 }, { 256, 6, 2, 0 }, { 256, 5, 2, 0 },
+    { 256, 5, 2, 2 }, { 256, 5, 2, 3 },
 };
 
 static inline int blocks_for(const Geom &g, int nt) { return (g.ntiles + nt / TILE - 1) / (nt / TILE); }
@@ -86,12 +87,13 @@ static void launch_shape(const Geom &g0, const void *fat, const void *lng, const
                          hipStream_t s, const SolverFlags *flags, int gate)
 {
     Geom g = g0;
-    if (ORD && !blocked_order(g)) {  // the lattice has no blocked order: plain order
+    if (ORD) apply_order(g, ORD);
+    if (ORD && !g.oP) {  // the lattice has no such order: plain order
         launch_shape<P, NT, W, UNR, 0>(g0, fat, lng, src, dst, parity, s, flags, gate);
         return;
     }
     const int nb = blocks_for(g, NT);
-    hipLaunchKernelGGL((k_dslash<P, NT, W, UNR, ORD>), dim3(xcd_grid(nb)), dim3(NT), 0, s, g, (const char *)fat,
+    hipLaunchKernelGGL((k_dslash<P, NT, W, UNR, (ORD != 0)>), dim3(xcd_grid(nb)), dim3(NT), 0, s, g, (const char *)fat,
                        (const char *)lng, (const typename P::cvec *)src, (typename P::cvec *)dst, parity, nb, flags,
                        gate);
 }
@@ -111,6 +113,8 @@ hipError_t launch_dslash_shape(int shape, const Geom &g, const void *fat, const 
     case 8: launch_shape<P, 256, 6, 1, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     case 9: launch_shape<P, 256, 6, 2>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     case 10: launch_shape<P, 256, 5, 2>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 11: launch_shape<P, 256, 5, 2, 2>(g, fat, lng, src, dst, parity, s, flags, gate); break;
+    case 12: launch_shape<P, 256, 5, 2, 3>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     default: launch_shape<P, 256, 8, 1>(g, fat, lng, src, dst, parity, s, flags, gate); break;
     }
     return hipGetLastError();

@@ -137,9 +137,9 @@ struct DslashShape {
     int nt;      // threads per block
     int waves;   // minimum wavefronts per SIMD the compiler must allow
     int unroll;  // terms of the 16 unrolled together
-    int order;   // 1: blocked tile order (blocked_order), 0: tile k k-th
+    int order;   // tile order (apply_order): 0 plain, 1 default blocks, 2 and 3 8- and 4-plane t-blocks by all z
 };
-constexpr int N_DSLASH_SHAPES = 11;
+constexpr int N_DSLASH_SHAPES = 13;
 extern const DslashShape DSLASH_SHAPES[N_DSLASH_SHAPES];
 int tuned_dslash_shape(const Geom &g, int prec);            // tune.cpp
 int tuned_choice(const char *kind, const Geom &g, int prec, int n, int fallback);

@@ -46,6 +46,13 @@ int make_geom(const int dims[4], Geom &g);  // HISQ_OK or HISQ_EDIMS/EINVAL
 // Switch g to the blocked tile order; false (g unchanged) when a tile would
 // straddle two (z, t) planes (Lx/2 * Ly not a multiple of 64).
 bool blocked_order(Geom &g);
+// Tile orders of the Dslash-type kernels: 0 plain; 1 blocked in the default
+// (z, t) blocks (blocked_order); 2, 3, 4 blocks of 8, 4, 2 t-planes by the
+// whole z extent; 5 blocks of 8 t- by 16 z-planes.  The XCDs take contiguous
+// ranges of the order, so with 2-4 each XCD still holds whole t-slabs while t
+// is the fast direction inside them.  g is left in plain order where the
+// lattice does not allow the requested one.
+void apply_order(Geom &g, int order);
 
 // tile processed k-th
 __device__ __forceinline__ int tile_of(const Geom &g, int k)

@@ -128,7 +128,7 @@ struct SliceRaw {
     int kind;  // 0: T_0 (v is the result), 1: transport, 2: padding (zero)
 };
 
-template <int CIN>
+template <int CIN, bool SIGNED = false>
 __device__ __forceinline__ void slice_load(const Geom &g, const char *__restrict__ fat, const float2 *__restrict__ in,
                                            int p, int tile, int lane, const NetSite &st, int j, int q, SliceRaw &r)
 {
@@ -145,7 +145,7 @@ __device__ __forceinline__ void slice_load(const Geom &g, const char *__restrict
         hn = nbr_h(g, st.hc, st.x, st.y, st.z, st.t, d & 3, d >= 4 ? -1 : 1);
         pn = 1 - p;
         load_link32(fat + (((size_t)p * g.ntiles + tile) * 8 + d) * PF32::block_bytes, lane, r.m);
-        r.sg = d >= 4 ? -1.0f : 1.0f;
+        r.sg = (SIGNED && d >= 4) ? -1.0f : 1.0f;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -155,7 +155,7 @@ __device__ __forceinline__ void slice_load(const Geom &g, const char *__restrict
     }
 }
 
-__device__ __forceinline__ void slice_finish(const SliceRaw &r, bool valid, float tv[4][6])
+__device__ __forceinline__ void slice_finish(const SliceRaw &r, float tv[4][6])
 {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -168,32 +168,34 @@ __device__ __forceinline__ void slice_finish(const SliceRaw &r, bool valid, floa
                 tv[i][2 * a + 1] = r.kind == 0 ? r.v[i][a].y : 0.f;
             }
         }
-        if (!valid)
-#pragma unroll
-            for (int e = 0; e < 6; ++e) tv[i][e] = 0.f;
     }
 }
 
 // The four (transport, channel) pairs 4q..4q+3 of slice j at the thread's
 // site of parity p (lane `lane` of `tile`): tv[i] = (T_k phi^c)(x) for pair
-// 4q + i, colours (re, im) x 3; zero for padding pairs and sites past Vh.
-// T_0 = 1; T_{1+d}: packed direction d (0..3 = +x..+t holds F_mu(x), 4..7 =
-// -x..-t holds -F_mu(x-mu)^dag) times the neighbour one hop along d.
+// 4q + i, colours (re, im) x 3; zero for padding pairs.  T_0 = 1; T_{1+d}:
+// packed direction d (0..3 = +x..+t holds F_mu(x), 4..7 = -x..-t holds
+// -F_mu(x-mu)^dag) times the neighbour one hop along d.  With SIGNED the
+// backward transports get the packed link's sign undone; without it they come
+// out as -T_k, and the kernels carry the sign in the weights instead
+// (k_net_prep negates them, k_net_wgrad_reduce their gradients): negation is
+// exact in BF16, so the products are the same bits, and 24 multiplies per
+// slice and wavefront are saved.  Lanes past Vh (clamped to the last site)
+// get finite values that no stored output uses: the layer stores only sites
+// below Vh, and the weight gradient multiplies them by zero upstream gradients.
 // in: the channels of one batch entry, [c][parity][Vh][3].
-template <int CIN>
+template <int CIN, bool SIGNED = false>
 __device__ __forceinline__ void slice_transport(const Geom &g, const char *__restrict__ fat,
                                                 const float2 *__restrict__ in, int p, int tile, int lane,
                                                 const NetSite &st, int j, int q, float tv[4][6])
 {
-    constexpr int KG = Slices<CIN>::KG;
-    const bool valid = st.valid;
     const int hc = st.hc, x = st.x, y = st.y, z = st.z, t = st.t;
     const size_t ch_stride = (size_t)2 * g.Vh * 3;
     const char *tb = fat + ((size_t)p * g.ntiles + tile) * 8 * PF32::block_bytes;
     if constexpr (CIN >= 4) {
         SliceRaw r;
-        slice_load<CIN>(g, fat, in, p, tile, lane, st, j, q, r);
-        slice_finish(r, valid, tv);
+        slice_load<CIN, SIGNED>(g, fat, in, p, tile, lane, st, j, q, r);
+        slice_finish(r, tv);
         return;
     } else {
         // CIN == 1: one slice holds every transport; pair i of group q is transport 4q + i
@@ -214,18 +216,12 @@ __device__ __forceinline__ void slice_transport(const Geom &g, const char *__res
                 float m[18];
                 load_link32(tb + (size_t)d * PF32::block_bytes, lane, m);
                 const float2 *v = in + (size_t)(1 - p) * g.Vh * 3 + (size_t)nh * 3;
-                matvec32(m, d >= 4 ? -1.0f : 1.0f, v[0], v[1], v[2], tv[i]);
+                matvec32(m, (SIGNED && d >= 4) ? -1.0f : 1.0f, v[0], v[1], v[2], tv[i]);
             } else {
 #pragma unroll
                 for (int e = 0; e < 6; ++e) tv[i][e] = 0.f;
             }
         }
-    }
-    if (!valid) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int e = 0; e < 6; ++e) tv[i][e] = 0.f;
     }
 }
 
@@ -233,7 +229,9 @@ __device__ __forceinline__ void slice_transport(const Geom &g, const char *__res
 // A[j][m][kk] (slices x 32 x 32) for out = sum_k W_k T_k in: row m < COUT'
 // is Re out^m, row COUT' + a is Im out^a; column kk < 16 takes the real
 // part of pair kk of slice j, kk >= 16 the imaginary part of pair kk - 16;
-// the real embedding [[Wr, -Wi], [Wi, Wr]].  adjoint: the matrix of the
+// the real embedding [[Wr, -Wi], [Wi, Wr]], negated for the backward
+// transports k = 5..8 (the kernels take them without the packed sign).
+// adjoint: the matrix of the
 // input-gradient layer (C_in' = COUT, C_out' = CIN, W'_k^{ac} =
 // conj(W_{adj k}^{ca}), T_{+mu}^dag = T_{-mu}).
 template <int CIN, int COUT>
@@ -257,6 +255,7 @@ __global__ void k_net_prep(const float2 *__restrict__ W, __bf16 *__restrict__ A,
                 w = make_float2(u.x, -u.y);
             }
             v = !im_row ? (!im_col ? w.x : -w.y) : (!im_col ? w.y : w.x);
+            if (k >= 5) v = -v;  // the kernels transport backward without the packed sign
         }
         A[i] = (__bf16)v;
     }
@@ -340,7 +339,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_layer(Geom g, const char *__rest
             mix(F[j & 1], j);
             if (more) {
                 float tv[4][6];
-                slice_finish(r, site.valid, tv);
+                slice_finish(r, tv);
                 put(F[(j + 1) & 1], tv);
             }
         } else {
@@ -394,7 +393,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_transport(Geom g, const char *__
     const NetSite site = net_site(g, p, tile, lane);
     for (int j = 0; j < S::N; ++j) {
         float tv[4][6];
-        slice_transport<CIN>(g, fat, inb, p, tile, lane, site, j, q, tv);
+        slice_transport<CIN, true>(g, fat, inb, p, tile, lane, site, j, q, tv);
         if (h >= g.Vh) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -490,7 +489,7 @@ __global__ __launch_bounds__(NET_NT, 3) void k_net_wgrad(Geom g, const char *__r
             }
             if (more) {
                 float tv[4][6];
-                if constexpr (CIN >= 4) slice_finish(r, site.valid, tv);
+                if constexpr (CIN >= 4) slice_finish(r, tv);
                 else slice_transport<CIN>(g, fat, inb, p, tile, lane, site, j + 1, q, tv);
                 put(Fbuf[(j + 1) & 1], tv);
             }
@@ -553,7 +552,8 @@ __global__ __launch_bounds__(256) void k_net_wgrad_reduce(const float *__restric
     const int k = j * S::KG + pi / CIN, c = pi % CIN;
     if (m >= 2 * COUT || k >= 9) return;
     const int a = m < COUT ? m : m - COUT;
-    gw[2 * (((size_t)k * COUT + a) * CIN + c) + (m < COUT ? 0 : 1)] = (float)tot;
+    // backward transports were taken without the packed sign (the weights carry it)
+    gw[2 * (((size_t)k * COUT + a) * CIN + c) + (m < COUT ? 0 : 1)] = (float)(k >= 5 ? -tot : tot);
 }
 
 // ------------------------------------------------------------------ embedding, loss, Adam

@@ -288,8 +288,9 @@ def test_fcg_trained_gain_16_4(hq):
     the residual objective, then flexible CG on held-out sources against plain FP64 CG and against flexible CG
     with K = identity.  What is established (parity of the gain itself unpinned): every solution is certified
     by the oracle; K = 1 tracks plain CG within 1 %; the trained network does not cut the iteration count by
-    more than 10 % (measured 1.02-1.49 times plain CG's iterations: the residual objective fits the bulk of the
-    spectrum, not its low end, and the fat-link layers cannot reach the three-hop terms of the operator)."""
+    more than 10 % (measured 1.0-2.1 times plain CG's iterations, by width and training length: the residual
+    objective fits the bulk of the spectrum, not its low end, and the fat-link layers cannot reach the three-hop
+    terms of the operator)."""
     import torch
     from paper_1411_2087_amd import train
     dims, mass, C = (16, 16, 16, 16), 0.005, 16
