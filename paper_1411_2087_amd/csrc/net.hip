@@ -410,14 +410,15 @@ __global__ __launch_bounds__(NET_NT) void k_net_transport(Geom g, const char *__
 // G_k^{ac} = sum_x <T_k in^c, g^a>: per 64-site tile the real GEMM
 //   [Re G; Im G] (2 COUT x 16 pairs) += [[gr, gi], [gi, -gr]] (2 COUT x 384) x [Re T; Im T] (384 x 16)
 // with K = (column, re/im) interleaved.  g goes to LDS once per tile, each
-// slice's transports once per slice; wave q takes the 16-row tile q % MT and
-// a quarter (MT = 1) or half (MT = 2) of the 12 K steps, and keeps that
-// tile's accumulators of every slice.  Blocks stride over (batch, parity, tile)
-// units; the four waves are summed in a fixed order at the end and each block
-// writes its partial [slice][row][pair] (FP32), summed in FP64 by
+// slice's transports once per slice (all four waves, into registers while the
+// slice before is multiplied, then into the one LDS slice buffer); the MFMAs
+// of slice j (every row tile, all 12 K steps) belong to wave j % 4, which
+// keeps the accumulators of its slices only (at most 3).  37.5 KB of LDS and
+// at most 128 VGPRs: 4 workgroups per CU.  Blocks stride over (batch, tile, parity) units;
+// each block writes its partial [slice][row][pair] (FP32), summed in FP64 by
 // k_net_wgrad_reduce.
 template <int CIN, int COUT>
-__global__ __launch_bounds__(NET_NT, 3) void k_net_wgrad(Geom g, const char *__restrict__ fat,
+__global__ __launch_bounds__(NET_NT, 4) void k_net_wgrad(Geom g, const char *__restrict__ fat,
                                                       const float2 *__restrict__ in, const float2 *__restrict__ gout,
                                                       int batch, float *__restrict__ partials)
 {
@@ -426,17 +427,18 @@ __global__ __launch_bounds__(NET_NT, 3) void k_net_wgrad(Geom g, const char *__r
     constexpr int KT = 2 * NCOL;  // K per tile
     constexpr int PK = KT + 8;    // LDS pitch (bf16)
     constexpr int PART = S::N * MT * 256;
-    __shared__ __align__(16) __bf16 lds[(32 + MT * 16) * PK];
-    __bf16 *Fbuf[2] = { lds, lds + 16 * PK };  // B: [pair][K], two slices (one mixed while the next is written)
-    __bf16 *Ga = lds + 32 * PK;                // A: [row][K]
-    static_assert(PART * 4 <= (32 + MT * 16) * PK * 2, "partial reduction does not fit the LDS operands");
-    constexpr int KSW = 3 * MT;  // K steps of a wave
+    __shared__ __align__(16) __bf16 lds[(16 + MT * 16) * PK];
+    __bf16 *Fb = lds;                          // B: [pair][K], one slice
+    __bf16 *Ga = lds + 16 * PK;                // A: [row][K]
+    static_assert(PART * 4 <= (16 + MT * 16) * PK * 2, "partial reduction does not fit the LDS operands");
+    constexpr int NSL = (S::N + 3) / 4;  // slices a wave owns: j = q, q + 4, ...
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int r16 = lane & 15, k8 = 8 * (lane >> 4);
-    const int wmt = q % MT, ks0 = (q / MT) * KSW;
-    floatx4 acc[S::N];
+    floatx4 acc[NSL][MT];
 #pragma unroll
-    for (int j = 0; j < S::N; ++j) acc[j] = floatx4{ 0.f, 0.f, 0.f, 0.f };
+    for (int jj = 0; jj < NSL; ++jj)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[jj][mt] = floatx4{ 0.f, 0.f, 0.f, 0.f };
     // rows 2 COUT .. 16 MT - 1 of the g operand stay zero
     for (int i = threadIdx.x; i < (MT * 16 - 2 * COUT) * PK; i += NET_NT) Ga[2 * COUT * PK + i] = (__bf16)0.f;
     // persistent: XCD k walks the k-th contiguous range of units (gridDim.x is a multiple of NXCD)
@@ -450,7 +452,7 @@ __global__ __launch_bounds__(NET_NT, 3) void k_net_wgrad(Geom g, const char *__r
         net_unit(u, g.ntiles, b, tile, p);
         const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
         const NetSite site = net_site(g, p, tile, lane);
-        __syncthreads();  // the previous unit's operands have been read
+        // (the previous unit's last slice ended with a barrier: its operands have been read)
         for (int i = threadIdx.x; i < COUT * NCOL; i += NET_NT) {
             const int a = i / NCOL, jc = i % NCOL, h = tile * TILE + jc / 3;
             float2 v = make_float2(0.f, 0.f);
@@ -470,48 +472,47 @@ __global__ __launch_bounds__(NET_NT, 3) void k_net_wgrad(Geom g, const char *__r
         {
             float tv[4][6];
             slice_transport<CIN>(g, fat, inb, p, tile, lane, site, 0, q, tv);
-            put(Fbuf[0], tv);
+            put(Fb, tv);
         }
         __syncthreads();  // g and slice 0 are in LDS
         // unrolled: acc[j] must stay in registers; slice j + 1's loads are in flight over slice j's MFMA
 #pragma unroll
         for (int j = 0; j < S::N; ++j) {
             const bool more = j + 1 < S::N;
-            SliceRaw r;
-            if constexpr (CIN >= 4)
-                if (more) slice_load<CIN>(g, fat, inb, p, tile, lane, site, j + 1, q, r);
-            const __bf16 *Fb = Fbuf[j & 1];
+            float tv[4][6];
+            // the next slice's transport goes to registers while the owner wave multiplies this one
+            if (more) slice_transport<CIN>(g, fat, inb, p, tile, lane, site, j + 1, q, tv);
+            if (q == (j & 3)) {  // this slice's owner (wave-uniform)
 #pragma unroll
-            for (int ks = ks0; ks < ks0 + KSW; ++ks) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Fb + r16 * PK + SK * ks + k8);
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Ga + (wmt * 16 + r16) * PK + SK * ks + k8);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+                for (int ks = 0; ks < KT / SK; ++ks) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Fb + r16 * PK + SK * ks + k8);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Ga + (mt * 16 + r16) * PK + SK * ks + k8);
+                        acc[j >> 2][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j >> 2][mt], 0, 0, 0);
+                    }
+                }
             }
             if (more) {
-                float tv[4][6];
-                if constexpr (CIN >= 4) slice_finish(r, tv);
-                else slice_transport<CIN>(g, fat, inb, p, tile, lane, site, j + 1, q, tv);
-                put(Fbuf[(j + 1) & 1], tv);
+                __syncthreads();  // every wave is done with slice j
+                put(Fb, tv);
             }
             __syncthreads();
         }
     }
-    // the waves' accumulators of each row tile, summed in wave order through LDS
+    // every (slice, row tile) accumulator has one owner: gathered through LDS for a coalesced store
     float *red = reinterpret_cast<float *>(lds);
     __syncthreads();
-#pragma unroll 1
-    for (int w = 0; w < 4; ++w) {
-        if (q == w) {
 #pragma unroll
-            for (int j = 0; j < S::N; ++j)
+    for (int jj = 0; jj < NSL; ++jj) {
+        const int j = q + 4 * jj;
+        if (j < S::N)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int idx = ((j * MT + wmt) * 16 + 4 * (lane >> 4) + i) * 16 + r16;
-                    red[idx] = (w < MT ? 0.f : red[idx]) + acc[j][i];
-                }
-        }
-        __syncthreads();
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) red[((j * MT + mt) * 16 + 4 * (lane >> 4) + i) * 16 + r16] = acc[jj][mt][i];
     }
+    __syncthreads();
     float *dst = partials + (size_t)blockIdx.x * PART;
     for (int i = threadIdx.x; i < PART; i += NET_NT) dst[i] = red[i];
 }
