@@ -230,7 +230,8 @@ def cpu_baseline(fat, lng, b, vh, budget_s=15.0, cg_budget_s=45.0):
       - the value: CG iterations of the same 32^4 FP64 CG for about budget_s, as sustained Dslash GB/s;
       - the oracle Dslash on 8^4, 16^4, 32^4 and 48^3x96 (median of 5; of 3 single-threaded on the
         largest), with every thread and with one, as algorithmic GB/s and GFLOP/s (1146 flops per site);
-      - the oracle CG to completion (1e-10) on 8^4 (m = 0.05) and 16^4 (m = 0.005)."""
+      - the oracle CG to completion (1e-10) on 8^4 (m = 0.05) and 16^4 (m = 0.005), and 50 iterations on 48^3x96
+        (m = 0.005) scaled to the GPU solve's 7610 iterations (marked extrapolated)."""
     import tempfile
 
     import numpy as np
@@ -285,13 +286,17 @@ def cpu_baseline(fat, lng, b, vh, budget_s=15.0, cg_budget_s=45.0):
     # to completion when the oracle's measured Dslash rate says it fits cg_budget_s, else 200 iterations,
     # extrapolated to the GPU solve's iteration count and marked so)
     cgs = {}
-    for dims, mass, cfg, gpu_iters in (((8, 8, 8, 8), 0.05, 1, 753), ((16, 16, 16, 16), 0.005, 5, 7582)):
+    # 48^3x96 (m = 0.005, ~28 GB of traffic per iteration) is timed for 50 iterations and scaled to the GPU's
+    # 7610, marked as extrapolated
+    for dims, mass, cfg, gpu_iters, sample in (((8, 8, 8, 8), 0.05, 1, 753, 200),
+                                               ((16, 16, 16, 16), 0.005, 5, 7582, 200),
+                                               ((48, 48, 48, 96), 0.005, 3, 7610, 50)):
         f_, l_ = synth.links(dims, synth.gauge_seed(cfg))
         s_ = synth.source(dims, synth.source_seed(cfg))
         est = 2.2 * gpu_iters * dsl["x".join(map(str, dims))][f"threads_{nthreads}"]["s"]
         full = est <= cg_budget_s
         t1 = time.perf_counter()
-        _, ci = oracle.cg(dims, mass, f_, l_, s_, tol=TOL if full else 1e-30, max_iter=100000 if full else 200,
+        _, ci = oracle.cg(dims, mass, f_, l_, s_, tol=TOL if full else 1e-30, max_iter=100000 if full else sample,
                          lib=lib)
         t = time.perf_counter() - t1
         row = {"mass": mass, "iters": ci["iters"]}
@@ -302,6 +307,7 @@ def cpu_baseline(fat, lng, b, vh, budget_s=15.0, cg_budget_s=45.0):
                         "from": f"{ci['iters']} iterations in {t:.2f} s, scaled to {gpu_iters} iterations"})
         cgs["x".join(map(str, dims))] = row
         log(f"[cpu] oracle CG {'x'.join(map(str, dims))} m={mass}: {row}")
+        del f_, l_, s_
     out["cg_to_1e-10"] = cgs
     return out
 
