@@ -378,7 +378,17 @@ __global__ __launch_bounds__(NT) HISQ_WAVES(W) void k_cg_Ap_upd(Geom g, const ch
             for (int c = 0; c < 3; ++c) {
                 const size_t i = (size_t)h * 3 + c;
                 const typename P::cvec pv = p[i];
-                typename P::cvec xv = x[i], rv = r[i];
+                // x and r are streamed (read once, written once per iteration): in FP64 streaming loads keep
+                // them from evicting the gathered t and the p that the next Dslash gathers (48^3x96: 2663 ->
+                // 2615 us per launch)
+                typename P::cvec xv, rv;
+                if constexpr (sizeof(typename P::real) == 8) {
+                    xv = ntload(x + i);
+                    rv = ntload(r + i);
+                } else {
+                    xv = x[i];
+                    rv = r[i];
+                }
                 const R apx = fma(m, pv.x, -acc[2 * c]), apy = fma(m, pv.y, -acc[2 * c + 1]);
                 xv.x = fma(a, pv.x, xv.x);
                 xv.y = fma(a, pv.y, xv.y);
