@@ -102,6 +102,13 @@ def net_layer_bytes(cin, cout, sites):
     return (4 * 72 + (cin + cout) * 24) * sites
 
 
+def net_bwd_bytes(ci, co, sites):
+    """Algorithmic bytes of the fused backward of a layer with CO input and CI output channels (input gradient
+    through the adjoint layer and the weight gradient from the same transports): the links, the upstream
+    gradient (CI channels), the layer input and the input gradient (CO channels each)."""
+    return (4 * 72 + (ci + 2 * co) * 24) * sites
+
+
 def summarize_counters(kind, fetch_dir, write_dir):
     """HBM traffic per launch from a pair of rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, in KiB per
     dispatch) of a traffic probe, each counter scaled by what it reads for the probe's 1 GiB device copy.
@@ -160,11 +167,12 @@ def summarize_counters(kind, fetch_dir, write_dir):
         algo = {}
 
         def label(name):
-            m = re.search(r"(k_net_layer|k_net_wgrad)<(\d+), ?(\d+)", name)
+            m = re.search(r"(k_net_layer|k_net_wgrad|k_net_bwd)<(\d+), ?(\d+)", name)
             if not m:
                 return None
             lab = f"{m.group(1)}<{m.group(2)},{m.group(3)}>"
-            algo[lab] = net_layer_bytes(int(m.group(2)), int(m.group(3)), V * batch)
+            nbytes = net_bwd_bytes if m.group(1) == "k_net_bwd" else net_layer_bytes
+            algo[lab] = nbytes(int(m.group(2)), int(m.group(3)), V * batch)
             return lab
     else:
         raise SystemExit(f"unknown counter summary kind {kind}")
@@ -594,11 +602,13 @@ def run_mdslash(args, nrhs=(8, 16), reps=20):
 
 
 def run_net_kernels(args, dims=(16, 16, 16, 16), C=16, batch=16, reps=5):
-    """The network's kernels alone on the training shape: forward (4 layers) and backward (4 weight
-    gradients, 3 input gradients) of a batch of 16 sources at 16^4, C = 16, timed with HIP events on the
-    stream they run on.  Algorithmic bytes per full-lattice site of a C_in -> C_out layer: the fat links
-    (four FP32 matrices, each serving two sites) and the input and output features (24 bytes per
-    channel); of a weight gradient the links, the input features and the upstream gradient."""
+    """The network's kernels alone on the training shape: forward (4 layers) and backward (layers 4, 3, 2
+    fused input and weight gradients, layer 1's weight gradient and input gradient) of a batch of 16
+    sources at 16^4, C = 16, timed with HIP events on the stream they run on.  Algorithmic bytes per
+    full-lattice site of a C_in -> C_out layer: the fat links (four FP32 matrices, each serving two sites)
+    and the input and output features (24 bytes per channel); of a weight gradient the links, the input
+    features and the upstream gradient; of a fused backward the links, the upstream gradient, the layer
+    input and the input gradient."""
     import numpy as np
     import torch
 
@@ -643,8 +653,9 @@ def run_net_kernels(args, dims=(16, 16, 16, 16), C=16, batch=16, reps=5):
     t_b = timed(bwd, reps, stream) * 1e-6
     layer_bytes = lambda ci, co: net_layer_bytes(ci, co, V * batch)
     fwd_bytes = layer_bytes(1, C) + 2 * layer_bytes(C, C) + layer_bytes(C, 1)
-    # backward: weight gradients (links, input, upstream gradient) and the three input gradients it needs
-    bwd_bytes = fwd_bytes + layer_bytes(1, C) + 2 * layer_bytes(C, C)
+    # backward: the fused layers 4, 3, 2, then layer 1's weight gradient and (grad_in given) input gradient
+    bwd_bytes = (net_bwd_bytes(1, C, V * batch) + 2 * net_bwd_bytes(C, C, V * batch) + layer_bytes(1, C)
+                 + layer_bytes(C, 1))
     out = {"workload": f"network forward / backward, {'x'.join(map(str, dims))}, C {C}, batch {batch}",
            "forward_ms": round(t_f * 1e3, 3), "backward_ms": round(t_b * 1e3, 3),
            "forward_gbs": round(fwd_bytes / t_f / 1e9, 1), "backward_gbs": round(bwd_bytes / t_b / 1e9, 1),

@@ -118,6 +118,56 @@ __device__ __forceinline__ NetSite net_site(const Geom &g, int p, int tile, int 
     return s;
 }
 
+// The CH channels of a unit's tile (64 sites of one parity and batch entry)
+// as float4 pairs of consecutive colour entries, TileFeat::NV per thread, all
+// loads issued before any value is used.  Every extent is even, so Vh and a
+// tile's first site are multiples of 8: the tile's entries in the lattice end
+// at an even index, a pair lies wholly inside or outside, and pairs outside
+// read as zero.
+template <int CH> struct TileFeat {
+    static constexpr int NP = CH * NCOL / 2;  // pairs of the tile
+    static constexpr int NV = (NP + NET_NT - 1) / NET_NT;
+    float4 v[NV];
+};
+// (The thread index goes through an opaque copy: in a loop over units the
+// compiler would otherwise keep every entry's offsets from the first unit on,
+// in registers the loop needs.)
+__device__ __forceinline__ int opaque_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+template <int CH>
+__device__ __forceinline__ void tile_feat_load(const Geom &g, const float2 *__restrict__ f, int b, int p, int tile,
+                                               TileFeat<CH> &t)
+{
+    const int nvalid = min(NCOL, (g.Vh - tile * TILE) * 3), tid = opaque_tid();
+#pragma unroll
+    for (int it = 0; it < TileFeat<CH>::NV; ++it) {
+        const int i = tid + it * NET_NT, c = i / (NCOL / 2), jc = 2 * (i % (NCOL / 2));
+        t.v[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i < TileFeat<CH>::NP && jc < nvalid)
+            t.v[it] = *reinterpret_cast<const float4 *>(f + feat_idx(b, CH, c, p, g.Vh, tile * TILE) + jc);
+    }
+}
+// Row c of `rows` gets (s0 e_r, s0 e_i) and row c + CH (s1 e_i, s2 e_r) of
+// each entry e of channel c, as BF16 at K = 2 jc, 2 jc + 1 (pitch PK).
+template <int CH, int PK>
+__device__ __forceinline__ void tile_feat_put(const TileFeat<CH> &t, __bf16 *rows, float s1, float s2)
+{
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int it = 0; it < TileFeat<CH>::NV; ++it) {
+        const int i = tid + it * NET_NT, c = i / (NCOL / 2), jc = 2 * (i % (NCOL / 2));
+        if (i >= TileFeat<CH>::NP) continue;
+        const float4 e = t.v[it];
+        *reinterpret_cast<bf16x4 *>(rows + c * PK + 2 * jc) = bf16x4{ (__bf16)e.x, (__bf16)e.y, (__bf16)e.z, (__bf16)e.w };
+        *reinterpret_cast<bf16x4 *>(rows + (CH + c) * PK + 2 * jc) =
+            bf16x4{ (__bf16)(s1 * e.y), (__bf16)(s2 * e.x), (__bf16)(s1 * e.w), (__bf16)(s2 * e.z) };
+    }
+}
+
 // The loads of a thread's four pairs of one slice when they share one
 // transport (C_in >= 4): the link and the four neighbour (or own) vectors,
 // kept raw so that the MFMA of the previous slice can run while they arrive.
@@ -452,13 +502,12 @@ __global__ __launch_bounds__(NET_NT, 4) void k_net_wgrad(Geom g, const char *__r
         net_unit(u, g.ntiles, b, tile, p);
         const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
         const NetSite site = net_site(g, p, tile, lane);
-        // (the previous unit's last slice ended with a barrier: its operands have been read)
-        for (int i = threadIdx.x; i < COUT * NCOL; i += NET_NT) {
-            const int a = i / NCOL, jc = i % NCOL, h = tile * TILE + jc / 3;
-            float2 v = make_float2(0.f, 0.f);
-            if (h < g.Vh) v = gout[feat_idx(b, COUT, a, p, g.Vh, h) + jc % 3];
-            *reinterpret_cast<bf16x2 *>(Ga + a * PK + 2 * jc) = bf16x2{ (__bf16)v.x, (__bf16)v.y };
-            *reinterpret_cast<bf16x2 *>(Ga + (COUT + a) * PK + 2 * jc) = bf16x2{ (__bf16)v.y, (__bf16)(-v.x) };
+        // g's rows [g_r, g_i] and [g_i, -g_r]; (the previous unit's last slice ended with a barrier: its
+        // operands have been read)
+        {
+            TileFeat<COUT> gt;
+            tile_feat_load<COUT>(g, gout, b, p, tile, gt);
+            tile_feat_put<COUT, PK>(gt, Ga, 1.f, -1.f);
         }
         auto put = [&](__bf16 *Fb, const float tv[4][6]) {
 #pragma unroll
@@ -511,6 +560,193 @@ __global__ __launch_bounds__(NET_NT, 4) void k_net_wgrad(Geom g, const char *__r
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) red[((j * MT + mt) * 16 + 4 * (lane >> 4) + i) * 16 + r16] = acc[jj][mt][i];
+    }
+    __syncthreads();
+    float *dst = partials + (size_t)blockIdx.x * PART;
+    for (int i = threadIdx.x; i < PART; i += NET_NT) dst[i] = red[i];
+}
+
+// ------------------------------------------------------------------ fused backward of a layer
+// For a layer with input x (CO channels) and upstream gradient g (CI
+// channels): the input gradient dx = sum_k W'_k T_k g (the adjoint layer,
+// as k_net_layer<CI, CO>) and the weight gradient re-associated onto the
+// same transports of g,
+//     G_k^{ac} = sum_x <T_k x^c, g^a> = sum_y <x^c, T_k^dag g^a> = sum_y <x^c, T_{adj k} g^a>,
+// so each slice of transported g is computed once and serves both GEMMs.
+// The mixing is the layer kernel's; for the weight gradient x's own-site
+// values go to LDS once per unit as the A operand [[x_r, x_i], [-x_i, x_r]]
+// (rows Re and Im of channel c, K = (column, re/im)), the slice once more as
+// B [pair][K], and R_{(k',a)}^c = sum_y conj(x^c) T'_{k'} g^a accumulates on
+// the owner wave j % 4 as in k_net_wgrad.  The packed backward slots give
+// T'_{k'} = -T_{k'} for k' >= 5; the partial stores, at slot k = adj k' of
+// the forward layer's layout, the sum k_net_wgrad would have formed there
+// with unsigned transports: -R for k' >= 1 and R for k' = 0, so that
+// k_net_wgrad_reduce<CO, CI> finishes it unchanged.  Persistent workgroups
+// over the units in XCD order (as k_net_wgrad); the input gradient of each
+// unit is stored when its slices are done.  One slice buffer of each layout,
+// 53 KB of LDS for CO = 16: three workgroups per CU.
+template <int CI, int CO>
+__global__ __launch_bounds__(NET_NT, 3) void k_net_bwd(Geom g, const char *__restrict__ fat,
+                                                    const float2 *__restrict__ gup, const float2 *__restrict__ x,
+                                                    float2 *__restrict__ dx, const __bf16 *__restrict__ A, int batch,
+                                                    float *__restrict__ partials)
+{
+    using S = Slices<CI>;                   // slices of the transported upstream gradient
+    constexpr int MTX = (2 * CO + 15) / 16;  // 16-row tiles of dx and of the x operand
+    constexpr int KT = 2 * NCOL, PK = KT + 8, PB = SK + 8;
+    constexpr int KGF = Slices<CO>::KG;      // the forward layer's partial layout
+    constexpr int MTF = (2 * CI + 15) / 16;
+    constexpr int PART = Slices<CO>::N * MTF * 256;
+    constexpr int NSL = (S::N + 3) / 4;
+    __shared__ __align__(16) __bf16 lds[(MTX * 16 + 16) * PK + NCOL * PB];
+    __bf16 *Xa = lds;                  // weight gradient A: [row][K]
+    __bf16 *Fb = lds + MTX * 16 * PK;  // weight gradient B: [pair][K]
+    __bf16 *F = Fb + 16 * PK;          // mixing B: [column][pairs re | pairs im]
+    static_assert(PART * 4 <= (int)sizeof(lds), "partial reduction does not fit the LDS operands");
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int r16 = lane & 15, k8 = 8 * (lane >> 4);
+    floatx4 accw[NSL][MTX];
+#pragma unroll
+    for (int jj = 0; jj < NSL; ++jj)
+#pragma unroll
+        for (int mt = 0; mt < MTX; ++mt) accw[jj][mt] = floatx4{ 0.f, 0.f, 0.f, 0.f };
+    // rows 2 CO .. 16 MTX - 1 of the x operand stay zero
+    for (int i = threadIdx.x; i < (MTX * 16 - 2 * CO) * PK; i += NET_NT) Xa[2 * CO * PK + i] = (__bf16)0.f;
+    auto put = [&](const float tv[4][6]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            __bf16 *row = Fb + (4 * q + i) * PK + 6 * lane;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                *reinterpret_cast<bf16x2 *>(row + 2 * a) = bf16x2{ (__bf16)tv[i][2 * a], (__bf16)tv[i][2 * a + 1] };
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            __bf16 *col = F + (3 * lane + a) * PB;
+            const bf16x4 re = { (__bf16)tv[0][2 * a], (__bf16)tv[1][2 * a], (__bf16)tv[2][2 * a], (__bf16)tv[3][2 * a] };
+            const bf16x4 im = { (__bf16)tv[0][2 * a + 1], (__bf16)tv[1][2 * a + 1], (__bf16)tv[2][2 * a + 1],
+                                (__bf16)tv[3][2 * a + 1] };
+            *reinterpret_cast<bf16x4 *>(col + 4 * q) = re;
+            *reinterpret_cast<bf16x4 *>(col + 16 + 4 * q) = im;
+        }
+    };
+    const int units = batch * 2 * g.ntiles;
+    const int xcd = blockIdx.x % NXCD, per_xcd = gridDim.x / NXCD, units_per_xcd = (units + NXCD - 1) / NXCD;
+#pragma unroll 1
+    for (int v = blockIdx.x / NXCD; v < units_per_xcd; v += per_xcd) {
+        const int u = xcd * units_per_xcd + v;
+        if (u >= units) break;
+        int b, tile, p;
+        net_unit(u, g.ntiles, b, tile, p);
+        const float2 *gb = gup + (size_t)b * CI * 2 * g.Vh * 3;
+        const NetSite site = net_site(g, p, tile, lane);
+        // the weights operand does not depend on the unit: an opaque copy of its
+        // pointer keeps the compiler from hoisting every slice's load out of the
+        // unit loop (72 registers held for the whole kernel)
+        const __bf16 *Au = A;
+        asm volatile("" : "+s"(Au));
+        // x's rows [x_r, x_i] and [-x_i, x_r]; (the previous unit's last slice ended with a barrier: its
+        // operands have been read)
+        {
+            TileFeat<CO> xt;
+            tile_feat_load<CO>(g, x, b, p, tile, xt);
+            tile_feat_put<CO, PK>(xt, Xa, -1.f, 1.f);
+        }
+        floatx4 acc[3][MTX];
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+            for (int mt = 0; mt < MTX; ++mt) acc[n][mt] = floatx4{ 0.f, 0.f, 0.f, 0.f };
+        {
+            float tv[4][6];
+            slice_transport<CI>(g, fat, gb, p, tile, lane, site, 0, q, tv);
+            put(tv);
+        }
+        __syncthreads();  // x and slice 0 are in LDS
+        // unrolled: accw[j >> 2] must stay in registers; slice j + 1's loads are in flight over slice j's MFMA
+#pragma unroll
+        for (int j = 0; j < S::N; ++j) {
+            const bool more = j + 1 < S::N;
+            // the next slice's transport goes to registers while this one is multiplied
+            float tv[4][6];
+            if (more) slice_transport<CI>(g, fat, gb, p, tile, lane, site, j + 1, q, tv);
+            {  // mixing: the layer kernel's column tiles 3q..3q+2
+                bf16x8 av[MTX];
+#pragma unroll
+                for (int mt = 0; mt < MTX; ++mt)
+                    av[mt] = *reinterpret_cast<const bf16x8 *>(Au + ((size_t)j * MPAD + mt * 16 + r16) * SK + k8);
+#pragma unroll
+                for (int n = 0; n < 3; ++n) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(F + ((3 * q + n) * 16 + r16) * PB + k8);
+#pragma unroll
+                    for (int mt = 0; mt < MTX; ++mt)
+                        acc[n][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[n][mt], 0, 0, 0);
+                }
+            }
+            if (q == (j & 3)) {  // this slice's weight-gradient owner (wave-uniform)
+#pragma unroll
+                for (int ks = 0; ks < KT / SK; ++ks) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Fb + r16 * PK + SK * ks + k8);
+#pragma unroll
+                    for (int mt = 0; mt < MTX; ++mt) {
+                        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Xa + (mt * 16 + r16) * PK + SK * ks + k8);
+                        accw[j >> 2][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, accw[j >> 2][mt], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();  // every wave is done with slice j
+            if (more) {
+                put(tv);
+                __syncthreads();
+            }
+        }
+        // the unit's input gradient (the layer kernel's store)
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+            const int col = (3 * q + n) * 16 + r16, s = col / 3, a = col % 3, h = tile * TILE + s;
+            if (h >= g.Vh) continue;
+            if constexpr (CO == 16) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    dx[feat_idx(b, CO, 4 * (lane >> 4) + i, p, g.Vh, h) + a] = make_float2(acc[n][0][i], acc[n][1][i]);
+                continue;
+            }
+            float *o = reinterpret_cast<float *>(dx);
+#pragma unroll
+            for (int mt = 0; mt < MTX; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int m = mt * 16 + 4 * (lane >> 4) + i;
+                    if (m < 2 * CO) {
+                        const int ch = m < CO ? m : m - CO;
+                        o[2 * (feat_idx(b, CO, ch, p, g.Vh, h) + a) + (m < CO ? 0 : 1)] = acc[n][mt][i];
+                    }
+                }
+        }
+    }
+    // scatter every owned (slice, row tile) into the forward layer's partial layout, then a coalesced store
+    float *red = reinterpret_cast<float *>(lds);
+    __syncthreads();
+    for (int i = threadIdx.x; i < PART; i += NET_NT) red[i] = 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < NSL; ++jj) {
+        const int j = q + 4 * jj;
+        if (j >= S::N) continue;
+        const int kp = j * S::KG + r16 / CI, a = r16 % CI;  // column: pair (k', a) of the slice
+        if (kp >= 9) continue;
+        const int kf = ADJ[kp], jf = kf / KGF;
+#pragma unroll
+        for (int mt = 0; mt < MTX; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = mt * 16 + 4 * (lane >> 4) + i;
+                if (row >= 2 * CO) continue;
+                const bool re = row < CO;
+                const int c = re ? row : row - CO, mf = re ? a : CI + a;
+                const float val = kp ? -accw[jj][mt][i] : accw[jj][mt][i];
+                red[((jf * MTF + mf / 16) * 16 + mf % 16) * 16 + (kf % KGF) * CO + c] = val;
+            }
     }
     __syncthreads();
     float *dst = partials + (size_t)blockIdx.x * PART;
@@ -729,18 +965,14 @@ static int net_forward_t(const Geom &g, const void *fat, const float2 *W, const 
 static_assert(WG_MAX_BLOCKS % NXCD == 0, "the weight-gradient grid is a whole number of XCD groups");
 constexpr size_t WG_PART_FLOATS = (size_t)9 * 2 * 256;  // the largest per-block partial (9 slices, 32 rows)
 
-// The persistent weight-gradient grid: the workgroups that are resident at
-// once (occupancy x CUs), at most one per unit and WG_MAX_BLOCKS, rounded up
-// to a whole number of XCD groups.
-template <int CIN, int COUT>
-static int wgrad_blocks(const Geom &g, int batch)
+// A persistent weight-gradient grid: the workgroups of `kern` that are
+// resident at once (occupancy x CUs, found once per kernel), at most one per
+// unit and WG_MAX_BLOCKS, rounded up to a whole number of XCD groups.
+static int persistent_blocks(const void *kern, int &resident, const Geom &g, int batch)
 {
-    static int resident = 0;
     if (!resident) {
         int occ = 0, cus = 0, dev = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_net_wgrad<CIN, COUT>, NET_NT, 0) !=
-                hipSuccess || occ <= 0)
-            occ = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, NET_NT, 0) != hipSuccess || occ <= 0) occ = 1;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
@@ -748,6 +980,18 @@ static int wgrad_blocks(const Geom &g, int batch)
     }
     const long long units = (long long)batch * 2 * g.ntiles;
     return xcd_grid((int)std::min<long long>(std::min<long long>(units, resident), WG_MAX_BLOCKS));
+}
+template <int CIN, int COUT>
+static int wgrad_blocks(const Geom &g, int batch)
+{
+    static int resident = 0;
+    return persistent_blocks((const void *)k_net_wgrad<CIN, COUT>, resident, g, batch);
+}
+template <int CI, int CO>
+static int bwd_blocks(const Geom &g, int batch)
+{
+    static int resident = 0;
+    return persistent_blocks((const void *)k_net_bwd<CI, CO>, resident, g, batch);
 }
 
 // Backward workspace: dl/d in4, dl/d in3, dl/d in2 (C channels each), dl/d out
@@ -791,6 +1035,22 @@ static void wgrad_launch(const Geom &g, const void *fat, const float2 *in, const
                        (const float *)part, nb, (float *)gw);
 }
 
+// The backward of a layer with input x (CO channels) and upstream gradient
+// gup (CI channels): dx through the adjoint layer and the layer's weight
+// gradient from the same transports of gup (k_net_bwd), then the fixed-order
+// reduction of the partials in the layout of the forward layer <CO, CI>.
+template <int CI, int CO>
+static void bwd_launch(const Geom &g, const void *fat, const float2 *gup, const float2 *x, float2 *dx,
+                       const __bf16 *A, int batch, float *part, float2 *gw, hipStream_t s)
+{
+    const int nb = bwd_blocks<CI, CO>(g, batch);
+    hipLaunchKernelGGL((k_net_bwd<CI, CO>), dim3(nb), dim3(NET_NT), 0, s, g, (const char *)fat, gup, x, dx, A, batch,
+                       part);
+    constexpr int part_entries = Slices<CO>::N * ((2 * CI + 15) / 16) * 256;
+    hipLaunchKernelGGL((k_net_wgrad_reduce<CO, CI>), dim3((part_entries + 63) / 64), dim3(256), 0, s,
+                       (const float *)part, nb, (float *)gw);
+}
+
 template <int C>
 static int net_backward_t(const Geom &g, const void *fat, const float2 *W, const void *acts, const float2 *gout_even,
                           float2 *gw, float2 *gin_even, int batch, void *ws, hipStream_t s)
@@ -805,12 +1065,11 @@ static int net_backward_t(const Geom &g, const void *fat, const float2 *W, const
     prep_launch<C, C>(W + w_off(C, 2), d.A[2], 1, s);
     prep_launch<C, C>(W + w_off(C, 1), d.A[1], 1, s);
     prep_launch<1, C>(W + w_off(C, 0), d.A[0], 1, s);
-    wgrad_launch<C, 1>(g, fat, a.in[3], d.gout, batch, d.part, gw + w_off(C, 3), s);
-    layer_launch<1, C>(g, fat, d.gout, d.gin[3], d.A[3], batch, s);   // dl/d in4 (adjoint layer: 1 -> C)
-    wgrad_launch<C, C>(g, fat, a.in[2], d.gin[3], batch, d.part, gw + w_off(C, 2), s);
-    layer_launch<C, C>(g, fat, d.gin[3], d.gin[2], d.A[2], batch, s);  // dl/d in3
-    wgrad_launch<C, C>(g, fat, a.in[1], d.gin[2], batch, d.part, gw + w_off(C, 1), s);
-    layer_launch<C, C>(g, fat, d.gin[2], d.gin[1], d.A[1], batch, s);  // dl/d in2
+    // layers 4, 3, 2: dl/d in and dl/dW from one set of transports of the upstream gradient
+    bwd_launch<1, C>(g, fat, d.gout, a.in[3], d.gin[3], d.A[3], batch, d.part, gw + w_off(C, 3), s);
+    bwd_launch<C, C>(g, fat, d.gin[3], a.in[2], d.gin[2], d.A[2], batch, d.part, gw + w_off(C, 2), s);
+    bwd_launch<C, C>(g, fat, d.gin[2], a.in[1], d.gin[1], d.A[1], batch, d.part, gw + w_off(C, 1), s);
+    // layer 1 (one input channel): its weight gradient transports the input instead
     wgrad_launch<1, C>(g, fat, a.in[0], d.gin[1], batch, d.part, gw + w_off(C, 0), s);
     if (gin_even) {
         layer_launch<C, 1>(g, fat, d.gin[1], d.gin[0], d.A[0], batch, s);  // dl/d in1 (C -> 1)

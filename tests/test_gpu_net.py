@@ -180,10 +180,13 @@ def test_net_forward_layers(hq, C, dims):
 @pytest.mark.parametrize("dims", NET_DIMS)
 def test_net_backward(hq, C, dims):
     """Every layer's weight gradient and input gradient against FP64 sums of the BF16 operands
-    the GPU used, componentwise within TOL_MIX: dW_k^{ac} = sum conj(bf16(T_k x^c)) bf16(g^a)
-    with x the GPU's layer input (acts) and g the GPU's upstream gradient (left in the
-    workspace), and dl/dx^c = sum_k sum_a bf16(conj(W_{adj k}^{ac})) bf16(T_k g^a).  The
-    returned dl/d input is the even part of the first layer's input gradient, bit for bit."""
+    the GPU used, componentwise within TOL_MIX, with x the GPU's layer input (acts) and g the
+    GPU's upstream gradient (left in the workspace): dl/dx^c = sum_k sum_a
+    bf16(conj(W_{adj k}^{ac})) bf16(T_k g^a); the first layer's weight gradient
+    dW_k^{ac} = sum conj(bf16(T_k x^c)) bf16(g^a), and that of layers 2-4, taken from the same
+    transports of g as their input gradient, sum conj(bf16(x^c)) bf16(T_{adj k} g^a) (equal in
+    exact arithmetic, T_k^dag = T_{adj k}).  The returned dl/d input is the even part of the
+    first layer's input gradient, bit for bit."""
     import torch
     from paper_1411_2087_amd import train
     fat, _ = fields(dims, 1000)
@@ -206,13 +209,19 @@ def test_net_backward(hq, C, dims):
     ups = [ginv[1], ginv[2], ginv[3], goutv]  # dl/d (output of layer l)
     ew, ex = [], []
     for l in range(4):
-        gb = N._bf16c(ups[l].astype(np.complex64))
-        Tx = N._bf16c(gpu_transport(hq, L32.fat, views[l], dims).astype(np.complex64))
-        want = np.einsum("nkcpvs,napvs->kac", Tx.conj(), gb)
-        scale = np.einsum("nkcpvs,napvs->kac", np.abs(Tx), np.abs(gb))
+        Tg = N._bf16c(gpu_transport(hq, L32.fat, ups[l], dims).astype(np.complex64))
+        if l == 0:
+            gb = N._bf16c(ups[l].astype(np.complex64))
+            Tx = N._bf16c(gpu_transport(hq, L32.fat, views[l], dims).astype(np.complex64))
+            want = np.einsum("nkcpvs,napvs->kac", Tx.conj(), gb)
+            scale = np.einsum("nkcpvs,napvs->kac", np.abs(Tx), np.abs(gb))
+        else:
+            xb = N._bf16c(views[l].astype(np.complex64))
+            Tga = Tg[:, N.ADJOINT]
+            want = np.einsum("ncpvs,nkapvs->kac", xb.conj(), Tga)
+            scale = np.einsum("ncpvs,nkapvs->kac", np.abs(xb), np.abs(Tga))
         ew.append(cw_err(gws[l], want, scale))
         # input gradient: the adjoint layer on the upstream gradient
-        Tg = N._bf16c(gpu_transport(hq, L32.fat, ups[l], dims).astype(np.complex64))
         Wadj = N._bf16c(np.stack([np.conj(Ws[l][N.ADJOINT[k]]).T for k in range(9)]).astype(np.complex64))
         want_x, scale_x = mix(Wadj, Tg)
         ex.append(cw_err(ginv[l], want_x, scale_x))
