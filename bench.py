@@ -169,7 +169,12 @@ def summarize_counters(kind, fetch_dir, write_dir):
         def label(name):
             m = re.search(r"(k_net_layer|k_net_wgrad|k_net_bwd)<(\d+), ?(\d+)", name)
             if not m:
-                return None
+                m1 = re.search(r"k_net_layer_mt<(\d+)>", name)  # the C -> 1 layer
+                if not m1:
+                    return None
+                lab = f"k_net_layer_mt<{m1.group(1)}>"
+                algo[lab] = net_layer_bytes(int(m1.group(1)), 1, V * batch)
+                return lab
             lab = f"{m.group(1)}<{m.group(2)},{m.group(3)}>"
             nbytes = net_bwd_bytes if m.group(1) == "k_net_bwd" else net_layer_bytes
             algo[lab] = nbytes(int(m.group(2)), int(m.group(3)), V * batch)

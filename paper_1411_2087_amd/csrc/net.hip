@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "dslash_core.hpp"
 
@@ -426,6 +427,82 @@ __global__ __launch_bounds__(NET_NT) void k_net_layer(Geom g, const char *__rest
                 }
             }
     }
+}
+
+// ------------------------------------------------------------------ C -> 1 layer: mix, then transport
+// With one output channel the two linear maps are cheaper the other way
+// round: out(x) = sum_k T_k (sum_c W_k^c in^c)(x).  At the neighbour x + k_d
+// the CIN channels are mixed into one colour vector, which the link then
+// carries: 12 CIN + 36 FMAs per transport instead of 36 CIN and the mixing,
+// in FP32 on the VALU (no MFMA, no rounding of the operands to BF16).  One
+// workgroup per unit (64-site tile of one parity and batch entry, units in
+// XCD order, so that a CU's few units in flight keep their neighbour tiles
+// in its XCD's L2); wave q takes the directions 2q and 2q + 1 and the
+// channels 4q .. 4q + 3 of T_0, one thread per site, and the four partial
+// sums meet in LDS.  W: the layer's FP32 weights [9][1][CIN]; with adjoint,
+// those of a 1 -> CIN layer [9][CIN][1] taken as conj(W_{adj k}^{c}) (the
+// input gradient of that layer).
+template <int CIN>
+__global__ __launch_bounds__(NET_NT) void k_net_layer_mt(Geom g, const char *__restrict__ fat,
+                                                         const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                         const float2 *__restrict__ W, int batch, int adjoint)
+{
+    static_assert(CIN % 4 == 0, "four waves share the channels of T_0");
+    __shared__ float part[4][6][TILE];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int u = xcd_block(blockIdx.x, gridDim.x);
+    if (u >= batch * 2 * g.ntiles) return;  // the grid is rounded up to a multiple of the XCD count
+    int b, tile, p;
+    net_unit(u, g.ntiles, b, tile, p);
+    const NetSite st = net_site(g, p, tile, lane);
+    const float2 *inb = in + (size_t)b * CIN * 2 * g.Vh * 3;
+    const size_t ch_stride = (size_t)2 * g.Vh * 3;
+    const char *tb = fat + ((size_t)p * g.ntiles + tile) * 8 * PF32::block_bytes;
+    const float wsg = adjoint ? -1.f : 1.f;  // conjugate for the adjoint
+    // v += sum over channels c0 .. c0 + NC - 1 of W_k^c in^c at (parity pn, site hn)
+    auto mixin = [&](int k, int pn, int hn, int c0, auto nc, float v[6]) {
+        const float2 *src = inb + (size_t)pn * g.Vh * 3 + (size_t)hn * 3;
+        const float2 *wk = W + (size_t)(adjoint ? ADJ[k] : k) * CIN;
+#pragma unroll
+        for (int i = 0; i < decltype(nc)::value; ++i) {
+            const int c = c0 + i;
+            const float2 w = wk[c];
+            const float wr = w.x, wi = wsg * w.y;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float2 e = src[c * ch_stride + a];
+                v[2 * a] = fmaf(wr, e.x, v[2 * a]);
+                v[2 * a] = fmaf(-wi, e.y, v[2 * a]);
+                v[2 * a + 1] = fmaf(wr, e.y, v[2 * a + 1]);
+                v[2 * a + 1] = fmaf(wi, e.x, v[2 * a + 1]);
+            }
+        }
+    };
+    float o[6] = { 0.f, 0.f, 0.f, 0.f, 0.f, 0.f };
+    mixin(0, p, st.hc, q * (CIN / 4), std::integral_constant<int, CIN / 4>{}, o);
+#pragma unroll 1
+    for (int dd = 0; dd < 2; ++dd) {
+        const int d = 2 * q + dd;
+        const int hn = nbr_h(g, st.hc, st.x, st.y, st.z, st.t, d & 3, d >= 4 ? -1 : 1);
+        float v[6] = { 0.f, 0.f, 0.f, 0.f, 0.f, 0.f }, m[18], t[6];
+        mixin(d + 1, 1 - p, hn, 0, std::integral_constant<int, CIN>{}, v);
+        load_link32(tb + (size_t)d * PF32::block_bytes, lane, m);
+        // the backward slots hold -F^dag: undo the sign
+        matvec32(m, d >= 4 ? -1.f : 1.f, make_float2(v[0], v[1]), make_float2(v[2], v[3]), make_float2(v[4], v[5]),
+                 t);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) o[i] += t[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) part[q][i][lane] = o[i];
+    __syncthreads();
+    // thread (wave a, lane) stores colour a of site lane: the four partials in a fixed order
+    const int a = q;
+    if (a >= 3 || tile * TILE + lane >= g.Vh) return;
+    const float re = ((part[0][2 * a][lane] + part[1][2 * a][lane]) + part[2][2 * a][lane]) + part[3][2 * a][lane];
+    const float im =
+        ((part[0][2 * a + 1][lane] + part[1][2 * a + 1][lane]) + part[2][2 * a + 1][lane]) + part[3][2 * a + 1][lane];
+    out[feat_idx(b, 1, 0, p, g.Vh, tile * TILE + lane) + a] = make_float2(re, im);
 }
 
 // ------------------------------------------------------------------ transports (inspection of the operands)
@@ -935,6 +1012,15 @@ static void layer_launch(const Geom &g, const void *fat, const float2 *in, float
                        batch);
 }
 
+template <int CIN>
+static void layer_mt_launch(const Geom &g, const void *fat, const float2 *in, float2 *out, const float2 *W, int batch,
+                            int adjoint, hipStream_t s)
+{
+    const int grid = xcd_grid(batch * 2 * g.ntiles);
+    hipLaunchKernelGGL((k_net_layer_mt<CIN>), dim3(grid), dim3(NET_NT), 0, s, g, (const char *)fat, in, out, W, batch,
+                       adjoint);
+}
+
 template <int CIN, int COUT>
 static void prep_launch(const float2 *W, __bf16 *A, int adjoint, hipStream_t s)
 {
@@ -949,14 +1035,13 @@ static int net_forward_t(const Geom &g, const void *fat, const float2 *W, const 
     prep_launch<1, C>(W + w_off(C, 0), a.A[0], 0, s);
     prep_launch<C, C>(W + w_off(C, 1), a.A[1], 0, s);
     prep_launch<C, C>(W + w_off(C, 2), a.A[2], 0, s);
-    prep_launch<C, 1>(W + w_off(C, 3), a.A[3], 0, s);
     const long long ne = (long long)batch * 2 * g.Vh * 3;
     const int nb = (int)std::min<long long>((ne + 255) / 256, 4096);
     hipLaunchKernelGGL(k_net_embed, dim3(nb), dim3(256), 0, s, in_even, a.in[0], batch, g.Vh);
     layer_launch<1, C>(g, fat, a.in[0], a.in[1], a.A[0], batch, s);
     layer_launch<C, C>(g, fat, a.in[1], a.in[2], a.A[1], batch, s);
     layer_launch<C, C>(g, fat, a.in[2], a.in[3], a.A[2], batch, s);
-    layer_launch<C, 1>(g, fat, a.in[3], a.out, a.A[3], batch, s);
+    layer_mt_launch<C>(g, fat, a.in[3], a.out, W + w_off(C, 3), batch, 0, s);
     if (out_even) hipLaunchKernelGGL(k_net_extract, dim3(nb), dim3(256), 0, s, (const float2 *)a.out, out_even, batch, g.Vh);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
@@ -1064,7 +1149,6 @@ static int net_backward_t(const Geom &g, const void *fat, const float2 *W, const
     prep_launch<C, 1>(W + w_off(C, 3), d.A[3], 1, s);
     prep_launch<C, C>(W + w_off(C, 2), d.A[2], 1, s);
     prep_launch<C, C>(W + w_off(C, 1), d.A[1], 1, s);
-    prep_launch<1, C>(W + w_off(C, 0), d.A[0], 1, s);
     // layers 4, 3, 2: dl/d in and dl/dW from one set of transports of the upstream gradient
     bwd_launch<1, C>(g, fat, d.gout, a.in[3], d.gin[3], d.A[3], batch, d.part, gw + w_off(C, 3), s);
     bwd_launch<C, C>(g, fat, d.gin[3], a.in[2], d.gin[2], d.A[2], batch, d.part, gw + w_off(C, 2), s);
@@ -1072,7 +1156,7 @@ static int net_backward_t(const Geom &g, const void *fat, const float2 *W, const
     // layer 1 (one input channel): its weight gradient transports the input instead
     wgrad_launch<1, C>(g, fat, a.in[0], d.gin[1], batch, d.part, gw + w_off(C, 0), s);
     if (gin_even) {
-        layer_launch<C, 1>(g, fat, d.gin[1], d.gin[0], d.A[0], batch, s);  // dl/d in1 (C -> 1)
+        layer_mt_launch<C>(g, fat, d.gin[1], d.gin[0], W + w_off(C, 0), batch, 1, s);  // dl/d in1 (C -> 1)
         hipLaunchKernelGGL(k_net_extract, dim3(nb), dim3(256), 0, s, (const float2 *)d.gin[0], gin_even, batch, g.Vh);
     }
     HISQ_HIP(hipGetLastError());

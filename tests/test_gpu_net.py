@@ -114,6 +114,36 @@ def cw_err(got, want, scale):
     return float(np.max(np.abs(got - want) / np.maximum(scale, 1e-300)))
 
 
+TOL_FP32 = 1e-5  # FP32 products and sums of 16 channels and a 3x3 link: ~22 roundings of 2^-24
+
+
+def fp32_layer_ref(dims, fat, W, feats):
+    """The C -> 1 layer as the GPU computes it, in FP32 without BF16 operands: FP64
+    out = sum_k sum_c W_k^c T_k x^c over the FP32-rounded weights and links, and the
+    componentwise scale sum_k |T_k| (sum_c |W_k^c| |x^c|) (entrywise absolute links) that
+    bounds its rounding.  feats: (batch, C, 2, Vh, 3); W: [9][1][C].  Returns (batch, 1, 2, Vh, 3)."""
+    W32 = W.astype(np.complex64).astype(np.complex128)
+    f32 = fat.astype(np.complex64).astype(np.complex128)
+    afat = np.abs(f32)
+    vh = int(np.prod(dims)) // 2
+    outs, scales = [], []
+    for n in range(feats.shape[0]):
+        X = eo_to_lex(dims, feats[n])
+        o = np.zeros(X.shape[1:], np.complex128)
+        sc = np.zeros(X.shape[1:])
+        for k in range(9):
+            o += N.transport(dims, f32, np.einsum("c,cvs->vs", W32[k, 0], X), k)
+            sc += N.transport(dims, afat, np.einsum("c,cvs->vs", np.abs(W32[k, 0]), np.abs(X)), k).real
+        oe = np.zeros((1, 2, vh, 3), np.complex128)
+        se = np.zeros((1, 2, vh, 3))
+        for p in (0, 1):
+            oe[0, p] = o[lattice.parity_sites(dims, p)]
+            se[0, p] = sc[lattice.parity_sites(dims, p)]
+        outs.append(oe)
+        scales.append(se)
+    return np.stack(outs), np.stack(scales)
+
+
 @pytest.mark.parametrize("C", [4, 16])
 @pytest.mark.parametrize("dims", NET_DIMS)
 def test_net_transport(hq, C, dims):
@@ -146,24 +176,29 @@ def test_net_transport(hq, C, dims):
 @pytest.mark.parametrize("C", [4, 8, 16])
 @pytest.mark.parametrize("dims", NET_DIMS)
 def test_net_forward_layers(hq, C, dims):
-    """Every layer's output against the FP64 mixing of the very BF16 operands the MFMA used:
-    the GPU's own layer input, transported by the same device code (net_transport) and
-    rounded to BF16 (round to nearest even, as the kernels convert), and the BF16-rounded
-    weights.  Componentwise within TOL_MIX of sum |W| |T phi|: only the FP32 accumulation
-    differs.  The network output is the even part of the last layer, bit for bit."""
+    """Layers 1-3 against the FP64 mixing of the very BF16 operands the MFMA used: the
+    GPU's own layer input, transported by the same device code (net_transport) and rounded
+    to BF16 (round to nearest even, as the kernels convert), and the BF16-rounded weights;
+    componentwise within TOL_MIX of sum |W| |T phi|: only the FP32 accumulation differs.  The
+    C -> 1 layer (mixed in FP32, then transported) against the FP64 layer over the FP32 weights
+    and links, componentwise within TOL_FP32.  The network output is the even part of the last
+    layer, bit for bit."""
     fat, _ = fields(dims, 1000)
     Ws = rand_weights(C, 3)
     bs = [synth.source(dims, 60 + i) for i in range(2)]
     L32, w, b, y, acts = gpu_forward(hq, dims, fat, Ws, C, bs)
     views = acts_views(acts.cpu().numpy(), dims, C, 2)
     worst = 0.0
-    for l in range(4):
+    for l in range(3):
         Tb = N._bf16c(gpu_transport(hq, L32.fat, views[l], dims).astype(np.complex64))
         Wb = N._bf16c(Ws[l].astype(np.complex64))
         want, scale = mix(Wb, Tb)
         e = cw_err(views[l + 1], want, scale)
         worst = max(worst, e)
         assert e <= TOL_MIX, (l, e)
+    want, scale = fp32_layer_ref(dims, fat, Ws[3], views[3])
+    e3 = cw_err(views[4], want, scale)
+    assert e3 <= TOL_FP32, e3
     assert np.array_equal(y.cpu().numpy(), views[4][:, 0, 0].astype(np.complex64))
     # the first layer's input is the embedded source (odd sites zero)
     assert np.array_equal(views[0][:, 0, 0], np.stack(bs).astype(np.complex64).astype(np.complex128))
@@ -171,8 +206,8 @@ def test_net_forward_layers(hq, C, dims):
     # end to end against pure FP64 (reported; BF16 rounding of every operand)
     ye, _ = N.net_forward(dims, fat, Ws, bs[0])
     e2e = np.linalg.norm(y.cpu().numpy()[0] - ye) / np.linalg.norm(ye)
-    say(f"net forward C={C} dims={dims}: layers vs BF16-operand FP64 mixing {worst:.2e} (componentwise); "
-        f"end-to-end vs FP64 {e2e:.2e}")
+    say(f"net forward C={C} dims={dims}: layers 1-3 vs BF16-operand FP64 mixing {worst:.2e}, layer 4 vs FP64 "
+        f"{e3:.2e} (componentwise); end-to-end vs FP64 {e2e:.2e}")
     assert e2e < 5e-2
 
 
@@ -182,7 +217,9 @@ def test_net_backward(hq, C, dims):
     """Every layer's weight gradient and input gradient against FP64 sums of the BF16 operands
     the GPU used, componentwise within TOL_MIX, with x the GPU's layer input (acts) and g the
     GPU's upstream gradient (left in the workspace): dl/dx^c = sum_k sum_a
-    bf16(conj(W_{adj k}^{ac})) bf16(T_k g^a); the first layer's weight gradient
+    bf16(conj(W_{adj k}^{ac})) bf16(T_k g^a) for layers 2-4, and for the first layer (its
+    adjoint is a C -> 1 layer, mixed in FP32, then transported) the FP64 value over the FP32
+    weights and links within TOL_FP32; the first layer's weight gradient
     dW_k^{ac} = sum conj(bf16(T_k x^c)) bf16(g^a), and that of layers 2-4, taken from the same
     transports of g as their input gradient, sum conj(bf16(x^c)) bf16(T_{adj k} g^a) (equal in
     exact arithmetic, T_k^dag = T_{adj k}).  The returned dl/d input is the even part of the
@@ -222,12 +259,19 @@ def test_net_backward(hq, C, dims):
             scale = np.einsum("ncpvs,nkapvs->kac", np.abs(xb), np.abs(Tga))
         ew.append(cw_err(gws[l], want, scale))
         # input gradient: the adjoint layer on the upstream gradient
-        Wadj = N._bf16c(np.stack([np.conj(Ws[l][N.ADJOINT[k]]).T for k in range(9)]).astype(np.complex64))
-        want_x, scale_x = mix(Wadj, Tg)
-        ex.append(cw_err(ginv[l], want_x, scale_x))
+        if l == 0:
+            Wadj = np.stack([np.conj(Ws[l][N.ADJOINT[k]]).T for k in range(9)])
+            want_x, scale_x = fp32_layer_ref(dims, fat, Wadj, ups[l])
+            ex0 = cw_err(ginv[l], want_x, scale_x)
+            assert ex0 <= TOL_FP32, ex0
+            ex.append(ex0)
+        else:
+            Wadj = N._bf16c(np.stack([np.conj(Ws[l][N.ADJOINT[k]]).T for k in range(9)]).astype(np.complex64))
+            want_x, scale_x = mix(Wadj, Tg)
+            ex.append(cw_err(ginv[l], want_x, scale_x))
     say(f"net backward C={C} dims={dims}: dW per layer {['%.1e' % v for v in ew]}, "
         f"d input per layer {['%.1e' % v for v in ex]} (componentwise, BF16 operands)")
-    assert max(ew) <= TOL_MIX and max(ex) <= TOL_MIX
+    assert max(ew) <= TOL_MIX and max(ex[1:]) <= TOL_MIX
     assert np.array_equal(gin.cpu().numpy(), ginv[0][:, 0, 0].astype(np.complex64))
 
 
