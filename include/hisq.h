@@ -312,7 +312,9 @@ int hisq_tune_multi(const void *fat, const void *lng, const void *src, void *dst
  *     out^a(x) = sum_b sum_{k=0..8} W_k^{ab} (T_k in^b)(x),
  * T_0 = 1, T_{+mu} phi(x) = F_mu(x) phi(x+mu), T_{-mu} phi(x) =
  * F_mu(x-mu)^dag phi(x-mu), F the fat links of the operator (Sec. 3).  The
- * channel mixing runs on BF16 MFMA with FP32 accumulation, features are FP32.
+ * channel mixing runs on BF16 MFMA with FP32 accumulation, features are FP32;
+ * the C -> 1 layer instead mixes the C channels at each neighbour in FP32 and
+ * transports the one result (sum_k T_k sum_c W_k^c in^c, the same map).
  * Weights: complex64, the four layers' [9][C_out][C_in] arrays back to back
  * (net_weight_count() complex numbers).  Fields: complex64.  An even-site
  * input [batch][Vh][3] is embedded on the full lattice (odd sites zero); the
@@ -321,7 +323,7 @@ int hisq_tune_multi(const void *fat, const void *lng, const void *src, void *dst
 size_t net_weight_count(int channels);
 /* bytes of the activation buffer of net_forward (every layer's input is kept
  * for net_backward) and of net_backward's workspace.  Activation layout: four
- * BF16 weight-operand slots of 18432 bytes, then the inputs of layers 1..4
+ * BF16 weight-operand slots of 18432 bytes (the fourth unused), then the inputs of layers 1..4
  * and the output of layer 4, each [batch][channels][parity][Vh][3]
  * complex64 (1, C, C, C and 1 channels), every block starting at a multiple
  * of 256 bytes. */
@@ -331,7 +333,10 @@ int net_forward(const void *fat, const void *weights, int channels, const void *
                 size_t act_bytes, int batch, const int dims[4], void *stream);
 /* grad_out: dl/d out [batch][Vh][3]; grad_w: dl/dW summed over the batch
  * (complex, dl/dRe + i dl/dIm); grad_in (may be NULL): dl/d in.  acts: the
- * buffer filled by the net_forward of the same batch.  On return the
+ * buffer filled by the net_forward of the same batch.  Layers 4, 3 and 2 take
+ * their weight gradient from the transports of the upstream gradient g that
+ * their input gradient computes anyway (sum_x <T_k x, g> = sum_x <x, T_{adj k} g>),
+ * layer 1 from the transports of its one-channel input.  On return the
  * workspace starts with the gradients with respect to the input of layers 4,
  * 3 and 2 ([batch][channels][parity][Vh][3] complex64 each), then the
  * embedded grad_out and the gradient with respect to the input of layer 1

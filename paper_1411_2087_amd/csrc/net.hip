@@ -22,8 +22,10 @@
 // The gradient with respect to the input is the same kernel with
 // W'_{k'}^{ba} = conj(W_{k}^{ab}), k' the adjoint transport of k
 // (T_{+mu}^dag = T_{-mu}); the weight gradient G_k^{ab} = sum_x <T_k in^b, g^a>
-// reuses the slice transport, with the sites (and Re/Im) as the K dimension,
-// and a fixed-order FP64 sum of the per-workgroup partials.
+// = sum_x <in^b, T_{adj k} g^a> is taken in the same kernel from those
+// transports of g (k_net_bwd), with the sites (and Re/Im) as the K dimension,
+// and a fixed-order FP64 sum of the per-workgroup partials.  The C -> 1 layer
+// mixes first and transports once (k_net_layer_mt, FP32).
 //
 // Feature layout: [batch][channel][parity][h][colour] complex64.
 #include <hip/hip_runtime.h>
