@@ -388,7 +388,7 @@ def polynomial_reference(hq, log, dims, mass, fat, lng, sources, C=4):
         wd = torch.from_numpy(w).cuda()
         wsc, wsf = hq.fields.workspace("cg", dims), hq.fields.workspace("fcg", dims, 1, 0, C)
         r = {"lambda_max": round(lmax, 3), "p_coeffs": [round(float(c), 6) for c in coef], "plain_iters": [],
-             "plain_s": [], "fcg_iters": [], "fcg_s": [], "fallback_used": []}
+             "plain_s": [], "fcg_iters": [], "fcg_s": [], "fallback_used": [], "fallback_iters": []}
         for src in sources:
             bd = torch.from_numpy(np.ascontiguousarray(src)).cuda()
             xp, xf = torch.zeros_like(bd), torch.zeros_like(bd)
@@ -399,6 +399,7 @@ def polynomial_reference(hq, log, dims, mass, fat, lng, sources, C=4):
             r["fcg_iters"].append(sf["iters"])
             r["fcg_s"].append(round(sf["time_s"], 4))
             r["fallback_used"].append(sf["fallback_used"])
+            r["fallback_iters"].append(sf["fallback_iters"])
         r["iteration_ratio_vs_plain"] = round(sum(r["fcg_iters"]) / sum(r["plain_iters"]), 3)
         log(f"[polynomial K, {name} operator] lambda_max {lmax:.3f}: plain {r['plain_iters']} {r['plain_s']}s, "
             f"fcg {r['fcg_iters']} {r['fcg_s']}s (fallback {r['fallback_used']})")
@@ -1121,6 +1122,10 @@ def main():
                                                   hq.HISQ_CG_MIXED_I16SC, forms["multi_rhs_8"])
         forms["multi_shift_8_i16sc"] = form_batched(hq, DIMS, L64C, LI16C, hq.HISQ_MULTI_SHIFT, 8, log,
                                                     hq.HISQ_CG_MIXED_I16SC, forms["multi_shift_8"])
+        # 16 masses of one source (the multi-mass solve), against its 16 sequential plain FP64 solves
+        forms["multi_shift_16"] = form_batched(hq, DIMS, L64, L32, hq.HISQ_MULTI_SHIFT, 16, log)
+        forms["multi_shift_16_i16sc"] = form_batched(hq, DIMS, L64C, LI16C, hq.HISQ_MULTI_SHIFT, 16, log,
+                                                     hq.HISQ_CG_MIXED_I16SC, forms["multi_shift_16"])
     del L16, LI16, L64C, L32C, LI16C
     torch.cuda.empty_cache()
     if not args.no_forms and not args.no_learned:
