@@ -275,6 +275,62 @@ def test_net_backward(hq, C, dims):
     assert np.array_equal(gin.cpu().numpy(), ginv[0][:, 0, 0].astype(np.complex64))
 
 
+def test_net_backward_many_units(hq):
+    """The persistent backward kernels with several units per workgroup: 8^4 with a batch of 32 gives 2048
+    (batch entry, tile, parity) units, two to three per resident workgroup of k_net_bwd and k_net_wgrad (the
+    training shape runs ~21).  Every weight gradient and input gradient against the same BF16-operand (and,
+    for the C -> 1 kernel, FP32) FP64 references as test_net_backward, componentwise; the sums over the batch
+    are accumulated entry by entry."""
+    import torch
+    from paper_1411_2087_amd import train
+    dims, C, B = (8, 8, 8, 8), 16, 32
+    fat, _ = fields(dims, 1001)
+    Ws = rand_weights(C, 6)
+    bs = [synth.source(dims, 90 + i) for i in range(B)]
+    L32, w, b, y, acts = gpu_forward(hq, dims, fat, Ws, C, bs)
+    g = np.stack([synth.source(dims, 130 + i) for i in range(B)]).astype(np.complex64)
+    gd = torch.from_numpy(g).cuda()
+    gw = torch.zeros(hq.net_weight_count(C), dtype=torch.complex64, device="cuda")
+    gin = torch.empty_like(gd)
+    ws = torch.empty(hq.net_backward_ws_bytes(dims, C, B), dtype=torch.uint8, device="cuda")
+    hq.net_backward(L32.fat, w, C, acts, gd, gw, gin, B, dims, ws)
+    torch.cuda.synchronize()
+    gws = train.unflatten(gw.cpu().numpy(), C)
+    views = acts_views(acts.cpu().numpy(), dims, C, B)
+    ginv, goutv = grads_views(ws.cpu().numpy(), dims, C, B)
+    ups = [ginv[1], ginv[2], ginv[3], goutv]
+    ew, ex = [], []
+    for l in range(4):
+        want = np.zeros(gws[l].shape, np.complex128)
+        scale = np.zeros(gws[l].shape)
+        ex_l = 0.0
+        Wadj = np.stack([np.conj(Ws[l][N.ADJOINT[k]]).T for k in range(9)])
+        Wadj_b = N._bf16c(Wadj.astype(np.complex64))
+        for n in range(B):
+            un = ups[l][n:n + 1]
+            Tg = N._bf16c(gpu_transport(hq, L32.fat, un, dims).astype(np.complex64))
+            if l == 0:
+                gb = N._bf16c(un.astype(np.complex64))
+                Tx = N._bf16c(gpu_transport(hq, L32.fat, views[l][n:n + 1], dims).astype(np.complex64))
+                want += np.einsum("nkcpvs,napvs->kac", Tx.conj(), gb, optimize=True)
+                scale += np.einsum("nkcpvs,napvs->kac", np.abs(Tx), np.abs(gb), optimize=True)
+                wx, sx = fp32_layer_ref(dims, fat, Wadj, un)
+                ex_l = max(ex_l, cw_err(ginv[l][n:n + 1], wx, sx))
+            else:
+                xb = N._bf16c(views[l][n:n + 1].astype(np.complex64))
+                Tga = Tg[:, N.ADJOINT]
+                want += np.einsum("ncpvs,nkapvs->kac", xb.conj(), Tga, optimize=True)
+                scale += np.einsum("ncpvs,nkapvs->kac", np.abs(xb), np.abs(Tga), optimize=True)
+                wx = np.einsum("kab,nkbpvc->napvc", Wadj_b, Tg, optimize=True)
+                sx = np.einsum("kab,nkbpvc->napvc", np.abs(Wadj_b), np.abs(Tg), optimize=True)
+                ex_l = max(ex_l, cw_err(ginv[l][n:n + 1], wx, sx))
+        ew.append(cw_err(gws[l], want, scale))
+        ex.append(ex_l)
+    say(f"net backward, 8^4 x 32 (several units per workgroup): dW per layer {['%.1e' % v for v in ew]}, "
+        f"d input per layer {['%.1e' % v for v in ex]} (componentwise)")
+    assert max(ew) <= TOL_MIX and max(ex[1:]) <= TOL_MIX and ex[0] <= TOL_FP32
+
+
 def test_net_loss_and_adam(hq):
     import torch
     dims = (4, 4, 4, 6)
