@@ -275,12 +275,12 @@ def test_net_backward(hq, C, dims):
     assert np.array_equal(gin.cpu().numpy(), ginv[0][:, 0, 0].astype(np.complex64))
 
 
-def test_net_backward_many_units(hq):
-    """The persistent backward kernels with several units per workgroup: 8^4 with a batch of 32 gives 2048
-    (batch entry, tile, parity) units, two to three per resident workgroup of k_net_bwd and k_net_wgrad (the
-    training shape runs ~21).  Every weight gradient and input gradient against the same BF16-operand (and,
-    for the C -> 1 kernel, FP32) FP64 references as test_net_backward, componentwise; the sums over the batch
-    are accumulated entry by entry."""
+def test_net_many_units(hq):
+    """The network on large grids: 8^4 with a batch of 32 gives 2048 (batch entry, tile, parity) units, one
+    workgroup each in the layer kernels and two to three per resident workgroup of the persistent k_net_bwd
+    and k_net_wgrad (the training shape runs ~21).  Every layer output, weight gradient and input gradient
+    against the same BF16-operand (and, for the C -> 1 kernel, FP32) FP64 references as test_net_forward_layers
+    and test_net_backward, componentwise; the sums over the batch are accumulated entry by entry."""
     import torch
     from paper_1411_2087_amd import train
     dims, C, B = (8, 8, 8, 8), 16, 32
@@ -298,6 +298,20 @@ def test_net_backward_many_units(hq):
     gws = train.unflatten(gw.cpu().numpy(), C)
     views = acts_views(acts.cpu().numpy(), dims, C, B)
     ginv, goutv = grads_views(ws.cpu().numpy(), dims, C, B)
+    # the forward layers on the same 2048-workgroup grids
+    ef = []
+    for l in range(4):
+        e_l = 0.0
+        for n in range(B):
+            if l < 3:
+                Tb = N._bf16c(gpu_transport(hq, L32.fat, views[l][n:n + 1], dims).astype(np.complex64))
+                Wb = N._bf16c(Ws[l].astype(np.complex64))
+                wf = np.einsum("kab,nkbpvc->napvc", Wb, Tb, optimize=True)
+                sf = np.einsum("kab,nkbpvc->napvc", np.abs(Wb), np.abs(Tb), optimize=True)
+            else:
+                wf, sf = fp32_layer_ref(dims, fat, Ws[3], views[3][n:n + 1])
+            e_l = max(e_l, cw_err(views[l + 1][n:n + 1], wf, sf))
+        ef.append(e_l)
     ups = [ginv[1], ginv[2], ginv[3], goutv]
     ew, ex = [], []
     for l in range(4):
@@ -326,8 +340,9 @@ def test_net_backward_many_units(hq):
                 ex_l = max(ex_l, cw_err(ginv[l][n:n + 1], wx, sx))
         ew.append(cw_err(gws[l], want, scale))
         ex.append(ex_l)
-    say(f"net backward, 8^4 x 32 (several units per workgroup): dW per layer {['%.1e' % v for v in ew]}, "
-        f"d input per layer {['%.1e' % v for v in ex]} (componentwise)")
+    say(f"net, 8^4 x 32 (several units per workgroup): forward per layer {['%.1e' % v for v in ef]}, "
+        f"dW per layer {['%.1e' % v for v in ew]}, d input per layer {['%.1e' % v for v in ex]} (componentwise)")
+    assert max(ef[:3]) <= TOL_MIX and ef[3] <= TOL_FP32
     assert max(ew) <= TOL_MIX and max(ex[1:]) <= TOL_MIX and ex[0] <= TOL_FP32
 
 
