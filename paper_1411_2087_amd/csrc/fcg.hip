@@ -24,8 +24,9 @@
 
 namespace hisq {
 
-int net_forward_dispatch(const Geom &g, const void *fat, const void *W, int C, const void *in_even, void *out_even,
-                         void *acts, int batch, hipStream_t s);
+int net_prep_dispatch(const Geom &g, const void *W, int C, void *acts, int batch, hipStream_t s);
+int net_layers_dispatch(const Geom &g, const void *fat, const void *W, int C, void *acts, int batch, hipStream_t s);
+void net_acts_io(void *acts, const Geom &g, int C, int batch, void **in_full, void **out_full);
 size_t net_act_bytes_g(const Geom &g, int C, int batch);
 int cg_plain_f64(double mass, double tol, const void *fat, const void *lng, const void *b, void *x, const Geom &g,
                  const hisq_cg_opts &o, void *ws, size_t ws_bytes, hisq_cg_stats &stats, hipStream_t s);
@@ -299,9 +300,9 @@ static double fcg_iter_bytes(const Geom &g, int C)
 
 size_t fcg_ws_bytes(const Geom &g, int C)
 {
-    const size_t v64 = a256f((size_t)g.Vh * 3 * 16), v32 = a256f((size_t)g.Vh * 3 * 8);
+    const size_t v64 = a256f((size_t)g.Vh * 3 * 16);
     const size_t nparts = std::max<size_t>((size_t)(g.ntiles + 3) / 4, 2 * (size_t)f_blocks((long long)g.Vh * 3)) + 64;
-    const size_t own = a256f(sizeof(FState)) + a256f(nparts * sizeof(double)) + 7 * v64 + 2 * v32 +
+    const size_t own = a256f(sizeof(FState)) + a256f(nparts * sizeof(double)) + 7 * v64 +
                        a256f(net_act_bytes_g(g, C, 1));
     return std::max(own, cg_workspace_bytes(g, HISQ_CG_PLAIN_F64));
 }
@@ -321,13 +322,20 @@ static int fcg_impl(double mass, double tol, const void *fat, const void *lng, c
     double2 *r = (double2 *)take(v64), *rp = (double2 *)take(v64), *z = (double2 *)take(v64),
             *pv = (double2 *)take(v64), *ap = (double2 *)take(v64), *t = (double2 *)take(v64);
     take(v64);
-    float2 *r32 = (float2 *)take(v32), *z32 = (float2 *)take(v32);
     void *acts = take(net_act_bytes_g(g, C, 1));
+    // the network's input slot takes float(r) on the even sites (its odd half stays zero) and its output slot's
+    // even half is z: no embedding or extraction per application
+    void *in_full = nullptr, *out_full = nullptr;
+    net_acts_io(acts, g, C, 1, &in_full, &out_full);
+    float2 *r32 = (float2 *)in_full;
+    const float2 *z32 = (const float2 *)out_full;
     FState *hs = (FState *)pinned_slot(PIN_FCG);
     if (!hs) return fail(HISQ_EHIP, "fcg_solve: pinned state allocation failed");
     const dim3 gb(nbf), gd(xcd_grid(nbd));
     auto t0 = std::chrono::steady_clock::now();
     hipLaunchKernelGGL(k_f_init, dim3(1), dim3(1), 0, s, st, tol * tol, 4.0 * mass * mass);
+    HISQ_HIP(hipMemsetAsync(r32 + (size_t)g.Vh * 3, 0, v32, s));  // the odd half of the network's input
+    if (net_prep_dispatch(g, W, C, acts, 1, s)) return HISQ_EHIP;
     hipLaunchKernelGGL(k_f_norm, gb, dim3(F_NT), 0, s, (const double2 *)b, n, part);
     hipLaunchKernelGGL(k_f_fin, dim3(1), dim3(256), 0, s, (const double *)part, nbf, 0, st, (int)FF_BB);
     // r = r_prev = b - A x0
@@ -349,9 +357,9 @@ static int fcg_impl(double mass, double tol, const void *fat, const void *lng, c
     }
     auto iter = [&](hipStream_t q) -> hipError_t {
         hipLaunchKernelGGL(k_f_tofloat, gb, dim3(F_NT), 0, q, (const double2 *)r, r32, n, (const FState *)st);
-        int rc = net_forward_dispatch(g, fat32, W, C, r32, z32, acts, 1, q);
+        int rc = net_layers_dispatch(g, fat32, W, C, acts, 1, q);
         if (rc) return hipErrorUnknown;
-        hipLaunchKernelGGL(k_f_z, gb, dim3(F_NT), 0, q, (const float2 *)z32, z, (const double2 *)r, (const double2 *)rp,
+        hipLaunchKernelGGL(k_f_z, gb, dim3(F_NT), 0, q, z32, z, (const double2 *)r, (const double2 *)rp,
                            n, part, (const FState *)st);
         hipLaunchKernelGGL(k_f_fin, dim3(1), dim3(256), 0, q, (const double *)part, nbf, 1, st, (int)FF_Z);
         hipLaunchKernelGGL(k_f_p, gb, dim3(F_NT), 0, q, pv, (const double2 *)z, n, (const FState *)st);

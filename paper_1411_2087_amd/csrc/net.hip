@@ -1029,21 +1029,35 @@ static void prep_launch(const float2 *W, __bf16 *A, int adjoint, hipStream_t s)
     hipLaunchKernelGGL((k_net_prep<CIN, COUT>), dim3(8), dim3(256), 0, s, W, A, adjoint);
 }
 
+// The BF16 weight operands of layers 1-3 (layer 4 reads its FP32 weights).
+template <int C>
+static void net_prep_t(const float2 *W, const NetActs &a, hipStream_t s)
+{
+    prep_launch<1, C>(W + w_off(C, 0), a.A[0], 0, s);
+    prep_launch<C, C>(W + w_off(C, 1), a.A[1], 0, s);
+    prep_launch<C, C>(W + w_off(C, 2), a.A[2], 0, s);
+}
+
+// The four layers, from the embedded input slot to the last layer's output slot.
+template <int C>
+static void net_layers_t(const Geom &g, const void *fat, const float2 *W, const NetActs &a, int batch, hipStream_t s)
+{
+    layer_launch<1, C>(g, fat, a.in[0], a.in[1], a.A[0], batch, s);
+    layer_launch<C, C>(g, fat, a.in[1], a.in[2], a.A[1], batch, s);
+    layer_launch<C, C>(g, fat, a.in[2], a.in[3], a.A[2], batch, s);
+    layer_mt_launch<C>(g, fat, a.in[3], a.out, W + w_off(C, 3), batch, 0, s);
+}
+
 template <int C>
 static int net_forward_t(const Geom &g, const void *fat, const float2 *W, const float2 *in_even, float2 *out_even,
                          void *acts, int batch, hipStream_t s)
 {
     NetActs a = net_acts(acts, g, C, batch);
-    prep_launch<1, C>(W + w_off(C, 0), a.A[0], 0, s);
-    prep_launch<C, C>(W + w_off(C, 1), a.A[1], 0, s);
-    prep_launch<C, C>(W + w_off(C, 2), a.A[2], 0, s);
+    net_prep_t<C>(W, a, s);
     const long long ne = (long long)batch * 2 * g.Vh * 3;
     const int nb = (int)std::min<long long>((ne + 255) / 256, 4096);
     hipLaunchKernelGGL(k_net_embed, dim3(nb), dim3(256), 0, s, in_even, a.in[0], batch, g.Vh);
-    layer_launch<1, C>(g, fat, a.in[0], a.in[1], a.A[0], batch, s);
-    layer_launch<C, C>(g, fat, a.in[1], a.in[2], a.A[1], batch, s);
-    layer_launch<C, C>(g, fat, a.in[2], a.in[3], a.A[2], batch, s);
-    layer_mt_launch<C>(g, fat, a.in[3], a.out, W + w_off(C, 3), batch, 0, s);
+    net_layers_t<C>(g, fat, W, a, batch, s);
     if (out_even) hipLaunchKernelGGL(k_net_extract, dim3(nb), dim3(256), 0, s, (const float2 *)a.out, out_even, batch, g.Vh);
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
@@ -1163,6 +1177,41 @@ static int net_backward_t(const Geom &g, const void *fat, const float2 *W, const
     }
     HISQ_HIP(hipGetLastError());
     return HISQ_OK;
+}
+
+// For a caller that applies the network repeatedly with fixed weights (the
+// flexible CG): the weight operands once (net_prep_dispatch), then per
+// application the four layers alone (net_layers_dispatch), reading the
+// embedded input slot of `acts` and leaving the last layer's full-lattice
+// output in its output slot; net_acts_io gives both slots ([batch][1][parity]
+// [Vh][3] complex64, even parity first).
+int net_prep_dispatch(const Geom &g, const void *W, int C, void *acts, int batch, hipStream_t s)
+{
+    switch (C) {
+    case 4: net_prep_t<4>((const float2 *)W, net_acts(acts, g, 4, batch), s); break;
+    case 8: net_prep_t<8>((const float2 *)W, net_acts(acts, g, 8, batch), s); break;
+    default: net_prep_t<16>((const float2 *)W, net_acts(acts, g, 16, batch), s); break;
+    }
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+int net_layers_dispatch(const Geom &g, const void *fat, const void *W, int C, void *acts, int batch, hipStream_t s)
+{
+    switch (C) {
+    case 4: net_layers_t<4>(g, fat, (const float2 *)W, net_acts(acts, g, 4, batch), batch, s); break;
+    case 8: net_layers_t<8>(g, fat, (const float2 *)W, net_acts(acts, g, 8, batch), batch, s); break;
+    default: net_layers_t<16>(g, fat, (const float2 *)W, net_acts(acts, g, 16, batch), batch, s); break;
+    }
+    HISQ_HIP(hipGetLastError());
+    return HISQ_OK;
+}
+
+void net_acts_io(void *acts, const Geom &g, int C, int batch, void **in_full, void **out_full)
+{
+    const NetActs a = net_acts(acts, g, C, batch);
+    *in_full = a.in[0];
+    *out_full = a.out;
 }
 
 int net_forward_dispatch(const Geom &g, const void *fat, const void *W, int C, const void *in_even, void *out_even,
