@@ -145,11 +145,11 @@ __global__ __launch_bounds__(256) HISQ_WAVES(8) void k_f_ap(Geom g, const char *
     block_partial<256>(s, partials, blk);
 }
 
-// x += alpha p ; r_prev = r ; r -= alpha Ap ; partials of |r|^2
+// x += alpha p ; r_prev = r ; r -= alpha Ap ; r32 = float(r) ; partials of |r|^2
 __global__ __launch_bounds__(F_NT) void k_f_upd(double2 *__restrict__ x, double2 *__restrict__ r,
                                                 double2 *__restrict__ rp, const double2 *__restrict__ p,
-                                                const double2 *__restrict__ ap, long long n, double *partials,
-                                                const FState *st)
+                                                const double2 *__restrict__ ap, float2 *__restrict__ r32, long long n,
+                                                double *partials, const FState *st)
 {
     if (st->flags.done) return;
     const double al = st->alpha;
@@ -167,6 +167,7 @@ __global__ __launch_bounds__(F_NT) void k_f_upd(double2 *__restrict__ x, double2
             rv.y = fma(-al, av.y, rv.y);
             x[i] = xv;
             r[i] = rv;
+            r32[i] = make_float2((float)rv.x, (float)rv.y);  // the next application's network input
             s = fma(rv.x, rv.x, fma(rv.y, rv.y, s));
         }
     }
@@ -343,6 +344,8 @@ static int fcg_impl(double mass, double tol, const void *fat, const void *lng, c
     hipLaunchKernelGGL(k_f_resid, gd, dim3(256), 0, s, g, (const char *)fat, (const char *)lng, (const double2 *)t,
                        (const double2 *)x, (const double2 *)b, r, rp, nbd, part, (const FState *)st);
     hipLaunchKernelGGL(k_f_fin, dim3(1), dim3(256), 0, s, (const double *)part, nbd, 0, st, (int)FF_INIT);
+    // the first network input; later ones come from k_f_upd
+    hipLaunchKernelGGL(k_f_tofloat, gb, dim3(F_NT), 0, s, (const double2 *)r, r32, n, (const FState *)st);
     HISQ_HIP(hipGetLastError());
     HISQ_HIP(hipMemcpyAsync(hs, st, sizeof(FState), hipMemcpyDeviceToHost, s));
     HISQ_HIP(hipStreamSynchronize(s));
@@ -356,7 +359,6 @@ static int fcg_impl(double mass, double tol, const void *fat, const void *lng, c
         return HISQ_OK;
     }
     auto iter = [&](hipStream_t q) -> hipError_t {
-        hipLaunchKernelGGL(k_f_tofloat, gb, dim3(F_NT), 0, q, (const double2 *)r, r32, n, (const FState *)st);
         int rc = net_layers_dispatch(g, fat32, W, C, acts, 1, q);
         if (rc) return hipErrorUnknown;
         hipLaunchKernelGGL(k_f_z, gb, dim3(F_NT), 0, q, z32, z, (const double2 *)r, (const double2 *)rp,
@@ -369,7 +371,7 @@ static int fcg_impl(double mass, double tol, const void *fat, const void *lng, c
                            (const double2 *)pv, ap, nbd, part, (const FState *)st);
         hipLaunchKernelGGL(k_f_fin, dim3(1), dim3(256), 0, q, (const double *)part, nbd, 0, st, (int)FF_PAP);
         hipLaunchKernelGGL(k_f_upd, gb, dim3(F_NT), 0, q, (double2 *)x, r, rp, (const double2 *)pv, (const double2 *)ap,
-                           n, part, (const FState *)st);
+                           r32, n, part, (const FState *)st);
         hipLaunchKernelGGL(k_f_fin, dim3(1), dim3(256), 0, q, (const double *)part, nbf, 0, st, (int)FF_UPD);
         return hipGetLastError();
     };
