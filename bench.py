@@ -407,6 +407,53 @@ def polynomial_reference(hq, log, dims, mass, fat, lng, sources, C=4):
     return rows
 
 
+def trained_naive_reference(hq, log, dims, mass, fat, lng, sources, held, C=8, steps=1500):
+    """A network trained where the fat-link layers can represent a good K: the naive operator (long links zero),
+    the residual objective over a shuffled mix of Gaussian sources and normalised solutions x = A^-1 b (half
+    each), from K = s 1; flexible CG with it against plain FP64 CG on the held-out sources."""
+    import numpy as np
+    import torch
+    from paper_1411_2087_amd import train
+    lng0 = np.zeros_like(lng)
+    L64 = hq.fields.Links.pack(fat, lng0, dims, hq.HISQ_F64)
+    L32 = hq.fields.Links.pack(fat, lng0, dims, hq.HISQ_F32)
+    n = sources.shape[0]
+    t0 = time.perf_counter()
+    b, x, _, _ = train.make_pairs(dims, mass, L64, L32, sources)
+    t_pairs = time.perf_counter() - t0
+    nb = torch.linalg.vector_norm(b.reshape(n, -1), dim=1).reshape(-1, 1, 1)
+    xn = x / torch.linalg.vector_norm(x.reshape(n, -1), dim=1).reshape(-1, 1, 1) * nb
+    perm = torch.randperm(n, generator=torch.Generator().manual_seed(4)).cuda()
+    inp = torch.cat([b[:n - n // 2], xn[:n // 2]])[perm]
+    w0 = train.initial_weights(C, train.residual_scale(inp[:16], L32, mass, dims), 0.05, 99)
+    tr = train.Trainer(dims, C, L32.fat, w0, batch=16, objective="residual", links32=L32, mass=mass)
+    t0 = time.perf_counter()
+    hist = tr.fit(inp[:-32], inp[:-32], steps=steps, lr=2e-3, log_every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    wsc, wsf = hq.fields.workspace("cg", dims), hq.fields.workspace("fcg", dims, 1, 0, C)
+    r = {"recipe": f"naive operator, C {C}, residual objective over {n - n // 2} Gaussian sources and {n // 2} "
+                   f"normalised solutions, {steps} Adam steps", "pair_s": round(t_pairs, 2),
+         "train_s": round(t_train, 2), "loss_log": [(s_, round(l, 4)) for s_, l in hist], "plain_iters": [],
+         "plain_s": [], "fcg_iters": [], "fcg_s": [], "fallback_used": [], "fcg_true_resid": []}
+    for src in held:
+        bd = torch.from_numpy(np.ascontiguousarray(src)).cuda()
+        xp, xf = torch.zeros_like(bd), torch.zeros_like(bd)
+        sp = hq.cg_solve(mass, TOL, L64.fat, L64.lng, None, None, bd, xp, dims, None, wsc)
+        sf = hq.fcg_solve(mass, TOL, L64.fat, L64.lng, L32.fat, tr.w, C, bd, xf, dims, None, wsf)
+        r["plain_iters"].append(sp["iters"])
+        r["plain_s"].append(round(sp["time_s"], 4))
+        r["fcg_iters"].append(sf["iters"])
+        r["fcg_s"].append(round(sf["time_s"], 4))
+        r["fallback_used"].append(sf["fallback_used"])
+        r["fcg_true_resid"].append(sf["true_resid"])
+    r["iteration_ratio_vs_plain"] = round(sum(r["fcg_iters"]) / sum(r["plain_iters"]), 3)
+    r["speedup_vs_plain"] = round(sum(r["plain_s"]) / sum(r["fcg_s"]), 3)
+    log(f"[trained K, naive operator] pairs {t_pairs:.1f}s train {t_train:.1f}s: plain {r['plain_iters']} "
+        f"{r['plain_s']}s, fcg {r['fcg_iters']} {r['fcg_s']}s (fallback {r['fallback_used']})")
+    return r
+
+
 def form_learned(hq, log, dims=(16, 16, 16, 16), mass=0.005, C=16, npairs=512, nheld=64, steps=600):
     """Learned preconditioner: 512 pairs from the batched CG (448 to train, 64 held out), GPU training with the
     residual objective, then flexible CG with the trained network, and with K = identity, against plain FP64 CG on
@@ -445,6 +492,7 @@ def form_learned(hq, log, dims=(16, 16, 16, 16), mass=0.005, C=16, npairs=512, n
         f"{sp['iters']} it {sp['time_s']:.3f}s; fcg {sf['iters']} it (fallback {sf['fallback_used']}) "
         f"{sf['time_s']:.3f}s; fcg with K = 1 {si['iters']} it {si['time_s']:.3f}s")
     poly = polynomial_reference(hq, log, dims, mass, fat, lng, src[ntr:ntr + 1])
+    naive = trained_naive_reference(hq, log, dims, mass, fat, lng, src[:256], src[ntr:ntr + 1])
     return {"workload": f"16^4, m {mass}, C {C}, residual objective, {npairs} pairs ({ntr} train / {nheld} held out)",
             "pairs": npairs, "pair_s": round(t_pairs, 2), "train_steps": steps, "train_s": round(t_train, 2),
             "held_out_loss": [round(l0, 4), round(l1, 4)], "loss_log": [(s_, round(l, 4)) for s_, l in hist],
@@ -452,7 +500,8 @@ def form_learned(hq, log, dims=(16, 16, 16, 16), mass=0.005, C=16, npairs=512, n
             "fcg_iters": sf["iters"], "fallback_used": sf["fallback_used"], "fallback_iters": sf["fallback_iters"],
             "fcg_true_resid": sf["true_resid"], "fcg_identity_iters": si["iters"], "fcg_identity_s": round(si["time_s"], 4),
             "speedup_vs_plain": round(sp["time_s"] / sf["time_s"], 3),
-            "iteration_ratio_vs_plain": round(sf["iters"] / sp["iters"], 3), "polynomial_K_C4": poly}
+            "iteration_ratio_vs_plain": round(sf["iters"] / sp["iters"], 3), "polynomial_K_C4": poly,
+            "trained_naive_C8": naive}
 
 
 def run_learned(args, dims=(16, 16, 16, 16), mass=0.005, npairs=512, nheld=64, steps=600, channels=(8, 16),
