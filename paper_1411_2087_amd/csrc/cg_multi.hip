@@ -117,8 +117,15 @@ __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__
     constexpr int MD_C4 = (64 / TPS) * MD_K4;             // chunks per wavefront and direction
     constexpr int MD_RR = (MD_C4 + 63) / 64;              // load rounds
     constexpr bool MD_PIPE = PIPE && MD_LDS && std::is_same<P, PF32>::value;
+    // PIPE with TPS >= 2: the S links of a wavefront's sites are loaded once, cooperatively, and staged in LDS
+    // (pitch 20 floats per site: 16-byte aligned, the S sites' 4-bank groups distinct)
+    constexpr int MD_S = 64 / TPS;
+    constexpr bool MD_LSH = MD_PIPE && TPS >= 2;
+    constexpr int MD_LR = (4 * MD_S + 63) / 64;  // rounds of the 4 S 16-byte link chunks
     __shared__ float4 stage_all[MD_LDS ? NT / 64 : 1][MD_LDS ? MD_C4 : 1];
+    __shared__ __align__(16) float lstage_all[MD_LSH ? NT / 64 : 1][MD_LSH ? MD_S * 20 : 4];
     float4 *stage = stage_all[MD_LDS ? (threadIdx.x >> 6) : 0];
+    float *lstage = lstage_all[MD_LSH ? (threadIdx.x >> 6) : 0];
     const int wl = threadIdx.x & 63;
     if (solver_gate_closed(&st->flags, gate)) return;
     const unsigned mask = pick_mask(st, which_mask);
@@ -160,31 +167,77 @@ __global__ __launch_bounds__(NT) void k_mdslash(Geom g, const char *__restrict__
         if constexpr (MD_PIPE) {
             // native vectors: copies of HIP's float4 struct go through memory
             typedef float f4v __attribute__((ext_vector_type(4)));
-            R mn[18];             // the link of the next direction, in flight
+            typedef float f2v __attribute__((ext_vector_type(2)));
+            R mn[18];             // the link of the next direction, in flight (TPS = 1)
+            f4v lpre[MD_LR];      // its chunks (TPS >= 2): chunk j = row j / S (4 floats) of site j % S
+            f2v ltail = { 0.f, 0.f };  // entries 16, 17 of site wl (wl < S)
             f4v pre[MD_RR];       // its neighbour chunks, in flight
+            // the wavefront's sites are lanes L0 .. L0 + S - 1 of one tile (S divides 64); a wavefront past
+            // the lattice reads the last tile (its results are not stored)
+            const int s_w = unit * SPB + (threadIdx.x >> 6) * MD_S;
+            const int blk64 = s_w / TILE, L0 = s_w % TILE;
+            const int wtile = blk64 < g.ntiles ? tile_of(g, blk64) : g.ntiles - 1;
+            const size_t wtix = (size_t)parity * g.ntiles + wtile;
+            const char *wfat = fat + wtix * P::Fat::tile_bytes, *wlng = lng + wtix * P::Long::tile_bytes;
             // step d: publish direction d, issue the loads of d + 1, then the products of d
             // (step -1 only issues direction 0)
 #pragma unroll 1
             for (int d = -1; d < 16; ++d) {
                 R m[18];
                 if (d >= 0) {
+                    if constexpr (!MD_LSH) {
 #pragma unroll
-                    for (int i = 0; i < 18; ++i) m[i] = mn[i];
-                    wave_sync();  // every lane has read the previous direction's blocks
+                        for (int i = 0; i < 18; ++i) m[i] = mn[i];
+                    }
+                    wave_sync();  // every lane has read the previous direction's blocks and link
 #pragma unroll
                     for (int q = 0; q < MD_RR; ++q) {
                         const int j = q * 64 + wl;
                         if ((MD_C4 % 64 == 0) || j < MD_C4) reinterpret_cast<f4v *>(stage)[j] = pre[q];
                     }
+                    if constexpr (MD_LSH) {
+#pragma unroll
+                        for (int q = 0; q < MD_LR; ++q) {
+                            const int j = q * 64 + wl;
+                            if (((4 * MD_S) % 64 == 0) || j < 4 * MD_S)
+                                *reinterpret_cast<f4v *>(lstage + (j % MD_S) * 20 + 4 * (j / MD_S)) = lpre[q];
+                        }
+                        if (wl < MD_S) *reinterpret_cast<f2v *>(lstage + wl * 20 + 16) = ltail;
+                    }
                     wave_sync();
+                    if constexpr (MD_LSH) {
+                        const float *ms = lstage + (wl / TPS) * 20;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const f4v v = *reinterpret_cast<const f4v *>(ms + 4 * r);
+                            m[4 * r] = v.x; m[4 * r + 1] = v.y; m[4 * r + 2] = v.z; m[4 * r + 3] = v.w;
+                        }
+                        const f2v t2 = *reinterpret_cast<const f2v *>(ms + 16);
+                        m[16] = t2.x;
+                        m[17] = t2.y;
+                    }
                 }
                 if (d + 1 < 16) {
                     const int dn = d + 1, mu = dn & 3;
                     const bool is_long = dn >= 8;
                     const int k = (is_long ? 3 : 1) * (((dn >> 2) & 1) ? -1 : 1);
                     const int nh = nbr_h(g, h, cx, cy, cz, ct, mu, k);
-                    if (is_long) P::Long::load_dir(lng_t, dn & 7, lane, mn);
-                    else P::Fat::load_dir(fat_t, dn & 7, lane, mn);
+                    if constexpr (MD_LSH) {
+                        const char *blk = (is_long ? wlng : wfat) + (size_t)(dn & 7) * P::Fat::block_bytes;
+#pragma unroll
+                        for (int q = 0; q < MD_LR; ++q) {
+                            const int j = q * 64 + wl;
+                            if (((4 * MD_S) % 64 == 0) || j < 4 * MD_S)
+                                lpre[q] = __builtin_nontemporal_load(
+                                    reinterpret_cast<const f4v *>(blk) + (j / MD_S) * TILE + L0 + j % MD_S);
+                        }
+                        if (wl < MD_S)
+                            ltail = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(blk + 4 * TILE * 16) + L0 + wl);
+                    } else if (is_long) {
+                        P::Long::load_dir(lng_t, dn & 7, lane, mn);
+                    } else {
+                        P::Fat::load_dir(fat_t, dn & 7, lane, mn);
+                    }
 #pragma unroll
                     for (int q = 0; q < MD_RR; ++q) {
                         const int j = q * 64 + wl;
