@@ -66,6 +66,18 @@ __device__ __forceinline__ size_t feat_idx(int b, int C, int c, int p, int Vh, i
     return ((((size_t)b * C + c) * 2 + p) * Vh + h) * 3;
 }
 
+// The colour vector of site h (3 complex64, 24 bytes at 24 h of a 16-byte aligned field block) with one 16-byte
+// and one 8-byte load: for even h the first two colours are 16-byte aligned, for odd h the last two.
+__device__ __forceinline__ void load_cvec(const float2 *__restrict__ v, int h, float2 out[3])
+{
+    const bool odd = h & 1;
+    const float4 q4 = *reinterpret_cast<const float4 *>(v + (odd ? 1 : 0));
+    const float2 q2 = v[odd ? 0 : 2];
+    out[0] = odd ? q2 : make_float2(q4.x, q4.y);
+    out[1] = odd ? make_float2(q4.x, q4.y) : make_float2(q4.z, q4.w);
+    out[2] = odd ? make_float2(q4.z, q4.w) : q2;
+}
+
 // One packed FP32 link (18 floats) with plain loads: the four pair groups of
 // a slice read the same matrix, so it should stay in the caches.
 __device__ __forceinline__ void load_link32(const char *__restrict__ blk, int lane, float m[18])
@@ -181,7 +193,7 @@ struct SliceRaw {
     int kind;  // 0: T_0 (v is the result), 1: transport, 2: padding (zero)
 };
 
-template <int CIN, bool SIGNED = false>
+template <int CIN, bool SIGNED = false, bool WIDE = false>
 __device__ __forceinline__ void slice_load(const Geom &g, const char *__restrict__ fat, const float2 *__restrict__ in,
                                            int p, int tile, int lane, const NetSite &st, int j, int q, SliceRaw &r)
 {
@@ -203,8 +215,12 @@ __device__ __forceinline__ void slice_load(const Geom &g, const char *__restrict
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float2 *v = in + (c0 + i) * ch_stride + (size_t)pn * g.Vh * 3 + (size_t)hn * 3;
+        if constexpr (WIDE) {
+            load_cvec(v, hn, r.v[i]);
+        } else {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) r.v[i][a] = v[a];
+            for (int a = 0; a < 3; ++a) r.v[i][a] = v[a];
+        }
     }
 }
 
@@ -237,7 +253,7 @@ __device__ __forceinline__ void slice_finish(const SliceRaw &r, float tv[4][6])
 // get finite values that no stored output uses: the layer stores only sites
 // below Vh, and the weight gradient multiplies them by zero upstream gradients.
 // in: the channels of one batch entry, [c][parity][Vh][3].
-template <int CIN, bool SIGNED = false>
+template <int CIN, bool SIGNED = false, bool WIDE = false>
 __device__ __forceinline__ void slice_transport(const Geom &g, const char *__restrict__ fat,
                                                 const float2 *__restrict__ in, int p, int tile, int lane,
                                                 const NetSite &st, int j, int q, float tv[4][6])
@@ -247,7 +263,7 @@ __device__ __forceinline__ void slice_transport(const Geom &g, const char *__res
     const char *tb = fat + ((size_t)p * g.ntiles + tile) * 8 * PF32::block_bytes;
     if constexpr (CIN >= 4) {
         SliceRaw r;
-        slice_load<CIN, SIGNED>(g, fat, in, p, tile, lane, st, j, q, r);
+        slice_load<CIN, SIGNED, WIDE>(g, fat, in, p, tile, lane, st, j, q, r);
         slice_finish(r, tv);
         return;
     } else {
@@ -256,20 +272,25 @@ __device__ __forceinline__ void slice_transport(const Geom &g, const char *__res
         for (int i = 0; i < 4; ++i) {
             const int k = 4 * q + i;
             if (k == 0) {
+                float2 e[3];
                 const float2 *v = in + (size_t)p * g.Vh * 3 + (size_t)hc * 3;
+                if constexpr (WIDE) load_cvec(v, hc, e);
+                else for (int a = 0; a < 3; ++a) e[a] = v[a];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const float2 e = v[a];
-                    tv[i][2 * a] = e.x;
-                    tv[i][2 * a + 1] = e.y;
+                    tv[i][2 * a] = e[a].x;
+                    tv[i][2 * a + 1] = e[a].y;
                 }
             } else if (k < 9) {
                 const int d = k - 1;
                 const int nh = nbr_h(g, hc, x, y, z, t, d & 3, d >= 4 ? -1 : 1);
                 float m[18];
                 load_link32(tb + (size_t)d * PF32::block_bytes, lane, m);
+                float2 e[3];
                 const float2 *v = in + (size_t)(1 - p) * g.Vh * 3 + (size_t)nh * 3;
-                matvec32(m, (SIGNED && d >= 4) ? -1.0f : 1.0f, v[0], v[1], v[2], tv[i]);
+                if constexpr (WIDE) load_cvec(v, nh, e);
+                else for (int a = 0; a < 3; ++a) e[a] = v[a];
+                matvec32(m, (SIGNED && d >= 4) ? -1.0f : 1.0f, e[0], e[1], e[2], tv[i]);
             } else {
 #pragma unroll
                 for (int e = 0; e < 6; ++e) tv[i][e] = 0.f;
@@ -599,7 +620,7 @@ __global__ __launch_bounds__(NET_NT, 4) void k_net_wgrad(Geom g, const char *__r
         };
         {
             float tv[4][6];
-            slice_transport<CIN>(g, fat, inb, p, tile, lane, site, 0, q, tv);
+            slice_transport<CIN, false, CIN == 1>(g, fat, inb, p, tile, lane, site, 0, q, tv);
             put(Fb, tv);
         }
         __syncthreads();  // g and slice 0 are in LDS
@@ -609,7 +630,7 @@ __global__ __launch_bounds__(NET_NT, 4) void k_net_wgrad(Geom g, const char *__r
             const bool more = j + 1 < S::N;
             float tv[4][6];
             // the next slice's transport goes to registers while the owner wave multiplies this one
-            if (more) slice_transport<CIN>(g, fat, inb, p, tile, lane, site, j + 1, q, tv);
+            if (more) slice_transport<CIN, false, CIN == 1>(g, fat, inb, p, tile, lane, site, j + 1, q, tv);
             if (q == (j & 3)) {  // this slice's owner (wave-uniform)
 #pragma unroll
                 for (int ks = 0; ks < KT / SK; ++ks) {
@@ -738,7 +759,7 @@ __global__ __launch_bounds__(NET_NT, 3) void k_net_bwd(Geom g, const char *__res
             for (int mt = 0; mt < MTX; ++mt) acc[n][mt] = floatx4{ 0.f, 0.f, 0.f, 0.f };
         {
             float tv[4][6];
-            slice_transport<CI>(g, fat, gb, p, tile, lane, site, 0, q, tv);
+            slice_transport<CI, false, CI == 1>(g, fat, gb, p, tile, lane, site, 0, q, tv);
             put(tv);
         }
         __syncthreads();  // x and slice 0 are in LDS
@@ -748,7 +769,7 @@ __global__ __launch_bounds__(NET_NT, 3) void k_net_bwd(Geom g, const char *__res
             const bool more = j + 1 < S::N;
             // the next slice's transport goes to registers while this one is multiplied
             float tv[4][6];
-            if (more) slice_transport<CI>(g, fat, gb, p, tile, lane, site, j + 1, q, tv);
+            if (more) slice_transport<CI, false, CI == 1>(g, fat, gb, p, tile, lane, site, j + 1, q, tv);
             {  // mixing: the layer kernel's column tiles 3q..3q+2
                 bf16x8 av[MTX];
 #pragma unroll
