@@ -399,7 +399,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_layer(Geom g, const char *__rest
     };
     {
         float tv[4][6];
-        slice_transport<CIN>(g, fat, inb, p, tile, lane, site, 0, q, tv);
+        slice_transport<CIN, false, CIN == 1>(g, fat, inb, p, tile, lane, site, 0, q, tv);
         put(F[0], tv);
     }
     __syncthreads();
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(NET_NT) void k_net_layer(Geom g, const char *__rest
             mix(F[j & 1], j);
             if (j + 1 < S::N) {
                 float tv[4][6];
-                slice_transport<CIN>(g, fat, inb, p, tile, lane, site, j + 1, q, tv);
+                slice_transport<CIN, false, CIN == 1>(g, fat, inb, p, tile, lane, site, j + 1, q, tv);
                 put(F[(j + 1) & 1], tv);
             }
         }
