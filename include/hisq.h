@@ -327,8 +327,9 @@ size_t net_weight_count(int channels);
  * and the output of layer 4, each [batch][channels][parity][Vh][3]
  * complex64 (1, C, C, C and 1 channels), every block starting at a multiple
  * of 256 bytes from the buffer's start.  The kernels read these buffers with
- * 16-byte loads: pass acts and workspace 256-byte aligned, as device
- * allocations are. */
+ * 16-byte loads: acts and workspace (and fcg_solve's workspace) must be
+ * 16-byte aligned (device allocations are 256-byte aligned), else
+ * HISQ_EINVAL. */
 size_t net_act_bytes(const int dims[4], int channels, int batch);
 size_t net_backward_ws_bytes(const int dims[4], int channels, int batch);
 int net_forward(const void *fat, const void *weights, int channels, const void *in, void *out, void *acts,

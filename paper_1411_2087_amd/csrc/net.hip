@@ -32,6 +32,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <type_traits>
 
@@ -1275,6 +1276,7 @@ extern "C" int net_forward(const void *fat, const void *weights, int channels, c
     if (batch < 1) return fail(HISQ_EINVAL, "net_forward: batch must be >= 1");
     if (!fat || !weights || !in || !acts) return fail(HISQ_EINVAL, "net_forward: NULL pointer");
     if (act_bytes < net_act_bytes_g(g, channels, batch)) return fail(HISQ_EWORKSPACE, "net_forward: acts buffer too small");
+    if ((uintptr_t)acts & 15) return fail(HISQ_EINVAL, "net_forward: acts must be 16-byte aligned");
     if (in == out) return fail(HISQ_EALIAS, "net_forward: in and out alias");
     return net_forward_dispatch(g, fat, weights, channels, in, out, acts, batch, (hipStream_t)stream);
 }
@@ -1291,6 +1293,8 @@ extern "C" int net_backward(const void *fat, const void *weights, int channels, 
     if (!fat || !weights || !acts || !grad_out || !grad_w || !workspace) return fail(HISQ_EINVAL, "net_backward: NULL pointer");
     if (act_bytes < net_act_bytes_g(g, channels, batch)) return fail(HISQ_EWORKSPACE, "net_backward: acts buffer too small");
     if (ws_bytes < net_bwd_ws_bytes_g(g, channels, batch)) return fail(HISQ_EWORKSPACE, "net_backward: workspace too small");
+    if (((uintptr_t)acts | (uintptr_t)workspace) & 15)
+        return fail(HISQ_EINVAL, "net_backward: acts and workspace must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     switch (channels) {
     case 4: return net_backward_t<4>(g, fat, (const float2 *)weights, acts, (const float2 *)grad_out, (float2 *)grad_w, (float2 *)grad_in, batch, workspace, s);

@@ -139,3 +139,18 @@ def test_dot_noalloc_validation_without_gpu():
     assert lib.hisq_dot_noalloc(p[0], p[1], 1 << 38, 0, out, None) == -1 and b"2^37" in lib.hisq_last_error()
     assert lib.hisq_dot_noalloc(None, p[1], 10, 0, out, None) == -1
     assert lib.hisq_dot_noalloc(p[0], p[1], 10, 9, out, None) == -1
+
+
+def test_network_alignment_validation_without_gpu():
+    """The network's activation and workspace buffers are read with 16-byte loads: a misaligned one is refused
+    before any GPU work."""
+    import paper_1411_2087_amd as hq
+    lib = hq._lib
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    p = [ctypes.c_void_p(0x10000 * (i + 1)) for i in range(4)]
+    bad = ctypes.c_void_p(0x10008)
+    assert lib.net_forward(p[0], p[1], 4, p[2], p[3], bad, 1 << 40, 1, dims, None) == -1
+    assert b"aligned" in lib.hisq_last_error()
+    assert lib.net_backward(p[0], p[1], 4, bad, 1 << 40, p[2], p[3], None, 1, dims, p[3], 1 << 40, None) == -1
+    assert lib.net_backward(p[0], p[1], 4, p[2], 1 << 40, p[2], p[3], None, 1, dims, bad, 1 << 40, None) == -1
+    assert b"aligned" in lib.hisq_last_error()
