@@ -16,7 +16,8 @@ def hq():
     return hq
 
 
-@pytest.mark.parametrize("dims", [(6, 4, 4, 10), (8, 8, 8, 8)])
+# (8, 6, 6, 6): x rows of 4 sites and a ragged last tile (13.5 tiles per parity)
+@pytest.mark.parametrize("dims", [(6, 4, 4, 10), (8, 8, 8, 8), (8, 6, 6, 6)])
 @pytest.mark.parametrize("nrhs", [1, 2, 4, 8, 16])
 def test_dslash_multi_parity(hq, dims, nrhs):
     import torch
