@@ -30,6 +30,9 @@
  * the caller (for instance a torch tensor's data_ptr()); the library never
  * frees caller memory and does not allocate device memory on the solve path:
  * solvers take a caller-provided workspace sized by hisq_workspace_bytes().
+ * The kernels read fields, links and workspaces with 16-byte loads: every
+ * device pointer must be 16-byte aligned (device allocations are 256-byte
+ * aligned), else HISQ_EINVAL.
  * `stream` is a hipStream_t (NULL = the null stream).  Calls are asynchronous
  * on `stream` except the solvers, which return when the solve has finished.
  *
@@ -326,10 +329,7 @@ size_t net_weight_count(int channels);
  * BF16 weight-operand slots of 18432 bytes (the fourth unused), then the inputs of layers 1..4
  * and the output of layer 4, each [batch][channels][parity][Vh][3]
  * complex64 (1, C, C, C and 1 channels), every block starting at a multiple
- * of 256 bytes from the buffer's start.  The kernels read these buffers with
- * 16-byte loads: acts and workspace (and fcg_solve's workspace) must be
- * 16-byte aligned (device allocations are 256-byte aligned), else
- * HISQ_EINVAL. */
+ * of 256 bytes from the buffer's start. */
 size_t net_act_bytes(const int dims[4], int channels, int batch);
 size_t net_backward_ws_bytes(const int dims[4], int channels, int batch);
 int net_forward(const void *fat, const void *weights, int channels, const void *in, void *out, void *acts,

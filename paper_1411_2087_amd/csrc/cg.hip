@@ -1014,6 +1014,8 @@ extern "C" int cg_solve(double mass, double tol, const void *fat, const void *ln
     if (rc) return st.status = rc;
     hisq_cg_opts o = resolve_opts(opts, g);
     if (!fat || !lng || !b || !x) return st.status = fail(HISQ_EINVAL, "cg_solve: NULL pointer");
+    if (!aligned16({fat, lng, fat_lo, lng_lo, b, x, workspace}))
+        return st.status = fail(HISQ_EINVAL, "cg_solve: device pointers must be 16-byte aligned");
     if (b == x) return st.status = fail(HISQ_EALIAS, "cg_solve: b and x alias");
     if (!(tol > 0) || !(mass >= 0)) return st.status = fail(HISQ_EINVAL, "cg_solve: need tol > 0 and mass >= 0");
     if (o.mode != HISQ_CG_PLAIN_F64 && o.mode != HISQ_CG_PLAIN_F64C && (!fat_lo || !lng_lo))
@@ -1080,6 +1082,8 @@ extern "C" int hisq_dot(const void *x, const void *y, long long n, int prec, dou
                         size_t ws_bytes, void *stream)
 {
     if (!x || !y || !out_host || n < 0) return fail(HISQ_EINVAL, "hisq_dot: bad argument");
+    if (!aligned16({x, y, workspace}))
+        return fail(HISQ_EINVAL, "hisq_dot: device pointers must be 16-byte aligned");
     if (prec < HISQ_F64 || prec > HISQ_I16SC) return fail(HISQ_EINVAL, "hisq_dot: bad precision");
     if (!workspace || ws_bytes < DOT_WS_BYTES)
         return fail(HISQ_EWORKSPACE, "hisq_dot: workspace NULL or smaller than hisq_workspace_bytes(\"dot\")");

@@ -1799,6 +1799,8 @@ extern "C" int cg_solve_multi(int nrhs, const double *masses, double tol, int mo
     if (nrhs < 1 || nrhs > MAXR) return fail(HISQ_EINVAL, "cg_solve_multi: nrhs must be 1..16");
     if (mode != HISQ_MULTI_RHS && mode != HISQ_MULTI_SHIFT) return fail(HISQ_EINVAL, "cg_solve_multi: unknown mode");
     if (!masses || !fat || !lng || !fat_lo || !lng_lo || !b || !x) return fail(HISQ_EINVAL, "cg_solve_multi: NULL pointer");
+    if (!aligned16({fat, lng, fat_lo, lng_lo, b, x, workspace}))
+        return fail(HISQ_EINVAL, "cg_solve_multi: device pointers must be 16-byte aligned");
     if (b == x) return fail(HISQ_EALIAS, "cg_solve_multi: b and x alias");
     if (!(tol > 0)) return fail(HISQ_EINVAL, "cg_solve_multi: need tol > 0");
     for (int r = 0; r < nrhs; ++r)
@@ -1838,6 +1840,8 @@ extern "C" int hisq_tune_multi(const void *fat, const void *lng, const void *src
     int rc = make_geom(dims, g);
     if (rc) return rc;
     if (!fat || !lng || !src || !dst || !workspace) return fail(HISQ_EINVAL, "hisq_tune_multi: NULL pointer");
+    if (!aligned16({fat, lng, src, dst, workspace}))
+        return fail(HISQ_EINVAL, "hisq_tune_multi: device pointers must be 16-byte aligned");
     if (src == dst) return fail(HISQ_EALIAS, "hisq_tune_multi: src and dst alias");
     if (nrhs != pad_n(nrhs) || nrhs > MAXR) return fail(HISQ_EINVAL, "hisq_tune_multi: nrhs must be 1, 2, 4, 8 or 16");
     if (reps <= 0) reps = 10;
@@ -1858,6 +1862,8 @@ extern "C" int hisq_dslash_multi(const void *fat, const void *lng, const void *s
     int rc = make_geom(dims, g);
     if (rc) return rc;
     if (!fat || !lng || !src || !dst || !workspace) return fail(HISQ_EINVAL, "hisq_dslash_multi: NULL pointer");
+    if (!aligned16({fat, lng, src, dst, workspace}))
+        return fail(HISQ_EINVAL, "hisq_dslash_multi: device pointers must be 16-byte aligned");
     if (src == dst) return fail(HISQ_EALIAS, "hisq_dslash_multi: src and dst alias");
     if (parity != 0 && parity != 1) return fail(HISQ_EINVAL, "hisq_dslash_multi: parity must be 0 or 1");
     if (nrhs != pad_n(nrhs) || nrhs > MAXR) return fail(HISQ_EINVAL, "hisq_dslash_multi: nrhs must be 1, 2, 4, 8 or 16");

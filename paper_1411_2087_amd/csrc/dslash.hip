@@ -167,6 +167,8 @@ extern "C" int dslash_apply(const void *fat, const void *lng, const void *src, v
     int rc = make_geom(dims, g);
     if (rc) return rc;
     if (!fat || !lng || !src || !dst) return fail(HISQ_EINVAL, "dslash_apply: NULL pointer");
+    if (!aligned16({fat, lng, src, dst}))
+        return fail(HISQ_EINVAL, "dslash_apply: device pointers must be 16-byte aligned");
     if (parity != 0 && parity != 1) return fail(HISQ_EINVAL, "dslash_apply: parity must be 0 or 1");
     if (src == dst) return fail(HISQ_EALIAS, "dslash_apply: src and dst alias");
     hipStream_t s = (hipStream_t)stream;
@@ -192,6 +194,8 @@ extern "C" int hisq_apply_A(double mass, const void *fat, const void *lng, const
     int rc = make_geom(dims, g);
     if (rc) return rc;
     if (!fat || !lng || !x || !y || !tmp) return fail(HISQ_EINVAL, "hisq_apply_A: NULL pointer");
+    if (!aligned16({fat, lng, x, y, tmp}))
+        return fail(HISQ_EINVAL, "hisq_apply_A: device pointers must be 16-byte aligned");
     if (x == y || x == tmp || y == tmp) return fail(HISQ_EALIAS, "hisq_apply_A: x, y, tmp must be distinct");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;

@@ -18,7 +18,6 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <cstdint>
 #include <cstring>
 
 #include "cg_internal.hpp"
@@ -497,7 +496,8 @@ extern "C" int fcg_solve(double mass, double tol, const void *fat, const void *l
     if (!(tol > 0) || !(mass >= 0)) return st.status = fail(HISQ_EINVAL, "fcg_solve: need tol > 0 and mass >= 0");
     if (!workspace || ws_bytes < fcg_ws_bytes(g, channels))
         return st.status = fail(HISQ_EWORKSPACE, "fcg_solve: workspace NULL or smaller than hisq_workspace_bytes()");
-    if ((uintptr_t)workspace & 15) return st.status = fail(HISQ_EINVAL, "fcg_solve: workspace must be 16-byte aligned");
+    if (!aligned16({fat, lng, fat32, weights, b, x, workspace}))
+        return st.status = fail(HISQ_EINVAL, "fcg_solve: device pointers must be 16-byte aligned");
     hisq_cg_opts o = resolve_opts(opts, g);
     if (!opts || opts->check_every <= 0) o.check_every = 10;
     hipStream_t s = (hipStream_t)stream;

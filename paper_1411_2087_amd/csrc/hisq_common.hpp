@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <initializer_list>
 #include <string>
 
 #include "../../include/hisq.h"
@@ -16,6 +17,15 @@ namespace hisq {
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
+// The kernels read fields, links and workspaces with 16-byte loads: every
+// device pointer an entry point takes must be 16-byte aligned (device
+// allocations are 256-byte aligned).  NULL counts as aligned.
+inline bool aligned16(std::initializer_list<const void *> ps)
+{
+    for (const void *p : ps)
+        if (reinterpret_cast<uintptr_t>(p) & 15) return false;
+    return true;
+}
 
 #define HISQ_HIP(call)                                        \
     do {                                                      \

@@ -300,6 +300,8 @@ extern "C" int hisq_three_link(const void *thin, void *out, const int dims[4], v
     int rc = make_lex(dims, l);
     if (rc) return rc;
     if (!thin || !out) return fail(HISQ_EINVAL, "hisq_three_link: NULL pointer");
+    if (!aligned16({thin, out}))
+        return fail(HISQ_EINVAL, "hisq_three_link: device pointers must be 16-byte aligned");
     const size_t bytes = (size_t)l.V * 4 * 144;
     if (overlaps(thin, bytes, out, bytes)) return fail(HISQ_EALIAS, "hisq_three_link: out overlaps thin");
     dim3 grid((unsigned)((l.V + LNT - 1) / LNT), 4);
@@ -315,6 +317,8 @@ extern "C" int hisq_fat_paths(const void *thin, const double coeff[5], void *out
     int rc = make_lex(dims, l);
     if (rc) return rc;
     if (!thin || !out || !coeff) return fail(HISQ_EINVAL, "hisq_fat_paths: NULL pointer");
+    if (!aligned16({thin, out, workspace}))
+        return fail(HISQ_EINVAL, "hisq_fat_paths: device pointers must be 16-byte aligned");
     for (int i = 0; i < 5; ++i)
         if (!std::isfinite(coeff[i])) return fail(HISQ_EINVAL, "hisq_fat_paths: coefficient not finite");
     const size_t bytes = (size_t)l.V * 4 * 144;
@@ -379,6 +383,8 @@ extern "C" int hisq_fold_links(void *links, const int dims[4], int hop, int anti
     int rc = make_lex(dims, l);
     if (rc) return rc;
     if (!links) return fail(HISQ_EINVAL, "hisq_fold_links: NULL pointer");
+    if (!aligned16({links}))
+        return fail(HISQ_EINVAL, "hisq_fold_links: device pointers must be 16-byte aligned");
     if (hop != 1 && hop != 3) return fail(HISQ_EINVAL, "hisq_fold_links: hop must be 1 or 3");
     dim3 grid((unsigned)((l.V + LNT - 1) / LNT), 4);
     hipLaunchKernelGGL(k_fold<LNT>, grid, dim3(LNT), 0, (hipStream_t)stream, l, (double2 *)links, hop,

@@ -32,7 +32,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstdint>
 #include <cstring>
 #include <type_traits>
 
@@ -1276,7 +1275,8 @@ extern "C" int net_forward(const void *fat, const void *weights, int channels, c
     if (batch < 1) return fail(HISQ_EINVAL, "net_forward: batch must be >= 1");
     if (!fat || !weights || !in || !acts) return fail(HISQ_EINVAL, "net_forward: NULL pointer");
     if (act_bytes < net_act_bytes_g(g, channels, batch)) return fail(HISQ_EWORKSPACE, "net_forward: acts buffer too small");
-    if ((uintptr_t)acts & 15) return fail(HISQ_EINVAL, "net_forward: acts must be 16-byte aligned");
+    if (!aligned16({fat, weights, in, out, acts}))
+        return fail(HISQ_EINVAL, "net_forward: device pointers must be 16-byte aligned");
     if (in == out) return fail(HISQ_EALIAS, "net_forward: in and out alias");
     return net_forward_dispatch(g, fat, weights, channels, in, out, acts, batch, (hipStream_t)stream);
 }
@@ -1293,8 +1293,8 @@ extern "C" int net_backward(const void *fat, const void *weights, int channels, 
     if (!fat || !weights || !acts || !grad_out || !grad_w || !workspace) return fail(HISQ_EINVAL, "net_backward: NULL pointer");
     if (act_bytes < net_act_bytes_g(g, channels, batch)) return fail(HISQ_EWORKSPACE, "net_backward: acts buffer too small");
     if (ws_bytes < net_bwd_ws_bytes_g(g, channels, batch)) return fail(HISQ_EWORKSPACE, "net_backward: workspace too small");
-    if (((uintptr_t)acts | (uintptr_t)workspace) & 15)
-        return fail(HISQ_EINVAL, "net_backward: acts and workspace must be 16-byte aligned");
+    if (!aligned16({fat, weights, acts, grad_out, grad_w, grad_in, workspace}))
+        return fail(HISQ_EINVAL, "net_backward: device pointers must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     switch (channels) {
     case 4: return net_backward_t<4>(g, fat, (const float2 *)weights, acts, (const float2 *)grad_out, (float2 *)grad_w, (float2 *)grad_in, batch, workspace, s);
@@ -1312,6 +1312,8 @@ extern "C" int net_transport(const void *fat, const void *in, void *out, int cha
     if (channels != 1 && !net_channels_ok(channels)) return fail(HISQ_EINVAL, "net_transport: channels must be 1, 4, 8 or 16");
     if (batch < 1) return fail(HISQ_EINVAL, "net_transport: batch must be >= 1");
     if (!fat || !in || !out) return fail(HISQ_EINVAL, "net_transport: NULL pointer");
+    if (!aligned16({fat, in, out}))
+        return fail(HISQ_EINVAL, "net_transport: device pointers must be 16-byte aligned");
     if (in == out) return fail(HISQ_EALIAS, "net_transport: in and out alias");
     const dim3 grid(g.ntiles, 2, batch);
     hipStream_t s = (hipStream_t)stream;
@@ -1332,6 +1334,8 @@ extern "C" int net_loss(const void *y, const void *x, int batch, const int dims[
     int rc = make_geom(dims, g);
     if (rc) return rc;
     if (!y || !x || batch < 1) return fail(HISQ_EINVAL, "net_loss: bad argument");
+    if (!aligned16({y, x, grad_y, workspace}))
+        return fail(HISQ_EINVAL, "net_loss: device pointers must be 16-byte aligned");
     const int nb = 64;
     const size_t need = a256((size_t)batch * nb * 2 * sizeof(double)) + a256((size_t)(batch + 1) * sizeof(double));
     if (!workspace || ws_bytes < need) return fail(HISQ_EWORKSPACE, "net_loss: workspace too small");
@@ -1358,6 +1362,8 @@ extern "C" int net_adam_step(void *weights, const void *grad_w, void *m, void *v
 {
     if (!weights || !grad_w || !m || !v || n_complex <= 0 || step < 1 || !(lr > 0))
         return fail(HISQ_EINVAL, "net_adam_step: bad argument");
+    if (!aligned16({weights, grad_w, m, v}))
+        return fail(HISQ_EINVAL, "net_adam_step: device pointers must be 16-byte aligned");
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = (float)(1.0 - std::pow(0.9, step)), c2 = (float)(1.0 - std::pow(0.999, step));
     const long long n = 2 * n_complex;

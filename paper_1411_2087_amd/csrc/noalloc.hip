@@ -52,6 +52,8 @@ using namespace hisq;
 extern "C" int hisq_dot_noalloc(const void *x, const void *y, long long n, int prec, double out_host[2], void *stream)
 {
     if (!x || !y || !out_host || n < 0) return fail(HISQ_EINVAL, "hisq_dot_noalloc: bad argument");
+    if (!aligned16({x, y}))
+        return fail(HISQ_EINVAL, "hisq_dot_noalloc: device pointers must be 16-byte aligned");
     if (n > NOALLOC_MAX_N) return fail(HISQ_EINVAL, "hisq_dot_noalloc: n exceeds 2^37 complex entries");
     if (prec < HISQ_F64 || prec > HISQ_I16SC) return fail(HISQ_EINVAL, "hisq_dot_noalloc: bad precision");
     void *ws = nullptr;

@@ -263,6 +263,8 @@ extern "C" int hisq_pack_links(const void *fat_canon, const void *long_canon, co
     int rc = make_geom(dims, g);
     if (rc) return rc;
     if (!fat_canon || !long_canon || !fat_out || !long_out) return fail(HISQ_EINVAL, "hisq_pack_links: NULL pointer");
+    if (!aligned16({fat_canon, long_canon, fat_out, long_out}))
+        return fail(HISQ_EINVAL, "hisq_pack_links: device pointers must be 16-byte aligned");
     if (fat_out == long_out) return fail(HISQ_EALIAS, "hisq_pack_links: fat_out and long_out alias");
     const size_t bb = dir_block_bytes(prec);
     if (!bb) return fail(HISQ_EINVAL, "hisq_pack_links: unknown precision");

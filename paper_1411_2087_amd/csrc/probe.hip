@@ -39,6 +39,8 @@ extern "C" int hisq_read_probe(const void *buf, size_t bytes, void *sink, size_t
 {
     constexpr int GRID = 8192;
     if (!buf || !sink || !us) return fail(HISQ_EINVAL, "hisq_read_probe: NULL pointer");
+    if (!aligned16({buf, sink}))
+        return fail(HISQ_EINVAL, "hisq_read_probe: device pointers must be 16-byte aligned");
     if (bytes < 16 || sink_bytes < GRID * sizeof(double))
         return fail(HISQ_EINVAL, "hisq_read_probe: need bytes >= 16 and sink_bytes >= 65536");
     if (reps <= 0) reps = 5;

@@ -158,6 +158,8 @@ extern "C" int hisq_tune_dslash(const void *fat, const void *lng, const void *sr
     int rc = make_geom(dims, g);
     if (rc) return rc;
     if (!fat || !lng || !src || !dst) return fail(HISQ_EINVAL, "hisq_tune_dslash: NULL pointer");
+    if (!aligned16({fat, lng, src, dst}))
+        return fail(HISQ_EINVAL, "hisq_tune_dslash: device pointers must be 16-byte aligned");
     if (src == dst) return fail(HISQ_EALIAS, "hisq_tune_dslash: src and dst alias");
     if (reps <= 0) reps = 20;
     hipStream_t s = (hipStream_t)stream;

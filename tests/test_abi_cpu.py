@@ -141,16 +141,52 @@ def test_dot_noalloc_validation_without_gpu():
     assert lib.hisq_dot_noalloc(p[0], p[1], 10, 9, out, None) == -1
 
 
-def test_network_alignment_validation_without_gpu():
-    """The network's activation and workspace buffers are read with 16-byte loads: a misaligned one is refused
-    before any GPU work."""
+def test_alignment_validation_without_gpu():
+    """Fields, links and workspaces are read with 16-byte loads: every entry point refuses a device pointer
+    that is not 16-byte aligned, before any GPU work."""
     import paper_1411_2087_amd as hq
     lib = hq._lib
     dims = (ctypes.c_int * 4)(4, 4, 4, 4)
-    p = [ctypes.c_void_p(0x10000 * (i + 1)) for i in range(4)]
+    p = [ctypes.c_void_p(0x10000 * (i + 1)) for i in range(8)]
     bad = ctypes.c_void_p(0x10008)
-    assert lib.net_forward(p[0], p[1], 4, p[2], p[3], bad, 1 << 40, 1, dims, None) == -1
-    assert b"aligned" in lib.hisq_last_error()
-    assert lib.net_backward(p[0], p[1], 4, bad, 1 << 40, p[2], p[3], None, 1, dims, p[3], 1 << 40, None) == -1
-    assert lib.net_backward(p[0], p[1], 4, p[2], 1 << 40, p[2], p[3], None, 1, dims, bad, 1 << 40, None) == -1
-    assert b"aligned" in lib.hisq_last_error()
+    big = 1 << 40
+    out = (ctypes.c_double * 2)()
+    coeff = (ctypes.c_double * 5)(1, 0, 0, 0, 0)
+    st = hq.CGStats()
+    o = hq.CGOpts(mode=0, max_iter=0, check_every=0, use_graph=1, delta=0.0)
+    masses = (ctypes.c_double * 2)(0.01, 0.1)
+    best, us = ctypes.c_int(), (ctypes.c_double * 16)()
+    calls = {
+        "hisq_pack_links": lambda: lib.hisq_pack_links(p[0], p[1], dims, 0, bad, p[2], None),
+        "dslash_apply": lambda: lib.dslash_apply(p[0], p[1], bad, p[2], 0, dims, 0, None),
+        "hisq_apply_A": lambda: lib.hisq_apply_A(0.1, p[0], p[1], p[2], p[3], bad, dims, 0, None),
+        "hisq_dot": lambda: lib.hisq_dot(p[0], p[1], 10, 0, out, bad, big, None),
+        "hisq_dot_noalloc": lambda: lib.hisq_dot_noalloc(bad, p[1], 10, 0, out, None),
+        "hisq_tune_dslash": lambda: lib.hisq_tune_dslash(p[0], bad, p[1], p[2], dims, 0, 1, ctypes.byref(best), us,
+                                                         None),
+        "cg_solve": lambda: lib.cg_solve(0.1, 1e-10, p[0], p[1], None, None, bad, p[2], dims, ctypes.byref(o), p[3],
+                                         big, ctypes.byref(st), None),
+        "cg_solve_multi": lambda: lib.cg_solve_multi(2, masses, 1e-10, hq.HISQ_MULTI_RHS, p[0], p[1], p[2], p[3],
+                                                     p[4], p[5], dims, None, bad, big, None, None),
+        "hisq_dslash_multi": lambda: lib.hisq_dslash_multi(p[0], p[1], p[2], bad, 0, 8, dims, p[3], big, None),
+        "hisq_tune_multi": lambda: lib.hisq_tune_multi(p[0], p[1], p[2], p[3], dims, 8, bad, big, 1,
+                                                       ctypes.byref(best), us, None),
+        "net_forward": lambda: lib.net_forward(p[0], p[1], 4, p[2], p[3], bad, big, 1, dims, None),
+        "net_backward acts": lambda: lib.net_backward(p[0], p[1], 4, bad, big, p[2], p[3], None, 1, dims, p[4], big,
+                                                      None),
+        "net_backward workspace": lambda: lib.net_backward(p[0], p[1], 4, p[2], big, p[3], p[4], None, 1, dims, bad,
+                                                           big, None),
+        "net_transport": lambda: lib.net_transport(p[0], bad, p[1], 4, 1, dims, None),
+        "net_loss": lambda: lib.net_loss(p[0], bad, 1, dims, None, None, p[1], big, None),
+        "net_adam_step": lambda: lib.net_adam_step(p[0], p[1], p[2], bad, 10, 1e-3, 1, None),
+        "fcg_solve": lambda: lib.fcg_solve(0.1, 1e-10, p[0], p[1], p[2], p[3], 4, p[4], p[5], dims, None, bad, big,
+                                           ctypes.byref(st), None),
+        "hisq_three_link": lambda: lib.hisq_three_link(bad, p[0], dims, None),
+        "hisq_fat_paths": lambda: lib.hisq_fat_paths(p[0], coeff, p[1], dims, bad, big, None),
+        "hisq_fold_links": lambda: lib.hisq_fold_links(bad, dims, 1, 1, None),
+        "hisq_read_probe": lambda: lib.hisq_read_probe(bad, 1 << 20, p[0], 1 << 20, 1, us, None),
+    }
+    for name, call in calls.items():
+        assert call() == -1, name
+        assert b"16-byte aligned" in lib.hisq_last_error(), (name, lib.hisq_last_error())
+
