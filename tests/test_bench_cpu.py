@@ -49,6 +49,18 @@ def test_cg_traffic_profile_matches_the_cg_sources():
         assert bench.cg_traffic_from_profile(vh, name) == round(row["bytes_per_launch"])
 
 
+
+def test_net_traffic_profile_matches_the_network_sources():
+    """The network kernels' committed traffic belongs to the current sources, and every kernel moves at least
+    its algorithmic bytes."""
+    import bench
+    with open(bench.NET_TRAFFIC_FILE) as f:
+        t = json.load(f)
+    assert t["source_sha"] == bench.dslash_source_sha(bench.NET_SOURCES), \
+        "network kernel sources changed since the FETCH_SIZE/WRITE_SIZE runs: rerun them and regenerate the profile"
+    for name, row in t["kernels"].items():
+        assert 0.98 <= row["bytes_per_launch"] / row["algorithmic_bytes"] <= 3.0, name
+
 def test_counter_summary_calibration(tmp_path, monkeypatch, capsys):
     """--counter-summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by what they read for the 1 GiB
     device copy, averages per kernel and divides by the algorithmic bytes: checked on synthetic counter files."""
