@@ -134,14 +134,21 @@ template <class P>
 static int tune_dslash_impl(const Geom &g, const void *fat, const void *lng, const void *src, void *dst, int reps,
                             int *best, double *us_out, hipStream_t s)
 {
-    double best_us = 1e300;
-    int best_i = 0;
+    double best_us = 1e300, plain_us = 1e300;
+    int best_i = 0, plain_i = -1;
     for (int i = 0; i < N_DSLASH_SHAPES; ++i) {
         double us = time_launches([&]() { return launch_dslash_shape<P>(i, g, fat, lng, src, dst, 1, s); }, reps, s);
         if (us_out) us_out[i] = us;
         if (us < 0) return fail(HISQ_EHIP, "autotune: timing failed");
         if (us < best_us) { best_us = us; best_i = i; }
+        if (DSLASH_SHAPES[i].order == 0 && us < plain_us) { plain_us = us; plain_i = i; }
     }
+    // FP64: the plain CG's fused kernels take the tile order of this choice, and inside the solve every blocked
+    // order is slower than the plain one (32^4, m = 0.01: 1.80-1.86 s against 1.76 s per solve, the same in
+    // three alternating rounds), while the bare Dslash times the orders within 2 % of each other either way.
+    // A blocked shape is kept only when it beats the best plain-order shape by more than 3 %.
+    if (P::prec == HISQ_F64 && plain_i >= 0 && DSLASH_SHAPES[best_i].order != 0 && best_us > 0.97 * plain_us)
+        best_i = plain_i;
     set_tuned_dslash_shape(g, P::prec, best_i);
     if (best) *best = best_i;
     return HISQ_OK;
