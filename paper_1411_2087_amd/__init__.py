@@ -65,7 +65,7 @@ class CGStats(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        raise ImportError(f"{LIB_PATH} is not built; run python paper_1411_2087_amd/build.py (hipcc, gfx950)")
     lib = ctypes.CDLL(LIB_PATH)
     vp, ip, sz, d = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_size_t, ctypes.c_double
     lib.hisq_version.restype = ctypes.c_char_p
