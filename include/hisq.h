@@ -236,7 +236,11 @@ int hisq_dot_noalloc(const void *x, const void *y, long long n, int prec, double
  * buffers (dst = D src on parity 1, `reps` launches each, 20 if <= 0),
  * remembers the fastest for (dims, prec) in this process -- and in the file
  * named by the environment variable HISQ_TUNE_CACHE, if set -- and uses it
- * in every later Dslash of that lattice and precision.  All shapes give
+ * in every later Dslash of that lattice and precision.  The plain CG's fused
+ * kernels take the tile order of the chosen shape; for HISQ_F64 a shape with
+ * a blocked tile order is chosen only when it is more than 3 % faster than
+ * the fastest plain-order shape (the blocked orders slow the CG solve down
+ * although the bare Dslash times them close to the plain one).  All shapes give
  * bitwise-identical results.  best_shape (may be NULL) receives the chosen
  * index, us_per_shape (may be NULL, room for hisq_dslash_shape(dims, prec,
  * -2) entries) the measured microseconds.  Synchronises `stream`. */
